@@ -1,0 +1,126 @@
+/*
+ * fpmul.h -- C ABI of the MI355X (gfx950) library that multiplies long bit
+ * polynomials in GF(2)[x] with the Frobenius-partition additive FFT of
+ * Chen, Cheng, Kuo, Li and Yang, "Multiplying boolean Polynomials with
+ * Frobenius Partitions in Additive Fast Fourier Transform" (arXiv 1803.11301).
+ *
+ * Data layout (all entry points)
+ *   A bit polynomial of length L bits is ceil(L / 64) 64-bit words; bit k
+ *   (the coefficient of x^k) is bit (k % 64) of word (k / 64), little-endian.
+ *   Bits at or above L in the last input word are ignored.
+ *
+ * Memory ownership
+ *   Every data pointer below is a DEVICE pointer (memory of the GPU the
+ *   context was made for, e.g. allocated by torch).  The caller owns it; the
+ *   library never frees it.  The library owns its own workspace and constant
+ *   tables, held by the context.
+ *
+ * Errors
+ *   Every int-returning call returns 0 on success or a negative errno-style
+ *   code: POLYMUL_EINVAL (bad argument: null or host pointer, overlapping
+ *   output, length beyond the limit), POLYMUL_ENOMEM (workspace above the
+ *   context's cap, or a failed device allocation), POLYMUL_EIO (a HIP runtime
+ *   error).  polymul_last_error() gives the message of the last failure on
+ *   the calling thread.  A failed call leaves its output undefined.
+ *
+ * Threading and streams
+ *   A context owns one workspace, so calls on one context must be ordered:
+ *   issue them from one host thread, on one stream (or synchronise between
+ *   streams).  Different contexts are independent.
+ */
+#ifndef FPMUL_H
+#define FPMUL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define POLYMUL_OK 0
+#define POLYMUL_EIO (-5)
+#define POLYMUL_ENOMEM (-12)
+#define POLYMUL_EINVAL (-22)
+
+/* Largest supported product length in bits: n <= (m/2) 2^(m/2) with m = 64
+ * (Sec. 3.1, the bound that follows Prop. 2; the partition needs l < m/2). */
+#define POLYMUL_MAX_PRODUCT_BITS (1ull << 37)
+
+typedef struct polymul_ctx polymul_ctx;
+
+/*
+ * polymul -- C = A * B in GF(2)[x]  (Alg. 5, FP_Polymul).
+ *
+ * a_bits, b_bits: device words of A (len_a bits) and B (len_b bits).
+ * out: device words, at least ceil((len_a + len_b - 1) / 64); exactly
+ *      len_a + len_b - 1 bits are written and the rest of the last word is
+ *      zeroed.  If len_a or len_b is 0 the product is empty and nothing is
+ *      written.  out must not overlap a_bits or b_bits.
+ * Uses a context owned by the library for the current HIP device and that
+ * device's null stream; returns after the result is in out.
+ * len_a + len_b - 1 > POLYMUL_MAX_PRODUCT_BITS -> POLYMUL_EINVAL.
+ */
+int polymul(const uint64_t *a_bits, uint64_t len_a, const uint64_t *b_bits, uint64_t len_b,
+            uint64_t *out);
+
+/*
+ * polymul_ctx_create -- context for GPU `device`: uploads the constant tables
+ * (Cantor basis, Encode matrix and its inverse, butterfly multiplier tables)
+ * and holds a workspace that grows on demand up to workspace_cap bytes
+ * (0 = no cap beyond device memory).
+ */
+int polymul_ctx_create(polymul_ctx **ctx, int device, size_t workspace_cap);
+int polymul_ctx_destroy(polymul_ctx *ctx);
+
+/*
+ * polymul_ex -- same product as polymul(), stream-ordered on `stream`
+ * (a hipStream_t; NULL = null stream).  Returns once the work is enqueued;
+ * the result is in out when the stream reaches that point.
+ */
+int polymul_ex(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a,
+               const uint64_t *b_bits, uint64_t len_b, uint64_t *out, void *stream);
+
+/*
+ * polymul_addfft -- the modified additive FFT of Sec. 3.4: BasisCvt (Alg. 1),
+ * Encode (Alg. 4) and Butterfly (Alg. 2) at alpha = v_{l+32}.  Evaluates A
+ * (len_a bits, len_a <= 2^log2n) at the n/64 points of the Frobenius
+ * partition Sigma = v_{l+32} + V_l, l = log2n - 6 (Eq. 5, Eq. 8).
+ * values: device, 2^(log2n-6) words; word j is A(v_{l+32} + j) with j read
+ * as Cantor coordinates, each value a GF(2^64) element written in the
+ * polynomial basis modulo x^64 + x^4 + x^3 + x + 1 (Sec. 4.3).
+ * 6 <= log2n <= 37.
+ */
+int polymul_addfft(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a, int log2n,
+                   uint64_t *values, void *stream);
+
+/*
+ * polymul_iaddfft -- inverse of polymul_addfft for the same log2n:
+ * iButterfly, Decode and iBasisCvt (Alg. 5 lines 8-10).  Reads 2^(log2n-6)
+ * values, writes the first out_bits bits (<= 2^log2n) of the polynomial of
+ * degree < 2^log2n they determine (Prop. 2), zeroing the rest of the last
+ * word.  values is not modified.
+ */
+int polymul_iaddfft(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_t *out,
+                    uint64_t out_bits, void *stream);
+
+/*
+ * polymul_basiscvt -- Alg. 1 alone: monomial -> novelpoly coefficients of a
+ * bit polynomial of len bits, written as 2^log2n bits (log2n >= ceil(log2
+ * len), zero-padded).  inverse != 0 runs iBasisCvt on 2^log2n bits instead.
+ * out receives ceil(2^log2n / 64) words and must not overlap in.
+ */
+int polymul_basiscvt(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int log2n, int inverse,
+                     uint64_t *out, void *stream);
+
+/* Message of the last failure on this thread ("" if none). */
+const char *polymul_last_error(void);
+
+/* Library version string. */
+const char *polymul_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPMUL_H */

@@ -1,0 +1,673 @@
+// fpmul.hip -- gfx950 kernels and the C ABI (include/fpmul.h) for the product
+// of bit polynomials with Frobenius partitions in the additive FFT.
+//
+// Pipeline of one product (Alg. 5, FP_Polymul), n = transform length in bits,
+// l = log2(n) - 6, n_p = 2^l points of Sigma = v_{l+32} + V_l (Eq. 5):
+//   BasisCvt(A), Encode, Butterfly      (Alg. 1, Alg. 4, Alg. 2 at v_{l+32})
+//   BasisCvt(B), Encode, Butterfly
+//   pointwise products in GF(2^64)      (Alg. 5 line 7)
+//   iButterfly, Decode, iBasisCvt       (Alg. 5 lines 8-10)
+//
+// Field elements are uint64_t in the polynomial basis modulo
+// x^64 + x^4 + x^3 + x + 1 (Sec. 4.3).  Butterfly multipliers are built on the
+// device from Cantor coordinates: layer i of block b multiplies by
+// s_i(v_{l+32} + b 2^(i+1)) whose Cantor vector is 2^(32+d) XOR 2b, d = l - i
+// (Eq. 4 and the recursion of Alg. 2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cerrno>
+#include <cstdint>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fpmul.h"
+#include "consts_host.h"
+
+#define FPMUL_VERSION "fpmul 0.1 (gfx950)"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t _e = (expr);                                                         \
+        if (_e != hipSuccess)                                                           \
+            return fail(POLYMUL_EIO, std::string(#expr ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+#define LAUNCH_CHECK(name)                                                               \
+    do {                                                                                 \
+        hipError_t _e = hipGetLastError();                                               \
+        if (_e != hipSuccess)                                                            \
+            return fail(POLYMUL_EIO, std::string("launch " name ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// device constants
+// ---------------------------------------------------------------------------
+
+struct DevTables {
+    uint64_t iota[8][256];   // Cantor vector -> polynomial representation, by bytes
+    uint64_t enc[64];        // Encode rows r_j
+    uint64_t dec[64];        // inverse Encode rows
+};
+
+// ---------------------------------------------------------------------------
+// GF(2^64) arithmetic on the device
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t gf_reduce(uint64_t lo, uint64_t hi)
+{
+    uint64_t t = hi ^ (hi << 1) ^ (hi << 3) ^ (hi << 4);
+    uint64_t o = (hi >> 63) ^ (hi >> 61) ^ (hi >> 60);
+    return lo ^ t ^ o ^ (o << 1) ^ (o << 3) ^ (o << 4);
+}
+
+// general product, one bit of b at a time
+__device__ __forceinline__ uint64_t gf_mul_generic(uint64_t a, uint64_t b)
+{
+    uint64_t lo = 0, hi = 0;
+    for (int i = 0; i < 64; ++i) {
+        uint64_t m = 0ull - ((b >> i) & 1ull);
+        lo ^= (a << i) & m;
+        hi ^= (i ? (a >> (64 - i)) : 0ull) & m;
+    }
+    return gf_reduce(lo, hi);
+}
+
+__device__ __forceinline__ uint64_t iota_dev(const DevTables *T, uint64_t cvec)
+{
+    uint64_t r = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r ^= T->iota[k][(cvec >> (8 * k)) & 255u];
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// elementary kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t gid() { return (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// dst[0 .. dst_words) = src bits [0, len) zero-padded
+__global__ void k_load_mask(const uint64_t *__restrict__ src, uint64_t len, uint64_t *__restrict__ dst,
+                            uint64_t dst_words)
+{
+    uint64_t w = gid();
+    if (w >= dst_words) return;
+    uint64_t nw = (len + 63) / 64;
+    uint64_t v = 0;
+    if (w < nw) {
+        v = src[w];
+        if (w == nw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+    }
+    dst[w] = v;
+}
+
+// out[0 .. ceil(len/64)) = src bits [0, len), tail zeroed
+__global__ void k_store_mask(const uint64_t *__restrict__ src, uint64_t len, uint64_t *__restrict__ out)
+{
+    uint64_t w = gid();
+    uint64_t nw = (len + 63) / 64;
+    if (w >= nw) return;
+    uint64_t v = src[w];
+    if (w == nw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+    out[w] = v;
+}
+
+// ---------------------------------------------------------------------------
+// BasisCvt (Alg. 1) as a list of Taylor steps
+//
+// Alg. 1 writes f(x) = sum_j h_j(x) s^j with s = s_{2^k}(x) = x^tau + x
+// (tau = 2^(2^k) the largest with tau <= deg f), converts the sequence (h_j)
+// as a polynomial in y (block-vector coefficients, because X_j(s(x)) =
+// X_{j 2^(2^k)}(x)), and converts each tau-bit block.  The Taylor expansion
+// splits a segment of S coefficients in halves lo, hi of H = S/2 and uses
+// x^H = s^(H/tau) + x^(H/tau) (Frobenius in GF(2)[x]):
+//     hi[0, d) ^= hi[H-d, H);   lo[d, H) ^= hi[0, H-d);   d = H / tau,
+// then recurses on both halves.  Every step is such a pair on all S-aligned
+// segments; outer (block-vector) steps are the same with element size tau.
+// The inverse undoes the two updates in reverse order.
+// ---------------------------------------------------------------------------
+
+struct BStep {
+    uint64_t S, d;   // segment length and shift, in bits
+};
+
+static void bcvt_steps(uint64_t N, uint64_t e, std::vector<BStep> &out)
+{
+    if (N <= 2) return;
+    uint64_t tau = 2;
+    while (tau * tau > tau && tau * tau <= N / 2) tau = tau * tau;
+    for (uint64_t S = N; S >= 2 * tau; S /= 2) out.push_back({S * e, (S / (2 * tau)) * e});
+    bcvt_steps(N / tau, tau * e, out);   // outer conversion on tau-element blocks
+    bcvt_steps(tau, e, out);             // inner conversion of each block
+}
+
+__device__ __forceinline__ uint64_t lowmask(int64_t x)
+{
+    return x >= 64 ? ~0ull : (x <= 0 ? 0ull : ((1ull << x) - 1ull));
+}
+
+__device__ __forceinline__ int64_t floordiv64(int64_t x) { return x >= 0 ? x / 64 : -((-x + 63) / 64); }
+
+// 64 bits of the half-array hp (HW words) from bit offset off; bits outside read 0
+__device__ __forceinline__ uint64_t bits_at(const uint64_t *hp, int64_t HW, int64_t off)
+{
+    int64_t i0 = floordiv64(off);
+    int s = (int)(off - i0 * 64);
+    uint64_t w0 = (i0 >= 0 && i0 < HW) ? hp[i0] : 0ull;
+    uint64_t w1 = (i0 + 1 >= 0 && i0 + 1 < HW) ? hp[i0 + 1] : 0ull;
+    return s ? ((w0 >> s) | (w1 << (64 - s))) : w0;
+}
+
+// word k of hi' = hi with hi[0, d) ^= hi[H-d, H)
+__device__ __forceinline__ uint64_t hi_prime(const uint64_t *hp, int64_t HW, int64_t H, int64_t d, int64_t k)
+{
+    uint64_t w = hp[k];
+    int64_t rem = d - 64 * k;
+    if (rem > 0) w ^= bits_at(hp, HW, 64 * k + H - d) & lowmask(rem);
+    return w;
+}
+
+__device__ __forceinline__ uint64_t bits_at_prime(const uint64_t *hp, int64_t HW, int64_t H, int64_t d, int64_t off)
+{
+    int64_t i0 = floordiv64(off);
+    int s = (int)(off - i0 * 64);
+    uint64_t w0 = (i0 >= 0 && i0 < HW) ? hi_prime(hp, HW, H, d, i0) : 0ull;
+    uint64_t w1 = (i0 + 1 >= 0 && i0 + 1 < HW) ? hi_prime(hp, HW, H, d, i0 + 1) : 0ull;
+    return s ? ((w0 >> s) | (w1 << (64 - s))) : w0;
+}
+
+// one step on words [0, nw); segments of S >= 128 bits; out-of-place
+__global__ void k_bcvt_step_wide(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t nw,
+                                 uint64_t S, uint64_t d, int inverse)
+{
+    uint64_t w = gid();
+    if (w >= nw) return;
+    const int64_t SW = (int64_t)(S / 64), HW = SW / 2, H = (int64_t)(S / 2);
+    const int64_t q = (int64_t)(w % (uint64_t)SW);
+    const uint64_t *seg = in + (w - (uint64_t)q);
+    const uint64_t *hp = seg + HW;
+    uint64_t r;
+    if (q >= HW) {
+        r = hi_prime(hp, HW, H, (int64_t)d, q - HW);
+    } else if (!inverse) {
+        r = seg[q] ^ bits_at_prime(hp, HW, H, (int64_t)d, 64 * q - (int64_t)d);
+    } else {
+        r = seg[q] ^ bits_at(hp, HW, 64 * q - (int64_t)d);
+    }
+    out[w] = r;
+}
+
+// one step with S <= 64 inside each word (L: low-half mask, D: low-d mask per segment)
+__global__ void k_bcvt_step_word(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t nw,
+                                 int H, int d, uint64_t L, uint64_t D, int inverse)
+{
+    uint64_t w = gid();
+    if (w >= nw) return;
+    uint64_t x = in[w];
+    uint64_t lo = x & L, hi = (x >> H) & L;
+    if (!inverse) {
+        hi ^= (hi >> (H - d)) & D;
+        lo ^= (hi << d) & L;
+    } else {
+        lo ^= (hi << d) & L;
+        hi ^= (hi >> (H - d)) & D;
+    }
+    out[w] = lo | (hi << H);
+}
+
+// ---------------------------------------------------------------------------
+// Encode (Alg. 4): f_i = sum_j a_{j n_p + i} r_j
+// ---------------------------------------------------------------------------
+
+__global__ void k_encode(const uint64_t *__restrict__ bits, int l, const DevTables *__restrict__ T,
+                         uint64_t *__restrict__ vals)
+{
+    uint64_t i = gid();
+    uint64_t n_p = 1ull << l;
+    if (i >= n_p) return;
+    uint64_t f = 0;
+    for (int j = 0; j < 64; ++j) {
+        uint64_t p = ((uint64_t)j << l) + i;
+        if ((bits[p >> 6] >> (p & 63)) & 1ull) f ^= T->enc[j];
+    }
+    vals[i] = f;
+}
+
+// Decode part 1: each value -> its 64 bits (a = XOR_{t in h} dec[t]), in place
+__global__ void k_decode_vec(uint64_t *__restrict__ vals, int l, const DevTables *__restrict__ T)
+{
+    uint64_t i = gid();
+    if (i >= (1ull << l)) return;
+    uint64_t h = vals[i], a = 0;
+    for (int t = 0; t < 64; ++t)
+        if ((h >> t) & 1ull) a ^= T->dec[t];
+    vals[i] = a;
+}
+
+// Decode part 2: bit j of vector i goes to bit j n_p + i
+__global__ void k_decode_scatter(const uint64_t *__restrict__ vecs, int l, uint64_t *__restrict__ bits)
+{
+    uint64_t W = gid();
+    uint64_t nw = 1ull << l;   // n / 64 words
+    if (W >= nw) return;
+    uint64_t mask = (1ull << l) - 1, r = 0;
+    for (int t = 0; t < 64; ++t) {
+        uint64_t p = 64 * W + t;
+        uint64_t j = p >> l, i = p & mask;
+        r |= ((vecs[i] >> j) & 1ull) << t;
+    }
+    bits[W] = r;
+}
+
+// ---------------------------------------------------------------------------
+// Butterfly (Alg. 2) layer i, and its inverse
+// ---------------------------------------------------------------------------
+
+__global__ void k_bfly_layer(uint64_t *__restrict__ v, int l, int i, int inverse, const DevTables *__restrict__ T)
+{
+    uint64_t t = gid();
+    if (t >= (1ull << (l - 1))) return;
+    uint64_t b = t >> i, off = t & ((1ull << i) - 1);
+    uint64_t p0 = (b << (i + 1)) | off, p1 = p0 | (1ull << i);
+    int d = l - i;
+    uint64_t c = iota_dev(T, (1ull << (32 + d)) ^ (b << 1));
+    uint64_t x0 = v[p0], x1 = v[p1];
+    if (!inverse) {
+        uint64_t h0 = x0 ^ gf_mul_generic(c, x1);
+        v[p0] = h0;
+        v[p1] = h0 ^ x1;
+    } else {
+        uint64_t q1 = x0 ^ x1;
+        v[p0] = x0 ^ gf_mul_generic(c, q1);
+        v[p1] = q1;
+    }
+}
+
+__global__ void k_pointwise(uint64_t *__restrict__ a, const uint64_t *__restrict__ b, uint64_t n)
+{
+    uint64_t i = gid();
+    if (i >= n) return;
+    a[i] = gf_mul_generic(a[i], b[i]);
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+struct polymul_ctx {
+    int device = 0;
+    size_t cap = 0;
+    uint64_t *ws[3] = {nullptr, nullptr, nullptr};
+    uint64_t ws_words = 0;   // words per workspace buffer
+    DevTables *tables = nullptr;
+};
+
+static unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+static int ensure_ws(polymul_ctx *ctx, uint64_t words)
+{
+    if (words <= ctx->ws_words) return 0;
+    size_t bytes = (size_t)words * 8;
+    if (ctx->cap && 3 * bytes > ctx->cap)
+        return fail(POLYMUL_ENOMEM, "workspace of " + std::to_string(3 * bytes) + " bytes exceeds the cap of " +
+                                        std::to_string(ctx->cap));
+    for (int k = 0; k < 3; ++k) {
+        if (ctx->ws[k]) { (void)hipFree(ctx->ws[k]); ctx->ws[k] = nullptr; }
+    }
+    ctx->ws_words = 0;
+    for (int k = 0; k < 3; ++k) {
+        hipError_t e = hipMalloc(&ctx->ws[k], bytes);
+        if (e != hipSuccess) {
+            for (int j = 0; j < 3; ++j)
+                if (ctx->ws[j]) { (void)hipFree(ctx->ws[j]); ctx->ws[j] = nullptr; }
+            return fail(POLYMUL_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
+        }
+    }
+    ctx->ws_words = words;
+    return 0;
+}
+
+static int check_dev_ptr(const void *p, const char *name)
+{
+    if (!p) return fail(POLYMUL_EINVAL, std::string(name) + " is null");
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(POLYMUL_EINVAL, std::string(name) + " is not a device pointer");
+    }
+    if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+        return fail(POLYMUL_EINVAL, std::string(name) + " is not device memory");
+    return 0;
+}
+
+static uint64_t next_pow2(uint64_t x)
+{
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+static int ilog2(uint64_t x)
+{
+    int r = 0;
+    while ((1ull << r) < x) ++r;
+    return r;
+}
+
+// run the BasisCvt steps for N bits (or their inverse) on buffers of nw words
+static int run_bcvt(uint64_t N, bool inverse, uint64_t *&cur, uint64_t *&spare, uint64_t nw, hipStream_t s)
+{
+    std::vector<BStep> steps;
+    bcvt_steps(N, 1, steps);
+    if (inverse) std::reverse(steps.begin(), steps.end());
+    const unsigned bs = 256;
+    for (const BStep &st : steps) {
+        if (st.S >= 128) {
+            k_bcvt_step_wide<<<grid_for(nw, bs), bs, 0, s>>>(cur, spare, nw, st.S, st.d, inverse ? 1 : 0);
+            LAUNCH_CHECK("bcvt_wide");
+        } else {
+            int H = (int)(st.S / 2), d = (int)st.d;
+            uint64_t L = 0, D = 0;
+            for (int b = 0; b < 64; ++b) {
+                int r = b % (int)st.S;
+                if (r < H) L |= 1ull << b;
+                if (r < d) D |= 1ull << b;
+            }
+            k_bcvt_step_word<<<grid_for(nw, bs), bs, 0, s>>>(cur, spare, nw, H, d, L, D, inverse ? 1 : 0);
+            LAUNCH_CHECK("bcvt_word");
+        }
+        std::swap(cur, spare);
+    }
+    return 0;
+}
+
+// A (len bits) -> n_p values in *cur (cur/spare swapped as needed)
+static int run_forward(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int log2n, uint64_t *&cur,
+                       uint64_t *&spare, hipStream_t s)
+{
+    const int l = log2n - 6;
+    const uint64_t nw = 1ull << l, n_p = 1ull << l;
+    const unsigned bs = 256;
+    k_load_mask<<<grid_for(nw, bs), bs, 0, s>>>(a, len, cur, nw);
+    LAUNCH_CHECK("load");
+    int rc = run_bcvt(next_pow2(std::max<uint64_t>(len, 1)), false, cur, spare, nw, s);
+    if (rc) return rc;
+    k_encode<<<grid_for(n_p, bs), bs, 0, s>>>(cur, l, ctx->tables, spare);
+    LAUNCH_CHECK("encode");
+    std::swap(cur, spare);
+    for (int i = l - 1; i >= 0; --i) {
+        k_bfly_layer<<<grid_for(n_p / 2, bs), bs, 0, s>>>(cur, l, i, 0, ctx->tables);
+        LAUNCH_CHECK("butterfly");
+    }
+    return 0;
+}
+
+// values in *cur (destroyed) -> n bits in *cur
+static int run_inverse(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t *&spare, hipStream_t s)
+{
+    const int l = log2n - 6;
+    const uint64_t nw = 1ull << l, n_p = 1ull << l;
+    const unsigned bs = 256;
+    for (int i = 0; i < l; ++i) {
+        k_bfly_layer<<<grid_for(n_p / 2, bs), bs, 0, s>>>(cur, l, i, 1, ctx->tables);
+        LAUNCH_CHECK("ibutterfly");
+    }
+    k_decode_vec<<<grid_for(n_p, bs), bs, 0, s>>>(cur, l, ctx->tables);
+    LAUNCH_CHECK("decode_vec");
+    k_decode_scatter<<<grid_for(nw, bs), bs, 0, s>>>(cur, l, spare);
+    LAUNCH_CHECK("decode_scatter");
+    std::swap(cur, spare);
+    return run_bcvt(1ull << log2n, true, cur, spare, nw, s);
+}
+
+static int transform_log2(uint64_t len_a, uint64_t len_b)
+{
+    uint64_t lc = len_a + len_b - 1;
+    return std::max(6, ilog2(lc));
+}
+
+static int ranges_overlap(const void *a, size_t an, const void *b, size_t bn)
+{
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bn && y < x + an;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char *polymul_last_error(void) { return g_err.c_str(); }
+
+const char *polymul_version(void) { return FPMUL_VERSION; }
+
+int polymul_ctx_create(polymul_ctx **out, int device, size_t workspace_cap)
+{
+    if (!out) return fail(POLYMUL_EINVAL, "ctx out pointer is null");
+    *out = nullptr;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(POLYMUL_EINVAL, "no such device");
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    HIP_TRY(hipSetDevice(device));
+    polymul_ctx *ctx = new polymul_ctx();
+    ctx->device = device;
+    ctx->cap = workspace_cap;
+    fpmul_host::Tables H;
+    try {
+        fpmul_host::build_tables(H);
+    } catch (const std::exception &ex) {
+        delete ctx;
+        (void)hipSetDevice(prev);
+        return fail(POLYMUL_EIO, std::string("constant tables: ") + ex.what());
+    }
+    DevTables D;
+    std::memcpy(D.iota, H.iota, sizeof(D.iota));
+    std::memcpy(D.enc, H.enc, sizeof(D.enc));
+    std::memcpy(D.dec, H.dec, sizeof(D.dec));
+    hipError_t e = hipMalloc(&ctx->tables, sizeof(DevTables));
+    if (e == hipSuccess) e = hipMemcpy(ctx->tables, &D, sizeof(DevTables), hipMemcpyHostToDevice);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (ctx->tables) (void)hipFree(ctx->tables);
+        delete ctx;
+        return fail(POLYMUL_EIO, std::string("upload tables: ") + hipGetErrorString(e));
+    }
+    *out = ctx;
+    return 0;
+}
+
+int polymul_ctx_destroy(polymul_ctx *ctx)
+{
+    if (!ctx) return 0;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (int k = 0; k < 3; ++k)
+        if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
+    if (ctx->tables) (void)hipFree(ctx->tables);
+    (void)hipSetDevice(prev);
+    delete ctx;
+    return 0;
+}
+
+int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
+               uint64_t *out, void *stream)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (len_a == 0 || len_b == 0) return 0;
+    uint64_t lc = len_a + len_b - 1;
+    if (lc > POLYMUL_MAX_PRODUCT_BITS || len_a > POLYMUL_MAX_PRODUCT_BITS || len_b > POLYMUL_MAX_PRODUCT_BITS)
+        return fail(POLYMUL_EINVAL, "product length exceeds 2^37 bits");
+    int rc;
+    if ((rc = check_dev_ptr(a, "a_bits")) || (rc = check_dev_ptr(b, "b_bits")) || (rc = check_dev_ptr(out, "out")))
+        return rc;
+    size_t ob = (size_t)((lc + 63) / 64) * 8;
+    if (ranges_overlap(out, ob, a, (size_t)((len_a + 63) / 64) * 8) ||
+        ranges_overlap(out, ob, b, (size_t)((len_b + 63) / 64) * 8))
+        return fail(POLYMUL_EINVAL, "out overlaps an input");
+    hipStream_t s = (hipStream_t)stream;
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int log2n = transform_log2(len_a, len_b);
+    const uint64_t nw = 1ull << (log2n - 6);
+    rc = ensure_ws(ctx, nw);
+    if (!rc) {
+        uint64_t *X = ctx->ws[0], *Y = ctx->ws[1], *Z = ctx->ws[2];
+        uint64_t *pa = X, *sa = Z;
+        rc = run_forward(ctx, a, len_a, log2n, pa, sa, s);
+        uint64_t *pb = Y, *sb = sa;
+        if (!rc) rc = run_forward(ctx, b, len_b, log2n, pb, sb, s);
+        if (!rc) {
+            k_pointwise<<<grid_for(nw, 256), 256, 0, s>>>(pa, pb, nw);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch pointwise: ") + hipGetErrorString(e));
+        }
+        if (!rc) {
+            uint64_t *cur = pa, *spare = pb;
+            rc = run_inverse(ctx, log2n, cur, spare, s);
+            if (!rc) {
+                k_store_mask<<<grid_for((lc + 63) / 64, 256), 256, 0, s>>>(cur, lc, out);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch store: ") + hipGetErrorString(e));
+            }
+        }
+    }
+    (void)hipSetDevice(prev);
+    return rc;
+}
+
+int polymul_addfft(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int log2n, uint64_t *values, void *stream)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (log2n < 6 || log2n > 37) return fail(POLYMUL_EINVAL, "log2n must be in [6, 37]");
+    if (len_a > (1ull << log2n)) return fail(POLYMUL_EINVAL, "len_a exceeds 2^log2n");
+    int rc;
+    if ((rc = check_dev_ptr(values, "values"))) return rc;
+    if (len_a && (rc = check_dev_ptr(a, "a_bits"))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint64_t nw = 1ull << (log2n - 6);
+    rc = ensure_ws(ctx, nw);
+    if (!rc) {
+        uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+        rc = run_forward(ctx, len_a ? a : ctx->ws[2], len_a, log2n, cur, spare, s);
+        if (!rc) {
+            hipError_t e = hipMemcpyAsync(values, cur, nw * 8, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("copy values: ") + hipGetErrorString(e));
+        }
+    }
+    (void)hipSetDevice(prev);
+    return rc;
+}
+
+int polymul_iaddfft(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_t *out, uint64_t out_bits,
+                    void *stream)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (log2n < 6 || log2n > 37) return fail(POLYMUL_EINVAL, "log2n must be in [6, 37]");
+    if (out_bits > (1ull << log2n)) return fail(POLYMUL_EINVAL, "out_bits exceeds 2^log2n");
+    int rc;
+    if ((rc = check_dev_ptr(values, "values")) || (rc = check_dev_ptr(out, "out"))) return rc;
+    if (out_bits == 0) return 0;
+    hipStream_t s = (hipStream_t)stream;
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint64_t nw = 1ull << (log2n - 6);
+    rc = ensure_ws(ctx, nw);
+    if (!rc) {
+        uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+        hipError_t e = hipMemcpyAsync(cur, values, nw * 8, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("copy values: ") + hipGetErrorString(e));
+        if (!rc) rc = run_inverse(ctx, log2n, cur, spare, s);
+        if (!rc) {
+            k_store_mask<<<grid_for((out_bits + 63) / 64, 256), 256, 0, s>>>(cur, out_bits, out);
+            e = hipGetLastError();
+            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch store: ") + hipGetErrorString(e));
+        }
+    }
+    (void)hipSetDevice(prev);
+    return rc;
+}
+
+int polymul_basiscvt(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int log2n, int inverse, uint64_t *out,
+                     void *stream)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (log2n < 0 || log2n > 37) return fail(POLYMUL_EINVAL, "log2n must be in [0, 37]");
+    if (len > (1ull << log2n)) return fail(POLYMUL_EINVAL, "len exceeds 2^log2n");
+    int rc;
+    if ((rc = check_dev_ptr(in, "in")) || (rc = check_dev_ptr(out, "out"))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int prev = 0;
+    HIP_TRY(hipGetDevice(&prev));
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint64_t nbits = 1ull << log2n, nw = (nbits + 63) / 64;
+    rc = ensure_ws(ctx, nw);
+    if (!rc) {
+        uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+        k_load_mask<<<grid_for(nw, 256), 256, 0, s>>>(in, inverse ? nbits : len, cur, nw);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch load: ") + hipGetErrorString(e));
+        if (!rc) rc = run_bcvt(inverse ? nbits : next_pow2(std::max<uint64_t>(len, 1)), inverse != 0, cur, spare, nw, s);
+        if (!rc) {
+            k_store_mask<<<grid_for(nw, 256), 256, 0, s>>>(cur, nbits, out);
+            e = hipGetLastError();
+            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch store: ") + hipGetErrorString(e));
+        }
+    }
+    (void)hipSetDevice(prev);
+    return rc;
+}
+
+int polymul(const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b, uint64_t *out)
+{
+    static std::mutex mu;
+    static std::map<int, polymul_ctx *> ctxs;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    polymul_ctx *ctx = nullptr;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = ctxs.find(dev);
+        if (it == ctxs.end()) {
+            int rc = polymul_ctx_create(&ctx, dev, 0);
+            if (rc) return rc;
+            ctxs[dev] = ctx;
+        } else {
+            ctx = it->second;
+        }
+        int rc = polymul_ex(ctx, a, len_a, b, len_b, out, nullptr);
+        if (rc) return rc;
+        HIP_TRY(hipStreamSynchronize(nullptr));
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,150 @@
+"""Thin Python binding of libfpmul.so (C ABI in include/fpmul.h).
+
+Argument marshalling only: every step of a product runs in the HIP kernels
+of the library.  Word arrays live on the GPU as torch ``int64`` tensors (bit
+patterns of the uint64 words); torch is used for device memory and streams.
+If the library is missing, every call raises: there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpmul.so")
+
+EIO, ENOMEM, EINVAL = -5, -12, -22
+MAX_PRODUCT_BITS = 1 << 37
+
+# (name, restype, argtypes) of every symbol include/fpmul.h declares
+_V, _U64, _I, _SZ, _P = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
+SIGNATURES = {
+    "polymul": (_I, [_P, _U64, _P, _U64, _P]),
+    "polymul_ctx_create": (_I, [ctypes.POINTER(_V), _I, _SZ]),
+    "polymul_ctx_destroy": (_I, [_V]),
+    "polymul_ex": (_I, [_V, _P, _U64, _P, _U64, _P, _V]),
+    "polymul_addfft": (_I, [_V, _P, _U64, _I, _P, _V]),
+    "polymul_iaddfft": (_I, [_V, _P, _I, _P, _U64, _V]),
+    "polymul_basiscvt": (_I, [_V, _P, _U64, _I, _I, _P, _V]),
+    "polymul_last_error": (ctypes.c_char_p, []),
+    "polymul_version": (ctypes.c_char_p, []),
+}
+
+
+class FpmulError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libfpmul.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError(
+                f"{LIB_PATH} is missing: build it with paper_1803_11301_amd/build.py "
+                "(there is no fallback path)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise FpmulError(rc, lib().polymul_last_error().decode())
+
+
+def _dptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError("expected a CUDA tensor")
+    if not t.is_contiguous() or t.dtype != torch.int64:
+        raise ValueError("expected a contiguous int64 tensor of 64-bit words")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def nwords(bits: int) -> int:
+    return (bits + 63) // 64
+
+
+class Context:
+    """A library context (constant tables and workspace) for one GPU."""
+
+    def __init__(self, device: int = 0, workspace_cap: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().polymul_ctx_create(ctypes.byref(h), device, workspace_cap))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().polymul_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def polymul(self, a, len_a: int, b, len_b: int, out=None, stream=None):
+        """C = A * B, stream-ordered.  Returns the output tensor."""
+        import torch
+        lc = len_a + len_b - 1 if (len_a and len_b) else 0
+        if out is None:
+            out = torch.empty(max(1, nwords(lc)), dtype=torch.int64, device=a.device)
+        _check(lib().polymul_ex(self.handle, _dptr(a), len_a, _dptr(b), len_b, _dptr(out), _stream(stream)))
+        return out
+
+    def addfft(self, a, len_a: int, log2n: int, values=None, stream=None):
+        import torch
+        if values is None:
+            values = torch.empty(1 << (log2n - 6), dtype=torch.int64, device=a.device)
+        _check(lib().polymul_addfft(self.handle, _dptr(a), len_a, log2n, _dptr(values), _stream(stream)))
+        return values
+
+    def iaddfft(self, values, log2n: int, out_bits: int, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(max(1, nwords(out_bits)), dtype=torch.int64, device=values.device)
+        _check(lib().polymul_iaddfft(self.handle, _dptr(values), log2n, _dptr(out), out_bits, _stream(stream)))
+        return out
+
+    def basiscvt(self, x, length: int, log2n: int, inverse: bool = False, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(max(1, nwords(1 << log2n)), dtype=torch.int64, device=x.device)
+        _check(lib().polymul_basiscvt(self.handle, _dptr(x), length, log2n, 1 if inverse else 0,
+                                      _dptr(out), _stream(stream)))
+        return out
+
+
+def polymul(a, len_a: int, b, len_b: int, out=None):
+    """Synchronous product on the current device (library-owned context)."""
+    import torch
+    lc = len_a + len_b - 1 if (len_a and len_b) else 0
+    if out is None:
+        out = torch.empty(max(1, nwords(lc)), dtype=torch.int64, device=a.device)
+    _check(lib().polymul(_dptr(a), len_a, _dptr(b), len_b, _dptr(out)))
+    return out
+
+
+def version() -> str:
+    return lib().polymul_version().decode()

@@ -1,0 +1,247 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Every case prints its name, sizes and seed before touching the GPU.
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import cantor as F
+from paper_1803_11301_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_11301_amd import fpmul
+    c = fpmul.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(words):
+    w = np.ascontiguousarray(words, dtype=np.uint64)
+    if w.size == 0:
+        w = np.zeros(1, np.uint64)
+    return torch.from_numpy(w.view(np.int64)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(np.uint64)
+
+
+def gpu_product(ctx, a, la, b, lb):
+    out = ctx.polymul(dev(a), la, dev(b), lb)
+    return host(out)[: O.nwords(la + lb - 1)]
+
+
+def rand_words(rng, length):
+    return O.int_to_words(rng.getrandbits(length) if length else 0, length)
+
+
+# --------------------------------------------------------------------------
+# stages
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("log2n", [0, 1, 2, 3, 5, 6, 7, 8, 10, 12])
+def test_basiscvt_against_definition(ctx, log2n):
+    say("basiscvt", log2n)
+    rng = random.Random(log2n)
+    n = 1 << log2n
+    for length in sorted({1, n // 2 + 1, n}):
+        if length > n:
+            continue
+        f = rng.getrandbits(length)
+        got = host(ctx.basiscvt(dev(O.int_to_words(f, length)), length, log2n))
+        g = O.words_to_int(got, n)
+        assert g == F.to_novelpoly(f, n)
+        back = host(ctx.basiscvt(dev(got), n, log2n, inverse=True))
+        assert O.words_to_int(back, n) == f
+
+
+@pytest.mark.parametrize("log2n", [6, 7, 8, 9, 12, 13, 16])
+def test_addfft_is_evaluation_at_sigma(ctx, log2n):
+    say("addfft", log2n)
+    rng = random.Random(100 + log2n)
+    n = 1 << log2n
+    l = log2n - 6
+    la = n // 2
+    a = rand_words(rng, la)
+    vals = host(ctx.addfft(dev(a), la, log2n))
+    js = sorted({0, (1 << l) - 1} | {rng.randrange(1 << l) for _ in range(12)})
+    for j in js:
+        assert int(vals[j]) == O.eval_at(a, la, F.point(l, j)), j
+    back = host(ctx.iaddfft(dev(vals), log2n, la))
+    assert np.array_equal(back[: O.nwords(la)], a)
+
+
+def test_addfft_full_length_operand_round_trip(ctx):
+    say("addfft full length")
+    rng = random.Random(7)
+    log2n = 14
+    n = 1 << log2n
+    a = rand_words(rng, n)
+    vals = host(ctx.addfft(dev(a), n, log2n))
+    for j in (0, 3, 255):
+        assert int(vals[j]) == O.eval_at(a, n, F.point(log2n - 6, j))
+    assert np.array_equal(host(ctx.iaddfft(dev(vals), log2n, n)), a)
+
+
+def test_frobenius_identity_on_transform(ctx):
+    # the transform of A^2 is the elementwise square of the transform of A (Eq. 1)
+    say("frobenius")
+    rng = random.Random(3)
+    log2n, la = 12, 1500
+    a = rand_words(rng, la)
+    a2 = O.polymul(a, la, a, la)
+    va = host(ctx.addfft(dev(a), la, log2n))
+    va2 = host(ctx.addfft(dev(a2), 2 * la - 1, log2n))
+    for j in range(0, va.size, 7):
+        assert int(va2[j]) == F.sqr(int(va[j]))
+
+
+# --------------------------------------------------------------------------
+# products
+# --------------------------------------------------------------------------
+
+def test_small_config_exact(ctx):
+    L = 1 << 16
+    say("2^16 x 2^16", hex(synth.SEED_SMALL))
+    a, b = synth.single_pair(synth.SEED_SMALL, L)
+    assert np.array_equal(gpu_product(ctx, a, L, b, L), O.polymul(a, L, b, L, threads=8))
+
+
+@pytest.mark.parametrize("la,lb", [(1, 1), (1, 2), (2, 1), (3, 5), (31, 34), (32, 33), (33, 32), (63, 1), (64, 1),
+                                   (65, 1), (64, 64), (65, 64), (100, 29), (127, 128), (1000, 3), (4096, 4096),
+                                   (4097, 4095), (1, 1 << 16), ((1 << 16) + 1, 77), (12345, 6789), (1 << 17, 1),
+                                   (70001, 60001)])
+def test_length_sweep(ctx, la, lb):
+    say("sweep", la, lb)
+    rng = random.Random(la * 131 + lb)
+    a, b = rand_words(rng, la), rand_words(rng, lb)
+    assert np.array_equal(gpu_product(ctx, a, la, b, lb), O.polymul(a, la, b, lb, threads=8))
+
+
+def test_every_small_length_pair(ctx):
+    say("all lengths 1..40")
+    rng = random.Random(77)
+    for la in range(1, 41):
+        for lb in range(1, 41, 3):
+            a, b = rand_words(rng, la), rand_words(rng, lb)
+            assert np.array_equal(gpu_product(ctx, a, la, b, lb), O.polymul(a, la, b, lb)), (la, lb)
+
+
+def test_closed_forms(ctx):
+    say("closed forms")
+    rng = random.Random(5)
+    la = 20000
+    a = rand_words(rng, la)
+    av = O.words_to_int(a, la)
+    sq = O.words_to_int(gpu_product(ctx, a, la, a, la), 2 * la - 1)
+    spread = 0
+    for k in range(la):
+        if (av >> k) & 1:
+            spread |= 1 << (2 * k)
+    assert sq == spread
+    for p, q in ((0, 0), (5, 70), (4095, 4097), (40000, 123)):
+        x = O.int_to_words(1 << p, p + 1)
+        y = O.int_to_words(1 << q, q + 1)
+        assert O.words_to_int(gpu_product(ctx, x, p + 1, y, q + 1), p + q + 1) == 1 << (p + q)
+    k = 9999
+    ones = O.int_to_words((1 << k) - 1, k)
+    assert O.words_to_int(gpu_product(ctx, O.int_to_words(3, 2), 2, ones, k), k + 1) == (1 << k) | 1
+
+
+def test_tail_bits_ignored_and_output_tail_zeroed(ctx):
+    say("tails")
+    la, lb = 130, 70
+    a = np.full(3, np.uint64(0xFFFFFFFFFFFFFFFF))
+    b = np.full(2, np.uint64(0xFFFFFFFFFFFFFFFF))
+    out = torch.full((5,), -1, dtype=torch.int64, device="cuda")
+    ctx.polymul(dev(a), la, dev(b), lb, out=out)
+    got = host(out)
+    ref = O.polymul(a, la, b, lb)
+    assert ref.size == 4
+    assert np.array_equal(got[: ref.size], ref)
+    assert int(got[ref.size - 1]) >> ((la + lb - 1) % 64) == 0
+    assert int(got[4]) == 0xFFFFFFFFFFFFFFFF   # beyond the product: untouched
+
+
+def test_empty_operand_writes_nothing(ctx):
+    say("empty")
+    out = torch.full((2,), 7, dtype=torch.int64, device="cuda")
+    ctx.polymul(dev(np.ones(1, np.uint64)), 0, dev(np.ones(1, np.uint64)), 5, out=out)
+    assert host(out).tolist() == [7, 7]
+
+
+def test_sparse_operands(ctx):
+    say("sparse")
+    la, lb = 300000, 200000
+    a = synth.sparse_poly(11, la)
+    b = synth.sparse_poly(12, lb)
+    assert np.array_equal(gpu_product(ctx, a, la, b, lb), O.polymul(a, la, b, lb, threads=8))
+
+
+def test_mid_config_exact(ctx):
+    L = 1 << 24
+    say("2^24 x 2^24 top bit", hex(synth.SEED_MID))
+    a, b = synth.single_pair(synth.SEED_MID, L, top_bit=True)
+    got = gpu_product(ctx, a, L, b, L)
+    assert np.array_equal(got, O.polymul(a, L, b, L, threads=16))
+    assert int(got[-1]) >> 62 == 1   # degree 2^25 - 2 is present
+
+
+def test_large_config_sampled(ctx):
+    L = 1 << 30
+    say("2^30 x 2^30 sampled", hex(synth.SEED_LARGE))
+    a, b = synth.single_pair(synth.SEED_LARGE, L)
+    got = gpu_product(ctx, a, L, b, L)
+    rng = random.Random(30)
+    nw = got.size
+    idx = np.array(sorted({0, 1, nw // 2 - 1, nw // 2, nw - 1} | {rng.randrange(nw) for _ in range(11)}), np.uint64)
+    ref = O.product_words(a, L, b, L, idx)
+    assert np.array_equal(got[idx.astype(np.int64)], ref)
+    z = rng.getrandbits(64)
+    assert O.eval_at(got, 2 * L - 1, z) == O.gf64_mul(O.eval_at(a, L, z), O.eval_at(b, L, z))
+
+
+# --------------------------------------------------------------------------
+# errors
+# --------------------------------------------------------------------------
+
+def test_error_codes(ctx):
+    say("errors")
+    from paper_1803_11301_amd import fpmul
+    L = fpmul.lib()
+    a = dev(np.ones(2, np.uint64))
+    out = dev(np.zeros(4, np.uint64))
+    # output overlapping an input
+    assert L.polymul_ex(ctx.handle, a.data_ptr(), 64, a.data_ptr(), 64, a.data_ptr(), None) == fpmul.EINVAL
+    # host memory is not accepted
+    host_buf = np.zeros(4, np.uint64)
+    assert L.polymul_ex(ctx.handle, host_buf.ctypes.data, 64, a.data_ptr(), 64, out.data_ptr(), None) == fpmul.EINVAL
+    # beyond the 2^37-bit limit (rejected before any launch)
+    assert L.polymul_ex(ctx.handle, a.data_ptr(), 1 << 37, a.data_ptr(), 2, out.data_ptr(), None) == fpmul.EINVAL
+    assert "2^37" in L.polymul_last_error().decode()
+    # workspace above the context cap
+    big = dev(np.zeros(2000, np.uint64))
+    big_out = dev(np.zeros(4000, np.uint64))
+    small = fpmul.Context(0, workspace_cap=1 << 10)
+    assert L.polymul_ex(small.handle, big.data_ptr(), 100000, big.data_ptr(), 100000, big_out.data_ptr(), None) \
+        == fpmul.ENOMEM
+    small.close()
