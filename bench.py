@@ -1,0 +1,180 @@
+#!/usr/bin/env python3
+"""Benchmark: ms per product of two 2^30-bit polynomials in GF(2)[x] on one MI355X.
+
+One step = one full product (BasisCvt, Encode, Butterfly for both operands,
+pointwise products, iButterfly, Decode, iBasisCvt) with the operands already
+resident in HBM.  Prints ONE JSON line on stdout; details go to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--workload large|mid|small] [--no-cpu]
+
+Per-kernel durations come from HIP events the library records on the launch
+stream during the timed steps (polymul_profile_enable).  The roofline entry
+is for the kernel with the largest total time, priced against HBM at 8 TB/s
+with the nominal algorithmic bytes of its stage (each stage streams its input
+and output once): BasisCvt 2A+2B, Encode A+B+2N, Butterfly 2N per transform,
+pointwise 3N, iButterfly 2N, Decode 2N, iBasisCvt 2N (A, B operand bytes,
+N transform bytes); a stage's bytes are split evenly over its launches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (operand bits, seed, top bit forced, description)
+    "small": (1 << 16, 0x5EED0016, False, "single product 2^16 x 2^16 bits, uniform random"),
+    "mid": (1 << 24, 0x5EED0024, True, "single product 2^24 x 2^24 bits, uniform random, top bit forced"),
+    "large": (1 << 30, 0x5EED0030, False, "single product 2^30 x 2^30 bits, uniform random"),
+}
+
+# kernel name -> stage of the nominal byte model
+STAGE_OF = {
+    "basiscvt_wide": "basiscvt", "basiscvt_word": "basiscvt", "basiscvt": "basiscvt",
+    "encode": "encode", "butterfly": "butterfly", "pointwise": "pointwise",
+    "ibutterfly": "ibutterfly", "decode_vec": "decode", "decode_scatter": "decode", "decode": "decode",
+    "ibasiscvt_wide": "ibasiscvt", "ibasiscvt_word": "ibasiscvt", "ibasiscvt": "ibasiscvt",
+}
+
+
+def stage_bytes(A: int, B: int, N: int) -> dict:
+    return {"basiscvt": 2 * A + 2 * B, "encode": A + B + 2 * N, "butterfly": 4 * N, "pointwise": 3 * N,
+            "ibutterfly": 2 * N, "decode": 2 * N, "ibasiscvt": 2 * N}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(log2_len: int, target_log2: int):
+    """The oracle (as it stands) on a bounded sample of the same workload: one
+    product of 2^log2_len-bit operands from the same generator, on all host
+    threads, projected to 2^target_log2-bit operands by the 3x-per-doubling
+    cost of its Karatsuba recursion."""
+    import oracle as O
+    from paper_1803_11301_amd import synth
+    O.build(force=False)
+    L = 1 << log2_len
+    a, b = synth.single_pair(synth.SEED_LARGE, L)
+    threads = O.max_threads()
+    t0 = time.perf_counter()
+    O.polymul(a, L, b, L, threads=threads)
+    sec = time.perf_counter() - t0
+    scale = 3 ** (target_log2 - log2_len)
+    return {"value": round(sec * 1e3 * scale, 3), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": f"one 2^{log2_len} x 2^{log2_len}-bit product ({sec:.2f} s on {threads} threads, "
+                      f"Karatsuba oracle), x3^{target_log2 - log2_len} for 2^{target_log2}-bit operands"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--cpu-log2", type=int, default=27, help="operand size of the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(products shard without exchange across GPUs, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1803_11301_amd import fpmul, synth
+
+    L, seed, top, desc = WORKLOADS[args.workload]
+    a_np, b_np = synth.single_pair(seed, L, top_bit=top)
+    dev = torch.device("cuda:0")
+    a = torch.from_numpy(a_np.view(np.int64)).to(dev)
+    b = torch.from_numpy(b_np.view(np.int64)).to(dev)
+    lc = 2 * L - 1
+    out = torch.empty((lc + 63) // 64, dtype=torch.int64, device=dev)
+    ctx = fpmul.Context(0)
+    stream = torch.cuda.current_stream()
+
+    log(f"[bench] {desc}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ctx.polymul(a, L, b, L, out=out, stream=stream)
+    torch.cuda.synchronize()
+
+    ctx.profile(True)
+    log(f"[bench] timing {args.steps} steps")
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        ctx.polymul(a, L, b, L, out=out, stream=stream)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_stop)
+    ms = ms_total / args.steps
+    prof = ctx.profile_report()
+    ctx.profile(False)
+
+    # nominal bytes of the workload
+    A = B = L // 8
+    log2n = max(6, (lc - 1).bit_length())
+    N = (1 << log2n) // 8
+    sb = stage_bytes(A, B, N)
+    nominal = sum(sb.values())
+    # per stage: launches and time per product
+    launches_per_stage = {}
+    for name, (cnt, tot) in prof.items():
+        st = STAGE_OF.get(name)
+        if st:
+            launches_per_stage[st] = launches_per_stage.get(st, 0) + cnt / args.steps
+    per_kernel = {}
+    for name, (cnt, tot) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        per_kernel[name] = {"launches_per_step": cnt / args.steps, "ms_per_step": tot / args.steps,
+                            "avg_launch_us": 1e3 * tot / cnt}
+        log(f"[bench] {name:18s} {cnt / args.steps:7.1f} launches/step {tot / args.steps:9.4f} ms/step "
+            f"{1e3 * tot / cnt:9.2f} us/launch")
+    dom = max((n for n in prof if STAGE_OF.get(n)), key=lambda n: prof[n][1])
+    dst = STAGE_OF[dom]
+    cnt, tot = prof[dom]
+    bytes_per_launch = sb[dst] / launches_per_stage[dst]
+    avg_s = tot / cnt / 1e3
+    achieved = bytes_per_launch / avg_s / 1e9
+    product_gbs = nominal / (ms / 1e3) / 1e9
+    log(f"[bench] {ms:.3f} ms/product; nominal {nominal / 1e9:.3f} GB -> {product_gbs:.1f} GB/s "
+        f"({100 * product_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+
+    cpu = None
+    if not args.no_cpu:
+        log(f"[bench] oracle sample 2^{args.cpu_log2} on the host")
+        target = L.bit_length() - 1
+        cpu = cpu_baseline(min(args.cpu_log2, target), target)
+        log(f"[bench] cpu baseline {cpu}")
+
+    rec = {
+        "metric": "ms per 2^30-bit x 2^30-bit product" if args.workload == "large"
+        else f"ms per 2^{L.bit_length() - 1}-bit product",
+        "value": round(ms, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic (seeded SplitMix64 bits, resident in HBM)",
+        "config": {"workload": desc, "len_a": L, "len_b": L, "transform_bits": 1 << log2n,
+                   "seed": hex(seed), "field": "GF(2^64)"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_s * 1e6, 3)},
+        "product_roofline": {"nominal_bytes": nominal, "achieved": round(product_gbs, 2), "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": round(product_gbs / HBM_PEAK_GBS, 5)},
+        "kernels": per_kernel,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

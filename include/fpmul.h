@@ -113,6 +113,20 @@ int polymul_iaddfft(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_
 int polymul_basiscvt(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int log2n, int inverse,
                      uint64_t *out, void *stream);
 
+/*
+ * polymul_profile_enable -- per-kernel timing: when on, every kernel the
+ * context launches is bracketed by HIP events recorded on its launch stream.
+ * Enabling or disabling clears the counters.
+ */
+int polymul_profile_enable(polymul_ctx *ctx, int on);
+
+/*
+ * polymul_profile_report -- waits for the recorded events and writes one line
+ * per kernel name, "name launches total_ms\n", NUL-terminated, into buf
+ * (buflen bytes; POLYMUL_EINVAL if it does not fit).
+ */
+int polymul_profile_report(polymul_ctx *ctx, char *buf, size_t buflen);
+
 /* Message of the last failure on this thread ("" if none). */
 const char *polymul_last_error(void);
 

@@ -312,13 +312,77 @@ __global__ void k_pointwise(uint64_t *__restrict__ a, const uint64_t *__restrict
 // context
 // ---------------------------------------------------------------------------
 
+struct ProfRec {
+    std::string name;
+    hipEvent_t start, stop;
+};
+
 struct polymul_ctx {
     int device = 0;
     size_t cap = 0;
     uint64_t *ws[3] = {nullptr, nullptr, nullptr};
     uint64_t ws_words = 0;   // words per workspace buffer
     DevTables *tables = nullptr;
+    // per-kernel timing with HIP events on the launch stream (off by default)
+    bool prof = false;
+    std::vector<ProfRec> prof_live;       // recorded, not yet read
+    std::vector<hipEvent_t> prof_pool;    // free events
+    std::map<std::string, std::pair<uint64_t, double>> prof_acc;   // name -> (launches, ms)
 };
+
+static hipEvent_t prof_event(polymul_ctx *c)
+{
+    if (!c->prof_pool.empty()) {
+        hipEvent_t e = c->prof_pool.back();
+        c->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+static void prof_begin(polymul_ctx *c, hipStream_t s, const char *name)
+{
+    if (!c || !c->prof) return;
+    ProfRec r{name, prof_event(c), prof_event(c)};
+    if (r.start) (void)hipEventRecord(r.start, s);
+    c->prof_live.push_back(r);
+}
+
+static void prof_end(polymul_ctx *c, hipStream_t s)
+{
+    if (!c || !c->prof || c->prof_live.empty()) return;
+    if (c->prof_live.back().stop) (void)hipEventRecord(c->prof_live.back().stop, s);
+}
+
+static void prof_collect(polymul_ctx *c)
+{
+    for (ProfRec &r : c->prof_live) {
+        if (r.start && r.stop && hipEventSynchronize(r.stop) == hipSuccess) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) {
+                auto &a = c->prof_acc[r.name];
+                a.first += 1;
+                a.second += ms;
+            }
+        }
+        if (r.start) c->prof_pool.push_back(r.start);
+        if (r.stop) c->prof_pool.push_back(r.stop);
+    }
+    c->prof_live.clear();
+}
+
+// launch a kernel on stream s, timed when profiling is on; returns on error
+#define KLAUNCH(ctx, s, name, kernel, grid, block, ...)        \
+    do {                                                       \
+        prof_begin((ctx), (s), (name));                        \
+        kernel<<<(grid), (block), 0, (s)>>>(__VA_ARGS__);      \
+        hipError_t _le = hipGetLastError();                    \
+        prof_end((ctx), (s));                                  \
+        if (_le != hipSuccess)                                 \
+            return fail(POLYMUL_EIO, std::string("launch ") + (name) + ": " + hipGetErrorString(_le)); \
+    } while (0)
 
 static unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
@@ -374,7 +438,8 @@ static int ilog2(uint64_t x)
 }
 
 // run the BasisCvt steps for N bits (or their inverse) on buffers of nw words
-static int run_bcvt(uint64_t N, bool inverse, uint64_t *&cur, uint64_t *&spare, uint64_t nw, hipStream_t s)
+static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *&cur, uint64_t *&spare, uint64_t nw,
+                    hipStream_t s)
 {
     std::vector<BStep> steps;
     bcvt_steps(N, 1, steps);
@@ -382,8 +447,8 @@ static int run_bcvt(uint64_t N, bool inverse, uint64_t *&cur, uint64_t *&spare, 
     const unsigned bs = 256;
     for (const BStep &st : steps) {
         if (st.S >= 128) {
-            k_bcvt_step_wide<<<grid_for(nw, bs), bs, 0, s>>>(cur, spare, nw, st.S, st.d, inverse ? 1 : 0);
-            LAUNCH_CHECK("bcvt_wide");
+            KLAUNCH(ctx, s, inverse ? "ibasiscvt_wide" : "basiscvt_wide", k_bcvt_step_wide, grid_for(nw, bs), bs,
+                    cur, spare, nw, st.S, st.d, inverse ? 1 : 0);
         } else {
             int H = (int)(st.S / 2), d = (int)st.d;
             uint64_t L = 0, D = 0;
@@ -392,8 +457,8 @@ static int run_bcvt(uint64_t N, bool inverse, uint64_t *&cur, uint64_t *&spare, 
                 if (r < H) L |= 1ull << b;
                 if (r < d) D |= 1ull << b;
             }
-            k_bcvt_step_word<<<grid_for(nw, bs), bs, 0, s>>>(cur, spare, nw, H, d, L, D, inverse ? 1 : 0);
-            LAUNCH_CHECK("bcvt_word");
+            KLAUNCH(ctx, s, inverse ? "ibasiscvt_word" : "basiscvt_word", k_bcvt_step_word, grid_for(nw, bs), bs,
+                    cur, spare, nw, H, d, L, D, inverse ? 1 : 0);
         }
         std::swap(cur, spare);
     }
@@ -407,17 +472,13 @@ static int run_forward(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int lo
     const int l = log2n - 6;
     const uint64_t nw = 1ull << l, n_p = 1ull << l;
     const unsigned bs = 256;
-    k_load_mask<<<grid_for(nw, bs), bs, 0, s>>>(a, len, cur, nw);
-    LAUNCH_CHECK("load");
-    int rc = run_bcvt(next_pow2(std::max<uint64_t>(len, 1)), false, cur, spare, nw, s);
+    KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, bs), bs, a, len, cur, nw);
+    int rc = run_bcvt(ctx, next_pow2(std::max<uint64_t>(len, 1)), false, cur, spare, nw, s);
     if (rc) return rc;
-    k_encode<<<grid_for(n_p, bs), bs, 0, s>>>(cur, l, ctx->tables, spare);
-    LAUNCH_CHECK("encode");
+    KLAUNCH(ctx, s, "encode", k_encode, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
     std::swap(cur, spare);
-    for (int i = l - 1; i >= 0; --i) {
-        k_bfly_layer<<<grid_for(n_p / 2, bs), bs, 0, s>>>(cur, l, i, 0, ctx->tables);
-        LAUNCH_CHECK("butterfly");
-    }
+    for (int i = l - 1; i >= 0; --i)
+        KLAUNCH(ctx, s, "butterfly", k_bfly_layer, grid_for(n_p / 2, bs), bs, cur, l, i, 0, ctx->tables);
     return 0;
 }
 
@@ -427,16 +488,12 @@ static int run_inverse(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t *&s
     const int l = log2n - 6;
     const uint64_t nw = 1ull << l, n_p = 1ull << l;
     const unsigned bs = 256;
-    for (int i = 0; i < l; ++i) {
-        k_bfly_layer<<<grid_for(n_p / 2, bs), bs, 0, s>>>(cur, l, i, 1, ctx->tables);
-        LAUNCH_CHECK("ibutterfly");
-    }
-    k_decode_vec<<<grid_for(n_p, bs), bs, 0, s>>>(cur, l, ctx->tables);
-    LAUNCH_CHECK("decode_vec");
-    k_decode_scatter<<<grid_for(nw, bs), bs, 0, s>>>(cur, l, spare);
-    LAUNCH_CHECK("decode_scatter");
+    for (int i = 0; i < l; ++i)
+        KLAUNCH(ctx, s, "ibutterfly", k_bfly_layer, grid_for(n_p / 2, bs), bs, cur, l, i, 1, ctx->tables);
+    KLAUNCH(ctx, s, "decode_vec", k_decode_vec, grid_for(n_p, bs), bs, cur, l, ctx->tables);
+    KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
     std::swap(cur, spare);
-    return run_bcvt(1ull << log2n, true, cur, spare, nw, s);
+    return run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s);
 }
 
 static int transform_log2(uint64_t len_a, uint64_t len_b)
@@ -449,6 +506,81 @@ static int ranges_overlap(const void *a, size_t an, const void *b, size_t bn)
 {
     uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     return x < y + bn && y < x + an;
+}
+
+// makes ctx's device current for a scope and restores the caller's device
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
+                        uint64_t *out, hipStream_t s)
+{
+    const uint64_t lc = len_a + len_b - 1;
+    const int log2n = transform_log2(len_a, len_b);
+    const uint64_t nw = 1ull << (log2n - 6);
+    int rc = ensure_ws(ctx, nw);
+    if (rc) return rc;
+    uint64_t *pa = ctx->ws[0], *sa = ctx->ws[2];
+    if ((rc = run_forward(ctx, a, len_a, log2n, pa, sa, s))) return rc;
+    uint64_t *pb = ctx->ws[1], *sb = sa;
+    if ((rc = run_forward(ctx, b, len_b, log2n, pb, sb, s))) return rc;
+    KLAUNCH(ctx, s, "pointwise", k_pointwise, grid_for(nw, 256), 256, pa, pb, nw);
+    uint64_t *cur = pa, *spare = pb;
+    if ((rc = run_inverse(ctx, log2n, cur, spare, s))) return rc;
+    KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, cur, lc, out);
+    return 0;
+}
+
+static int addfft_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int log2n, uint64_t *values,
+                       hipStream_t s)
+{
+    const uint64_t nw = 1ull << (log2n - 6);
+    int rc = ensure_ws(ctx, nw);
+    if (rc) return rc;
+    uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+    if ((rc = run_forward(ctx, len_a ? a : ctx->ws[2], len_a, log2n, cur, spare, s))) return rc;
+    HIP_TRY(hipMemcpyAsync(values, cur, nw * 8, hipMemcpyDeviceToDevice, s));
+    return 0;
+}
+
+static int iaddfft_body(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_t *out, uint64_t out_bits,
+                        hipStream_t s)
+{
+    const uint64_t nw = 1ull << (log2n - 6);
+    int rc = ensure_ws(ctx, nw);
+    if (rc) return rc;
+    uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+    HIP_TRY(hipMemcpyAsync(cur, values, nw * 8, hipMemcpyDeviceToDevice, s));
+    if ((rc = run_inverse(ctx, log2n, cur, spare, s))) return rc;
+    KLAUNCH(ctx, s, "store", k_store_mask, grid_for((out_bits + 63) / 64, 256), 256, cur, out_bits, out);
+    return 0;
+}
+
+static int basiscvt_body(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int log2n, int inverse, uint64_t *out,
+                         hipStream_t s)
+{
+    const uint64_t nbits = 1ull << log2n, nw = (nbits + 63) / 64;
+    int rc = ensure_ws(ctx, nw);
+    if (rc) return rc;
+    uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+    KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, in, inverse ? nbits : len, cur, nw);
+    if ((rc = run_bcvt(ctx, inverse ? nbits : next_pow2(std::max<uint64_t>(len, 1)), inverse != 0, cur, spare, nw,
+                       s)))
+        return rc;
+    KLAUNCH(ctx, s, "store", k_store_mask, grid_for(nw, 256), 256, cur, nbits, out);
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -468,27 +600,23 @@ int polymul_ctx_create(polymul_ctx **out, int device, size_t workspace_cap)
     int ndev = 0;
     HIP_TRY(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) return fail(POLYMUL_EINVAL, "no such device");
-    int prev = 0;
-    HIP_TRY(hipGetDevice(&prev));
-    HIP_TRY(hipSetDevice(device));
-    polymul_ctx *ctx = new polymul_ctx();
-    ctx->device = device;
-    ctx->cap = workspace_cap;
+    DeviceGuard g(device);
+    HIP_TRY(g.err);
     fpmul_host::Tables H;
     try {
         fpmul_host::build_tables(H);
     } catch (const std::exception &ex) {
-        delete ctx;
-        (void)hipSetDevice(prev);
         return fail(POLYMUL_EIO, std::string("constant tables: ") + ex.what());
     }
     DevTables D;
     std::memcpy(D.iota, H.iota, sizeof(D.iota));
     std::memcpy(D.enc, H.enc, sizeof(D.enc));
     std::memcpy(D.dec, H.dec, sizeof(D.dec));
+    polymul_ctx *ctx = new polymul_ctx();
+    ctx->device = device;
+    ctx->cap = workspace_cap;
     hipError_t e = hipMalloc(&ctx->tables, sizeof(DevTables));
     if (e == hipSuccess) e = hipMemcpy(ctx->tables, &D, sizeof(DevTables), hipMemcpyHostToDevice);
-    (void)hipSetDevice(prev);
     if (e != hipSuccess) {
         if (ctx->tables) (void)hipFree(ctx->tables);
         delete ctx;
@@ -501,14 +629,16 @@ int polymul_ctx_create(polymul_ctx **out, int device, size_t workspace_cap)
 int polymul_ctx_destroy(polymul_ctx *ctx)
 {
     if (!ctx) return 0;
-    int prev = 0;
-    (void)hipGetDevice(&prev);
-    (void)hipSetDevice(ctx->device);
+    DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
     for (int k = 0; k < 3; ++k)
         if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
     if (ctx->tables) (void)hipFree(ctx->tables);
-    (void)hipSetDevice(prev);
+    for (ProfRec &r : ctx->prof_live) {
+        if (r.start) (void)hipEventDestroy(r.start);
+        if (r.stop) (void)hipEventDestroy(r.stop);
+    }
+    for (hipEvent_t e : ctx->prof_pool) (void)hipEventDestroy(e);
     delete ctx;
     return 0;
 }
@@ -518,9 +648,12 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
 {
     if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
     if (len_a == 0 || len_b == 0) return 0;
-    uint64_t lc = len_a + len_b - 1;
-    if (lc > POLYMUL_MAX_PRODUCT_BITS || len_a > POLYMUL_MAX_PRODUCT_BITS || len_b > POLYMUL_MAX_PRODUCT_BITS)
+    if (len_a > POLYMUL_MAX_PRODUCT_BITS || len_b > POLYMUL_MAX_PRODUCT_BITS ||
+        len_a + len_b - 1 > POLYMUL_MAX_PRODUCT_BITS)
         return fail(POLYMUL_EINVAL, "product length exceeds 2^37 bits");
+    const uint64_t lc = len_a + len_b - 1;
+    DeviceGuard g(ctx->device);
+    HIP_TRY(g.err);
     int rc;
     if ((rc = check_dev_ptr(a, "a_bits")) || (rc = check_dev_ptr(b, "b_bits")) || (rc = check_dev_ptr(out, "out")))
         return rc;
@@ -528,36 +661,7 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
     if (ranges_overlap(out, ob, a, (size_t)((len_a + 63) / 64) * 8) ||
         ranges_overlap(out, ob, b, (size_t)((len_b + 63) / 64) * 8))
         return fail(POLYMUL_EINVAL, "out overlaps an input");
-    hipStream_t s = (hipStream_t)stream;
-    int prev = 0;
-    HIP_TRY(hipGetDevice(&prev));
-    HIP_TRY(hipSetDevice(ctx->device));
-    const int log2n = transform_log2(len_a, len_b);
-    const uint64_t nw = 1ull << (log2n - 6);
-    rc = ensure_ws(ctx, nw);
-    if (!rc) {
-        uint64_t *X = ctx->ws[0], *Y = ctx->ws[1], *Z = ctx->ws[2];
-        uint64_t *pa = X, *sa = Z;
-        rc = run_forward(ctx, a, len_a, log2n, pa, sa, s);
-        uint64_t *pb = Y, *sb = sa;
-        if (!rc) rc = run_forward(ctx, b, len_b, log2n, pb, sb, s);
-        if (!rc) {
-            k_pointwise<<<grid_for(nw, 256), 256, 0, s>>>(pa, pb, nw);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch pointwise: ") + hipGetErrorString(e));
-        }
-        if (!rc) {
-            uint64_t *cur = pa, *spare = pb;
-            rc = run_inverse(ctx, log2n, cur, spare, s);
-            if (!rc) {
-                k_store_mask<<<grid_for((lc + 63) / 64, 256), 256, 0, s>>>(cur, lc, out);
-                hipError_t e = hipGetLastError();
-                if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch store: ") + hipGetErrorString(e));
-            }
-        }
-    }
-    (void)hipSetDevice(prev);
-    return rc;
+    return product_body(ctx, a, len_a, b, len_b, out, (hipStream_t)stream);
 }
 
 int polymul_addfft(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int log2n, uint64_t *values, void *stream)
@@ -565,25 +669,12 @@ int polymul_addfft(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int log2
     if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
     if (log2n < 6 || log2n > 37) return fail(POLYMUL_EINVAL, "log2n must be in [6, 37]");
     if (len_a > (1ull << log2n)) return fail(POLYMUL_EINVAL, "len_a exceeds 2^log2n");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(g.err);
     int rc;
     if ((rc = check_dev_ptr(values, "values"))) return rc;
     if (len_a && (rc = check_dev_ptr(a, "a_bits"))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    int prev = 0;
-    HIP_TRY(hipGetDevice(&prev));
-    HIP_TRY(hipSetDevice(ctx->device));
-    const uint64_t nw = 1ull << (log2n - 6);
-    rc = ensure_ws(ctx, nw);
-    if (!rc) {
-        uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
-        rc = run_forward(ctx, len_a ? a : ctx->ws[2], len_a, log2n, cur, spare, s);
-        if (!rc) {
-            hipError_t e = hipMemcpyAsync(values, cur, nw * 8, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("copy values: ") + hipGetErrorString(e));
-        }
-    }
-    (void)hipSetDevice(prev);
-    return rc;
+    return addfft_body(ctx, a, len_a, log2n, values, (hipStream_t)stream);
 }
 
 int polymul_iaddfft(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_t *out, uint64_t out_bits,
@@ -592,28 +683,12 @@ int polymul_iaddfft(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_
     if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
     if (log2n < 6 || log2n > 37) return fail(POLYMUL_EINVAL, "log2n must be in [6, 37]");
     if (out_bits > (1ull << log2n)) return fail(POLYMUL_EINVAL, "out_bits exceeds 2^log2n");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(g.err);
     int rc;
     if ((rc = check_dev_ptr(values, "values")) || (rc = check_dev_ptr(out, "out"))) return rc;
     if (out_bits == 0) return 0;
-    hipStream_t s = (hipStream_t)stream;
-    int prev = 0;
-    HIP_TRY(hipGetDevice(&prev));
-    HIP_TRY(hipSetDevice(ctx->device));
-    const uint64_t nw = 1ull << (log2n - 6);
-    rc = ensure_ws(ctx, nw);
-    if (!rc) {
-        uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
-        hipError_t e = hipMemcpyAsync(cur, values, nw * 8, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("copy values: ") + hipGetErrorString(e));
-        if (!rc) rc = run_inverse(ctx, log2n, cur, spare, s);
-        if (!rc) {
-            k_store_mask<<<grid_for((out_bits + 63) / 64, 256), 256, 0, s>>>(cur, out_bits, out);
-            e = hipGetLastError();
-            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch store: ") + hipGetErrorString(e));
-        }
-    }
-    (void)hipSetDevice(prev);
-    return rc;
+    return iaddfft_body(ctx, values, log2n, out, out_bits, (hipStream_t)stream);
 }
 
 int polymul_basiscvt(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int log2n, int inverse, uint64_t *out,
@@ -622,28 +697,38 @@ int polymul_basiscvt(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int log
     if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
     if (log2n < 0 || log2n > 37) return fail(POLYMUL_EINVAL, "log2n must be in [0, 37]");
     if (len > (1ull << log2n)) return fail(POLYMUL_EINVAL, "len exceeds 2^log2n");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(g.err);
     int rc;
     if ((rc = check_dev_ptr(in, "in")) || (rc = check_dev_ptr(out, "out"))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    int prev = 0;
-    HIP_TRY(hipGetDevice(&prev));
-    HIP_TRY(hipSetDevice(ctx->device));
-    const uint64_t nbits = 1ull << log2n, nw = (nbits + 63) / 64;
-    rc = ensure_ws(ctx, nw);
-    if (!rc) {
-        uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
-        k_load_mask<<<grid_for(nw, 256), 256, 0, s>>>(in, inverse ? nbits : len, cur, nw);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch load: ") + hipGetErrorString(e));
-        if (!rc) rc = run_bcvt(inverse ? nbits : next_pow2(std::max<uint64_t>(len, 1)), inverse != 0, cur, spare, nw, s);
-        if (!rc) {
-            k_store_mask<<<grid_for(nw, 256), 256, 0, s>>>(cur, nbits, out);
-            e = hipGetLastError();
-            if (e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("launch store: ") + hipGetErrorString(e));
-        }
+    return basiscvt_body(ctx, in, len, log2n, inverse, out, (hipStream_t)stream);
+}
+
+int polymul_profile_enable(polymul_ctx *ctx, int on)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    DeviceGuard g(ctx->device);
+    prof_collect(ctx);
+    ctx->prof_acc.clear();
+    ctx->prof = on != 0;
+    return 0;
+}
+
+int polymul_profile_report(polymul_ctx *ctx, char *buf, size_t buflen)
+{
+    if (!ctx || !buf || !buflen) return fail(POLYMUL_EINVAL, "bad argument");
+    DeviceGuard g(ctx->device);
+    prof_collect(ctx);
+    std::string txt;
+    for (auto &kv : ctx->prof_acc) {
+        char line[256];
+        std::snprintf(line, sizeof line, "%s %llu %.6f\n", kv.first.c_str(), (unsigned long long)kv.second.first,
+                      kv.second.second);
+        txt += line;
     }
-    (void)hipSetDevice(prev);
-    return rc;
+    if (txt.size() + 1 > buflen) return fail(POLYMUL_EINVAL, "report buffer too small");
+    std::memcpy(buf, txt.c_str(), txt.size() + 1);
+    return 0;
 }
 
 int polymul(const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b, uint64_t *out)
@@ -652,21 +737,19 @@ int polymul(const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b
     static std::map<int, polymul_ctx *> ctxs;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
     polymul_ctx *ctx = nullptr;
-    {
-        std::lock_guard<std::mutex> g(mu);
-        auto it = ctxs.find(dev);
-        if (it == ctxs.end()) {
-            int rc = polymul_ctx_create(&ctx, dev, 0);
-            if (rc) return rc;
-            ctxs[dev] = ctx;
-        } else {
-            ctx = it->second;
-        }
-        int rc = polymul_ex(ctx, a, len_a, b, len_b, out, nullptr);
+    auto it = ctxs.find(dev);
+    if (it == ctxs.end()) {
+        int rc = polymul_ctx_create(&ctx, dev, 0);
         if (rc) return rc;
-        HIP_TRY(hipStreamSynchronize(nullptr));
+        ctxs[dev] = ctx;
+    } else {
+        ctx = it->second;
     }
+    int rc = polymul_ex(ctx, a, len_a, b, len_b, out, nullptr);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(nullptr));
     return 0;
 }
 

@@ -26,6 +26,8 @@ SIGNATURES = {
     "polymul_addfft": (_I, [_V, _P, _U64, _I, _P, _V]),
     "polymul_iaddfft": (_I, [_V, _P, _I, _P, _U64, _V]),
     "polymul_basiscvt": (_I, [_V, _P, _U64, _I, _I, _P, _V]),
+    "polymul_profile_enable": (_I, [_V, _I]),
+    "polymul_profile_report": (_I, [_V, ctypes.c_char_p, _SZ]),
     "polymul_last_error": (ctypes.c_char_p, []),
     "polymul_version": (ctypes.c_char_p, []),
 }
@@ -103,6 +105,19 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def profile(self, on: bool = True):
+        _check(lib().polymul_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_report(self) -> dict:
+        """{kernel name: (launches, total ms)} since profiling was enabled."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().polymul_profile_report(self.handle, buf, len(buf)))
+        out = {}
+        for line in buf.value.decode().splitlines():
+            name, cnt, ms = line.split()
+            out[name] = (int(cnt), float(ms))
+        return out
 
     def polymul(self, a, len_a: int, b, len_b: int, out=None, stream=None):
         """C = A * B, stream-ordered.  Returns the output tensor."""
