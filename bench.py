@@ -13,7 +13,8 @@ is for the kernel with the largest total time, priced against HBM at 8 TB/s
 with the nominal algorithmic bytes of its stage (each stage streams its input
 and output once): BasisCvt 2A+2B, Encode A+B+2N, Butterfly 2N per transform,
 pointwise 3N, iButterfly 2N, Decode 2N, iBasisCvt 2N (A, B operand bytes,
-N transform bytes); a stage's bytes are split evenly over its launches.
+N transform bytes).  Fused kernels are priced by the data they transform,
+read once and written once (KERNEL_BYTES).
 """
 from __future__ import annotations
 
@@ -35,18 +36,28 @@ WORKLOADS = {
     "large": (1 << 30, 0x5EED0030, False, "single product 2^30 x 2^30 bits, uniform random"),
 }
 
-# kernel name -> stage of the nominal byte model
-STAGE_OF = {
-    "basiscvt_wide": "basiscvt", "basiscvt_word": "basiscvt", "basiscvt": "basiscvt",
-    "encode": "encode", "butterfly": "butterfly", "pointwise": "pointwise",
-    "ibutterfly": "ibutterfly", "decode_vec": "decode", "decode_scatter": "decode", "decode": "decode",
-    "ibasiscvt_wide": "ibasiscvt", "ibasiscvt_word": "ibasiscvt", "ibasiscvt": "ibasiscvt",
+# Algorithmic bytes per launch of each kernel of the large-size schedule: the
+# data it transforms read once and written once at natural size (A, B operand
+# bytes, N transform bytes).  Fused kernels count each input and output once.
+KERNEL_BYTES = {
+    "basiscvt_zeta": lambda A, B, N: 2 * A,             # two launches per operand
+    "basiscvt_rows": lambda A, B, N: 2 * A,             # one per operand
+    "basiscvt_outer_encode": lambda A, B, N: A + N,     # one per operand
+    "butterfly_upper": lambda A, B, N: 4 * N,           # A and B together
+    "butterfly_bottom_product": lambda A, B, N: 3 * N,  # read A, B; write C
+    "ibutterfly_upper": lambda A, B, N: 2 * N,
+    "decode_outer": lambda A, B, N: 2 * N,
+    "ibasiscvt_rows": lambda A, B, N: 2 * N,
+    "ibasiscvt_zeta": lambda A, B, N: 2 * N,
+    "ibasiscvt_store": lambda A, B, N: 2 * N,
 }
 
 
-def stage_bytes(A: int, B: int, N: int) -> dict:
-    return {"basiscvt": 2 * A + 2 * B, "encode": A + B + 2 * N, "butterfly": 4 * N, "pointwise": 3 * N,
-            "ibutterfly": 2 * N, "decode": 2 * N, "ibasiscvt": 2 * N}
+def nominal_bytes(A: int, B: int, N: int) -> int:
+    """Nominal algorithmic bytes of one product: each stage of Alg. 5 streams its
+    input and output once (BasisCvt 2A+2B, Encode A+B+2N, Butterfly 4N,
+    pointwise 3N, iButterfly 2N, Decode 2N, iBasisCvt 2N) = 3A + 3B + 15N."""
+    return 3 * A + 3 * B + 15 * N
 
 
 def log(*a):
@@ -125,26 +136,27 @@ def main():
     A = B = L // 8
     log2n = max(6, (lc - 1).bit_length())
     N = (1 << log2n) // 8
-    sb = stage_bytes(A, B, N)
-    nominal = sum(sb.values())
-    # per stage: launches and time per product
-    launches_per_stage = {}
-    for name, (cnt, tot) in prof.items():
-        st = STAGE_OF.get(name)
-        if st:
-            launches_per_stage[st] = launches_per_stage.get(st, 0) + cnt / args.steps
+    nominal = nominal_bytes(A, B, N)
     per_kernel = {}
     for name, (cnt, tot) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         per_kernel[name] = {"launches_per_step": cnt / args.steps, "ms_per_step": tot / args.steps,
                             "avg_launch_us": 1e3 * tot / cnt}
-        log(f"[bench] {name:18s} {cnt / args.steps:7.1f} launches/step {tot / args.steps:9.4f} ms/step "
+        if name in KERNEL_BYTES:
+            gbs = KERNEL_BYTES[name](A, B, N) / (tot / cnt / 1e3) / 1e9
+            per_kernel[name]["achieved_GBs"] = round(gbs, 1)
+        log(f"[bench] {name:26s} {cnt / args.steps:6.1f} launches/step {tot / args.steps:9.4f} ms/step "
             f"{1e3 * tot / cnt:9.2f} us/launch")
-    dom = max((n for n in prof if STAGE_OF.get(n)), key=lambda n: prof[n][1])
-    dst = STAGE_OF[dom]
-    cnt, tot = prof[dom]
-    bytes_per_launch = sb[dst] / launches_per_stage[dst]
-    avg_s = tot / cnt / 1e3
-    achieved = bytes_per_launch / avg_s / 1e9
+    known = [n for n in prof if n in KERNEL_BYTES]
+    dom = max(known, key=lambda n: prof[n][1]) if known else None
+    roof = None
+    if dom:
+        cnt, tot = prof[dom]
+        bytes_per_launch = KERNEL_BYTES[dom](A, B, N)
+        avg_s = tot / cnt / 1e3
+        achieved = bytes_per_launch / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "bytes_per_launch": int(bytes_per_launch),
+                "avg_launch_us": round(avg_s * 1e6, 3)}
     product_gbs = nominal / (ms / 1e3) / 1e9
     log(f"[bench] {ms:.3f} ms/product; nominal {nominal / 1e9:.3f} GB -> {product_gbs:.1f} GB/s "
         f"({100 * product_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
@@ -164,9 +176,7 @@ def main():
         "dtype": "u64", "data": "synthetic (seeded SplitMix64 bits, resident in HBM)",
         "config": {"workload": desc, "len_a": L, "len_b": L, "transform_bits": 1 << log2n,
                    "seed": hex(seed), "field": "GF(2^64)"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                     "bytes_per_launch": int(bytes_per_launch), "avg_launch_us": round(avg_s * 1e6, 3)},
+        "roofline": roof,
         "product_roofline": {"nominal_bytes": nominal, "achieved": round(product_gbs, 2), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(product_gbs / HBM_PEAK_GBS, 5)},
         "kernels": per_kernel,

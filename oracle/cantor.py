@@ -124,6 +124,40 @@ def iota(cvec: int) -> int:
     return r
 
 
+@lru_cache(maxsize=None)
+def tower_basis() -> tuple:
+    """Polynomial-representation images of the 64 unit vectors of the tower
+    representation the GPU path stores values in: unit 8k+u is v_u * W_k with
+    W_k = v_8^(k&1) v_16^((k>>1)&1) v_32^(k>>2).  (A representation choice of
+    the implementation, independent of the paper; the product does not depend
+    on it.)"""
+    v = cantor_basis()
+    out = []
+    for k in range(8):
+        w = 1
+        if k & 1:
+            w = mul(w, v[8])
+        if k & 2:
+            w = mul(w, v[16])
+        if k & 4:
+            w = mul(w, v[32])
+        for u in range(8):
+            out.append(mul(v[u], w))
+    return tuple(out)
+
+
+def tower_to_poly(x: int) -> int:
+    tb = tower_basis()
+    r = 0
+    t = 0
+    while x:
+        if x & 1:
+            r ^= tb[t]
+        x >>= 1
+        t += 1
+    return r
+
+
 def point(l: int, j: int) -> int:
     """Point j of Sigma = v_{l+32} + V_l: Cantor vector 2^(l+32) XOR j."""
     return iota((1 << (l + 32)) ^ j)

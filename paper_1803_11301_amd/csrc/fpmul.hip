@@ -8,9 +8,8 @@
 //   pointwise products in GF(2^64)      (Alg. 5 line 7)
 //   iButterfly, Decode, iBasisCvt       (Alg. 5 lines 8-10)
 //
-// Field elements are uint64_t in the polynomial basis modulo
-// x^64 + x^4 + x^3 + x + 1 (Sec. 4.3).  Butterfly multipliers are built on the
-// device from Cantor coordinates: layer i of block b multiplies by
+// Field elements are uint64_t in the tower representation over V_8 (see
+// consts_host.h and gf_device.h).  Layer i of block b multiplies by
 // s_i(v_{l+32} + b 2^(i+1)) whose Cantor vector is 2^(32+d) XOR 2b, d = l - i
 // (Eq. 4 and the recursion of Alg. 2).
 #include <hip/hip_runtime.h>
@@ -22,6 +21,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -57,46 +57,9 @@ static int fail(int code, const std::string &msg)
             return fail(POLYMUL_EIO, std::string("launch " name ": ") + hipGetErrorString(_e)); \
     } while (0)
 
-// ---------------------------------------------------------------------------
-// device constants
-// ---------------------------------------------------------------------------
-
-struct DevTables {
-    uint64_t iota[8][256];   // Cantor vector -> polynomial representation, by bytes
-    uint64_t enc[64];        // Encode rows r_j
-    uint64_t dec[64];        // inverse Encode rows
-};
-
-// ---------------------------------------------------------------------------
-// GF(2^64) arithmetic on the device
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ uint64_t gf_reduce(uint64_t lo, uint64_t hi)
-{
-    uint64_t t = hi ^ (hi << 1) ^ (hi << 3) ^ (hi << 4);
-    uint64_t o = (hi >> 63) ^ (hi >> 61) ^ (hi >> 60);
-    return lo ^ t ^ o ^ (o << 1) ^ (o << 3) ^ (o << 4);
-}
-
-// general product, one bit of b at a time
-__device__ __forceinline__ uint64_t gf_mul_generic(uint64_t a, uint64_t b)
-{
-    uint64_t lo = 0, hi = 0;
-    for (int i = 0; i < 64; ++i) {
-        uint64_t m = 0ull - ((b >> i) & 1ull);
-        lo ^= (a << i) & m;
-        hi ^= (i ? (a >> (64 - i)) : 0ull) & m;
-    }
-    return gf_reduce(lo, hi);
-}
-
-__device__ __forceinline__ uint64_t iota_dev(const DevTables *T, uint64_t cvec)
-{
-    uint64_t r = 0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k) r ^= T->iota[k][(cvec >> (8 * k)) & 255u];
-    return r;
-}
+#include "gf_device.h"
+#include "k_butterfly.h"
+#include "k_basiscvt.h"
 
 // ---------------------------------------------------------------------------
 // elementary kernels
@@ -234,7 +197,8 @@ __global__ void k_bcvt_step_word(const uint64_t *__restrict__ in, uint64_t *__re
 }
 
 // ---------------------------------------------------------------------------
-// Encode (Alg. 4): f_i = sum_j a_{j n_p + i} r_j
+// Encode (Alg. 4): f_i = sum_j a_{j n_p + i} r_j, the 64-bit column of bits
+// (a_{j n_p + i})_j multiplied into the rows r_j by 8-bit windows
 // ---------------------------------------------------------------------------
 
 __global__ void k_encode(const uint64_t *__restrict__ bits, int l, const DevTables *__restrict__ T,
@@ -243,22 +207,25 @@ __global__ void k_encode(const uint64_t *__restrict__ bits, int l, const DevTabl
     uint64_t i = gid();
     uint64_t n_p = 1ull << l;
     if (i >= n_p) return;
-    uint64_t f = 0;
+    uint64_t col = 0;
     for (int j = 0; j < 64; ++j) {
         uint64_t p = ((uint64_t)j << l) + i;
-        if ((bits[p >> 6] >> (p & 63)) & 1ull) f ^= T->enc[j];
+        col |= ((bits[p >> 6] >> (p & 63)) & 1ull) << j;
     }
+    uint64_t f = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(col >> (8 * k)) & 255u];
     vals[i] = f;
 }
 
-// Decode part 1: each value -> its 64 bits (a = XOR_{t in h} dec[t]), in place
+// Decode part 1: each value -> its 64 bits, in place
 __global__ void k_decode_vec(uint64_t *__restrict__ vals, int l, const DevTables *__restrict__ T)
 {
     uint64_t i = gid();
     if (i >= (1ull << l)) return;
     uint64_t h = vals[i], a = 0;
-    for (int t = 0; t < 64; ++t)
-        if ((h >> t) & 1ull) a ^= T->dec[t];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a ^= T->dec_win[k][(h >> (8 * k)) & 255u];
     vals[i] = a;
 }
 
@@ -278,37 +245,6 @@ __global__ void k_decode_scatter(const uint64_t *__restrict__ vecs, int l, uint6
 }
 
 // ---------------------------------------------------------------------------
-// Butterfly (Alg. 2) layer i, and its inverse
-// ---------------------------------------------------------------------------
-
-__global__ void k_bfly_layer(uint64_t *__restrict__ v, int l, int i, int inverse, const DevTables *__restrict__ T)
-{
-    uint64_t t = gid();
-    if (t >= (1ull << (l - 1))) return;
-    uint64_t b = t >> i, off = t & ((1ull << i) - 1);
-    uint64_t p0 = (b << (i + 1)) | off, p1 = p0 | (1ull << i);
-    int d = l - i;
-    uint64_t c = iota_dev(T, (1ull << (32 + d)) ^ (b << 1));
-    uint64_t x0 = v[p0], x1 = v[p1];
-    if (!inverse) {
-        uint64_t h0 = x0 ^ gf_mul_generic(c, x1);
-        v[p0] = h0;
-        v[p1] = h0 ^ x1;
-    } else {
-        uint64_t q1 = x0 ^ x1;
-        v[p0] = x0 ^ gf_mul_generic(c, q1);
-        v[p1] = q1;
-    }
-}
-
-__global__ void k_pointwise(uint64_t *__restrict__ a, const uint64_t *__restrict__ b, uint64_t n)
-{
-    uint64_t i = gid();
-    if (i >= n) return;
-    a[i] = gf_mul_generic(a[i], b[i]);
-}
-
-// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 
@@ -320,9 +256,10 @@ struct ProfRec {
 struct polymul_ctx {
     int device = 0;
     size_t cap = 0;
-    uint64_t *ws[3] = {nullptr, nullptr, nullptr};
+    uint64_t *ws[4] = {nullptr, nullptr, nullptr, nullptr};
     uint64_t ws_words = 0;   // words per workspace buffer
     DevTables *tables = nullptr;
+    int num_cu = 256;
     // per-kernel timing with HIP events on the launch stream (off by default)
     bool prof = false;
     std::vector<ProfRec> prof_live;       // recorded, not yet read
@@ -390,17 +327,17 @@ static int ensure_ws(polymul_ctx *ctx, uint64_t words)
 {
     if (words <= ctx->ws_words) return 0;
     size_t bytes = (size_t)words * 8;
-    if (ctx->cap && 3 * bytes > ctx->cap)
-        return fail(POLYMUL_ENOMEM, "workspace of " + std::to_string(3 * bytes) + " bytes exceeds the cap of " +
+    if (ctx->cap && 4 * bytes > ctx->cap)
+        return fail(POLYMUL_ENOMEM, "workspace of " + std::to_string(4 * bytes) + " bytes exceeds the cap of " +
                                         std::to_string(ctx->cap));
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         if (ctx->ws[k]) { (void)hipFree(ctx->ws[k]); ctx->ws[k] = nullptr; }
     }
     ctx->ws_words = 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         hipError_t e = hipMalloc(&ctx->ws[k], bytes);
         if (e != hipSuccess) {
-            for (int j = 0; j < 3; ++j)
+            for (int j = 0; j < 4; ++j)
                 if (ctx->ws[j]) { (void)hipFree(ctx->ws[j]); ctx->ws[j] = nullptr; }
             return fail(POLYMUL_ENOMEM, std::string("hipMalloc workspace: ") + hipGetErrorString(e));
         }
@@ -465,9 +402,9 @@ static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *&cur, 
     return 0;
 }
 
-// A (len bits) -> n_p values in *cur (cur/spare swapped as needed)
-static int run_forward(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int log2n, uint64_t *&cur,
-                       uint64_t *&spare, hipStream_t s)
+// A (len bits) -> BasisCvt -> Encode: n_p values in *cur (cur/spare swapped as needed)
+static int run_encode_in(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int log2n, uint64_t *&cur,
+                         uint64_t *&spare, hipStream_t s)
 {
     const int l = log2n - 6;
     const uint64_t nw = 1ull << l, n_p = 1ull << l;
@@ -477,23 +414,97 @@ static int run_forward(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int lo
     if (rc) return rc;
     KLAUNCH(ctx, s, "encode", k_encode, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
     std::swap(cur, spare);
-    for (int i = l - 1; i >= 0; --i)
-        KLAUNCH(ctx, s, "butterfly", k_bfly_layer, grid_for(n_p / 2, bs), bs, cur, l, i, 0, ctx->tables);
     return 0;
 }
 
-// values in *cur (destroyed) -> n bits in *cur
-static int run_inverse(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t *&spare, hipStream_t s)
+// values in *cur (destroyed) -> Decode -> iBasisCvt: n bits in *cur
+static int run_decode_out(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t *&spare, hipStream_t s)
 {
     const int l = log2n - 6;
     const uint64_t nw = 1ull << l, n_p = 1ull << l;
     const unsigned bs = 256;
-    for (int i = 0; i < l; ++i)
-        KLAUNCH(ctx, s, "ibutterfly", k_bfly_layer, grid_for(n_p / 2, bs), bs, cur, l, i, 1, ctx->tables);
     KLAUNCH(ctx, s, "decode_vec", k_decode_vec, grid_for(n_p, bs), bs, cur, l, ctx->tables);
     KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
     std::swap(cur, spare);
     return run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s);
+}
+
+// the layers above the bottom tile, as (i_lo, k) groups of at most BF_UPPER_MAXK, lowest first
+static std::vector<std::pair<int, int>> upper_groups(int l, int R)
+{
+    std::vector<std::pair<int, int>> g;
+    int U = l - R;
+    if (U <= 0) return g;
+    int ng = (U + BF_UPPER_MAXK - 1) / BF_UPPER_MAXK, base = U / ng, extra = U % ng, lo = R;
+    for (int q = 0; q < ng; ++q) {
+        int k = base + (q < extra ? 1 : 0);
+        g.push_back({lo, k});
+        lo += k;
+    }
+    return g;
+}
+
+static int set_lds_limits()
+{
+    static int done = 0;
+    if (done) return 0;
+    const int big = 160 * 1024;
+    HIP_TRY(hipFuncSetAttribute((const void *)k_bfly_bottom<BF_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_bfly_bottom<BF_INV>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_bfly_bottom<BF_PRODUCT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                big));
+    done = 1;
+    return 0;
+}
+
+#define KLAUNCH_LDS(ctx, s, name, kernel, grid, block, lds, ...)                                   \
+    do {                                                                                           \
+        prof_begin((ctx), (s), (name));                                                            \
+        kernel<<<(grid), (block), (lds), (s)>>>(__VA_ARGS__);                                      \
+        hipError_t _le = hipGetLastError();                                                        \
+        prof_end((ctx), (s));                                                                      \
+        if (_le != hipSuccess)                                                                     \
+            return fail(POLYMUL_EIO, std::string("launch ") + (name) + ": " + hipGetErrorString(_le)); \
+    } while (0)
+
+// Butterflies of one transform (mode BF_FWD or BF_INV) or of a product
+// (BF_PRODUCT: forward A and B, pointwise, inverse; result in A)
+static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B, int l, hipStream_t s)
+{
+    const int R = std::min(l, BF_BOTTOM_R);
+    const auto groups = upper_groups(l, R);
+    const dim3 blk(BF_THREADS), ublk(BF_UP_THREADS);
+    const uint64_t persist_up = (uint64_t)ctx->num_cu * 2, persist_bot = (uint64_t)ctx->num_cu;
+    if (mode != BF_INV) {
+        for (auto it = groups.rbegin(); it != groups.rend(); ++it) {
+            const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
+            const unsigned tiles = (unsigned)std::min<uint64_t>(1ull << (l - k - lgW), persist_up);
+            if (mode == BF_PRODUCT)
+                KLAUNCH(ctx, s, "butterfly_upper", k_bfly_upper<BF_FWD2>, tiles, ublk, A, B, l, i_lo, k, lgW,
+                        ctx->tables);
+            else
+                KLAUNCH(ctx, s, "butterfly_upper", k_bfly_upper<BF_FWD>, tiles, ublk, A, B, l, i_lo, k, lgW,
+                        ctx->tables);
+        }
+    }
+    const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - R), persist_bot);
+    if (mode == BF_PRODUCT)
+        KLAUNCH_LDS(ctx, s, "butterfly_bottom_product", k_bfly_bottom<BF_PRODUCT>, bt, blk, bf_bottom_lds(R, true), A,
+                    B, l, R, ctx->tables);
+    else if (mode == BF_FWD)
+        KLAUNCH_LDS(ctx, s, "butterfly_bottom", k_bfly_bottom<BF_FWD>, bt, blk, bf_bottom_lds(R, false), A, B, l, R,
+                    ctx->tables);
+    else
+        KLAUNCH_LDS(ctx, s, "ibutterfly_bottom", k_bfly_bottom<BF_INV>, bt, blk, bf_bottom_lds(R, false), A, B, l, R,
+                    ctx->tables);
+    if (mode != BF_FWD) {
+        for (auto it = groups.begin(); it != groups.end(); ++it) {
+            const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
+            const unsigned tiles = (unsigned)std::min<uint64_t>(1ull << (l - k - lgW), persist_up);
+            KLAUNCH(ctx, s, "ibutterfly_upper", k_bfly_upper<BF_INV>, tiles, ublk, A, B, l, i_lo, k, lgW, ctx->tables);
+        }
+    }
+    return 0;
 }
 
 static int transform_log2(uint64_t len_a, uint64_t len_b)
@@ -524,21 +535,139 @@ struct DeviceGuard {
     }
 };
 
+// ---------------------------------------------------------------------------
+// fast BasisCvt + Encode / Decode + iBasisCvt (k_basiscvt.h), 2^22 <= n <= 2^31
+// ---------------------------------------------------------------------------
+
+static bool fast_path(int log2n) { return log2n >= 22 && log2n <= 31; }
+
+static BcSteps make_steps(uint64_t N)
+{
+    std::vector<BStep> v;
+    bcvt_steps(N, 1, v);
+    BcSteps st;
+    std::memset(&st, 0, sizeof st);
+    st.n = (int)v.size();
+    for (size_t k = 0; k < v.size() && k < BC_MAX_STEPS; ++k) {
+        const int S = (int)v[k].S, d = (int)v[k].d, H = S / 2;
+        st.lgS[k] = (uint8_t)ilog2(v[k].S);
+        st.lgd[k] = (uint8_t)ilog2(v[k].d);
+        uint64_t L = 0, D = 0;
+        if (S <= 64)
+            for (int b = 0; b < 64; ++b) {
+                int r = b % S;
+                if (r < H) L |= 1ull << b;
+                if (r < d) D |= 1ull << b;
+            }
+        st.L[k] = L;
+        st.D[k] = D;
+    }
+    return st;
+}
+
+// words per skewed row: tau + R bits, the extension rounded up to 64 words
+static int bc_ew(int lgR)
+{
+    uint64_t R = 1ull << lgR, ext = (R + 63) / 64;
+    ext = (ext + 63) / 64 * 64;
+    return (int)(BC_TAU_WORDS + ext);
+}
+
+// workspace words one buffer needs for transform length 2^log2n
+static uint64_t ws_words_for(int log2n)
+{
+    uint64_t nw = 1ull << (log2n - 6);
+    if (!fast_path(log2n)) return nw;
+    const int lgR = log2n - 16;
+    return std::max<uint64_t>(nw, (1ull << lgR) * (uint64_t)bc_ew(lgR));
+}
+
+static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t *in, uint64_t len, int lgR, int EW,
+                    bool skew_first)
+{
+    const int nb1 = std::min(lgR, 8), nb2 = lgR - nb1;
+    for (int pass = 0; pass < 2; ++pass) {
+        const int b0 = pass ? nb1 : 0, nb = pass ? nb2 : nb1;
+        if (nb <= 0) continue;
+        const int lgWc = std::min(6, 11 - nb);
+        const uint64_t tiles = (1ull << (lgR - nb)) * (uint64_t)(EW >> lgWc);
+        const unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->num_cu * 8);
+        KLAUNCH(ctx, s, skew_first ? "basiscvt_zeta" : "ibasiscvt_zeta", k_bc_zeta, grid, BC_THREADS, X, in, len,
+                lgR, EW, b0, nb, lgWc, (pass == 0 && skew_first && in) ? 1 : 0);
+    }
+    return 0;
+}
+
+// operand (len bits) -> BasisCvt -> Encode -> vals (2^(log2n-6) words); X, Y scratch
+static int run_encode_fast(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int log2n, uint64_t *vals,
+                           uint64_t *X, uint64_t *Y, hipStream_t s)
+{
+    const int l = log2n - 6;
+    const uint64_t N = next_pow2(std::max<uint64_t>(len, 1));
+    const int lgR = N <= (1ull << 16) ? 0 : ilog2(N) - 16;
+    const int EW = bc_ew(lgR);
+    if (lgR >= 1) {
+        int rc = run_zeta(ctx, s, X, a, len, lgR, EW, true);
+        if (rc) return rc;
+    }
+    const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
+    const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / BC_ROWS,
+                                                                              (uint64_t)ctx->num_cu * 2));
+    KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_THREADS, X, a, len, lgR, EW, Y, inner);
+    KLAUNCH(ctx, s, "basiscvt_outer_encode", k_bc_outer_encode, (unsigned)std::min(BC_TAU_WORDS, ctx->num_cu),
+            BC_THREADS, Y, lgR, l, vals, outer, ctx->tables);
+    return 0;
+}
+
+// vals (destroyed? no: read only) -> Decode -> iBasisCvt -> out (len bits)
+static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, uint64_t *out, uint64_t len,
+                           uint64_t *X, uint64_t *Y, hipStream_t s)
+{
+    const int l = log2n - 6, lgR = log2n - 16, EW = bc_ew(lgR);
+    const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
+    KLAUNCH(ctx, s, "decode_outer", k_bc_decode_outer, (unsigned)std::min(2 * BC_TAU_WORDS, ctx->num_cu), BC_THREADS,
+            vals, lgR, l, reinterpret_cast<uint32_t *>(Y), outer, ctx->tables);
+    const unsigned grows = (unsigned)std::min<uint64_t>((1ull << lgR) / BC_ROWS, (uint64_t)ctx->num_cu * 2);
+    KLAUNCH(ctx, s, "ibasiscvt_rows", k_bc_inv_rows, grows, BC_THREADS, reinterpret_cast<const uint32_t *>(Y), lgR,
+            EW, X, inner);
+    int rc = run_zeta(ctx, s, X, nullptr, 0, lgR, EW, false);
+    if (rc) return rc;
+    KLAUNCH(ctx, s, "ibasiscvt_store", k_bc_inv_store, (unsigned)std::min<uint64_t>(1ull << lgR,
+                                                                                    (uint64_t)ctx->num_cu * 4),
+            BC_THREADS, X, lgR, EW, len, out);
+    return 0;
+}
+
 static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
                         uint64_t *out, hipStream_t s)
 {
     const uint64_t lc = len_a + len_b - 1;
     const int log2n = transform_log2(len_a, len_b);
-    const uint64_t nw = 1ull << (log2n - 6);
-    int rc = ensure_ws(ctx, nw);
+    int rc = ensure_ws(ctx, ws_words_for(log2n));
     if (rc) return rc;
-    uint64_t *pa = ctx->ws[0], *sa = ctx->ws[2];
-    if ((rc = run_forward(ctx, a, len_a, log2n, pa, sa, s))) return rc;
-    uint64_t *pb = ctx->ws[1], *sb = sa;
-    if ((rc = run_forward(ctx, b, len_b, log2n, pb, sb, s))) return rc;
-    KLAUNCH(ctx, s, "pointwise", k_pointwise, grid_for(nw, 256), 256, pa, pb, nw);
+    if ((rc = set_lds_limits())) return rc;
+    uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2], *W3 = ctx->ws[3];
+    uint64_t *pa, *pb;
+    // forward transforms of A into W0, of B into W1 (W2, W3 scratch)
+    for (int side = 0; side < 2; ++side) {
+        const uint64_t *src = side ? b : a;
+        const uint64_t len = side ? len_b : len_a;
+        uint64_t *dst = side ? W1 : W0;
+        const uint64_t N = next_pow2(std::max<uint64_t>(len, 1));
+        if (fast_path(log2n) && N <= (1ull << 30)) {
+            if ((rc = run_encode_fast(ctx, src, len, log2n, dst, W2, W3, s))) return rc;
+        } else {
+            uint64_t *cur = dst, *spare = W2;
+            if ((rc = run_encode_in(ctx, src, len, log2n, cur, spare, s))) return rc;
+            if (cur != dst) HIP_TRY(hipMemcpyAsync(dst, cur, (1ull << (log2n - 6)) * 8, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    pa = W0;
+    pb = W1;
+    if ((rc = run_butterflies(ctx, BF_PRODUCT, pa, pb, log2n - 6, s))) return rc;
+    if (fast_path(log2n)) return run_decode_fast(ctx, pa, log2n, out, lc, W2, W3, s);
     uint64_t *cur = pa, *spare = pb;
-    if ((rc = run_inverse(ctx, log2n, cur, spare, s))) return rc;
+    if ((rc = run_decode_out(ctx, log2n, cur, spare, s))) return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, cur, lc, out);
     return 0;
 }
@@ -547,10 +676,17 @@ static int addfft_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int 
                        hipStream_t s)
 {
     const uint64_t nw = 1ull << (log2n - 6);
-    int rc = ensure_ws(ctx, nw);
+    int rc = ensure_ws(ctx, ws_words_for(log2n));
     if (rc) return rc;
+    if ((rc = set_lds_limits())) return rc;
     uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
-    if ((rc = run_forward(ctx, len_a ? a : ctx->ws[2], len_a, log2n, cur, spare, s))) return rc;
+    const uint64_t N = next_pow2(std::max<uint64_t>(len_a, 1));
+    if (fast_path(log2n) && N <= (1ull << 30) && len_a) {
+        if ((rc = run_encode_fast(ctx, a, len_a, log2n, cur, ctx->ws[2], ctx->ws[3], s))) return rc;
+    } else {
+        if ((rc = run_encode_in(ctx, len_a ? a : ctx->ws[2], len_a, log2n, cur, spare, s))) return rc;
+    }
+    if ((rc = run_butterflies(ctx, BF_FWD, cur, nullptr, log2n - 6, s))) return rc;
     HIP_TRY(hipMemcpyAsync(values, cur, nw * 8, hipMemcpyDeviceToDevice, s));
     return 0;
 }
@@ -559,11 +695,14 @@ static int iaddfft_body(polymul_ctx *ctx, const uint64_t *values, int log2n, uin
                         hipStream_t s)
 {
     const uint64_t nw = 1ull << (log2n - 6);
-    int rc = ensure_ws(ctx, nw);
+    int rc = ensure_ws(ctx, ws_words_for(log2n));
     if (rc) return rc;
+    if ((rc = set_lds_limits())) return rc;
     uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
     HIP_TRY(hipMemcpyAsync(cur, values, nw * 8, hipMemcpyDeviceToDevice, s));
-    if ((rc = run_inverse(ctx, log2n, cur, spare, s))) return rc;
+    if ((rc = run_butterflies(ctx, BF_INV, cur, nullptr, log2n - 6, s))) return rc;
+    if (fast_path(log2n)) return run_decode_fast(ctx, cur, log2n, out, out_bits, ctx->ws[2], ctx->ws[3], s);
+    if ((rc = run_decode_out(ctx, log2n, cur, spare, s))) return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for((out_bits + 63) / 64, 256), 256, cur, out_bits, out);
     return 0;
 }
@@ -581,6 +720,32 @@ static int basiscvt_body(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int
         return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for(nw, 256), 256, cur, nbits, out);
     return 0;
+}
+
+static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
+{
+    const fpmul_host::Tower &tw = H.tw;
+    std::memcpy(D.iota, H.iota, sizeof(D.iota));
+    for (int k = 0; k < 8; ++k)
+        for (int e = 0; e < 256; ++e) {
+            uint64_t f = 0, a = 0;
+            for (int u = 0; u < 8; ++u)
+                if ((e >> u) & 1) {
+                    f ^= H.enc[8 * k + u];
+                    a ^= H.dec[8 * k + u];
+                }
+            D.enc_win[k][e] = f;
+            D.dec_win[k][e] = a;
+        }
+    for (int d = 0; d < 32; ++d)
+        for (int t = 0; t < 64; ++t) D.gbasis[d][t] = tw.m64(H.cantor[32 + d], 1ull << t);
+    for (int v = 0; v < 24; ++v)
+        for (int t = 0; t < 64; ++t) D.pbasis[v][t] = tw.m64(H.cantor[8 + v], 1ull << t);
+    std::memcpy(D.mul8, tw.mul8, sizeof(D.mul8));
+    for (int p = 0; p < 2; ++p)
+        for (int e = 0; e < 256; ++e) D.c15[p][e] = tw.m16(tw.v15, (uint16_t)(e << (8 * p)));
+    for (int p = 0; p < 4; ++p)
+        for (int e = 0; e < 256; ++e) D.c31[p][e] = tw.m32(tw.v31, (uint32_t)e << (8 * p));
 }
 
 // ---------------------------------------------------------------------------
@@ -602,21 +767,24 @@ int polymul_ctx_create(polymul_ctx **out, int device, size_t workspace_cap)
     if (device < 0 || device >= ndev) return fail(POLYMUL_EINVAL, "no such device");
     DeviceGuard g(device);
     HIP_TRY(g.err);
-    fpmul_host::Tables H;
+    std::unique_ptr<fpmul_host::Tables> H(new fpmul_host::Tables());
+    std::unique_ptr<DevTables> D(new DevTables());
     try {
-        fpmul_host::build_tables(H);
+        fpmul_host::build_tables(*H);
+        fill_dev_tables(*H, *D);
     } catch (const std::exception &ex) {
         return fail(POLYMUL_EIO, std::string("constant tables: ") + ex.what());
     }
-    DevTables D;
-    std::memcpy(D.iota, H.iota, sizeof(D.iota));
-    std::memcpy(D.enc, H.enc, sizeof(D.enc));
-    std::memcpy(D.dec, H.dec, sizeof(D.dec));
     polymul_ctx *ctx = new polymul_ctx();
     ctx->device = device;
     ctx->cap = workspace_cap;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+            ctx->num_cu = cus;
+    }
     hipError_t e = hipMalloc(&ctx->tables, sizeof(DevTables));
-    if (e == hipSuccess) e = hipMemcpy(ctx->tables, &D, sizeof(DevTables), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->tables, D.get(), sizeof(DevTables), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (ctx->tables) (void)hipFree(ctx->tables);
         delete ctx;
@@ -631,7 +799,7 @@ int polymul_ctx_destroy(polymul_ctx *ctx)
     if (!ctx) return 0;
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
         if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
     if (ctx->tables) (void)hipFree(ctx->tables);
     for (ProfRec &r : ctx->prof_live) {

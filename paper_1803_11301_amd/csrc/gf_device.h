@@ -1,0 +1,140 @@
+// gf_device.h -- GF(2^64) arithmetic on gfx950 in the tower representation
+// (bytes of GF(2^8) = V_8 in Cantor coordinates, towered by v_8, v_16, v_32;
+// see consts_host.h).
+//
+// Multiplications the kernels use:
+//   tmul  -- by a constant K through its 8-bit window table in LDS
+//            (tab[k*256 + e] = K * (e at byte k)): 8 lookups, 7 XORs.
+//   bmul  -- by an element beta of V_8: every byte is multiplied by beta on
+//            its own (the tower is V_8-linear), one GF(2^8) table row.
+//   gmul  -- general product (pointwise step of Alg. 5): Karatsuba over the
+//            tower, 27 GF(2^8) products plus the three reductions
+//            v_8^2 = v_8 + v_7, v_16^2 = v_16 + v_15, v_32^2 = v_32 + v_31.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+struct DevTables {
+    uint64_t iota[8][256];       // Cantor vector -> tower element, by bytes
+    uint64_t enc_win[8][256];    // Encode: byte window k of the bit column -> sum of r_j
+    uint64_t dec_win[8][256];    // Decode: byte window k of the value -> bits
+    uint64_t gbasis[32][64];     // v_{32+d} * unit_{8k+u}
+    uint64_t pbasis[24][64];     // v_{8+v} * unit_{8k+u}
+    uint8_t mul8[256][256];      // GF(2^8) products, Cantor coordinates
+    uint16_t c15[2][256];        // v_15 * (byte at position p) in GF(2^16)
+    uint32_t c31[4][256];        // v_31 * (byte at position p) in GF(2^32)
+};
+
+// ----------------------------------------------------------------- tmul ----
+
+__device__ __forceinline__ uint64_t tmul(const uint64_t *__restrict__ tab, uint64_t x)
+{
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    uint64_t r0 = tab[lo & 255u] ^ tab[256 + ((lo >> 8) & 255u)];
+    uint64_t r1 = tab[512 + ((lo >> 16) & 255u)] ^ tab[768 + (lo >> 24)];
+    uint64_t r2 = tab[1024 + (hi & 255u)] ^ tab[1280 + ((hi >> 8) & 255u)];
+    uint64_t r3 = tab[1536 + ((hi >> 16) & 255u)] ^ tab[1792 + (hi >> 24)];
+    return (r0 ^ r1) ^ (r2 ^ r3);
+}
+
+// ----------------------------------------------------------------- bmul ----
+
+// row = 256-byte GF(2^8) table row of beta
+__device__ __forceinline__ uint64_t bmul(const uint8_t *__restrict__ row, uint64_t x)
+{
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    uint32_t a = (uint32_t)row[lo & 255u] | ((uint32_t)row[(lo >> 8) & 255u] << 8) |
+                 ((uint32_t)row[(lo >> 16) & 255u] << 16) | ((uint32_t)row[lo >> 24] << 24);
+    uint32_t b = (uint32_t)row[hi & 255u] | ((uint32_t)row[(hi >> 8) & 255u] << 8) |
+                 ((uint32_t)row[(hi >> 16) & 255u] << 16) | ((uint32_t)row[hi >> 24] << 24);
+    return (uint64_t)a | ((uint64_t)b << 32);
+}
+
+// ----------------------------------------------------------------- gmul ----
+
+// LDS view of the full GF(2^8) table: row a at (a & 1) * 32768 + (a >> 1) * 256
+struct Mul8View {
+    const uint8_t *even;   // rows 0, 2, 4, ...
+    const uint8_t *odd;    // rows 1, 3, 5, ...
+    const uint16_t *c15;   // [2][256]
+    const uint32_t *c31;   // [4][256]
+    __device__ __forceinline__ uint32_t m8(uint32_t a, uint32_t b) const
+    {
+        const uint8_t *base = (a & 1u) ? odd : even;
+        return base[((a >> 1) << 8) | b];
+    }
+    __device__ __forceinline__ uint32_t m16(uint32_t a, uint32_t b) const
+    {
+        uint32_t a0 = a & 255u, a1 = a >> 8, b0 = b & 255u, b1 = b >> 8;
+        uint32_t p0 = m8(a0, b0), p2 = m8(a1, b1), p1 = m8(a0 ^ a1, b0 ^ b1);
+        uint32_t hi = p1 ^ p0, lo = p0 ^ m8(0x80u, p2);    // v_7 = Cantor byte 0x80
+        return lo | (hi << 8);
+    }
+    __device__ __forceinline__ uint32_t mv15(uint32_t x) const { return c15[x & 255u] ^ c15[256 + (x >> 8)]; }
+    __device__ __forceinline__ uint32_t m32(uint32_t a, uint32_t b) const
+    {
+        uint32_t a0 = a & 0xFFFFu, a1 = a >> 16, b0 = b & 0xFFFFu, b1 = b >> 16;
+        uint32_t p0 = m16(a0, b0), p2 = m16(a1, b1), p1 = m16(a0 ^ a1, b0 ^ b1);
+        uint32_t hi = p1 ^ p0, lo = p0 ^ mv15(p2);
+        return lo | (hi << 16);
+    }
+    __device__ __forceinline__ uint32_t mv31(uint32_t x) const
+    {
+        return c31[x & 255u] ^ c31[256 + ((x >> 8) & 255u)] ^ c31[512 + ((x >> 16) & 255u)] ^ c31[768 + (x >> 24)];
+    }
+    __device__ __forceinline__ uint64_t m64(uint64_t a, uint64_t b) const
+    {
+        uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+        uint32_t p0 = m32(a0, b0), p2 = m32(a1, b1), p1 = m32(a0 ^ a1, b0 ^ b1);
+        uint32_t hi = p1 ^ p0, lo = p0 ^ mv31(p2);
+        return (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+};
+
+// ------------------------------------------------------ K window tables ----
+//
+// Butterfly layer i of block b multiplies by the element with Cantor vector
+// 2^(32+d) XOR 2b, d = l - i (Eq. 4 applied to the base points of Alg. 2).
+// With b = bh * 128 + bl this is K + beta, K = Cantor(2^(32+d) XOR bh << 8)
+// and beta = Cantor(2 bl) in V_8, so x * (K + beta) = tmul(T_K, x) ^ bmul(beta, x).
+// T_K is built in LDS from its 64 basis images K * unit_{8k+u}, which are
+// linear in bh: gbasis[d] XOR the pbasis rows of the set bits of bh.
+
+// one thread per basis image (tid < 64); the 24 row loads are independent so
+// they are all in flight together
+__device__ __forceinline__ void ktable_basis(uint64_t *basis, int d, uint32_t bh, const DevTables *__restrict__ T,
+                                             int tid)
+{
+    if (tid < 64) {
+        uint64_t v = T->gbasis[d][tid];
+#pragma unroll
+        for (int b = 0; b < 24; ++b) {
+            uint64_t r = T->pbasis[b][tid];
+            v ^= ((bh >> b) & 1u) ? r : 0ull;
+        }
+        basis[tid] = v;
+    }
+}
+
+// fill entries [32 * item, 32 * item + 32) ... one work item = 8 consecutive entries
+__device__ __forceinline__ void ktable_fill_item(uint64_t *tab, const uint64_t *basis, int item)
+{
+    const int k = item >> 5, m = item & 31;
+    const uint64_t *bs = basis + 8 * k;
+    uint64_t base = 0;
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+        if ((m >> v) & 1) base ^= bs[3 + v];
+    const uint64_t b0 = bs[0], b1 = bs[1], b2 = bs[2];
+    uint64_t *t = tab + k * 256 + m * 8;
+    const uint64_t x01 = b0 ^ b1;
+    t[0] = base;
+    t[1] = base ^ b0;
+    t[2] = base ^ b1;
+    t[3] = base ^ x01;
+    t[4] = base ^ b2;
+    t[5] = base ^ b2 ^ b0;
+    t[6] = base ^ b2 ^ b1;
+    t[7] = base ^ b2 ^ x01;
+}

@@ -1,0 +1,430 @@
+// k_basiscvt.h -- BasisCvt (Alg. 1) and its inverse in a few HBM passes,
+// fused with Encode (Alg. 4) and Decode.
+//
+// Alg. 1 at the top level writes f = sum_q h_q s^q with s = x^tau + x,
+// tau = 2^16, deg h_q < tau (Taylor expansion), then converts the sequence
+// (h_q) as a polynomial with tau-bit vector coefficients ("outer", BasisCvt of
+// length R = N / tau on whole rows) and every tau-bit digit ("inner").  Outer
+// and inner act on different index bits and commute.
+//
+// Taylor expansion without shifted half-segments: with rows c_r (f =
+// sum_r c_r x^(tau r)) and x^tau = s + x, the binomial theorem over GF(2)
+// gives x^(tau r) = sum_{q subset of r} s^q x^(r-q).  Hence
+//     f = sum_q s^q P_q,   P_q = sum_{r superset of q} c_r x^(r-q),
+// i.e. after skewing row r left by r bits (Q_r = c_r x^r) P_q is the superset
+// sum of the Q_r shifted back by q: plain aligned XORs over the row index.
+// P_q has degree < tau + R; writing P_q = L_q + x^tau U_q, the digits are
+//     h_q = L_q + x U_q + U_{q-1}.
+// The inverse runs the same way: with H_q = h_q x^q, c'_r = (superset sum of
+// H)_r / x^r = lo_r + x^tau hi_r and c_r = lo_r + hi_{r-1}.
+//
+// Layout: rows of tau bits = 1024 words.  The skewed rows live in X with EW
+// words per row (tau + R bits rounded up).  Y holds the rows transposed
+// (column-major: Y[col][row]) so that the outer conversion sees one column as
+// a contiguous vector; the forward path uses 64-bit columns, the inverse
+// 32-bit columns.  Encode's input bit j n_p + i with i = r0 tau + c sits in
+// row j (n_p / tau) + r0, column c: the outer pass gathers those 64 rows of a
+// column, transposes 64 x 64 bits across a wavefront and applies the rows
+// r_j by 8-bit windows.  Decode is the mirror image.
+#pragma once
+
+#include "gf_device.h"
+
+#define BC_TAU_WORDS 1024            // tau = 2^16 bits
+#define BC_THREADS 256
+#define BC_MAX_STEPS 96
+
+struct BcSteps {
+    int n;
+    uint8_t lgS[BC_MAX_STEPS];       // log2 of the segment length (bits or elements)
+    uint8_t lgd[BC_MAX_STEPS];       // log2 of the shift (bits or elements)
+    uint64_t L[BC_MAX_STEPS];        // in-word steps (S <= 64): low-half mask of every segment
+    uint64_t D[BC_MAX_STEPS];        // in-word steps: low-d mask of every segment
+};
+
+// ------------------------------------------------------------ helpers ------
+
+__device__ __forceinline__ uint64_t bc_lowmask(int x)
+{
+    return x >= 64 ? ~0ull : (x <= 0 ? 0ull : ((1ull << x) - 1ull));
+}
+
+// 64 bits starting at bit offset off of a word array w[0, nw); outside reads 0
+__device__ __forceinline__ uint64_t bc_bits(const uint64_t *w, int nw, long off)
+{
+    const long i0 = off >> 6;                     // floor division
+    const int s = (int)(off & 63);
+    uint64_t a = (i0 >= 0 && i0 < nw) ? w[i0] : 0ull;
+    uint64_t b = (i0 + 1 >= 0 && i0 + 1 < nw) ? w[i0 + 1] : 0ull;
+    return s ? ((a >> s) | (b << (64 - s))) : a;
+}
+
+__device__ __forceinline__ uint64_t bc_word_step(uint64_t x, int H, int d, uint64_t L, uint64_t D, bool inverse)
+{
+    uint64_t lo = x & L, hi = (x >> H) & L;
+    if (!inverse) {
+        hi ^= (hi >> (H - d)) & D;
+        lo ^= (hi << d) & L;
+    } else {
+        lo ^= (hi << d) & L;
+        hi ^= (hi >> (H - d)) & D;
+    }
+    return lo | (hi << H);
+}
+
+// Alg. 1 steps on rows of bits in LDS (nwords words, in place), all threads.
+// A step (S, d): in every S-bit segment with halves lo, hi of H = S/2 bits,
+// hi[0, d) ^= hi[H-d, H) then lo[d, H) ^= hi[0, H-d); the inverse applies the
+// two updates in the reverse order.  Runs of in-word steps (S <= 64) are
+// applied to each word in registers with one barrier.
+__device__ void bc_row_steps(uint64_t *row, int nwords, const BcSteps &st, bool inverse, int tid, int nth)
+{
+    int k = 0;
+    while (k < st.n) {
+        const int idx = inverse ? st.n - 1 - k : k;
+        const int lgS = st.lgS[idx];
+        if (lgS <= 6) {
+            int k_end = k;
+            while (k_end < st.n && st.lgS[inverse ? st.n - 1 - k_end : k_end] <= 6) ++k_end;
+            for (int w = tid; w < nwords; w += nth) {
+                uint64_t x = row[w];
+                for (int kk = k; kk < k_end; ++kk) {
+                    const int j = inverse ? st.n - 1 - kk : kk;
+                    x = bc_word_step(x, 1 << (st.lgS[j] - 1), 1 << st.lgd[j], st.L[j], st.D[j], inverse);
+                }
+                row[w] = x;
+            }
+            __syncthreads();
+            k = k_end;
+            continue;
+        }
+        const int lgd = st.lgd[idx], d = 1 << lgd, H = 1 << (lgS - 1);
+        const int lgSW = lgS - 6, lgHW = lgSW - 1, HW = 1 << lgHW;
+        const int lgdw = lgd > 6 ? lgd - 6 : 0;          // words of hi touched by the first update
+        const int lgseg = 0;
+        (void)lgseg;
+        for (int phase = 0; phase < 2; ++phase) {
+            const bool fix_hi = (phase == 0) != inverse;
+            if (fix_hi) {
+                const int nt = (nwords >> lgSW) << lgdw;
+                for (int t = tid; t < nt; t += nth) {
+                    const int sg = t >> lgdw, kw = t & ((1 << lgdw) - 1);
+                    uint64_t *hp = row + (sg << lgSW) + HW;
+                    hp[kw] ^= bc_bits(hp, HW, 64L * kw + H - d) & bc_lowmask(d - 64 * kw);
+                }
+            } else {
+                const int nt = (nwords >> lgSW) << lgHW;
+                for (int t = tid; t < nt; t += nth) {
+                    const int sg = t >> lgHW, q = t & (HW - 1);
+                    uint64_t *lp = row + (sg << lgSW);
+                    lp[q] ^= bc_bits(lp + HW, HW, 64L * q - d);
+                }
+            }
+            __syncthreads();
+        }
+        ++k;
+    }
+}
+
+// Alg. 1 steps with whole elements (the outer conversion on a column vector of
+// R = 2^lgR elements of type T in LDS), in place.
+template <typename T>
+__device__ void bc_elem_steps(T *v, int lgR, const BcSteps &st, bool inverse, int tid, int nth)
+{
+    for (int k = 0; k < st.n; ++k) {
+        const int idx = inverse ? st.n - 1 - k : k;
+        const int lgS = st.lgS[idx], lgd = st.lgd[idx], lgH = lgS - 1;
+        const int S = 1 << lgS, H = 1 << lgH, d = 1 << lgd;
+        for (int phase = 0; phase < 2; ++phase) {
+            const bool fix_hi = (phase == 0) != inverse;
+            if (fix_hi) {
+                const int nt = 1 << (lgR - lgS + lgd);
+                for (int t = tid; t < nt; t += nth) {
+                    const int sg = t >> lgd, p = t & (d - 1);
+                    T *hp = v + (sg << lgS) + H;
+                    hp[p] ^= hp[p + H - d];
+                }
+            } else {
+                const int nt = 1 << (lgR - 1);           // all lo halves; p < d are left alone
+                for (int t = tid; t < nt; t += nth) {
+                    const int sg = t >> lgH, p = t & (H - 1);
+                    if (p >= d) {
+                        T *lp = v + (sg << lgS);
+                        lp[p] ^= lp[H + p - d];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        (void)S;
+    }
+}
+
+// ------------------------------------------------- zeta over row bits ------
+//
+// Superset sum over row-index bits [b0, b0 + nb) of X (R rows of EW words),
+// tile = 2^nb rows (the other row bits fixed) x W words.  With skew_in set the
+// tile is loaded from the unskewed rows of `in` (len bits, row r shifted left
+// by r bits) instead of from X.
+__global__ __launch_bounds__(BC_THREADS) void k_bc_zeta(uint64_t *__restrict__ X, const uint64_t *__restrict__ in,
+                                                        uint64_t len, int lgR, int EW, int b0, int nb, int lgWc,
+                                                        int skew_in)
+{
+    __shared__ uint64_t s[2048];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int Wc = 1 << lgWc, rows = 1 << nb;
+    const int ncolt = EW >> lgWc;
+    const uint64_t ntiles = (1ull << (lgR - nb)) * (uint64_t)ncolt;
+    const uint64_t inwords = (len + 63) / 64;
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int ct = (int)(tile % ncolt);
+        const uint64_t rt = tile / ncolt;                       // row bits outside [b0, b0+nb)
+        const uint64_t rlow = rt & ((1ull << b0) - 1), rhigh = rt >> b0;
+        const int w0 = ct << lgWc;
+        for (int e = tid; e < rows * Wc; e += nth) {
+            const int k = e >> lgWc, c = e & (Wc - 1);
+            const uint64_t r = (rhigh << (b0 + nb)) | ((uint64_t)k << b0) | rlow;
+            const int w = w0 + c;
+            uint64_t v;
+            if (skew_in) {
+                // stored word w of row r = row bits [64 w - r, 64 w - r + 64) of c_r
+                const long off = 64L * w - (long)r;
+                const uint64_t rb = r * BC_TAU_WORDS;          // first word of row r in `in`
+                long i0 = off >= 0 ? off / 64 : -((-off + 63) / 64);
+                int sh = (int)(off - i0 * 64);
+                uint64_t a = 0, b = 0;
+                if (i0 >= 0 && i0 < BC_TAU_WORDS && rb + i0 < inwords) a = in[rb + i0];
+                if (i0 + 1 >= 0 && i0 + 1 < BC_TAU_WORDS && rb + i0 + 1 < inwords) b = in[rb + i0 + 1];
+                // mask the bits at or above len (last input word)
+                if ((len & 63) && i0 >= 0 && rb + i0 == inwords - 1) a &= (~0ull) >> (64 - (len & 63));
+                if ((len & 63) && i0 + 1 >= 0 && rb + i0 + 1 == inwords - 1) b &= (~0ull) >> (64 - (len & 63));
+                v = sh ? ((a >> sh) | (b << (64 - sh))) : a;
+            } else {
+                v = X[r * EW + w];
+            }
+            s[e] = v;
+        }
+        __syncthreads();
+        for (int t = 0; t < nb; ++t) {
+            for (int e = tid; e < (rows >> 1) * Wc; e += nth) {
+                const int c = e & (Wc - 1), pr = e >> lgWc;
+                const int k0 = ((pr >> t) << (t + 1)) | (pr & ((1 << t) - 1));
+                s[(k0 << lgWc) | c] ^= s[((k0 | (1 << t)) << lgWc) | c];
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < rows * Wc; e += nth) {
+            const int k = e >> lgWc, c = e & (Wc - 1);
+            const uint64_t r = (rhigh << (b0 + nb)) | ((uint64_t)k << b0) | rlow;
+            X[r * EW + w0 + c] = s[e];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------ forward: unskew, carry, inner --------
+//
+// Rows q of X (skewed, superset-summed) -> digits h_q -> inner BasisCvt(2^16)
+// -> Y[col][q] (64-bit columns).  BC_ROWS consecutive rows per iteration so
+// the transposed store writes 64-byte runs.  With R == 1 (a single row, no
+// Taylor step) the row is read from `in` directly.
+#define BC_ROWS 8
+__global__ __launch_bounds__(BC_THREADS) void k_bc_fwd_rows(const uint64_t *__restrict__ X,
+                                                            const uint64_t *__restrict__ in, uint64_t len, int lgR,
+                                                            int EW, uint64_t *__restrict__ Y, BcSteps inner)
+{
+    __shared__ uint64_t rows[BC_ROWS * BC_TAU_WORDS];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
+    const uint64_t inwords = (len + 63) / 64;
+    for (int q0 = blockIdx.x * T; q0 < R; q0 += gridDim.x * T) {
+        for (int e = tid; e < T * BC_TAU_WORDS; e += nth) {
+            const int k = e / BC_TAU_WORDS, w = e % BC_TAU_WORDS, q = q0 + k;
+            uint64_t v;
+            if (R == 1) {
+                v = (uint64_t)w < inwords ? in[w] : 0ull;
+                if ((uint64_t)w == inwords - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+            } else {
+                const uint64_t *pq = X + (uint64_t)q * EW;
+                v = bc_bits(pq, EW, 64L * w + q);                                   // L_q
+                if (64 * w <= R) {                                                 // x U_q: U bit b -> bit b + 1
+                    uint64_t u = bc_bits(pq, EW, 64L * (BC_TAU_WORDS + w) + q - 1);
+                    uint64_t m = ~0ull;
+                    if (w == 0) m &= ~1ull;
+                    if ((long)R + 1 - 64L * w < 64) m &= bc_lowmask(R + 1 - 64 * w);
+                    v ^= u & m;
+                }
+                if (q > 0 && 64 * w < R) {                                         // U_{q-1}
+                    const uint64_t *pp = X + (uint64_t)(q - 1) * EW;
+                    uint64_t u = bc_bits(pp, EW, 64L * (BC_TAU_WORDS + w) + (q - 1));
+                    if (64 * (w + 1) > R) u &= bc_lowmask(R - 64 * w);
+                    v ^= u;
+                }
+            }
+            rows[e] = v;
+        }
+        __syncthreads();
+        bc_row_steps(rows, T * BC_TAU_WORDS, inner, false, tid, nth);
+        for (int e = tid; e < T * BC_TAU_WORDS; e += nth) {
+            const int k = e % T, w = e / T;
+            Y[(uint64_t)w * R + q0 + k] = rows[k * BC_TAU_WORDS + w];
+        }
+        __syncthreads();
+    }
+}
+
+// 64 x 64 bit transpose across a wavefront: lane i holds row i; afterwards
+// lane t holds column t (bit i = bit t of row i)
+__device__ __forceinline__ uint64_t bc_wave_transpose64(uint64_t x, int lane)
+{
+    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        const int j = 32 >> s;
+        const uint64_t m = masks[s];
+        uint32_t lo = __shfl_xor((uint32_t)x, j, 64), hi = __shfl_xor((uint32_t)(x >> 32), j, 64);
+        const uint64_t y = (uint64_t)lo | ((uint64_t)hi << 32);
+        if (lane & j)
+            x = ((y & ~m) >> j) | (x & ~m);
+        else
+            x = (x & m) | ((y & m) << j);
+    }
+    return x;
+}
+
+// Outer BasisCvt(R) on one 64-bit column of Y, then Encode: element
+// i = r0 tau + 64 col + t takes bits j n_p + i, found in rows j (n_p/tau) + r0.
+// One column per workgroup iteration; R <= 2^14 (the column fits LDS).
+__global__ __launch_bounds__(BC_THREADS) void k_bc_outer_encode(const uint64_t *__restrict__ Y, int lgR, int l,
+                                                                uint64_t *__restrict__ vals, BcSteps outer,
+                                                                const DevTables *__restrict__ T)
+{
+    __shared__ uint64_t col[1 << 14];
+    __shared__ uint64_t enc[8][256];
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+    const int R = 1 << lgR;
+    const int rows_per_j = 1 << (l - 16);          // n_p / tau
+    for (int i = tid; i < 8 * 256; i += nth) (&enc[0][0])[i] = (&T->enc_win[0][0])[i];
+    for (int c = blockIdx.x; c < BC_TAU_WORDS; c += gridDim.x) {
+        for (int r = tid; r < R; r += nth) col[r] = Y[(uint64_t)c * R + r];
+        __syncthreads();
+        bc_elem_steps<uint64_t>(col, lgR, outer, false, tid, nth);
+        for (int r0 = wave; r0 < rows_per_j; r0 += nwave) {
+            const int rr = lane * rows_per_j + r0;         // row of Encode input row j = lane
+            uint64_t x = rr < R ? col[rr] : 0ull;
+            x = bc_wave_transpose64(x, lane);
+            uint64_t f = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) f ^= enc[k][(x >> (8 * k)) & 255u];
+            vals[((uint64_t)r0 << 16) + 64u * c + lane] = f;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ inverse ------
+
+// Decode and the inverse outer conversion: for a 32-bit column c (bits
+// [32 c, 32 c + 32) of every row), element i = r0 tau + 32 c + t decodes to 64
+// bits; bit j goes to row j (n_p/tau) + r0.  Then iOuter on the column.
+__global__ __launch_bounds__(BC_THREADS) void k_bc_decode_outer(const uint64_t *__restrict__ vals, int lgR, int l,
+                                                                uint32_t *__restrict__ Y32, BcSteps outer,
+                                                                const DevTables *__restrict__ T)
+{
+    __shared__ uint32_t col[1 << 15];
+    __shared__ uint64_t dec[8][256];
+    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+    const int R = 1 << lgR;
+    const int rows_per_j = 1 << (l - 16);
+    for (int i = tid; i < 8 * 256; i += nth) (&dec[0][0])[i] = (&T->dec_win[0][0])[i];
+    __syncthreads();
+    for (int c = blockIdx.x; c < 2 * BC_TAU_WORDS; c += gridDim.x) {
+        // two r0 per wave pass: lanes 0..31 and 32..63 each decode 32 elements
+        for (int r0b = 2 * wave; r0b < rows_per_j; r0b += 2 * nwave) {
+            const int half = lane >> 5, t = lane & 31, r0 = r0b + half;
+            uint64_t a = 0;
+            if (r0 < rows_per_j) {
+                const uint64_t h = vals[((uint64_t)r0 << 16) + 32u * c + t];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a ^= dec[k][(h >> (8 * k)) & 255u];
+            }
+            // transpose the two 32 x 64 blocks (one per half-wave): afterwards lane
+            // (half, j) holds bits j and j + 32 of the 32 decoded vectors
+            uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
+            const uint32_t masks[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+            for (int s = 0; s < 5; ++s) {
+                const int j = 16 >> s;
+                const uint32_t m = masks[s];
+                uint32_t ylo = __shfl_xor(lo, j, 64), yhi = __shfl_xor(hi, j, 64);
+                if (t & j) {
+                    lo = ((ylo & ~m) >> j) | (lo & ~m);
+                    hi = ((yhi & ~m) >> j) | (hi & ~m);
+                } else {
+                    lo = (lo & m) | ((ylo & m) << j);
+                    hi = (hi & m) | ((yhi & m) << j);
+                }
+            }
+            if (r0 < rows_per_j) {
+                // lane t now holds bit t of vector s at bit s: that is row j = t (lo) and j = t + 32 (hi)
+                const int rlo = t * rows_per_j + r0, rhi = (t + 32) * rows_per_j + r0;
+                if (rlo < R) col[rlo] = lo;
+                if (rhi < R) col[rhi] = hi;
+            }
+        }
+        __syncthreads();
+        bc_elem_steps<uint32_t>(col, lgR, outer, true, tid, nth);
+        for (int r = tid; r < R; r += nth) Y32[(uint64_t)c * R + r] = col[r];
+        __syncthreads();
+    }
+}
+
+// Inverse inner conversion of rows (read from the 32-bit columns of Y32,
+// BC_ROWS per iteration), then skew: X row q = h_q << q (EW words).
+__global__ __launch_bounds__(BC_THREADS) void k_bc_inv_rows(const uint32_t *__restrict__ Y32, int lgR, int EW,
+                                                            uint64_t *__restrict__ X, BcSteps inner)
+{
+    __shared__ uint64_t rows[BC_ROWS * BC_TAU_WORDS];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
+    for (int q0 = blockIdx.x * T; q0 < R; q0 += gridDim.x * T) {
+        for (int e = tid; e < T * 2 * BC_TAU_WORDS; e += nth) {
+            const int k = e % T, c = e / T;                 // 32-bit column c of row q0 + k
+            reinterpret_cast<uint32_t *>(rows)[k * 2 * BC_TAU_WORDS + c] = Y32[(uint64_t)c * R + q0 + k];
+        }
+        __syncthreads();
+        bc_row_steps(rows, T * BC_TAU_WORDS, inner, true, tid, nth);
+        for (int e = tid; e < T * EW; e += nth) {
+            const int k = e / EW, w = e % EW, q = q0 + k;
+            X[(uint64_t)q * EW + w] = bc_bits(rows + k * BC_TAU_WORDS, BC_TAU_WORDS, 64L * w - q);
+        }
+        __syncthreads();
+    }
+}
+
+// Last inverse pass: unskew (c'_r = Z_r >> r), carry (c_r = lo_r + hi_{r-1})
+// and the masked store of the first len bits.  One row per iteration.
+__global__ __launch_bounds__(BC_THREADS) void k_bc_inv_store(const uint64_t *__restrict__ X, int lgR, int EW,
+                                                             uint64_t len, uint64_t *__restrict__ out)
+{
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int R = 1 << lgR;
+    const uint64_t outw = (len + 63) / 64;
+    for (int r = blockIdx.x; r < R; r += gridDim.x) {
+        const uint64_t *xr = X + (uint64_t)r * EW;
+        const uint64_t *xp = r ? X + (uint64_t)(r - 1) * EW : nullptr;
+        for (int w = tid; w < BC_TAU_WORDS; w += nth) {
+            const uint64_t ow = (uint64_t)r * BC_TAU_WORDS + w;
+            if (ow >= outw) continue;
+            uint64_t v = bc_bits(xr, EW, 64L * w + r);
+            if (xp && 64 * w < R) {
+                uint64_t h = bc_bits(xp, EW, 64L * (BC_TAU_WORDS + w) + (r - 1));
+                if (64 * (w + 1) > R) h &= bc_lowmask(R - 64 * w);
+                v ^= h;
+            }
+            if (ow == outw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+            out[ow] = v;
+        }
+    }
+}

@@ -1,0 +1,235 @@
+// k_butterfly.h -- Butterfly (Alg. 2) and its inverse as LDS-resident passes.
+//
+// The n_p = 2^l values of one transform are processed in passes over groups
+// of layers.  Layer i pairs indices j and j + 2^i inside blocks of 2^(i+1); the
+// block b = j >> (i+1) fixes the multiplier s_i(v_{l+32} + b 2^(i+1)) whose
+// Cantor vector is 2^(32+d) XOR 2b, d = l - i.
+//
+//  * bottom pass: layers R-1 .. 0 on contiguous tiles of 2^R values.  For a
+//    product it runs the forward layers of A and B, the pointwise products and
+//    the inverse layers of C on the same tile (Alg. 5 lines 3, 6, 7, 8 for the
+//    low layers), so those steps cost one HBM round trip.
+//  * upper pass: k <= 7 consecutive layers i_lo .. i_hi on tiles of 2^k rows
+//    (the index bits i_lo .. i_hi) by W contiguous columns (low index bits).
+//
+// Each multiplication is x * (K + beta) = tmul(T_K, x) ^ bmul(beta, x) with K
+// shared by 128 consecutive blocks (window table built in LDS) and beta in V_8
+// (gf_device.h).  In an upper pass with k <= 7 one K serves a whole layer of
+// the tile; in the bottom pass the low layers need up to 2^(R-8) of them.
+#pragma once
+
+#include "gf_device.h"
+
+#define BF_THREADS 512        // bottom pass
+#define BF_UP_THREADS 256     // upper pass (two workgroups per CU)
+#define BF_SLOTS 4            // K tables resident in LDS at once (16 KiB each)
+#define BF_BOTTOM_R 11        // log2 of the bottom tile
+#define BF_UPPER_MAXK 7       // layers per upper pass
+#define BF_UPPER_LGW 3        // log2 of the columns of an upper tile
+
+enum { BF_FWD = 0, BF_INV = 1, BF_PRODUCT = 2, BF_FWD2 = 3 };
+
+// LDS layout shared by both kernels (bytes)
+#define BF_OFF_MUL8 0
+#define BF_OFF_TAB (32 * 1024)
+#define BF_OFF_BASIS (BF_OFF_TAB + BF_SLOTS * 2048 * 8)
+#define BF_OFF_DATA (BF_OFF_BASIS + BF_SLOTS * 64 * 8)
+
+__device__ __forceinline__ void bf_load_mul8_even(uint8_t *s_mul8e, const DevTables *__restrict__ T, int tid, int nth)
+{
+    // row a = 2r of the GF(2^8) table -> s_mul8e[r * 256 ..]
+    const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_mul8e);
+    for (int idx = tid; idx < 128 * 16; idx += nth) {
+        int r = idx >> 4, c = idx & 15;
+        dst[idx] = src[(2 * r) * 16 + c];
+    }
+}
+
+// build the K tables for `cnt` consecutive values bh0 .. bh0+cnt-1 at depth d
+__device__ __forceinline__ void bf_build(uint64_t *s_tab, uint64_t *s_basis, int d, uint32_t bh0, int cnt,
+                                         const DevTables *__restrict__ T, int tid, int nth)
+{
+    int slot = tid >> 6;
+    if (slot < cnt) ktable_basis(s_basis + slot * 64, d, bh0 + slot, T, tid & 63);
+    __syncthreads();
+    for (int item = tid; item < 256 * cnt; item += nth)
+        ktable_fill_item(s_tab + (item >> 8) * 2048, s_basis + (item >> 8) * 64, item & 255);
+    __syncthreads();
+}
+
+__device__ __forceinline__ void bf_fwd_pair(uint64_t *X, uint32_t p0, uint32_t p1, const uint64_t *tab,
+                                            const uint8_t *row)
+{
+    uint64_t x0 = X[p0], x1 = X[p1];
+    uint64_t h0 = x0 ^ tmul(tab, x1) ^ bmul(row, x1);
+    X[p0] = h0;
+    X[p1] = h0 ^ x1;
+}
+
+__device__ __forceinline__ void bf_inv_pair(uint64_t *X, uint32_t p0, uint32_t p1, const uint64_t *tab,
+                                            const uint8_t *row)
+{
+    uint64_t h0 = X[p0], h1 = X[p1];
+    uint64_t q1 = h0 ^ h1;
+    X[p0] = h0 ^ tmul(tab, q1) ^ bmul(row, q1);
+    X[p1] = q1;
+}
+
+// one layer i of the bottom tile (tile index H, 2^R values), on X (and Y if set)
+__device__ void bf_bottom_layer(int i, bool inverse, uint64_t *X, uint64_t *Y, int l, int R, uint64_t H,
+                                uint8_t *s_mul8e, uint64_t *s_tab, uint64_t *s_basis,
+                                const DevTables *__restrict__ T, int tid, int nth)
+{
+    const int d = l - i;
+    const int lgb = R - 1 - i;                      // log2 of the blocks in the tile
+    const int lgpg = lgb < 7 ? lgb : 7;             // log2 of the blocks per K
+    const int ngroups = 1 << (lgb - lgpg);
+    const uint64_t bfirst = H << lgb;               // global block index of the first block
+    const uint32_t bh_first = (uint32_t)(bfirst >> 7);
+    const int per_group = 1 << (lgpg + i);          // butterflies per K group
+    for (int g0 = 0; g0 < ngroups; g0 += BF_SLOTS) {
+        const int cnt = ngroups - g0 < BF_SLOTS ? ngroups - g0 : BF_SLOTS;
+        bf_build(s_tab, s_basis, d, bh_first + g0, cnt, T, tid, nth);
+        const int total = cnt * per_group;
+        for (int q = tid; q < total; q += nth) {
+            const uint32_t qq = (uint32_t)(q + g0 * per_group);
+            const uint32_t tb = qq >> i, off = qq & ((1u << i) - 1u);
+            const uint32_t p0 = (tb << (i + 1)) | off, p1 = p0 | (1u << i);
+            const int slot = (int)(tb >> lgpg) - g0;
+            const uint32_t bl = (uint32_t)((bfirst + tb) & 127u);
+            const uint64_t *tab = s_tab + slot * 2048;
+            const uint8_t *row = s_mul8e + bl * 256;
+            if (!inverse) {
+                bf_fwd_pair(X, p0, p1, tab, row);
+                if (Y) bf_fwd_pair(Y, p0, p1, tab, row);
+            } else {
+                bf_inv_pair(X, p0, p1, tab, row);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Bottom pass.  grid = 2^(l-R) tiles.  MODE: BF_FWD / BF_INV on A, or
+// BF_PRODUCT: forward A and B, pointwise A*B, inverse; result written to A.
+template <int MODE>
+__global__ __launch_bounds__(BF_THREADS) void k_bfly_bottom(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
+                                                            int l, int R, const DevTables *__restrict__ T)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint8_t *s_mul8e = smem + BF_OFF_MUL8;
+    uint64_t *s_tab = reinterpret_cast<uint64_t *>(smem + BF_OFF_TAB);
+    uint64_t *s_basis = reinterpret_cast<uint64_t *>(smem + BF_OFF_BASIS);
+    uint64_t *s_A = reinterpret_cast<uint64_t *>(smem + BF_OFF_DATA);
+    uint64_t *s_B = s_A + (1u << R);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const uint64_t TT = 1ull << R, ntiles = 1ull << (l - R);
+
+    bf_load_mul8_even(s_mul8e, T, tid, nth);
+    for (uint64_t H = blockIdx.x; H < ntiles; H += gridDim.x) {
+        const uint64_t base = H << R;
+        for (uint32_t e = tid; e < TT; e += nth) {
+            s_A[e] = A[base + e];
+            if (MODE == BF_PRODUCT) s_B[e] = B[base + e];
+        }
+        __syncthreads();
+
+        if (MODE != BF_INV)
+            for (int i = R - 1; i >= 0; --i)
+                bf_bottom_layer(i, false, s_A, MODE == BF_PRODUCT ? s_B : nullptr, l, R, H, s_mul8e, s_tab, s_basis,
+                                T, tid, nth);
+
+        if (MODE == BF_PRODUCT) {
+            // the odd rows of the GF(2^8) table and the v_15 / v_31 tables go to the slot area
+            uint8_t *s_odd = reinterpret_cast<uint8_t *>(s_tab);
+            uint16_t *s_c15 = reinterpret_cast<uint16_t *>(s_odd + 32768);
+            uint32_t *s_c31 = reinterpret_cast<uint32_t *>(s_odd + 32768 + 1024);
+            const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
+            uint4 *dst = reinterpret_cast<uint4 *>(s_odd);
+            for (int idx = tid; idx < 128 * 16; idx += nth) dst[idx] = src[(2 * (idx >> 4) + 1) * 16 + (idx & 15)];
+            for (int idx = tid; idx < 512; idx += nth) s_c15[idx] = (&T->c15[0][0])[idx];
+            for (int idx = tid; idx < 1024; idx += nth) s_c31[idx] = (&T->c31[0][0])[idx];
+            __syncthreads();
+            Mul8View mv{s_mul8e, s_odd, s_c15, s_c31};
+            for (uint32_t e = tid; e < TT; e += nth) s_A[e] = mv.m64(s_A[e], s_B[e]);
+            __syncthreads();
+        }
+
+        if (MODE != BF_FWD)
+            for (int i = 0; i < R; ++i)
+                bf_bottom_layer(i, true, s_A, nullptr, l, R, H, s_mul8e, s_tab, s_basis, T, tid, nth);
+
+        for (uint32_t e = tid; e < TT; e += nth) A[base + e] = s_A[e];
+        __syncthreads();
+    }
+}
+
+// Upper pass: layers i_lo .. i_lo+k-1 (k <= 7), tiles of 2^k rows x 2^lgW columns
+// (lgW <= BF_UPPER_LGW), persistent over the tiles.
+// MODE: BF_FWD (A), BF_FWD2 (A and B, same multipliers), BF_INV (A).
+template <int MODE>
+__global__ __launch_bounds__(BF_UP_THREADS) void k_bfly_upper(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
+                                                              int l, int i_lo, int k, int lgW,
+                                                              const DevTables *__restrict__ T)
+{
+    __shared__ uint64_t s_tab[2048];                                 // the K table of the current layer
+    __shared__ __align__(16) uint8_t s_mul8e[128 * 256];             // even rows of the GF(2^8) table
+    __shared__ uint64_t s_basis[64];
+    __shared__ uint64_t s_A[1 << (BF_UPPER_MAXK + BF_UPPER_LGW)];
+    __shared__ uint64_t s_B[MODE == BF_FWD2 ? (1 << (BF_UPPER_MAXK + BF_UPPER_LGW)) : 1];
+    const int rows = 1 << k, W = 1 << lgW, nel = rows << lgW;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int i_hi = i_lo + k - 1;
+    const int lgchunks = i_lo - lgW;
+    const uint64_t ntiles = 1ull << (l - k - lgW);
+
+    bf_load_mul8_even(s_mul8e, T, tid, nth);
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t H = tile >> lgchunks, c0 = (tile & ((1ull << lgchunks) - 1)) << lgW;
+        const uint64_t gbase = (H << (i_hi + 1)) | c0;
+        for (int e = tid; e < nel; e += nth) {
+            const uint64_t j = gbase | ((uint64_t)(e >> lgW) << i_lo) | (uint64_t)(e & (W - 1));
+            s_A[e] = A[j];
+            if (MODE == BF_FWD2) s_B[e] = B[j];
+        }
+        for (int step = 0; step < k; ++step) {
+            const int i = (MODE == BF_INV) ? i_lo + step : i_hi - step;
+            const int s = i - i_lo;                        // row bit of this layer
+            const int d = l - i;
+            const uint64_t bfirst = H << (i_hi - i);       // global block of row pair 0
+            // (the barrier inside bf_build also orders the tile load / previous layer)
+            __syncthreads();
+            bf_build(s_tab, s_basis, d, (uint32_t)(bfirst >> 7), 1, T, tid, nth);
+            const int total = (rows >> 1) << lgW;
+            for (int q = tid; q < total; q += nth) {
+                const int c = q & (W - 1), pr = q >> lgW;
+                const int t0 = ((pr >> s) << (s + 1)) | (pr & ((1 << s) - 1));
+                const int t1 = t0 | (1 << s);
+                const uint32_t bl = (uint32_t)((bfirst + (uint64_t)(t0 >> (s + 1))) & 127u);
+                const uint8_t *row = s_mul8e + bl * 256;
+                const uint32_t p0 = (uint32_t)((t0 << lgW) | c), p1 = (uint32_t)((t1 << lgW) | c);
+                if (MODE == BF_INV) {
+                    bf_inv_pair(s_A, p0, p1, s_tab, row);
+                } else {
+                    bf_fwd_pair(s_A, p0, p1, s_tab, row);
+                    if (MODE == BF_FWD2) bf_fwd_pair(s_B, p0, p1, s_tab, row);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < nel; e += nth) {
+            const uint64_t j = gbase | ((uint64_t)(e >> lgW) << i_lo) | (uint64_t)(e & (W - 1));
+            A[j] = s_A[e];
+            if (MODE == BF_FWD2) B[j] = s_B[e];
+        }
+        __syncthreads();
+    }
+}
+
+static inline size_t bf_bottom_lds(int R, bool product)
+{
+    return BF_OFF_DATA + ((size_t)1 << R) * 8 * (product ? 2 : 1);
+}
+
+

@@ -200,3 +200,32 @@ def test_model_exhaustive_small():
     for a in range(0, 1 << 6):
         for b in range(0, 1 << 6, 3):
             assert MM.fp_polymul(a, 6, b, 6) == O.py_clmul(a, b)
+
+
+def test_tower_basis_is_a_basis_and_multiplicative():
+    # the 64 tower units are independent, and multiplying by an element of V_8
+    # acts on each byte alone (V_8 = GF(2^8) is a subfield, Sec. 2.2.1)
+    tb = F.tower_basis()
+    basis = {}
+    for t, x in enumerate(tb):
+        for b in sorted(basis, reverse=True):
+            if (x >> b) & 1:
+                x ^= basis[b]
+        assert x
+        basis[x.bit_length() - 1] = x
+    beta = F.iota(0b10110110)
+    for k in range(8):
+        for u in range(8):
+            prod = F.mul(tb[8 * k + u], beta)
+            # the product must lie in the span of the units of byte k
+            span = {}
+            for w in range(8):
+                y = tb[8 * k + w]
+                for b in sorted(span, reverse=True):
+                    if (y >> b) & 1:
+                        y ^= span[b]
+                span[y.bit_length() - 1] = y
+            for b in sorted(span, reverse=True):
+                if (prod >> b) & 1:
+                    prod ^= span[b]
+            assert prod == 0
