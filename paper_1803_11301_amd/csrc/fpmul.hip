@@ -613,9 +613,9 @@ static int run_encode_fast(polymul_ctx *ctx, const uint64_t *a, uint64_t len, in
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
     const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / BC_ROWS,
                                                                               (uint64_t)ctx->num_cu * 2));
-    KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_THREADS, X, a, len, lgR, EW, Y, inner);
+    KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_ROW_THREADS, X, a, len, lgR, EW, Y, inner);
     KLAUNCH(ctx, s, "basiscvt_outer_encode", k_bc_outer_encode, (unsigned)std::min(BC_TAU_WORDS, ctx->num_cu),
-            BC_THREADS, Y, lgR, l, vals, outer, ctx->tables);
+            BC_COL_THREADS, Y, lgR, l, vals, outer, ctx->tables);
     return 0;
 }
 
@@ -625,10 +625,10 @@ static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, ui
 {
     const int l = log2n - 6, lgR = log2n - 16, EW = bc_ew(lgR);
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
-    KLAUNCH(ctx, s, "decode_outer", k_bc_decode_outer, (unsigned)std::min(2 * BC_TAU_WORDS, ctx->num_cu), BC_THREADS,
+    KLAUNCH(ctx, s, "decode_outer", k_bc_decode_outer, (unsigned)std::min(2 * BC_TAU_WORDS, ctx->num_cu), BC_COL_THREADS,
             vals, lgR, l, reinterpret_cast<uint32_t *>(Y), outer, ctx->tables);
     const unsigned grows = (unsigned)std::min<uint64_t>((1ull << lgR) / BC_ROWS, (uint64_t)ctx->num_cu * 2);
-    KLAUNCH(ctx, s, "ibasiscvt_rows", k_bc_inv_rows, grows, BC_THREADS, reinterpret_cast<const uint32_t *>(Y), lgR,
+    KLAUNCH(ctx, s, "ibasiscvt_rows", k_bc_inv_rows, grows, BC_ROW_THREADS, reinterpret_cast<const uint32_t *>(Y), lgR,
             EW, X, inner);
     int rc = run_zeta(ctx, s, X, nullptr, 0, lgR, EW, false);
     if (rc) return rc;

@@ -31,7 +31,9 @@
 #include "gf_device.h"
 
 #define BC_TAU_WORDS 1024            // tau = 2^16 bits
-#define BC_THREADS 256
+#define BC_THREADS 256                // zeta tiles
+#define BC_ROW_THREADS 512            // row kernels (two workgroups per CU)
+#define BC_COL_THREADS 1024           // column kernels (one workgroup per CU)
 #define BC_MAX_STEPS 96
 
 struct BcSteps {
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_zeta(uint64_t *__restrict__ X
 // the transposed store writes 64-byte runs.  With R == 1 (a single row, no
 // Taylor step) the row is read from `in` directly.
 #define BC_ROWS 8
-__global__ __launch_bounds__(BC_THREADS) void k_bc_fwd_rows(const uint64_t *__restrict__ X,
+__global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *__restrict__ X,
                                                             const uint64_t *__restrict__ in, uint64_t len, int lgR,
                                                             int EW, uint64_t *__restrict__ Y, BcSteps inner)
 {
@@ -296,7 +298,7 @@ __device__ __forceinline__ uint64_t bc_wave_transpose64(uint64_t x, int lane)
 // Outer BasisCvt(R) on one 64-bit column of Y, then Encode: element
 // i = r0 tau + 64 col + t takes bits j n_p + i, found in rows j (n_p/tau) + r0.
 // One column per workgroup iteration; R <= 2^14 (the column fits LDS).
-__global__ __launch_bounds__(BC_THREADS) void k_bc_outer_encode(const uint64_t *__restrict__ Y, int lgR, int l,
+__global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64_t *__restrict__ Y, int lgR, int l,
                                                                 uint64_t *__restrict__ vals, BcSteps outer,
                                                                 const DevTables *__restrict__ T)
 {
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_outer_encode(const uint64_t *
 // Decode and the inverse outer conversion: for a 32-bit column c (bits
 // [32 c, 32 c + 32) of every row), element i = r0 tau + 32 c + t decodes to 64
 // bits; bit j goes to row j (n_p/tau) + r0.  Then iOuter on the column.
-__global__ __launch_bounds__(BC_THREADS) void k_bc_decode_outer(const uint64_t *__restrict__ vals, int lgR, int l,
+__global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64_t *__restrict__ vals, int lgR, int l,
                                                                 uint32_t *__restrict__ Y32, BcSteps outer,
                                                                 const DevTables *__restrict__ T)
 {
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_decode_outer(const uint64_t *
 
 // Inverse inner conversion of rows (read from the 32-bit columns of Y32,
 // BC_ROWS per iteration), then skew: X row q = h_q << q (EW words).
-__global__ __launch_bounds__(BC_THREADS) void k_bc_inv_rows(const uint32_t *__restrict__ Y32, int lgR, int EW,
+__global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *__restrict__ Y32, int lgR, int EW,
                                                             uint64_t *__restrict__ X, BcSteps inner)
 {
     __shared__ uint64_t rows[BC_ROWS * BC_TAU_WORDS];

@@ -20,8 +20,8 @@
 
 #include "gf_device.h"
 
-#define BF_THREADS 512        // bottom pass
-#define BF_UP_THREADS 256     // upper pass (two workgroups per CU)
+#define BF_THREADS 1024       // bottom pass (one workgroup per CU)
+#define BF_UP_THREADS 512     // upper pass (two workgroups per CU)
 #define BF_SLOTS 4            // K tables resident in LDS at once (16 KiB each)
 #define BF_BOTTOM_R 11        // log2 of the bottom tile
 #define BF_UPPER_MAXK 7       // layers per upper pass
@@ -52,6 +52,7 @@ __device__ __forceinline__ void bf_build(uint64_t *s_tab, uint64_t *s_basis, int
 {
     int slot = tid >> 6;
     if (slot < cnt) ktable_basis(s_basis + slot * 64, d, bh0 + slot, T, tid & 63);
+    // (tid >> 6 < cnt <= BF_SLOTS needs at least 64 * BF_SLOTS threads)
     __syncthreads();
     for (int item = tid; item < 256 * cnt; item += nth)
         ktable_fill_item(s_tab + (item >> 8) * 2048, s_basis + (item >> 8) * 64, item & 255);
