@@ -53,6 +53,36 @@ KERNEL_BYTES = {
 }
 
 
+# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE
+# passes, each scaled by what the counter reads for a plain 1 GiB device copy:
+# fetch x2.000, write x1.000), valid only for the kernel sources they were
+# taken on: the sha256 of the listed files must match, else traffic is null.
+MEASURED_TRAFFIC = {
+    "butterfly_bottom_product": {
+        "bytes": (262568 * 2 + 262144) * 1024,
+        "sources": ("paper_1803_11301_amd/csrc/k_butterfly.h", "paper_1803_11301_amd/csrc/gf_device.h",
+                    "paper_1803_11301_amd/csrc/fpmul.hip"),
+        "sha256": "2cbb0404ed505a0023a64ae4f537858ed0668488376bad61e99e2615440598c0",
+    },
+}
+
+
+def sources_sha256(paths) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec is None or sources_sha256(rec["sources"]) != rec["sha256"]:
+        return None
+    return rec["bytes"]
+
+
 def nominal_bytes(A: int, B: int, N: int) -> int:
     """Nominal algorithmic bytes of one product: each stage of Alg. 5 streams its
     input and output once (BasisCvt 2A+2B, Encode A+B+2N, Butterfly 4N,
@@ -92,6 +122,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--cpu-log2", type=int, default=27, help="operand size of the oracle sample")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1 "
@@ -101,6 +133,16 @@ def main():
     import numpy as np
     import torch
     from paper_1803_11301_amd import fpmul, synth
+
+    if args.copy_calibrate:
+        nbytes = args.copy_calibrate << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 3}), flush=True)
+        return
 
     L, seed, top, desc = WORKLOADS[args.workload]
     a_np, b_np = synth.single_pair(seed, L, top_bit=top)
@@ -155,7 +197,7 @@ def main():
         avg_s = tot / cnt / 1e3
         achieved = bytes_per_launch / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None, "bytes_per_launch": int(bytes_per_launch),
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom), "bytes_per_launch": int(bytes_per_launch),
                 "avg_launch_us": round(avg_s * 1e6, 3)}
     product_gbs = nominal / (ms / 1e3) / 1e9
     log(f"[bench] {ms:.3f} ms/product; nominal {nominal / 1e9:.3f} GB -> {product_gbs:.1f} GB/s "

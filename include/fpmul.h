@@ -85,7 +85,7 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a,
  * polymul_addfft -- the modified additive FFT of Sec. 3.4: BasisCvt (Alg. 1),
  * Encode (Alg. 4) and Butterfly (Alg. 2) at alpha = v_{l+32}.  Evaluates A
  * (len_a bits, len_a <= 2^log2n) at the n/64 points of the Frobenius
- * partition Sigma = v_{l+32} + V_l, l = log2n - 6 (Eq. 5, Eq. 8).
+ * partition Sigma = v_{l+32} + V_l, l = log2n - 6 (Eq. 6, Eq. 8).
  * values: device, 2^(log2n-6) words; word j is A(v_{l+32} + j) with j read
  * as Cantor coordinates, each value a GF(2^64) element written in the
  * polynomial basis modulo x^64 + x^4 + x^3 + x + 1 (Sec. 4.3).

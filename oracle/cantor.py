@@ -17,7 +17,7 @@ must equal by definition, so that HIP stages can be checked one by one:
   Bernstein-Chou form the paper describes in Sec. 2.3.1) -- the plain
   definition of the BasisCvt output;
 * the evaluation points of the Frobenius partition Sigma = v_{l+m/2} + V_l
-  (Eq. 5): point j is the element with Cantor vector 2^(l+32) XOR j, so that
+  (Eq. 6): point j is the element with Cantor vector 2^(l+32) XOR j, so that
   the transform output j is A(point j) (Eq. 8 together with Alg. 2's output
   order).
 """

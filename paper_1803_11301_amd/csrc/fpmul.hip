@@ -2,7 +2,7 @@
 // of bit polynomials with Frobenius partitions in the additive FFT.
 //
 // Pipeline of one product (Alg. 5, FP_Polymul), n = transform length in bits,
-// l = log2(n) - 6, n_p = 2^l points of Sigma = v_{l+32} + V_l (Eq. 5):
+// l = log2(n) - 6, n_p = 2^l points of Sigma = v_{l+32} + V_l (Eq. 6):
 //   BasisCvt(A), Encode, Butterfly      (Alg. 1, Alg. 4, Alg. 2 at v_{l+32})
 //   BasisCvt(B), Encode, Butterfly
 //   pointwise products in GF(2^64)      (Alg. 5 line 7)
@@ -589,7 +589,10 @@ static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t
     for (int pass = 0; pass < 2; ++pass) {
         const int b0 = pass ? nb1 : 0, nb = pass ? nb2 : nb1;
         if (nb <= 0) continue;
-        const int lgWc = std::min(6, 11 - nb);
+        // 2^nb rows x 2^lgWc words fill the tile; with nb <= 8 a row segment is
+        // at least 16 words (128 bytes, one full line)
+        const int lgWc = std::min(6, 12 - nb);
+        if ((1 << (nb + lgWc)) > BC_ZETA_LDS) return fail(POLYMUL_EINVAL, "zeta tile exceeds LDS");
         const uint64_t tiles = (1ull << (lgR - nb)) * (uint64_t)(EW >> lgWc);
         const unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->num_cu * 8);
         KLAUNCH(ctx, s, skew_first ? "basiscvt_zeta" : "ibasiscvt_zeta", k_bc_zeta, grid, BC_THREADS, X, in, len,

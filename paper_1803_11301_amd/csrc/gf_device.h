@@ -53,16 +53,18 @@ __device__ __forceinline__ uint64_t bmul(const uint8_t *__restrict__ row, uint64
 
 // ----------------------------------------------------------------- gmul ----
 
-// LDS view of the full GF(2^8) table: row a at (a & 1) * 32768 + (a >> 1) * 256
+// LDS view of the full GF(2^8) table and the reduction tables, all at fixed
+// offsets from one base: row a of the GF(2^8) table at
+// (a & 1) * 32768 + (a >> 1) * 256 (even rows first, then odd rows), the
+// v_15 table (u16[2][256]) at 65536 and the v_31 table (u32[4][256]) at 66560.
+#define M8V_OFF_C15 65536
+#define M8V_OFF_C31 (65536 + 1024)
+#define M8V_BYTES (65536 + 1024 + 4096)
 struct Mul8View {
-    const uint8_t *even;   // rows 0, 2, 4, ...
-    const uint8_t *odd;    // rows 1, 3, 5, ...
-    const uint16_t *c15;   // [2][256]
-    const uint32_t *c31;   // [4][256]
+    const uint8_t *base;
     __device__ __forceinline__ uint32_t m8(uint32_t a, uint32_t b) const
     {
-        const uint8_t *base = (a & 1u) ? odd : even;
-        return base[((a >> 1) << 8) | b];
+        return base[((a & 1u) << 15) | ((a >> 1) << 8) | b];
     }
     __device__ __forceinline__ uint32_t m16(uint32_t a, uint32_t b) const
     {
@@ -71,7 +73,11 @@ struct Mul8View {
         uint32_t hi = p1 ^ p0, lo = p0 ^ m8(0x80u, p2);    // v_7 = Cantor byte 0x80
         return lo | (hi << 8);
     }
-    __device__ __forceinline__ uint32_t mv15(uint32_t x) const { return c15[x & 255u] ^ c15[256 + (x >> 8)]; }
+    __device__ __forceinline__ uint32_t mv15(uint32_t x) const
+    {
+        const uint16_t *c15 = reinterpret_cast<const uint16_t *>(base + M8V_OFF_C15);
+        return c15[x & 255u] ^ c15[256 + (x >> 8)];
+    }
     __device__ __forceinline__ uint32_t m32(uint32_t a, uint32_t b) const
     {
         uint32_t a0 = a & 0xFFFFu, a1 = a >> 16, b0 = b & 0xFFFFu, b1 = b >> 16;
@@ -81,6 +87,7 @@ struct Mul8View {
     }
     __device__ __forceinline__ uint32_t mv31(uint32_t x) const
     {
+        const uint32_t *c31 = reinterpret_cast<const uint32_t *>(base + M8V_OFF_C31);
         return c31[x & 255u] ^ c31[256 + ((x >> 8) & 255u)] ^ c31[512 + ((x >> 16) & 255u)] ^ c31[768 + (x >> 24)];
     }
     __device__ __forceinline__ uint64_t m64(uint64_t a, uint64_t b) const

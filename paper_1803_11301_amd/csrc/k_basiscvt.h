@@ -31,7 +31,8 @@
 #include "gf_device.h"
 
 #define BC_TAU_WORDS 1024            // tau = 2^16 bits
-#define BC_THREADS 256                // zeta tiles
+#define BC_THREADS 256                // zeta tiles, final store
+#define BC_ZETA_LDS 4096              // words of a zeta tile (2^nb rows x 2^lgWc words)
 #define BC_ROW_THREADS 512            // row kernels (two workgroups per CU)
 #define BC_COL_THREADS 1024           // column kernels (one workgroup per CU)
 #define BC_MAX_STEPS 96
@@ -172,7 +173,7 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_zeta(uint64_t *__restrict__ X
                                                         uint64_t len, int lgR, int EW, int b0, int nb, int lgWc,
                                                         int skew_in)
 {
-    __shared__ uint64_t s[2048];
+    __shared__ uint64_t s[BC_ZETA_LDS];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int Wc = 1 << lgWc, rows = 1 << nb;
     const int ncolt = EW >> lgWc;

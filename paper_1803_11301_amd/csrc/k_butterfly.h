@@ -142,17 +142,20 @@ __global__ __launch_bounds__(BF_THREADS) void k_bfly_bottom(uint64_t *__restrict
                                 T, tid, nth);
 
         if (MODE == BF_PRODUCT) {
-            // the odd rows of the GF(2^8) table and the v_15 / v_31 tables go to the slot area
-            uint8_t *s_odd = reinterpret_cast<uint8_t *>(s_tab);
-            uint16_t *s_c15 = reinterpret_cast<uint16_t *>(s_odd + 32768);
-            uint32_t *s_c31 = reinterpret_cast<uint32_t *>(s_odd + 32768 + 1024);
+            // the odd rows of the GF(2^8) table and the v_15 / v_31 tables go to the
+            // slot area, which follows the even rows (the Mul8View layout)
+            static_assert(BF_OFF_TAB == BF_OFF_MUL8 + 32768, "odd rows must follow the even rows");
+            static_assert(BF_OFF_DATA - BF_OFF_MUL8 >= M8V_BYTES, "slot area too small for the product tables");
+            uint8_t *s_odd = smem + BF_OFF_TAB;
+            uint16_t *s_c15 = reinterpret_cast<uint16_t *>(smem + BF_OFF_MUL8 + M8V_OFF_C15);
+            uint32_t *s_c31 = reinterpret_cast<uint32_t *>(smem + BF_OFF_MUL8 + M8V_OFF_C31);
             const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
             uint4 *dst = reinterpret_cast<uint4 *>(s_odd);
             for (int idx = tid; idx < 128 * 16; idx += nth) dst[idx] = src[(2 * (idx >> 4) + 1) * 16 + (idx & 15)];
             for (int idx = tid; idx < 512; idx += nth) s_c15[idx] = (&T->c15[0][0])[idx];
             for (int idx = tid; idx < 1024; idx += nth) s_c31[idx] = (&T->c31[0][0])[idx];
             __syncthreads();
-            Mul8View mv{s_mul8e, s_odd, s_c15, s_c31};
+            const Mul8View mv{smem + BF_OFF_MUL8};
             for (uint32_t e = tid; e < TT; e += nth) s_A[e] = mv.m64(s_A[e], s_B[e]);
             __syncthreads();
         }

@@ -1,7 +1,7 @@
 """Pins for the Cantor-basis field facts and for the step-by-step model of Alg. 5.
 
 The facts checked are the ones the paper states (Sec. 2.2-3): the basis
-recursion, nested subfields, the order of squaring on basis elements (Eq. 6),
+recursion, nested subfields, the order of squaring on basis elements (Eq. 5),
 s_i(v_j) = v_{j-i} (Eq. 4), two-term subspace polynomials for power-of-two i,
 Prop. 1 (Sigma is a Frobenius partition, |Omega| = n) and Prop. 2 (E_Sigma is
 a bijection).  The model of the method must reproduce the plain product and
@@ -59,7 +59,7 @@ def test_nested_subfields(k):
 
 
 def test_order_of_squaring_on_basis():
-    # Ord_phi(v_i) = 2 * 2^floor(log2 i) for i > 0 (Eq. 6)
+    # Ord_phi(v_i) = 2 * 2^floor(log2 i) for i > 0 (Eq. 5)
     v = F.cantor_basis()
     for i in list(range(1, 20)) + [31, 32, 33, 47, 63]:
         x, j = v[i], 0
