@@ -114,6 +114,60 @@ def cpu_baseline(log2_len: int, target_log2: int):
                       f"Karatsuba oracle), x3^{target_log2 - log2_len} for 2^{target_log2}-bit operands"}
 
 
+def bench_batch(ctx, steps: int):
+    """The 4096-product mix (operands log-uniform in [2^10, 2^20] bits, 10%
+    sparse, seed 0x5EED4096): products/s of one polymul_batch launch against
+    one polymul_ex call per product, on the same resident operands."""
+    import numpy as np
+    import torch
+    from paper_1803_11301_amd import fpmul, synth
+    plan = synth.batch_plan()
+    As, Bs = zip(*[synth.batch_operands(it) for it in plan])
+    las = np.array([it.len_a for it in plan], dtype=np.uint64)
+    lbs = np.array([it.len_b for it in plan], dtype=np.uint64)
+    a_pool, a_off = fpmul.pack_words(As)
+    b_pool, b_off = fpmul.pack_words(Bs)
+    out_off, out_words = fpmul.out_layout(las.astype(np.int64), lbs.astype(np.int64))
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x).view(np.int64)).cuda()
+    ta, tb, tla, tlb, taoff, tboff, toff = d(a_pool), d(b_pool), d(las), d(lbs), d(a_off), d(b_off), d(out_off)
+    out = torch.empty(out_words, dtype=torch.int64, device="cuda")
+    status = torch.empty(len(plan), dtype=torch.int32, device="cuda")
+    max_bits = int((las + lbs - 1).max())
+    stream = torch.cuda.current_stream()
+    run = lambda: ctx.polymul_batch(ta, taoff, tla, tb, tboff, tlb, out, toff, max_bits, status, stream)
+    run()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        run()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = t0.elapsed_time(t1) / steps
+    ok = bool((status == 0).all().item())
+    # one stream-ordered call per product on the same operands (views of the pools)
+    views = [(ta[int(a_off[k]):], int(las[k]), tb[int(b_off[k]):], int(lbs[k]), out[int(out_off[k]):])
+             for k in range(len(plan))]
+    for v in views[:64]:
+        ctx.polymul(v[0], v[1], v[2], v[3], out=v[4], stream=stream)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for v in views:
+        ctx.polymul(v[0], v[1], v[2], v[3], out=v[4], stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_calls = t0.elapsed_time(t1)
+    n = len(plan)
+    rec = {"workload": "4096 products, operands log-uniform 2^10..2^20 bits, 10% sparse (density 0.01), "
+                       "seed 0x5eed4096", "products": n, "ms_per_batch": round(ms_batch, 4),
+           "products_per_s": round(n / (ms_batch / 1e3), 1), "per_call_ms": round(ms_calls, 3),
+           "per_call_products_per_s": round(n / (ms_calls / 1e3), 1),
+           "speedup_vs_per_call": round(ms_calls / ms_batch, 2), "all_status_ok": ok, "steps": steps}
+    log(f"[bench] batch: {ms_batch:.3f} ms per 4096 products ({rec['products_per_s']:.0f}/s); "
+        f"per-call {ms_calls:.1f} ms ({rec['per_call_products_per_s']:.0f}/s)")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +176,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--cpu-log2", type=int, default=27, help="operand size of the oracle sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -203,6 +259,10 @@ def main():
     log(f"[bench] {ms:.3f} ms/product; nominal {nominal / 1e9:.3f} GB -> {product_gbs:.1f} GB/s "
         f"({100 * product_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
 
+    batch = None
+    if not args.no_batch and args.workload == "large":
+        batch = bench_batch(ctx, args.batch_steps)
+
     cpu = None
     if not args.no_cpu:
         log(f"[bench] oracle sample 2^{args.cpu_log2} on the host")
@@ -222,6 +282,7 @@ def main():
         "product_roofline": {"nominal_bytes": nominal, "achieved": round(product_gbs, 2), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(product_gbs / HBM_PEAK_GBS, 5)},
         "kernels": per_kernel,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -81,6 +81,42 @@ int polymul_ctx_destroy(polymul_ctx *ctx);
 int polymul_ex(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a,
                const uint64_t *b_bits, uint64_t len_b, uint64_t *out, void *stream);
 
+/* Largest product length, in bits, of one item of polymul_batch. */
+#define POLYMUL_BATCH_MAX_PRODUCT_BITS (1ull << 22)
+
+/*
+ * polymul_batch -- count independent products C_k = A_k * B_k (Alg. 5 each)
+ * in one stream-ordered launch on `stream`.  Every workgroup takes whole
+ * products from a queue ordered by size (largest first) and chooses the
+ * transform depth of each product on the device from its two lengths.
+ *
+ * All arrays are DEVICE memory owned by the caller:
+ *   a_pool, b_pool: operand words; item k's A starts at word a_word_off[k] of
+ *                   a_pool and has len_a[k] bits (same layout as polymul),
+ *                   likewise B in b_pool.
+ *   out_pool:       item k's product is written at word out_word_off[k]:
+ *                   ceil((len_a[k] + len_b[k] - 1) / 64) words, tail bits of
+ *                   the last word zeroed; nothing is written for an empty
+ *                   operand.  Output ranges must not overlap each other or
+ *                   the operands.
+ *   len_a, len_b, a_word_off, b_word_off, out_word_off: count entries each.
+ *   status:         optional (may be NULL), count int32: 0 when item k was
+ *                   computed (or empty), POLYMUL_EINVAL when its product is
+ *                   longer than max_product_bits (its output is untouched).
+ * max_product_bits: an upper bound on len_a[k] + len_b[k] - 1, at most
+ *                   POLYMUL_BATCH_MAX_PRODUCT_BITS; it sizes the per-workgroup
+ *                   workspace (4 buffers of 2^ceil(log2 max_product_bits) bits
+ *                   per resident workgroup).
+ * The offsets are trusted: the library checks that every array is device
+ * memory but not that the ranges fit their pools.  Returns 0 once the work
+ * is enqueued, POLYMUL_EINVAL for a bad argument, POLYMUL_ENOMEM when the
+ * workspace would exceed the context's cap.
+ */
+int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, const uint64_t *a_word_off,
+                  const uint64_t *len_a, const uint64_t *b_pool, const uint64_t *b_word_off, const uint64_t *len_b,
+                  uint64_t *out_pool, const uint64_t *out_word_off, uint64_t max_product_bits, int32_t *status,
+                  void *stream);
+
 /*
  * polymul_addfft -- the modified additive FFT of Sec. 3.4: BasisCvt (Alg. 1),
  * Encode (Alg. 4) and Butterfly (Alg. 2) at alpha = v_{l+32}.  Evaluates A
@@ -96,7 +132,7 @@ int polymul_addfft(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a, int
 
 /*
  * polymul_iaddfft -- inverse of polymul_addfft for the same log2n:
- * iButterfly, Decode and iBasisCvt (Alg. 5 lines 8-10).  Reads 2^(log2n-6)
+ * iButterfly, Decode and iBasisCvt (the inverse steps of Alg. 5).  Reads 2^(log2n-6)
  * values, writes the first out_bits bits (<= 2^log2n) of the polynomial of
  * degree < 2^log2n they determine (Prop. 2), zeroing the rest of the last
  * word.  values is not modified.

@@ -134,7 +134,7 @@ def decode(h: list, n: int) -> int:
 
 
 def forward(a: int, n: int) -> list:
-    """BasisCvt, Encode, Butterfly at alpha = v_{l+m/2} (Alg. 5 lines 1-3)."""
+    """BasisCvt, Encode, Butterfly at alpha = v_{l+m/2} (Alg. 5, the forward steps)."""
     l, n_p = params(n)
     g = F.to_novelpoly(a, n)
     f = encode(g, n)
@@ -142,7 +142,7 @@ def forward(a: int, n: int) -> list:
 
 
 def inverse(vals: list, n: int) -> int:
-    """iButterfly, Decode, iBasisCvt (Alg. 5 lines 8-10)."""
+    """iButterfly, Decode, iBasisCvt (Alg. 5, the inverse steps)."""
     l, n_p = params(n)
     h = ibutterfly(vals, 1 << (l + M // 2))
     return F.from_novelpoly(decode(h, n))

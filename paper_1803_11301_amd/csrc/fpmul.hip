@@ -5,8 +5,8 @@
 // l = log2(n) - 6, n_p = 2^l points of Sigma = v_{l+32} + V_l (Eq. 6):
 //   BasisCvt(A), Encode, Butterfly      (Alg. 1, Alg. 4, Alg. 2 at v_{l+32})
 //   BasisCvt(B), Encode, Butterfly
-//   pointwise products in GF(2^64)      (Alg. 5 line 7)
-//   iButterfly, Decode, iBasisCvt       (Alg. 5 lines 8-10)
+//   pointwise products in GF(2^64)      (Alg. 5, the pointwise step)
+//   iButterfly, Decode, iBasisCvt       (Alg. 5, the inverse steps)
 //
 // Field elements are uint64_t in the tower representation over V_8 (see
 // consts_host.h and gf_device.h).  Layer i of block b multiplies by
@@ -60,6 +60,8 @@ static int fail(int code, const std::string &msg)
 #include "gf_device.h"
 #include "k_butterfly.h"
 #include "k_basiscvt.h"
+#include "k_steps.h"
+#include "k_batch.h"
 
 // ---------------------------------------------------------------------------
 // elementary kernels
@@ -122,60 +124,13 @@ static void bcvt_steps(uint64_t N, uint64_t e, std::vector<BStep> &out)
     bcvt_steps(tau, e, out);             // inner conversion of each block
 }
 
-__device__ __forceinline__ uint64_t lowmask(int64_t x)
-{
-    return x >= 64 ? ~0ull : (x <= 0 ? 0ull : ((1ull << x) - 1ull));
-}
-
-__device__ __forceinline__ int64_t floordiv64(int64_t x) { return x >= 0 ? x / 64 : -((-x + 63) / 64); }
-
-// 64 bits of the half-array hp (HW words) from bit offset off; bits outside read 0
-__device__ __forceinline__ uint64_t bits_at(const uint64_t *hp, int64_t HW, int64_t off)
-{
-    int64_t i0 = floordiv64(off);
-    int s = (int)(off - i0 * 64);
-    uint64_t w0 = (i0 >= 0 && i0 < HW) ? hp[i0] : 0ull;
-    uint64_t w1 = (i0 + 1 >= 0 && i0 + 1 < HW) ? hp[i0 + 1] : 0ull;
-    return s ? ((w0 >> s) | (w1 << (64 - s))) : w0;
-}
-
-// word k of hi' = hi with hi[0, d) ^= hi[H-d, H)
-__device__ __forceinline__ uint64_t hi_prime(const uint64_t *hp, int64_t HW, int64_t H, int64_t d, int64_t k)
-{
-    uint64_t w = hp[k];
-    int64_t rem = d - 64 * k;
-    if (rem > 0) w ^= bits_at(hp, HW, 64 * k + H - d) & lowmask(rem);
-    return w;
-}
-
-__device__ __forceinline__ uint64_t bits_at_prime(const uint64_t *hp, int64_t HW, int64_t H, int64_t d, int64_t off)
-{
-    int64_t i0 = floordiv64(off);
-    int s = (int)(off - i0 * 64);
-    uint64_t w0 = (i0 >= 0 && i0 < HW) ? hi_prime(hp, HW, H, d, i0) : 0ull;
-    uint64_t w1 = (i0 + 1 >= 0 && i0 + 1 < HW) ? hi_prime(hp, HW, H, d, i0 + 1) : 0ull;
-    return s ? ((w0 >> s) | (w1 << (64 - s))) : w0;
-}
-
 // one step on words [0, nw); segments of S >= 128 bits; out-of-place
 __global__ void k_bcvt_step_wide(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t nw,
                                  uint64_t S, uint64_t d, int inverse)
 {
     uint64_t w = gid();
     if (w >= nw) return;
-    const int64_t SW = (int64_t)(S / 64), HW = SW / 2, H = (int64_t)(S / 2);
-    const int64_t q = (int64_t)(w % (uint64_t)SW);
-    const uint64_t *seg = in + (w - (uint64_t)q);
-    const uint64_t *hp = seg + HW;
-    uint64_t r;
-    if (q >= HW) {
-        r = hi_prime(hp, HW, H, (int64_t)d, q - HW);
-    } else if (!inverse) {
-        r = seg[q] ^ bits_at_prime(hp, HW, H, (int64_t)d, 64 * q - (int64_t)d);
-    } else {
-        r = seg[q] ^ bits_at(hp, HW, 64 * q - (int64_t)d);
-    }
-    out[w] = r;
+    out[w] = bcvt_wide_word(in, w, S, d, inverse);
 }
 
 // one step with S <= 64 inside each word (L: low-half mask, D: low-d mask per segment)
@@ -184,16 +139,7 @@ __global__ void k_bcvt_step_word(const uint64_t *__restrict__ in, uint64_t *__re
 {
     uint64_t w = gid();
     if (w >= nw) return;
-    uint64_t x = in[w];
-    uint64_t lo = x & L, hi = (x >> H) & L;
-    if (!inverse) {
-        hi ^= (hi >> (H - d)) & D;
-        lo ^= (hi << d) & L;
-    } else {
-        lo ^= (hi << d) & L;
-        hi ^= (hi >> (H - d)) & D;
-    }
-    out[w] = lo | (hi << H);
+    out[w] = bcvt_in_word(in[w], H, d, L, D, inverse);
 }
 
 // ---------------------------------------------------------------------------
@@ -260,6 +206,11 @@ struct polymul_ctx {
     uint64_t ws_words = 0;   // words per workspace buffer
     DevTables *tables = nullptr;
     int num_cu = 256;
+    // batch: per-size BasisCvt steps, and one allocation holding the
+    // per-workgroup slabs, the queue order and the queue counter
+    BatchSteps *bsteps = nullptr;
+    void *bws = nullptr;
+    size_t bws_bytes = 0;
     // per-kernel timing with HIP events on the launch stream (off by default)
     bool prof = false;
     std::vector<ProfRec> prof_live;       // recorded, not yet read
@@ -453,6 +404,9 @@ static int set_lds_limits()
     HIP_TRY(hipFuncSetAttribute((const void *)k_bfly_bottom<BF_INV>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
     HIP_TRY(hipFuncSetAttribute((const void *)k_bfly_bottom<BF_PRODUCT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 big));
+    // k_batch also has static LDS, so its dynamic limit is exactly what it uses
+    HIP_TRY(hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)bf_bottom_lds(BF_BOTTOM_R, true)));
     done = 1;
     return 0;
 }
@@ -725,6 +679,87 @@ static int basiscvt_body(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int
     return 0;
 }
 
+// ---------------------------------------------------------------------------
+// batch
+// ---------------------------------------------------------------------------
+
+static int batch_steps_upload(polymul_ctx *ctx)
+{
+    if (ctx->bsteps) return 0;
+    std::unique_ptr<BatchSteps> H(new BatchSteps());
+    std::memset(H.get(), 0, sizeof(BatchSteps));
+    int pos = 0;
+    for (int k = BT_MIN_LOG2N; k <= BT_MAX_LOG2N; ++k) {
+        std::vector<BStep> v;
+        bcvt_steps(1ull << k, 1, v);
+        if (pos + (int)v.size() > BT_MAX_STEPS) return fail(POLYMUL_EIO, "batch step table too small");
+        H->first[k] = pos;
+        H->count[k] = (int)v.size();
+        for (const BStep &st : v) {
+            BatchStep &o = H->st[pos++];
+            o.S = st.S;
+            o.d = st.d;
+            o.L = o.D = 0;
+            if (st.S < 128) {
+                const int Hh = (int)(st.S / 2), d = (int)st.d;
+                for (int b = 0; b < 64; ++b) {
+                    const int r = b % (int)st.S;
+                    if (r < Hh) o.L |= 1ull << b;
+                    if (r < d) o.D |= 1ull << b;
+                }
+            }
+        }
+    }
+    HIP_TRY(hipMalloc(&ctx->bsteps, sizeof(BatchSteps)));
+    hipError_t e = hipMemcpy(ctx->bsteps, H.get(), sizeof(BatchSteps), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->bsteps);
+        ctx->bsteps = nullptr;
+        return fail(POLYMUL_EIO, std::string("upload batch steps: ") + hipGetErrorString(e));
+    }
+    return 0;
+}
+
+static int batch_body(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, const uint64_t *a_off,
+                      const uint64_t *len_a, const uint64_t *b_pool, const uint64_t *b_off, const uint64_t *len_b,
+                      uint64_t *out_pool, const uint64_t *out_off, uint64_t max_bits, int32_t *status,
+                      hipStream_t s)
+{
+    int rc;
+    if ((rc = batch_steps_upload(ctx)) || (rc = set_lds_limits())) return rc;
+    const int maxlog = std::max(BT_MIN_LOG2N, ilog2(max_bits));
+    const uint64_t slab_words = 1ull << (maxlog - 6);
+    const unsigned grid = (unsigned)std::min<uint64_t>(count, (uint64_t)ctx->num_cu);
+    const size_t slab_bytes = (size_t)grid * 4 * slab_words * 8;
+    const size_t order_bytes = ((size_t)count * 4 + 255) / 256 * 256;
+    const size_t need = slab_bytes + order_bytes + 256;
+    if (need > ctx->bws_bytes) {
+        if (ctx->cap && need > ctx->cap)
+            return fail(POLYMUL_ENOMEM, "batch workspace of " + std::to_string(need) + " bytes exceeds the cap of " +
+                                            std::to_string(ctx->cap));
+        if (ctx->bws) {
+            HIP_TRY(hipStreamSynchronize(s));
+            (void)hipFree(ctx->bws);
+            ctx->bws = nullptr;
+            ctx->bws_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&ctx->bws, need);
+        if (e != hipSuccess) {
+            ctx->bws = nullptr;
+            return fail(POLYMUL_ENOMEM, std::string("hipMalloc batch workspace: ") + hipGetErrorString(e));
+        }
+        ctx->bws_bytes = need;
+    }
+    uint64_t *slab = static_cast<uint64_t *>(ctx->bws);
+    uint32_t *order = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + slab_bytes);
+    uint32_t *counter = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + slab_bytes + order_bytes);
+    KLAUNCH(ctx, s, "batch_plan", k_batch_plan, 1, 1024, count, len_a, len_b, max_bits, order, counter);
+    KLAUNCH_LDS(ctx, s, "batch", k_batch, grid, BT_THREADS, bf_bottom_lds(BF_BOTTOM_R, true), a_pool, a_off, len_a,
+                b_pool, b_off, len_b, out_pool, out_off, status, count, max_bits, order, counter, slab, slab_words,
+                ctx->tables, ctx->bsteps);
+    return 0;
+}
+
 static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
 {
     const fpmul_host::Tower &tw = H.tw;
@@ -805,6 +840,8 @@ int polymul_ctx_destroy(polymul_ctx *ctx)
     for (int k = 0; k < 4; ++k)
         if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
     if (ctx->tables) (void)hipFree(ctx->tables);
+    if (ctx->bsteps) (void)hipFree(ctx->bsteps);
+    if (ctx->bws) (void)hipFree(ctx->bws);
     for (ProfRec &r : ctx->prof_live) {
         if (r.start) (void)hipEventDestroy(r.start);
         if (r.stop) (void)hipEventDestroy(r.stop);
@@ -833,6 +870,28 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
         ranges_overlap(out, ob, b, (size_t)((len_b + 63) / 64) * 8))
         return fail(POLYMUL_EINVAL, "out overlaps an input");
     return product_body(ctx, a, len_a, b, len_b, out, (hipStream_t)stream);
+}
+
+int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, const uint64_t *a_word_off,
+                  const uint64_t *len_a, const uint64_t *b_pool, const uint64_t *b_word_off, const uint64_t *len_b,
+                  uint64_t *out_pool, const uint64_t *out_word_off, uint64_t max_product_bits, int32_t *status,
+                  void *stream)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (count == 0) return 0;
+    if (max_product_bits == 0 || max_product_bits > POLYMUL_BATCH_MAX_PRODUCT_BITS)
+        return fail(POLYMUL_EINVAL, "max_product_bits must be in [1, 2^22]");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(g.err);
+    int rc;
+    if ((rc = check_dev_ptr(a_pool, "a_pool")) || (rc = check_dev_ptr(a_word_off, "a_word_off")) ||
+        (rc = check_dev_ptr(len_a, "len_a")) || (rc = check_dev_ptr(b_pool, "b_pool")) ||
+        (rc = check_dev_ptr(b_word_off, "b_word_off")) || (rc = check_dev_ptr(len_b, "len_b")) ||
+        (rc = check_dev_ptr(out_pool, "out_pool")) || (rc = check_dev_ptr(out_word_off, "out_word_off")))
+        return rc;
+    if (status && (rc = check_dev_ptr(status, "status"))) return rc;
+    return batch_body(ctx, count, a_pool, a_word_off, len_a, b_pool, b_word_off, len_b, out_pool, out_word_off,
+                      max_product_bits, status, (hipStream_t)stream);
 }
 
 int polymul_addfft(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int log2n, uint64_t *values, void *stream)

@@ -1,0 +1,285 @@
+// k_batch.h -- many independent products (Alg. 5 each) in one persistent launch.
+//
+// Each workgroup takes whole products from a size-sorted queue and runs
+// every step of FP_Polymul for that product on its own slab of device
+// memory: BasisCvt (Alg. 1) of both operands as Taylor steps, Encode (Alg. 4,
+// Eq. 9) through 64 x 64 wave transposes, the butterfly layers above the
+// bottom tile streamed through the slab (Alg. 2), the bottom tiles with the
+// pointwise products fused (the bottom pass of k_butterfly.h), the inverse
+// layers, Decode and the inverse BasisCvt.  The transform depth l of every
+// product is computed on the device from its two lengths.
+#pragma once
+
+#include "gf_device.h"
+#include "k_basiscvt.h"
+#include "k_butterfly.h"
+#include "k_steps.h"
+
+#define BT_THREADS 1024
+#define BT_MAX_LOG2N 22      // largest transform of a batch item: 2^22 bits (products below 2^22 bits)
+#define BT_MIN_LOG2N 6
+#define BT_MAX_STEPS 1024    // BasisCvt steps of all sizes 2^6 .. 2^22 together
+#define BT_NBINS (BT_MAX_LOG2N - BT_MIN_LOG2N + 2)
+
+// layers above the bottom tile must share one K table (block index < 128)
+static_assert(BT_MAX_LOG2N - 6 - BF_BOTTOM_R <= 7, "upper batch layers need one K table per layer");
+
+// Taylor steps of BasisCvt(2^k) for k in [6, 22]: entries first[k] .. first[k] + count[k] - 1
+struct BatchStep {
+    uint64_t S, d;   // segment length and shift in bits
+    uint64_t L, D;   // for S <= 64: low-half and low-d masks of every segment in a word
+};
+struct BatchSteps {
+    int first[BT_MAX_LOG2N + 1];
+    int count[BT_MAX_LOG2N + 1];
+    BatchStep st[BT_MAX_STEPS];
+};
+
+__device__ __forceinline__ int bt_ceil_log2(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll(x - 1); }
+
+// transform log2 of a product, or -1 if it has no bits, or BT_MAX_LOG2N + 1
+// if it is longer than max_bits
+__device__ __forceinline__ int bt_log2n(uint64_t la, uint64_t lb, uint64_t max_bits)
+{
+    if (la == 0 || lb == 0) return -1;
+    if (la > max_bits || lb > max_bits || la + lb - 1 > max_bits) return BT_MAX_LOG2N + 1;
+    const int k = bt_ceil_log2(la + lb - 1);
+    return k < BT_MIN_LOG2N ? BT_MIN_LOG2N : k;
+}
+
+// queue order: larger transforms first, empty and rejected items last; also
+// resets the queue counter.  One workgroup.
+__global__ __launch_bounds__(1024) void k_batch_plan(uint32_t count, const uint64_t *__restrict__ len_a,
+                                                     const uint64_t *__restrict__ len_b, uint64_t max_bits,
+                                                     uint32_t *__restrict__ order, uint32_t *__restrict__ counter)
+{
+    __shared__ uint32_t hist[BT_NBINS];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int k = tid; k < BT_NBINS; k += nth) hist[k] = 0;
+    __syncthreads();
+    for (uint32_t q = tid; q < count; q += nth) {
+        const int lg = bt_log2n(len_a[q], len_b[q], max_bits);
+        const int key = (lg < 0 || lg > BT_MAX_LOG2N) ? BT_NBINS - 1 : BT_MAX_LOG2N - lg;
+        atomicAdd(&hist[key], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < BT_NBINS; ++k) {
+            const uint32_t c = hist[k];
+            hist[k] = run;
+            run += c;
+        }
+        counter[0] = 0;
+    }
+    __syncthreads();
+    for (uint32_t q = tid; q < count; q += nth) {
+        const int lg = bt_log2n(len_a[q], len_b[q], max_bits);
+        const int key = (lg < 0 || lg > BT_MAX_LOG2N) ? BT_NBINS - 1 : BT_MAX_LOG2N - lg;
+        order[atomicAdd(&hist[key], 1u)] = q;
+    }
+}
+
+// dst[0, nw) = src bits [0, len), zero-padded
+__device__ __forceinline__ void bt_load(const uint64_t *__restrict__ src, uint64_t len, uint64_t *__restrict__ dst,
+                                        uint64_t nw, int tid, int nth)
+{
+    const uint64_t inw = (len + 63) / 64;
+    for (uint64_t w = tid; w < nw; w += nth) {
+        uint64_t v = 0;
+        if (w < inw) {
+            v = src[w];
+            if (w == inw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+        }
+        dst[w] = v;
+    }
+}
+
+// BasisCvt(2^lgN) (or its inverse) on words [0, 2^lgN / 64) of X, ping-pong
+// with Y; returns the buffer that holds the result
+__device__ uint64_t *bt_basiscvt(uint64_t *X, uint64_t *Y, int lgN, bool inverse, const BatchSteps *__restrict__ BS,
+                                 int tid, int nth)
+{
+    const uint64_t nw = (1ull << lgN) / 64;
+    const int first = BS->first[lgN], cnt = BS->count[lgN];
+    for (int k = 0; k < cnt; ++k) {
+        const BatchStep st = BS->st[first + (inverse ? cnt - 1 - k : k)];
+        if (st.S >= 128) {
+            for (uint64_t w = tid; w < nw; w += nth) Y[w] = bcvt_wide_word(X, w, st.S, st.d, inverse ? 1 : 0);
+        } else {
+            const int H = (int)(st.S / 2), d = (int)st.d;
+            for (uint64_t w = tid; w < nw; w += nth) Y[w] = bcvt_in_word(X[w], H, d, st.L, st.D, inverse ? 1 : 0);
+        }
+        __syncthreads();
+        uint64_t *t = X;
+        X = Y;
+        Y = t;
+    }
+    return X;
+}
+
+// Encode (Alg. 4): vals[i] = sum_j bit (j n_p + i) of `bits` times r_j, n_p = 2^l
+__device__ void bt_encode(const uint64_t *__restrict__ bits, int l, uint64_t *__restrict__ vals,
+                          const DevTables *__restrict__ T, int tid, int nth)
+{
+    const uint64_t n_p = 1ull << l;
+    if (l >= 6) {
+        const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+        const uint64_t groups = n_p >> 6;
+        for (uint64_t g = wave; g < groups; g += nwave) {
+            // lane j: bits j n_p + 64 g .. + 63, one word; after the transpose lane t
+            // holds the column of element 64 g + t
+            uint64_t x = bits[((uint64_t)lane << (l - 6)) + g];
+            x = bc_wave_transpose64(x, lane);
+            uint64_t f = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(x >> (8 * k)) & 255u];
+            vals[64 * g + lane] = f;
+        }
+    } else {
+        for (uint64_t i = tid; i < n_p; i += nth) {
+            uint64_t col = 0;
+            for (int j = 0; j < 64; ++j) {
+                const uint64_t p = ((uint64_t)j << l) + i;
+                col |= ((bits[p >> 6] >> (p & 63)) & 1ull) << j;
+            }
+            uint64_t f = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(col >> (8 * k)) & 255u];
+            vals[i] = f;
+        }
+    }
+}
+
+// Decode: bit j of R^-1 vals[i] goes to bit j n_p + i of `bits` (n_p words);
+// tmp (n_p words) is scratch for l < 6
+__device__ void bt_decode(const uint64_t *__restrict__ vals, int l, uint64_t *__restrict__ bits,
+                          uint64_t *__restrict__ tmp, const DevTables *__restrict__ T, int tid, int nth)
+{
+    const uint64_t n_p = 1ull << l;
+    if (l >= 6) {
+        const int lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+        const uint64_t groups = n_p >> 6;
+        for (uint64_t g = wave; g < groups; g += nwave) {
+            const uint64_t h = vals[64 * g + lane];
+            uint64_t a = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a ^= T->dec_win[k][(h >> (8 * k)) & 255u];
+            // lane j then holds bit j of the 64 vectors: bits j n_p + 64 g .. + 63
+            a = bc_wave_transpose64(a, lane);
+            bits[((uint64_t)lane << (l - 6)) + g] = a;
+        }
+    } else {
+        for (uint64_t i = tid; i < n_p; i += nth) {
+            const uint64_t h = vals[i];
+            uint64_t a = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a ^= T->dec_win[k][(h >> (8 * k)) & 255u];
+            tmp[i] = a;
+        }
+        __syncthreads();
+        const uint64_t mask = n_p - 1;
+        for (uint64_t W = tid; W < n_p; W += nth) {
+            uint64_t r = 0;
+            for (int t = 0; t < 64; ++t) {
+                const uint64_t p = 64 * W + t;
+                r |= ((tmp[p & mask] >> (p >> l)) & 1ull) << t;
+            }
+            bits[W] = r;
+        }
+    }
+}
+
+// one butterfly layer i >= the bottom tile, streamed through X (and Y, with
+// the same multipliers, for the forward pair); every block index is below
+// 128, so one K table serves the layer
+__device__ void bt_upper_layer(uint64_t *__restrict__ X, uint64_t *__restrict__ Y, int l, int i, bool inverse,
+                               uint8_t *smem, const DevTables *__restrict__ T, int tid, int nth)
+{
+    const uint8_t *s_mul8e = smem + BF_OFF_MUL8;
+    uint64_t *s_tab = reinterpret_cast<uint64_t *>(smem + BF_OFF_TAB);
+    uint64_t *s_basis = reinterpret_cast<uint64_t *>(smem + BF_OFF_BASIS);
+    bf_build(s_tab, s_basis, l - i, 0u, 1, T, tid, nth);
+    const uint32_t half = 1u << (l - 1);
+    for (uint32_t q = tid; q < half; q += nth) {
+        const uint32_t tb = q >> i, off = q & ((1u << i) - 1u);
+        const uint32_t p0 = (tb << (i + 1)) | off, p1 = p0 | (1u << i);
+        const uint8_t *row = s_mul8e + (tb & 127u) * 256;
+        if (inverse) {
+            bf_inv_pair(X, p0, p1, s_tab, row);
+        } else {
+            bf_fwd_pair(X, p0, p1, s_tab, row);
+            if (Y) bf_fwd_pair(Y, p0, p1, s_tab, row);
+        }
+    }
+    __syncthreads();
+}
+
+// grid: persistent workgroups; slab: 4 buffers of slab_words per workgroup
+__global__ __launch_bounds__(BT_THREADS) void k_batch(
+    const uint64_t *__restrict__ a_pool, const uint64_t *__restrict__ a_off, const uint64_t *__restrict__ len_a,
+    const uint64_t *__restrict__ b_pool, const uint64_t *__restrict__ b_off, const uint64_t *__restrict__ len_b,
+    uint64_t *__restrict__ out_pool, const uint64_t *__restrict__ out_off, int32_t *__restrict__ status,
+    uint32_t count, uint64_t max_bits, const uint32_t *__restrict__ order, uint32_t *__restrict__ counter,
+    uint64_t *__restrict__ slab, uint64_t slab_words, const DevTables *__restrict__ T,
+    const BatchSteps *__restrict__ BS)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_next;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    uint64_t *TA = slab + (uint64_t)blockIdx.x * 4 * slab_words;
+    uint64_t *TB = TA + slab_words, *X = TB + slab_words, *Y = X + slab_words;
+    bf_load_mul8_even(smem + BF_OFF_MUL8, T, tid, nth);
+
+    for (;;) {
+        if (tid == 0) s_next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t qpos = s_next;
+        __syncthreads();
+        if (qpos >= count) break;
+        const uint32_t q = order[qpos];
+        const uint64_t la = len_a[q], lb = len_b[q];
+        const int log2n = bt_log2n(la, lb, max_bits);
+        if (log2n < 0 || log2n > BT_MAX_LOG2N || (1ull << (log2n - 6)) > slab_words) {
+            if (tid == 0 && status) status[q] = log2n < 0 ? 0 : -22;
+            continue;
+        }
+        const int l = log2n - 6;
+        const uint64_t n_p = 1ull << l, lc = la + lb - 1;
+
+        // BasisCvt and Encode of both operands: A -> TA, B -> TB
+        for (int side = 0; side < 2; ++side) {
+            const uint64_t len = side ? lb : la;
+            const uint64_t *src = side ? b_pool + b_off[q] : a_pool + a_off[q];
+            int lgN = bt_ceil_log2(len);
+            if (lgN < BT_MIN_LOG2N) lgN = BT_MIN_LOG2N;
+            bt_load(src, len, X, n_p, tid, nth);
+            __syncthreads();
+            uint64_t *cur = bt_basiscvt(X, Y, lgN, false, BS, tid, nth);
+            for (uint64_t w = (1ull << lgN) / 64 + tid; w < n_p; w += nth) cur[w] = 0;
+            __syncthreads();
+            bt_encode(cur, l, side ? TB : TA, T, tid, nth);
+            __syncthreads();
+        }
+
+        // Butterfly of A and B, pointwise, iButterfly: result in TA
+        const int R = l < BF_BOTTOM_R ? l : BF_BOTTOM_R;
+        for (int i = l - 1; i >= R; --i) bt_upper_layer(TA, TB, l, i, false, smem, T, tid, nth);
+        for (uint64_t H = 0; H < (1ull << (l - R)); ++H) bf_bottom_tile<BF_PRODUCT>(TA, TB, l, R, H, smem, T, tid, nth);
+        for (int i = R; i < l; ++i) bt_upper_layer(TA, nullptr, l, i, true, smem, T, tid, nth);
+
+        // Decode and iBasisCvt(2^log2n), then the first lc bits to out
+        bt_decode(TA, l, X, TB, T, tid, nth);
+        __syncthreads();
+        const uint64_t *res = bt_basiscvt(X, Y, log2n, true, BS, tid, nth);
+        uint64_t *out = out_pool + out_off[q];
+        const uint64_t ow = (lc + 63) / 64;
+        for (uint64_t w = tid; w < ow; w += nth) {
+            uint64_t v = res[w];
+            if (w == ow - 1 && (lc & 63)) v &= (~0ull) >> (64 - (lc & 63));
+            out[w] = v;
+        }
+        if (tid == 0 && status) status[q] = 0;
+        __syncthreads();
+    }
+}

@@ -7,8 +7,9 @@
 //
 //  * bottom pass: layers R-1 .. 0 on contiguous tiles of 2^R values.  For a
 //    product it runs the forward layers of A and B, the pointwise products and
-//    the inverse layers of C on the same tile (Alg. 5 lines 3, 6, 7, 8 for the
-//    low layers), so those steps cost one HBM round trip.
+//    the inverse layers of C on the same tile (the low layers of the forward
+//    transforms, the pointwise step and the low layers of the inverse
+//    transform of Alg. 5), so those steps cost one HBM round trip.
 //  * upper pass: k <= 7 consecutive layers i_lo .. i_hi on tiles of 2^k rows
 //    (the index bits i_lo .. i_hi) by W contiguous columns (low index bits).
 //
@@ -112,61 +113,68 @@ __device__ void bf_bottom_layer(int i, bool inverse, uint64_t *X, uint64_t *Y, i
     }
 }
 
-// Bottom pass.  grid = 2^(l-R) tiles.  MODE: BF_FWD / BF_INV on A, or
+// One bottom tile H (2^R values at H * 2^R) on the LDS layout above, the even
+// rows of the GF(2^8) table already in place.  MODE: BF_FWD / BF_INV on A, or
 // BF_PRODUCT: forward A and B, pointwise A*B, inverse; result written to A.
 template <int MODE>
-__global__ __launch_bounds__(BF_THREADS) void k_bfly_bottom(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
-                                                            int l, int R, const DevTables *__restrict__ T)
+__device__ void bf_bottom_tile(uint64_t *__restrict__ A, const uint64_t *__restrict__ B, int l, int R, uint64_t H,
+                               uint8_t *smem, const DevTables *__restrict__ T, int tid, int nth)
 {
-    extern __shared__ __align__(16) uint8_t smem[];
     uint8_t *s_mul8e = smem + BF_OFF_MUL8;
     uint64_t *s_tab = reinterpret_cast<uint64_t *>(smem + BF_OFF_TAB);
     uint64_t *s_basis = reinterpret_cast<uint64_t *>(smem + BF_OFF_BASIS);
     uint64_t *s_A = reinterpret_cast<uint64_t *>(smem + BF_OFF_DATA);
     uint64_t *s_B = s_A + (1u << R);
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const uint64_t TT = 1ull << R, ntiles = 1ull << (l - R);
+    const uint64_t TT = 1ull << R;
+    const uint64_t base = H << R;
+    for (uint32_t e = tid; e < TT; e += nth) {
+        s_A[e] = A[base + e];
+        if (MODE == BF_PRODUCT) s_B[e] = B[base + e];
+    }
+    __syncthreads();
 
-    bf_load_mul8_even(s_mul8e, T, tid, nth);
-    for (uint64_t H = blockIdx.x; H < ntiles; H += gridDim.x) {
-        const uint64_t base = H << R;
-        for (uint32_t e = tid; e < TT; e += nth) {
-            s_A[e] = A[base + e];
-            if (MODE == BF_PRODUCT) s_B[e] = B[base + e];
-        }
+    if (MODE != BF_INV)
+        for (int i = R - 1; i >= 0; --i)
+            bf_bottom_layer(i, false, s_A, MODE == BF_PRODUCT ? s_B : nullptr, l, R, H, s_mul8e, s_tab, s_basis, T,
+                            tid, nth);
+
+    if (MODE == BF_PRODUCT) {
+        // the odd rows of the GF(2^8) table and the v_15 / v_31 tables go to the
+        // slot area, which follows the even rows (the Mul8View layout)
+        static_assert(BF_OFF_TAB == BF_OFF_MUL8 + 32768, "odd rows must follow the even rows");
+        static_assert(BF_OFF_DATA - BF_OFF_MUL8 >= M8V_BYTES, "slot area too small for the product tables");
+        uint8_t *s_odd = smem + BF_OFF_TAB;
+        uint16_t *s_c15 = reinterpret_cast<uint16_t *>(smem + BF_OFF_MUL8 + M8V_OFF_C15);
+        uint32_t *s_c31 = reinterpret_cast<uint32_t *>(smem + BF_OFF_MUL8 + M8V_OFF_C31);
+        const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_odd);
+        for (int idx = tid; idx < 128 * 16; idx += nth) dst[idx] = src[(2 * (idx >> 4) + 1) * 16 + (idx & 15)];
+        for (int idx = tid; idx < 512; idx += nth) s_c15[idx] = (&T->c15[0][0])[idx];
+        for (int idx = tid; idx < 1024; idx += nth) s_c31[idx] = (&T->c31[0][0])[idx];
         __syncthreads();
-
-        if (MODE != BF_INV)
-            for (int i = R - 1; i >= 0; --i)
-                bf_bottom_layer(i, false, s_A, MODE == BF_PRODUCT ? s_B : nullptr, l, R, H, s_mul8e, s_tab, s_basis,
-                                T, tid, nth);
-
-        if (MODE == BF_PRODUCT) {
-            // the odd rows of the GF(2^8) table and the v_15 / v_31 tables go to the
-            // slot area, which follows the even rows (the Mul8View layout)
-            static_assert(BF_OFF_TAB == BF_OFF_MUL8 + 32768, "odd rows must follow the even rows");
-            static_assert(BF_OFF_DATA - BF_OFF_MUL8 >= M8V_BYTES, "slot area too small for the product tables");
-            uint8_t *s_odd = smem + BF_OFF_TAB;
-            uint16_t *s_c15 = reinterpret_cast<uint16_t *>(smem + BF_OFF_MUL8 + M8V_OFF_C15);
-            uint32_t *s_c31 = reinterpret_cast<uint32_t *>(smem + BF_OFF_MUL8 + M8V_OFF_C31);
-            const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
-            uint4 *dst = reinterpret_cast<uint4 *>(s_odd);
-            for (int idx = tid; idx < 128 * 16; idx += nth) dst[idx] = src[(2 * (idx >> 4) + 1) * 16 + (idx & 15)];
-            for (int idx = tid; idx < 512; idx += nth) s_c15[idx] = (&T->c15[0][0])[idx];
-            for (int idx = tid; idx < 1024; idx += nth) s_c31[idx] = (&T->c31[0][0])[idx];
-            __syncthreads();
-            const Mul8View mv{smem + BF_OFF_MUL8};
-            for (uint32_t e = tid; e < TT; e += nth) s_A[e] = mv.m64(s_A[e], s_B[e]);
-            __syncthreads();
-        }
-
-        if (MODE != BF_FWD)
-            for (int i = 0; i < R; ++i)
-                bf_bottom_layer(i, true, s_A, nullptr, l, R, H, s_mul8e, s_tab, s_basis, T, tid, nth);
-
-        for (uint32_t e = tid; e < TT; e += nth) A[base + e] = s_A[e];
+        const Mul8View mv{smem + BF_OFF_MUL8};
+        for (uint32_t e = tid; e < TT; e += nth) s_A[e] = mv.m64(s_A[e], s_B[e]);
         __syncthreads();
     }
+
+    if (MODE != BF_FWD)
+        for (int i = 0; i < R; ++i)
+            bf_bottom_layer(i, true, s_A, nullptr, l, R, H, s_mul8e, s_tab, s_basis, T, tid, nth);
+
+    for (uint32_t e = tid; e < TT; e += nth) A[base + e] = s_A[e];
+    __syncthreads();
+}
+
+// Bottom pass.  grid <= 2^(l-R) persistent workgroups over the tiles.
+template <int MODE>
+__global__ __launch_bounds__(BF_THREADS) void k_bfly_bottom(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
+                                                            int l, int R, const DevTables *__restrict__ T)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const uint64_t ntiles = 1ull << (l - R);
+    bf_load_mul8_even(smem + BF_OFF_MUL8, T, tid, nth);
+    for (uint64_t H = blockIdx.x; H < ntiles; H += gridDim.x) bf_bottom_tile<MODE>(A, B, l, R, H, smem, T, tid, nth);
 }
 
 // Upper pass: layers i_lo .. i_lo+k-1 (k <= 7), tiles of 2^k rows x 2^lgW columns

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfpmul.so")
 
 EIO, ENOMEM, EINVAL = -5, -12, -22
 MAX_PRODUCT_BITS = 1 << 37
+BATCH_MAX_PRODUCT_BITS = 1 << 22
 
 # (name, restype, argtypes) of every symbol include/fpmul.h declares
 _V, _U64, _I, _SZ, _P = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p
@@ -23,6 +24,7 @@ SIGNATURES = {
     "polymul_ctx_create": (_I, [ctypes.POINTER(_V), _I, _SZ]),
     "polymul_ctx_destroy": (_I, [_V]),
     "polymul_ex": (_I, [_V, _P, _U64, _P, _U64, _P, _V]),
+    "polymul_batch": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _V]),
     "polymul_addfft": (_I, [_V, _P, _U64, _I, _P, _V]),
     "polymul_iaddfft": (_I, [_V, _P, _I, _P, _U64, _V]),
     "polymul_basiscvt": (_I, [_V, _P, _U64, _I, _I, _P, _V]),
@@ -128,6 +130,23 @@ class Context:
         _check(lib().polymul_ex(self.handle, _dptr(a), len_a, _dptr(b), len_b, _dptr(out), _stream(stream)))
         return out
 
+    def polymul_batch(self, a_pool, a_off, len_a, b_pool, b_off, len_b, out_pool, out_off,
+                      max_product_bits: int, status=None, stream=None):
+        """count = len(len_a) products in one launch; every argument is a CUDA
+        int64 tensor (status: int32 or None), see polymul_batch in fpmul.h."""
+        import torch
+        count = int(len_a.numel())
+        if status is not None and (status.dtype != torch.int32 or not status.is_contiguous()):
+            raise ValueError("status must be a contiguous int32 tensor")
+        for t in (a_off, b_off, len_b, out_off):
+            if int(t.numel()) != count:
+                raise ValueError("descriptor arrays must have one entry per product")
+        _check(lib().polymul_batch(self.handle, count, _dptr(a_pool), _dptr(a_off), _dptr(len_a),
+                                   _dptr(b_pool), _dptr(b_off), _dptr(len_b), _dptr(out_pool), _dptr(out_off),
+                                   max_product_bits, status.data_ptr() if status is not None else None,
+                                   _stream(stream)))
+        return out_pool
+
     def addfft(self, a, len_a: int, log2n: int, values=None, stream=None):
         import torch
         if values is None:
@@ -159,6 +178,32 @@ def polymul(a, len_a: int, b, len_b: int, out=None):
         out = torch.empty(max(1, nwords(lc)), dtype=torch.int64, device=a.device)
     _check(lib().polymul(_dptr(a), len_a, _dptr(b), len_b, _dptr(out)))
     return out
+
+
+def pack_words(arrays):
+    """Concatenate word arrays (numpy uint64) into one pool: returns
+    (pool, word offsets), each array starting at its offset."""
+    import numpy as np
+    offs = np.zeros(len(arrays), dtype=np.int64)
+    total = 0
+    for k, a in enumerate(arrays):
+        offs[k] = total
+        total += max(1, int(a.size))
+    pool = np.zeros(max(1, total), dtype=np.uint64)
+    for k, a in enumerate(arrays):
+        pool[offs[k]: offs[k] + a.size] = a
+    return pool, offs
+
+
+def out_layout(len_a, len_b):
+    """Word offsets and pool size for the products of a batch."""
+    import numpy as np
+    la = np.asarray(len_a, dtype=np.int64)
+    lb = np.asarray(len_b, dtype=np.int64)
+    words = np.where((la > 0) & (lb > 0), (la + lb - 1 + 63) // 64, 0)
+    words = np.maximum(words, 1)
+    offs = np.concatenate([[0], np.cumsum(words)[:-1]]).astype(np.int64)
+    return offs, int(words.sum())
 
 
 def version() -> str:
