@@ -168,6 +168,70 @@ def bench_batch(ctx, steps: int):
     return rec
 
 
+def bench_serve(ctx, count: int, warmup: int, rho: float):
+    """Poisson stream of products, operands log-uniform in [2^12, 2^24] bits
+    (seed 0x5EED05E5), through the continuous-batching server: first the
+    saturated throughput X (every request submitted at once), then arrivals
+    at rate rho * X; latency = submit to completion seen by the server."""
+    import numpy as np
+    import torch
+    from paper_1803_11301_amd import fpmul, synth
+    total = warmup + count
+    _, la, lb, sa, sb = synth.serve_plan(total, 1.0)
+    pool_bits = 1 << 25
+    pa = torch.from_numpy(synth.dense_poly(synth.SEED_SERVE + 1, pool_bits).view(np.int64)).cuda()
+    pb = torch.from_numpy(synth.dense_poly(synth.SEED_SERVE + 2, pool_bits).view(np.int64)).cuda()
+    pw = pool_bits // 64
+    aw = (la + 63) // 64
+    bw = (lb + 63) // 64
+    offa = (sa % np.uint64(1 << 40)).astype(np.int64) % (pw - aw + 1)
+    offb = (sb % np.uint64(1 << 40)).astype(np.int64) % (pw - bw + 1)
+    ow = (la + lb - 1 + 63) // 64
+    oofs = np.concatenate([[0], np.cumsum(ow)[:-1]])
+    out = torch.empty(int(ow.sum()), dtype=torch.int64, device="cuda")
+    ab, bb, ob = pa.data_ptr(), pb.data_ptr(), out.data_ptr()
+    args = [(ab + 8 * int(offa[k]), int(la[k]), bb + 8 * int(offb[k]), int(lb[k]), ob + 8 * int(oofs[k]))
+            for k in range(total)]
+    torch.cuda.synchronize()
+    srv = fpmul.Server(ctx, hbm_budget=8 << 30, slots=4)
+    # saturation: the warm-up requests plus the first measured ones all at once
+    nsat = max(warmup, 1)
+    t0 = time.perf_counter()
+    tks = [srv.submit(*args[k]) for k in range(nsat)]
+    for tk in tks:
+        srv.wait(tk)
+    X = nsat / (time.perf_counter() - t0)
+    # open-loop Poisson arrivals at rho * X
+    rate = rho * X
+    arr, _, _, _, _ = synth.serve_plan(count, rate)
+    tks = []
+    t0 = time.perf_counter()
+    for k in range(count):
+        due = t0 + float(arr[k])
+        while True:
+            now = time.perf_counter()
+            if now >= due:
+                break
+            if due - now > 2e-4:
+                time.sleep((due - now) - 1e-4)
+        tks.append(srv.submit(*args[warmup + k]))
+    for tk in tks:
+        srv.wait(tk)
+    wall = time.perf_counter() - t0
+    lat = np.array([(lambda s, st, d: (d - s) / 1e6)(*srv.times(tk)) for tk in tks])
+    queue = np.array([(lambda s, st, d: (st - s) / 1e6)(*srv.times(tk)) for tk in tks])
+    srv.close()
+    rec = {"workload": "Poisson stream, operands log-uniform 2^12..2^24 bits, seed 0x5eed05e5",
+           "requests": count, "warmup": warmup, "saturated_products_per_s": round(X, 1), "rho": rho,
+           "offered_per_s": round(rate, 1), "achieved_products_per_s": round(count / wall, 1),
+           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+           "mean_ms": round(float(lat.mean()), 3), "p99_queue_ms": round(float(np.percentile(queue, 99)), 3),
+           "slots": 4, "hbm_budget_bytes": 8 << 30}
+    log(f"[bench] serve: saturated {X:.0f}/s; at {rho:.2f}: {count / wall:.0f}/s, p50 {rec['p50_ms']} ms, "
+        f"p99 {rec['p99_ms']} ms")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +242,10 @@ def main():
     ap.add_argument("--cpu-log2", type=int, default=27, help="operand size of the oracle sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=200)
+    ap.add_argument("--serve-rho", type=float, default=0.8, help="offered load as a fraction of saturation")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -263,6 +331,10 @@ def main():
     if not args.no_batch and args.workload == "large":
         batch = bench_batch(ctx, args.batch_steps)
 
+    serve = None
+    if not args.no_serve and args.workload == "large":
+        serve = bench_serve(ctx, args.serve_requests, args.serve_warmup, args.serve_rho)
+
     cpu = None
     if not args.no_cpu:
         log(f"[bench] oracle sample 2^{args.cpu_log2} on the host")
@@ -283,6 +355,7 @@ def main():
                              "unit": "GB/s", "frac": round(product_gbs / HBM_PEAK_GBS, 5)},
         "kernels": per_kernel,
         "batch": batch,
+        "serve": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -118,6 +118,42 @@ int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, cons
                   void *stream);
 
 /*
+ * Product server: continuous batching of product requests on one GPU.
+ *
+ * polymul_server_create -- a server on `ctx`'s device (ctx must outlive it).
+ *   It allocates one device arena of hbm_budget_bytes (>= 1 MiB) at creation
+ *   and nothing afterwards, and runs max_slots (1..64) launch slots, each a
+ *   HIP stream.  A scheduler thread admits waiting requests whenever a slot
+ *   is free and the request's workspace fits in what is left of the arena:
+ *   all waiting products of at most POLYMUL_BATCH_MAX_PRODUCT_BITS bits go
+ *   out together as one batched launch (as polymul_batch), a larger product
+ *   runs alone (as polymul_ex).  A later request may pass an earlier one that
+ *   does not fit yet; one passed 64 times blocks later ones until it fits.
+ *   Launches on different slots overlap on the device.
+ * polymul_submit -- queues C = A * B (same arguments and rules as polymul;
+ *   device pointers the caller keeps alive and unmodified until the ticket is
+ *   done; the server copies nothing) and returns its ticket.  A product whose
+ *   workspace exceeds the whole arena is refused with POLYMUL_ENOMEM.
+ * polymul_poll -- *done = 1 once the ticket's product is in out; then returns
+ *   the product's result code (0, or the error of its launch).
+ * polymul_wait -- blocks until the ticket is done; returns its result code.
+ * polymul_ticket_times -- host steady-clock times (ns since server creation)
+ *   at which the ticket was submitted, launched and seen complete.
+ * polymul_server_destroy -- finishes every submitted request, then frees the
+ *   arena, streams and thread.
+ * submit, poll, wait and ticket_times may be called from any host thread.
+ */
+typedef struct polymul_server polymul_server;
+int polymul_server_create(polymul_server **srv, polymul_ctx *ctx, size_t hbm_budget_bytes, uint32_t max_slots);
+int polymul_server_destroy(polymul_server *srv);
+int polymul_submit(polymul_server *srv, const uint64_t *a_bits, uint64_t len_a, const uint64_t *b_bits,
+                   uint64_t len_b, uint64_t *out, uint64_t *ticket);
+int polymul_poll(polymul_server *srv, uint64_t ticket, int *done);
+int polymul_wait(polymul_server *srv, uint64_t ticket);
+int polymul_ticket_times(polymul_server *srv, uint64_t ticket, uint64_t *submit_ns, uint64_t *start_ns,
+                         uint64_t *done_ns);
+
+/*
  * polymul_addfft -- the modified additive FFT of Sec. 3.4: BasisCvt (Alg. 1),
  * Encode (Alg. 4) and Butterfly (Alg. 2) at alpha = v_{l+32}.  Evaluates A
  * (len_a bits, len_a <= 2^log2n) at the n/64 points of the Frobenius

@@ -144,15 +144,15 @@ def py_clmul(a: int, b: int) -> int:
 
 
 def words_to_int(w: np.ndarray, length: int) -> int:
-    v = 0
-    for i, x in enumerate(np.asarray(w, dtype=np.uint64).tolist()):
-        v |= int(x) << (64 * i)
+    """Little-endian words -> Python int (the first ``length`` bits)."""
+    v = int.from_bytes(np.ascontiguousarray(w, dtype="<u8").tobytes(), "little")
     return v & ((1 << length) - 1) if length >= 0 else v
 
 
 def int_to_words(v: int, length: int) -> np.ndarray:
+    """Python int -> ceil(length / 64) little-endian words (bits at or above length dropped)."""
     n = nwords(length)
-    out = np.zeros(max(n, 0), dtype=np.uint64)
-    for i in range(n):
-        out[i] = (v >> (64 * i)) & 0xFFFFFFFFFFFFFFFF
-    return out
+    if n <= 0:
+        return np.zeros(0, dtype=np.uint64)
+    v &= (1 << (64 * n)) - 1
+    return np.frombuffer(v.to_bytes(8 * n, "little"), dtype="<u8").astype(np.uint64)

@@ -397,7 +397,9 @@ static std::vector<std::pair<int, int>> upper_groups(int l, int R)
 
 static int set_lds_limits()
 {
+    static std::mutex mu;
     static int done = 0;
+    std::lock_guard<std::mutex> lk(mu);
     if (done) return 0;
     const int big = 160 * 1024;
     HIP_TRY(hipFuncSetAttribute((const void *)k_bfly_bottom<BF_FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -720,19 +722,42 @@ static int batch_steps_upload(polymul_ctx *ctx)
     return 0;
 }
 
+// layout of a batch workspace: per-workgroup slabs (4 buffers each), the
+// queue order, the queue counter
+struct BatchLayout {
+    unsigned grid;
+    uint64_t slab_words;
+    size_t slab_bytes, order_bytes, total;
+};
+
+static BatchLayout batch_layout(const polymul_ctx *ctx, uint32_t count, uint64_t max_bits)
+{
+    BatchLayout L;
+    const int maxlog = std::max(BT_MIN_LOG2N, ilog2(max_bits));
+    L.slab_words = 1ull << (maxlog - 6);
+    L.grid = (unsigned)std::min<uint64_t>(count, (uint64_t)ctx->num_cu);
+    L.slab_bytes = (size_t)L.grid * 4 * L.slab_words * 8;
+    L.order_bytes = ((size_t)count * 4 + 255) / 256 * 256;
+    L.total = L.slab_bytes + L.order_bytes + 256;
+    return L;
+}
+
+static size_t batch_ws_bytes(const polymul_ctx *ctx, uint32_t count, uint64_t max_bits)
+{
+    return batch_layout(ctx, count, max_bits).total;
+}
+
 static int batch_body(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, const uint64_t *a_off,
                       const uint64_t *len_a, const uint64_t *b_pool, const uint64_t *b_off, const uint64_t *len_b,
-                      uint64_t *out_pool, const uint64_t *out_off, uint64_t max_bits, int32_t *status,
-                      hipStream_t s)
+                      uint64_t *out_pool, const uint64_t *out_off, const BtDesc *desc, uint64_t max_bits,
+                      int32_t *status, hipStream_t s)
 {
     int rc;
     if ((rc = batch_steps_upload(ctx)) || (rc = set_lds_limits())) return rc;
-    const int maxlog = std::max(BT_MIN_LOG2N, ilog2(max_bits));
-    const uint64_t slab_words = 1ull << (maxlog - 6);
-    const unsigned grid = (unsigned)std::min<uint64_t>(count, (uint64_t)ctx->num_cu);
-    const size_t slab_bytes = (size_t)grid * 4 * slab_words * 8;
-    const size_t order_bytes = ((size_t)count * 4 + 255) / 256 * 256;
-    const size_t need = slab_bytes + order_bytes + 256;
+    const BatchLayout BL = batch_layout(ctx, count, max_bits);
+    const unsigned grid = BL.grid;
+    const uint64_t slab_words = BL.slab_words;
+    const size_t slab_bytes = BL.slab_bytes, order_bytes = BL.order_bytes, need = BL.total;
     if (need > ctx->bws_bytes) {
         if (ctx->cap && need > ctx->cap)
             return fail(POLYMUL_ENOMEM, "batch workspace of " + std::to_string(need) + " bytes exceeds the cap of " +
@@ -753,10 +778,10 @@ static int batch_body(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, 
     uint64_t *slab = static_cast<uint64_t *>(ctx->bws);
     uint32_t *order = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + slab_bytes);
     uint32_t *counter = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + slab_bytes + order_bytes);
-    KLAUNCH(ctx, s, "batch_plan", k_batch_plan, 1, 1024, count, len_a, len_b, max_bits, order, counter);
+    KLAUNCH(ctx, s, "batch_plan", k_batch_plan, 1, 1024, count, len_a, len_b, desc, max_bits, order, counter);
     KLAUNCH_LDS(ctx, s, "batch", k_batch, grid, BT_THREADS, bf_bottom_lds(BF_BOTTOM_R, true), a_pool, a_off, len_a,
-                b_pool, b_off, len_b, out_pool, out_off, status, count, max_bits, order, counter, slab, slab_words,
-                ctx->tables, ctx->bsteps);
+                b_pool, b_off, len_b, out_pool, out_off, desc, status, count, max_bits, order, counter, slab,
+                slab_words, ctx->tables, ctx->bsteps);
     return 0;
 }
 
@@ -891,7 +916,7 @@ int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, cons
         return rc;
     if (status && (rc = check_dev_ptr(status, "status"))) return rc;
     return batch_body(ctx, count, a_pool, a_word_off, len_a, b_pool, b_word_off, len_b, out_pool, out_word_off,
-                      max_product_bits, status, (hipStream_t)stream);
+                      nullptr, max_product_bits, status, (hipStream_t)stream);
 }
 
 int polymul_addfft(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int log2n, uint64_t *values, void *stream)
@@ -984,3 +1009,5 @@ int polymul(const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b
 }
 
 }  // extern "C"
+
+#include "server.h"

@@ -35,6 +35,14 @@ struct BatchSteps {
     BatchStep st[BT_MAX_STEPS];
 };
 
+// one item given by pointers (the server's batched launches) instead of pool
+// offsets
+struct BtDesc {
+    const uint64_t *a, *b;
+    uint64_t *out;
+    uint64_t la, lb;
+};
+
 __device__ __forceinline__ int bt_ceil_log2(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll(x - 1); }
 
 // transform log2 of a product, or -1 if it has no bits, or BT_MAX_LOG2N + 1
@@ -47,10 +55,24 @@ __device__ __forceinline__ int bt_log2n(uint64_t la, uint64_t lb, uint64_t max_b
     return k < BT_MIN_LOG2N ? BT_MIN_LOG2N : k;
 }
 
+// lengths of item q: from the descriptors when given, else from the arrays
+__device__ __forceinline__ void bt_lengths(const BtDesc *desc, const uint64_t *len_a, const uint64_t *len_b,
+                                           uint32_t q, uint64_t &la, uint64_t &lb)
+{
+    if (desc) {
+        la = desc[q].la;
+        lb = desc[q].lb;
+    } else {
+        la = len_a[q];
+        lb = len_b[q];
+    }
+}
+
 // queue order: larger transforms first, empty and rejected items last; also
 // resets the queue counter.  One workgroup.
 __global__ __launch_bounds__(1024) void k_batch_plan(uint32_t count, const uint64_t *__restrict__ len_a,
-                                                     const uint64_t *__restrict__ len_b, uint64_t max_bits,
+                                                     const uint64_t *__restrict__ len_b,
+                                                     const BtDesc *__restrict__ desc, uint64_t max_bits,
                                                      uint32_t *__restrict__ order, uint32_t *__restrict__ counter)
 {
     __shared__ uint32_t hist[BT_NBINS];
@@ -58,7 +80,9 @@ __global__ __launch_bounds__(1024) void k_batch_plan(uint32_t count, const uint6
     for (int k = tid; k < BT_NBINS; k += nth) hist[k] = 0;
     __syncthreads();
     for (uint32_t q = tid; q < count; q += nth) {
-        const int lg = bt_log2n(len_a[q], len_b[q], max_bits);
+        uint64_t la, lb;
+        bt_lengths(desc, len_a, len_b, q, la, lb);
+        const int lg = bt_log2n(la, lb, max_bits);
         const int key = (lg < 0 || lg > BT_MAX_LOG2N) ? BT_NBINS - 1 : BT_MAX_LOG2N - lg;
         atomicAdd(&hist[key], 1u);
     }
@@ -74,7 +98,9 @@ __global__ __launch_bounds__(1024) void k_batch_plan(uint32_t count, const uint6
     }
     __syncthreads();
     for (uint32_t q = tid; q < count; q += nth) {
-        const int lg = bt_log2n(len_a[q], len_b[q], max_bits);
+        uint64_t la, lb;
+        bt_lengths(desc, len_a, len_b, q, la, lb);
+        const int lg = bt_log2n(la, lb, max_bits);
         const int key = (lg < 0 || lg > BT_MAX_LOG2N) ? BT_NBINS - 1 : BT_MAX_LOG2N - lg;
         order[atomicAdd(&hist[key], 1u)] = q;
     }
@@ -215,11 +241,13 @@ __device__ void bt_upper_layer(uint64_t *__restrict__ X, uint64_t *__restrict__ 
     __syncthreads();
 }
 
-// grid: persistent workgroups; slab: 4 buffers of slab_words per workgroup
+// grid: persistent workgroups; slab: 4 buffers of slab_words per workgroup.
+// Items come from the pools and offset arrays, or from `desc` when it is set.
 __global__ __launch_bounds__(BT_THREADS) void k_batch(
     const uint64_t *__restrict__ a_pool, const uint64_t *__restrict__ a_off, const uint64_t *__restrict__ len_a,
     const uint64_t *__restrict__ b_pool, const uint64_t *__restrict__ b_off, const uint64_t *__restrict__ len_b,
-    uint64_t *__restrict__ out_pool, const uint64_t *__restrict__ out_off, int32_t *__restrict__ status,
+    uint64_t *__restrict__ out_pool, const uint64_t *__restrict__ out_off, const BtDesc *__restrict__ desc,
+    int32_t *__restrict__ status,
     uint32_t count, uint64_t max_bits, const uint32_t *__restrict__ order, uint32_t *__restrict__ counter,
     uint64_t *__restrict__ slab, uint64_t slab_words, const DevTables *__restrict__ T,
     const BatchSteps *__restrict__ BS)
@@ -238,7 +266,8 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
         __syncthreads();
         if (qpos >= count) break;
         const uint32_t q = order[qpos];
-        const uint64_t la = len_a[q], lb = len_b[q];
+        uint64_t la, lb;
+        bt_lengths(desc, len_a, len_b, q, la, lb);
         const int log2n = bt_log2n(la, lb, max_bits);
         if (log2n < 0 || log2n > BT_MAX_LOG2N || (1ull << (log2n - 6)) > slab_words) {
             if (tid == 0 && status) status[q] = log2n < 0 ? 0 : -22;
@@ -250,7 +279,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
         // BasisCvt and Encode of both operands: A -> TA, B -> TB
         for (int side = 0; side < 2; ++side) {
             const uint64_t len = side ? lb : la;
-            const uint64_t *src = side ? b_pool + b_off[q] : a_pool + a_off[q];
+            const uint64_t *src = desc ? (side ? desc[q].b : desc[q].a) : (side ? b_pool + b_off[q] : a_pool + a_off[q]);
             int lgN = bt_ceil_log2(len);
             if (lgN < BT_MIN_LOG2N) lgN = BT_MIN_LOG2N;
             bt_load(src, len, X, n_p, tid, nth);
@@ -272,7 +301,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
         bt_decode(TA, l, X, TB, T, tid, nth);
         __syncthreads();
         const uint64_t *res = bt_basiscvt(X, Y, log2n, true, BS, tid, nth);
-        uint64_t *out = out_pool + out_off[q];
+        uint64_t *out = desc ? desc[q].out : out_pool + out_off[q];
         const uint64_t ow = (lc + 63) / 64;
         for (uint64_t w = tid; w < ow; w += nth) {
             uint64_t v = res[w];

@@ -25,6 +25,12 @@ SIGNATURES = {
     "polymul_ctx_destroy": (_I, [_V]),
     "polymul_ex": (_I, [_V, _P, _U64, _P, _U64, _P, _V]),
     "polymul_batch": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _V]),
+    "polymul_server_create": (_I, [ctypes.POINTER(_V), _V, _SZ, ctypes.c_uint32]),
+    "polymul_server_destroy": (_I, [_V]),
+    "polymul_submit": (_I, [_V, _P, _U64, _P, _U64, _P, ctypes.POINTER(_U64)]),
+    "polymul_poll": (_I, [_V, _U64, ctypes.POINTER(_I)]),
+    "polymul_wait": (_I, [_V, _U64]),
+    "polymul_ticket_times": (_I, [_V, _U64, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "polymul_addfft": (_I, [_V, _P, _U64, _I, _P, _V]),
     "polymul_iaddfft": (_I, [_V, _P, _I, _P, _U64, _V]),
     "polymul_basiscvt": (_I, [_V, _P, _U64, _I, _I, _P, _V]),
@@ -178,6 +184,54 @@ def polymul(a, len_a: int, b, len_b: int, out=None):
         out = torch.empty(max(1, nwords(lc)), dtype=torch.int64, device=a.device)
     _check(lib().polymul(_dptr(a), len_a, _dptr(b), len_b, _dptr(out)))
     return out
+
+
+class Server:
+    """Continuous-batching product server on a Context (polymul_server_* in fpmul.h).
+
+    Operands and outputs are CUDA int64 tensors (or raw device addresses) the
+    caller keeps alive until the ticket is done."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 4 << 30, slots: int = 4):
+        h = ctypes.c_void_p()
+        _check(lib().polymul_server_create(ctypes.byref(h), ctx.handle, hbm_budget, slots))
+        self.handle = h
+        self.ctx = ctx
+
+    def close(self):
+        if self.handle:
+            lib().polymul_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _addr(x):
+        return x if isinstance(x, int) else _dptr(x)
+
+    def submit(self, a, len_a: int, b, len_b: int, out) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().polymul_submit(self.handle, self._addr(a), len_a, self._addr(b), len_b, self._addr(out),
+                                    ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int()
+        _check(lib().polymul_poll(self.handle, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(lib().polymul_wait(self.handle, ticket))
+
+    def times(self, ticket: int):
+        """(submit, launch, done) in ns since the server was created."""
+        s, st, d = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().polymul_ticket_times(self.handle, ticket, ctypes.byref(s), ctypes.byref(st), ctypes.byref(d)))
+        return s.value, st.value, d.value
 
 
 def pack_words(arrays):

@@ -1,0 +1,138 @@
+"""GPU tests of the continuous-batching product server.
+
+Each product computed in a mix of concurrent requests must equal the same
+product computed alone (polymul_ex) and the oracle; memory admission must
+serialise requests when the budget is tight and refuse a request larger than
+the whole budget.
+"""
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1803_11301_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_11301_amd import fpmul
+    c = fpmul.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev64(arr):
+    a = np.ascontiguousarray(arr, dtype=np.uint64)
+    if a.size == 0:
+        a = np.zeros(1, np.uint64)
+    return torch.from_numpy(a.view(np.int64)).cuda()
+
+
+def host(t, n):
+    return t.cpu().numpy().view(np.uint64)[:n]
+
+
+def check_against_oracle(a, la, b, lb, got, rng):
+    n = O.nwords(la + lb - 1)
+    if la <= (1 << 16) and lb <= (1 << 16):
+        assert np.array_equal(got, O.polymul(a, la, b, lb))
+        return
+    idx = np.array(sorted({0, n - 1, n // 2} | {rng.randrange(n) for _ in range(5)}), dtype=np.uint64)
+    assert np.array_equal(got[idx.astype(np.int64)], O.product_words(a, la, b, lb, idx))
+    z = rng.getrandbits(64) | 1
+    assert O.gf64_mul(O.eval_at(a, la, z), O.eval_at(b, lb, z)) == O.eval_at(got, la + lb - 1, z)
+
+
+def test_mix_equals_alone_and_oracle(ctx):
+    from paper_1803_11301_amd import fpmul
+    t, la, lb, sa, sb = synth.serve_plan(48, 1000.0, lo=12, hi=22)
+    lens = list(zip(la.tolist(), lb.tolist()))
+    lens += [(1 << 23, 1 << 23), ((1 << 24) - 3, 1 << 22), (1, 1 << 20), (5, 5)]
+    say("server mix", len(lens), "requests, largest", max(x + y for x, y in lens))
+    rng = random.Random(99)
+    ops = []
+    for k, (x, y) in enumerate(lens):
+        a = synth.dense_poly(int(sa[k % len(sa)]) + k, x)
+        b = synth.dense_poly(int(sb[k % len(sb)]) + k, y)
+        ops.append((a, x, b, y))
+    srv = fpmul.Server(ctx, hbm_budget=2 << 30, slots=4)
+    tensors, tickets = [], []
+    for a, x, b, y in ops:
+        ta, tb = dev64(a), dev64(b)
+        out = torch.zeros(O.nwords(x + y - 1), dtype=torch.int64, device="cuda")
+        tensors.append((ta, tb, out))
+    torch.cuda.synchronize()
+    for (a, x, b, y), (ta, tb, out) in zip(ops, tensors):
+        tickets.append(srv.submit(ta, x, tb, y, out))
+    for tk in tickets:
+        srv.wait(tk)
+        s, st, d = srv.times(tk)
+        assert s <= st <= d
+    srv.close()
+    for (a, x, b, y), (ta, tb, out) in zip(ops, tensors):
+        n = O.nwords(x + y - 1)
+        got = host(out, n)
+        alone = host(ctx.polymul(ta, x, tb, y), n)
+        assert np.array_equal(got, alone), (x, y)
+        check_against_oracle(a, x, b, y, got, rng)
+
+
+def test_tight_budget_serialises_and_refuses_too_large(ctx):
+    from paper_1803_11301_amd import fpmul
+    rng = random.Random(3)
+    # 64 MiB holds one 2^24 x 2^24-bit product's workspace (about 18 MiB) at a time with room
+    # for small batches, but not a 2^28-bit product
+    srv = fpmul.Server(ctx, hbm_budget=64 << 20, slots=3)
+    lens = [(1 << 24, 1 << 24), (3000, 4000), (1 << 24, (1 << 24) - 1), (100, 100), (1 << 23, 1 << 23)]
+    say("tight budget", lens)
+    ops, tickets = [], []
+    for k, (x, y) in enumerate(lens):
+        a, b = synth.dense_poly(0x5EED7000 + 2 * k, x), synth.dense_poly(0x5EED7001 + 2 * k, y)
+        ta, tb = dev64(a), dev64(b)
+        out = torch.zeros(O.nwords(x + y - 1), dtype=torch.int64, device="cuda")
+        ops.append((a, x, b, y, ta, tb, out))
+    torch.cuda.synchronize()
+    for a, x, b, y, ta, tb, out in ops:
+        tickets.append(srv.submit(ta, x, tb, y, out))
+    big = 1 << 28
+    tbig = torch.zeros(O.nwords(big), dtype=torch.int64, device="cuda")
+    obig = torch.zeros(O.nwords(2 * big), dtype=torch.int64, device="cuda")
+    with pytest.raises(fpmul.FpmulError) as ei:
+        srv.submit(tbig, big, tbig, big, obig)
+    assert ei.value.code == fpmul.ENOMEM
+    for tk in tickets:
+        srv.wait(tk)
+        assert srv.poll(tk)
+    srv.close()
+    for a, x, b, y, ta, tb, out in ops:
+        check_against_oracle(a, x, b, y, host(out, O.nwords(x + y - 1)), rng)
+
+
+def test_empty_and_errors(ctx):
+    from paper_1803_11301_amd import fpmul
+    srv = fpmul.Server(ctx, hbm_budget=16 << 20, slots=1)
+    t = torch.zeros(4, dtype=torch.int64, device="cuda")
+    o = torch.full((4,), 7, dtype=torch.int64, device="cuda")
+    tk = srv.submit(t, 0, t, 100, o)
+    assert srv.poll(tk)
+    srv.wait(tk)
+    assert int(o[0].item()) == 7
+    with pytest.raises(fpmul.FpmulError):
+        srv.submit(t, 64, t, 64, t)          # out overlaps the inputs
+    with pytest.raises(fpmul.FpmulError):
+        srv.wait(123456789)                  # unknown ticket
+    srv.close()
