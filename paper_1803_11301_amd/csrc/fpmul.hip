@@ -62,6 +62,7 @@ static int fail(int code, const std::string &msg)
 #include "k_basiscvt.h"
 #include "k_steps.h"
 #include "k_batch.h"
+#include "k_bf2.h"
 
 // ---------------------------------------------------------------------------
 // elementary kernels
@@ -423,6 +424,27 @@ static int set_lds_limits()
             return fail(POLYMUL_EIO, std::string("launch ") + (name) + ": " + hipGetErrorString(_le)); \
     } while (0)
 
+// upper layer group [i_lo, i_lo + k) with the register-resident passes
+template <int MODE>
+static int launch_bf2_upper(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l,
+                            int i_lo, int k)
+{
+    const unsigned grid = (unsigned)std::min<uint64_t>(1ull << (l - B2_TILE_LG), (uint64_t)ctx->num_cu * 2);
+    void (*kern)(uint64_t *, uint64_t *, int, int, const DevTables *) = nullptr;
+    switch (k) {
+    case 1: kern = k_bf2_upper<MODE, 1>; break;
+    case 2: kern = k_bf2_upper<MODE, 2>; break;
+    case 3: kern = k_bf2_upper<MODE, 3>; break;
+    case 4: kern = k_bf2_upper<MODE, 4>; break;
+    case 5: kern = k_bf2_upper<MODE, 5>; break;
+    case 6: kern = k_bf2_upper<MODE, 6>; break;
+    case 7: kern = k_bf2_upper<MODE, 7>; break;
+    default: return fail(POLYMUL_EINVAL, "upper layer group of more than 7 layers");
+    }
+    KLAUNCH(ctx, s, name, kern, grid, B2_THREADS, A, B, l, i_lo, ctx->tables);
+    return 0;
+}
+
 // Butterflies of one transform (mode BF_FWD or BF_INV) or of a product
 // (BF_PRODUCT: forward A and B, pointwise, inverse; result in A)
 static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B, int l, hipStream_t s)
@@ -434,13 +456,13 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
     if (mode != BF_INV) {
         for (auto it = groups.rbegin(); it != groups.rend(); ++it) {
             const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
-            const unsigned tiles = (unsigned)std::min<uint64_t>(1ull << (l - k - lgW), persist_up);
-            if (mode == BF_PRODUCT)
-                KLAUNCH(ctx, s, "butterfly_upper", k_bfly_upper<BF_FWD2>, tiles, ublk, A, B, l, i_lo, k, lgW,
-                        ctx->tables);
-            else
-                KLAUNCH(ctx, s, "butterfly_upper", k_bfly_upper<BF_FWD>, tiles, ublk, A, B, l, i_lo, k, lgW,
-                        ctx->tables);
+            (void)lgW;
+            (void)persist_up;
+            (void)ublk;
+            const int rc = mode == BF_PRODUCT
+                               ? launch_bf2_upper<BF_FWD2>(ctx, s, "butterfly_upper", A, B, l, i_lo, k)
+                               : launch_bf2_upper<BF_FWD>(ctx, s, "butterfly_upper", A, B, l, i_lo, k);
+            if (rc) return rc;
         }
     }
     const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - R), persist_bot);
@@ -456,8 +478,9 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
     if (mode != BF_FWD) {
         for (auto it = groups.begin(); it != groups.end(); ++it) {
             const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
-            const unsigned tiles = (unsigned)std::min<uint64_t>(1ull << (l - k - lgW), persist_up);
-            KLAUNCH(ctx, s, "ibutterfly_upper", k_bfly_upper<BF_INV>, tiles, ublk, A, B, l, i_lo, k, lgW, ctx->tables);
+            (void)lgW;
+            const int rc = launch_bf2_upper<BF_INV>(ctx, s, "ibutterfly_upper", A, B, l, i_lo, k);
+            if (rc) return rc;
         }
     }
     return 0;
@@ -809,6 +832,25 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
         for (int e = 0; e < 256; ++e) D.c15[p][e] = tw.m16(tw.v15, (uint16_t)(e << (8 * p)));
     for (int p = 0; p < 4; ++p)
         for (int e = 0; e < 256; ++e) D.c31[p][e] = tw.m32(tw.v31, (uint32_t)e << (8 * p));
+    for (int bl = 0; bl < 128; ++bl) {
+        const uint64_t beta = H.iota[0][2 * bl];   // iota(2 bl) lies in V_8: one tower byte
+        uint8_t g0[8], g1[8], g2[4];
+        for (int e = 0; e < 8; ++e) {
+            g0[e] = tw.mul8[beta][e];
+            g1[e] = tw.mul8[beta][e << 3];
+        }
+        for (int e = 0; e < 4; ++e) g2[e] = tw.mul8[beta][e << 6];
+        auto pack = [](const uint8_t *b) {
+            return (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
+        };
+        uint32_t *pt = D.pt_beta8[bl];
+        pt[0] = pack(g0);
+        pt[1] = pack(g0 + 4);
+        pt[2] = pack(g1);
+        pt[3] = pack(g1 + 4);
+        pt[4] = pack(g2);
+        pt[5] = pt[6] = pt[7] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -24,6 +24,9 @@ struct DevTables {
     uint8_t mul8[256][256];      // GF(2^8) products, Cantor coordinates
     uint16_t c15[2][256];        // v_15 * (byte at position p) in GF(2^16)
     uint32_t c31[4][256];        // v_31 * (byte at position p) in GF(2^32)
+    // v_perm byte tables of beta = iota(2 bl), bl < 128, on the bit groups
+    // {0,1,2}, {3,4,5}, {6,7} of a byte: t0lo t0hi t1lo t1hi t2 (3 words pad)
+    uint32_t pt_beta8[128][8];
 };
 
 // ----------------------------------------------------------------- tmul ----

@@ -1,0 +1,302 @@
+// k_bf2.h -- butterfly passes (Alg. 2 and its inverse) with the values in
+// registers across groups of three layers.
+//
+// A tile holds 2^11 values of a transform (per operand).  256 threads each
+// hold 8 of them, differing in the three tile bits of the current layer
+// group, so those layers run in registers; between groups the tile is
+// exchanged through LDS.  Each multiplication x * (K + beta) (gf_device.h) is
+//   tmul: 8 lookups in the 8-bit window table of K (one table per layer,
+//         shared by the whole tile), and
+//   pmul: beta in V_8 applied to all bytes at once with v_perm_b32 over the
+//         byte tables of beta on its three bit groups {0,1,2}, {3,4,5}, {6,7}
+//         (multiplication by beta is linear over GF(2)),
+// combined with three-input XORs.
+#pragma once
+
+#include <type_traits>
+
+#include "gf_device.h"
+#include "k_butterfly.h"
+
+#define B2_TILE_LG 11
+#define B2_THREADS 256
+#define B2_STAGE_WORDS (2048 + 256)   // one padded operand tile in the exchange area
+
+// byte tables of beta * y on the bit groups of y: t0 (bits 0-2, 8 entries in
+// two words), t1 (bits 3-5), t2 (bits 6-7, 4 entries); 32 bytes per entry
+struct PermTab {
+    uint32_t t0lo, t0hi, t1lo, t1hi, t2, pad0, pad1, pad2;
+};
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ int b2_pad(int e) { return e + (e >> 3); }
+
+// acc XOR x * (K + beta): tab = window table of K (compile-time LDS address in
+// the callers), (t01, t2) = byte tables of beta
+__device__ __forceinline__ uint64_t b2_mul_acc(const uint64_t *__restrict__ tab, uint4 t01, uint32_t t2, uint64_t x,
+                                               uint64_t acc)
+{
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const uint64_t v0 = tab[lo & 255u], v1 = tab[256 + ((lo >> 8) & 255u)];
+    const uint64_t v2 = tab[512 + ((lo >> 16) & 255u)], v3 = tab[768 + (lo >> 24)];
+    const uint64_t v4 = tab[1024 + (hi & 255u)], v5 = tab[1280 + ((hi >> 8) & 255u)];
+    const uint64_t v6 = tab[1536 + ((hi >> 16) & 255u)], v7 = tab[1792 + (hi >> 24)];
+    const uint32_t sl0 = lo & 0x07070707u, sl1 = (lo >> 3) & 0x07070707u, sl2 = (lo >> 6) & 0x03030303u;
+    const uint32_t sh0 = hi & 0x07070707u, sh1 = (hi >> 3) & 0x07070707u, sh2 = (hi >> 6) & 0x03030303u;
+    const uint32_t pl = xor3(__builtin_amdgcn_perm(t01.y, t01.x, sl0), __builtin_amdgcn_perm(t01.w, t01.z, sl1),
+                             __builtin_amdgcn_perm(t2, t2, sl2));
+    const uint32_t ph = xor3(__builtin_amdgcn_perm(t01.y, t01.x, sh0), __builtin_amdgcn_perm(t01.w, t01.z, sh1),
+                             __builtin_amdgcn_perm(t2, t2, sh2));
+    const uint32_t rl = xor3(xor3((uint32_t)v0, (uint32_t)v1, (uint32_t)v2), xor3((uint32_t)v3, (uint32_t)v4,
+                             (uint32_t)v5), xor3((uint32_t)v6, (uint32_t)v7, pl)) ^ (uint32_t)acc;
+    const uint32_t rh = xor3(xor3((uint32_t)(v0 >> 32), (uint32_t)(v1 >> 32), (uint32_t)(v2 >> 32)),
+                             xor3((uint32_t)(v3 >> 32), (uint32_t)(v4 >> 32), (uint32_t)(v5 >> 32)),
+                             xor3((uint32_t)(v6 >> 32), (uint32_t)(v7 >> 32), ph)) ^ (uint32_t)(acc >> 32);
+    return (uint64_t)rl | ((uint64_t)rh << 32);
+}
+
+// One layer on the registers: the layer bit is register bit M; the block
+// index of a pair is b_t | (register bits above M) * bw, beta = iota(2 (b mod 128)).
+template <int M, bool INV, bool TWO>
+__device__ __forceinline__ void b2_layer(uint64_t (&xa)[8], uint64_t (&xb)[8], const uint64_t *__restrict__ tab,
+                                         const PermTab *__restrict__ s_pt, uint32_t bl_t, uint32_t bw1, uint32_t bw2)
+{
+#pragma unroll
+    for (int u = 0; u < (1 << (2 - M)); ++u) {
+        uint32_t bl = bl_t;
+        if (M == 0) {
+            if (u & 1) bl ^= bw1;
+            if (u & 2) bl ^= bw2;
+        } else if (M == 1) {
+            if (u & 1) bl ^= bw2;
+        }
+        const PermTab *P = s_pt + (bl & 127u);
+        const uint4 t01 = *reinterpret_cast<const uint4 *>(P);
+        const uint32_t t2 = P->t2;
+#pragma unroll
+        for (int low = 0; low < (1 << M); ++low) {
+            const int r0 = low | (u << (M + 1)), r1 = r0 | (1 << M);
+            if (!INV) {
+                const uint64_t h0 = b2_mul_acc(tab, t01, t2, xa[r1], xa[r0]);
+                xa[r1] ^= h0;
+                xa[r0] = h0;
+                if (TWO) {
+                    const uint64_t g0 = b2_mul_acc(tab, t01, t2, xb[r1], xb[r0]);
+                    xb[r1] ^= g0;
+                    xb[r0] = g0;
+                }
+            } else {
+                const uint64_t p1 = xa[r0] ^ xa[r1];
+                xa[r0] = b2_mul_acc(tab, t01, t2, p1, xa[r0]);
+                xa[r1] = p1;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ upper pass ---
+//
+// Layers i_lo .. i_lo + K - 1 on tiles of 2^K rows (global bits i_lo ..) by
+// 2^(11-K) columns (global bits 0 ..).  Tile bits: columns 0 .. LGW-1, rows
+// LGW .. 10.  The rows are taken in groups of three from the top (forward)
+// or from the bottom (inverse); a group of fewer than three rows is padded
+// with the highest other tile bits, on which no layer runs.
+
+template <int K>
+struct B2Upper {
+    static constexpr int LGW = B2_TILE_LG - K;
+    static constexpr int NC = (K + 2) / 3;
+    // rows of group c (forward order): [lo, hi]
+    static constexpr int lo_row(int c) { return K - 3 * c - 3 < 0 ? 0 : K - 3 * c - 3; }
+    static constexpr int hi_row(int c) { return K - 3 * c - 1; }
+};
+
+// register bits (tile bits s0 < s1 < s2) of group c and which are layers
+struct B2Group {
+    int s[3];
+    int layer[3];   // 1 if a layer runs on register bit m
+};
+
+template <int K>
+__device__ __forceinline__ B2Group b2_upper_group(int c)
+{
+    using U = B2Upper<K>;
+    const int lo = U::lo_row(c), hi = U::hi_row(c), n = hi - lo + 1;
+    int bits[3], lay[3], cnt = 0;
+    for (int r = lo; r <= hi; ++r) {
+        bits[cnt] = U::LGW + r;
+        lay[cnt++] = 1;
+    }
+    for (int b = B2_TILE_LG - 1; cnt < 3 && b >= 0; --b) {
+        if (b >= U::LGW + lo && b <= U::LGW + hi) continue;
+        bits[cnt] = b;
+        lay[cnt++] = 0;
+    }
+    (void)n;
+    // sort ascending (three elements)
+    for (int a = 0; a < 3; ++a)
+        for (int b = a + 1; b < 3; ++b)
+            if (bits[b] < bits[a]) {
+                int t = bits[a];
+                bits[a] = bits[b];
+                bits[b] = t;
+                t = lay[a];
+                lay[a] = lay[b];
+                lay[b] = t;
+            }
+    B2Group g;
+    for (int m = 0; m < 3; ++m) {
+        g.s[m] = bits[m];
+        g.layer[m] = lay[m];
+    }
+    return g;
+}
+
+// tile index of thread t's value with register bits zero: the 8 thread bits
+// fill the tile bits outside the group, lowest first
+__device__ __forceinline__ int b2_thread_base(const B2Group &g, int t)
+{
+    int e = 0, q = 0;
+    for (int b = 0; b < B2_TILE_LG; ++b) {
+        if (b == g.s[0] || b == g.s[1] || b == g.s[2]) continue;
+        e |= ((t >> q) & 1) << b;
+        ++q;
+    }
+    return e;
+}
+
+template <int K>
+__device__ __forceinline__ uint64_t b2_upper_global(int e, uint64_t gbase, int i_lo)
+{
+    constexpr int LGW = B2Upper<K>::LGW;
+    return gbase | (uint64_t)(e & ((1 << LGW) - 1)) | ((uint64_t)(e >> LGW) << i_lo);
+}
+
+// basis images of the K tables of group g's layers (threads 64 m .. 64 m + 63 for register bit m)
+template <int K>
+__device__ __forceinline__ void b2_upper_basis(const B2Group &g, uint64_t (*s_basis)[64], uint64_t gbase, int l,
+                                               int i_lo, const DevTables *__restrict__ T, int tid)
+{
+    const int m = tid >> 6;
+    if (m < 3 && g.layer[m]) {
+        const int i = i_lo + g.s[m] - B2Upper<K>::LGW;
+        ktable_basis(s_basis[m], l - i, (uint32_t)(gbase >> (i + 8)), T, tid & 63);
+    }
+}
+
+__device__ __forceinline__ void b2_fill(const B2Group &g, uint64_t (*s_tab)[2048], const uint64_t (*s_basis)[64],
+                                        int tid, int nth)
+{
+    for (int item = tid; item < 3 * 256; item += nth) {
+        const int m = item >> 8;
+        if (g.layer[m]) ktable_fill_item(s_tab[m], s_basis[m], item & 255);
+    }
+}
+
+template <int K, bool INV, bool TWO>
+__device__ __forceinline__ void b2_upper_compute(const B2Group &g, uint64_t (&xa)[8], uint64_t (&xb)[8],
+                                                 uint64_t (*s_tab)[2048], const PermTab *s_pt, uint64_t gb_t,
+                                                 int i_lo)
+{
+    constexpr int LGW = B2Upper<K>::LGW;
+    // global weights of the register bits
+    uint64_t gw[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) gw[m] = b2_upper_global<K>(1 << g.s[m], 0, i_lo);
+    auto run = [&](auto Mc) {
+        constexpr int M = decltype(Mc)::value;
+        if (!g.layer[M]) return;
+        const int i = i_lo + g.s[M] - LGW;
+        const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
+        const uint32_t bw1 = (uint32_t)(gw[1] >> (i + 1)) & 127u, bw2 = (uint32_t)(gw[2] >> (i + 1)) & 127u;
+        b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_pt, bl_t, bw1, bw2);
+    };
+    if (!INV) {
+        run(std::integral_constant<int, 2>());
+        run(std::integral_constant<int, 1>());
+        run(std::integral_constant<int, 0>());
+    } else {
+        run(std::integral_constant<int, 0>());
+        run(std::integral_constant<int, 1>());
+        run(std::integral_constant<int, 2>());
+    }
+}
+
+// MODE: BF_FWD (A), BF_FWD2 (A and B, same multipliers), BF_INV (A)
+template <int MODE, int K>
+__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
+                                                             int l, int i_lo, const DevTables *__restrict__ T)
+{
+    constexpr bool INV = MODE == BF_INV, TWO = MODE == BF_FWD2;
+    constexpr int NC = B2Upper<K>::NC, LGW = B2Upper<K>::LGW;
+    __shared__ __align__(16) uint64_t s_tab[3][2048];   // K tables; the exchange area aliases them
+    __shared__ __align__(16) PermTab s_pt[128];
+    __shared__ uint64_t s_basis[3][64];
+    uint64_t *stA = &s_tab[0][0], *stB = stA + B2_STAGE_WORDS;
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    for (int q = tid; q < 128 * 8; q += nth)
+        reinterpret_cast<uint32_t *>(s_pt)[q] = reinterpret_cast<const uint32_t *>(T->pt_beta8)[q];
+
+    const int nlo = i_lo - LGW;
+    const uint64_t ntiles = 1ull << (l - B2_TILE_LG);
+    uint64_t xa[8], xb[8];
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t gbase = ((tile >> nlo) << (i_lo + K)) | ((tile & ((1ull << nlo) - 1)) << LGW);
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            const int c = INV ? NC - 1 - cc : cc;
+            const B2Group g = b2_upper_group<K>(c);
+            const int e_t = b2_thread_base(g, tid);
+            const uint64_t gb_t = b2_upper_global<K>(e_t, gbase, i_lo);
+            if (cc == 0) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    const uint64_t j = b2_upper_global<K>(e, gbase, i_lo);
+                    xa[r] = A[j];
+                    if (TWO) xb[r] = B[j];
+                }
+                __syncthreads();   // the previous tile is done with the tables
+                b2_upper_basis<K>(g, s_basis, gbase, l, i_lo, T, tid);
+                __syncthreads();
+            } else {
+                // values out in the previous group's arrangement, in again in this one's
+                const B2Group gp = b2_upper_group<K>(INV ? c + 1 : c - 1);
+                const int ep = b2_thread_base(gp, tid);
+                __syncthreads();   // done with the previous tables (the exchange area aliases them)
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = ep | ((r & 1) << gp.s[0]) | (((r >> 1) & 1) << gp.s[1]) | ((r >> 2) << gp.s[2]);
+                    stA[b2_pad(e)] = xa[r];
+                    if (TWO) stB[b2_pad(e)] = xb[r];
+                }
+                b2_upper_basis<K>(g, s_basis, gbase, l, i_lo, T, tid);
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    xa[r] = stA[b2_pad(e)];
+                    if (TWO) xb[r] = stB[b2_pad(e)];
+                }
+                __syncthreads();   // exchange area free for the tables
+            }
+            b2_fill(g, s_tab, s_basis, tid, nth);
+            __syncthreads();
+            b2_upper_compute<K, INV, TWO>(g, xa, xb, s_tab, s_pt, gb_t, i_lo);
+            if (cc == NC - 1) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    const uint64_t j = b2_upper_global<K>(e, gbase, i_lo);
+                    A[j] = xa[r];
+                    if (TWO) B[j] = xb[r];
+                }
+            }
+        }
+    }
+}
