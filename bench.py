@@ -44,7 +44,9 @@ KERNEL_BYTES = {
     "basiscvt_rows": lambda A, B, N: 2 * A,             # one per operand
     "basiscvt_outer_encode": lambda A, B, N: A + N,     # one per operand
     "butterfly_upper": lambda A, B, N: 4 * N,           # A and B together
-    "butterfly_bottom_product": lambda A, B, N: 3 * N,  # read A, B; write C
+    "butterfly_bottom": lambda A, B, N: 4 * N,          # A and B together
+    "pointwise": lambda A, B, N: 3 * N,                 # read A, B; write C
+    "ibutterfly_bottom": lambda A, B, N: 2 * N,
     "ibutterfly_upper": lambda A, B, N: 2 * N,
     "decode_outer": lambda A, B, N: 2 * N,
     "ibasiscvt_rows": lambda A, B, N: 2 * N,
@@ -58,7 +60,7 @@ KERNEL_BYTES = {
 # fetch x2.000, write x1.000), valid only for the kernel sources they were
 # taken on: the sha256 of the listed files must match, else traffic is null.
 MEASURED_TRAFFIC = {
-    "butterfly_bottom_product": {
+    "butterfly_upper": {
         "bytes": (262568 * 2 + 262144) * 1024,
         "sources": ("paper_1803_11301_amd/csrc/k_butterfly.h", "paper_1803_11301_amd/csrc/gf_device.h",
                     "paper_1803_11301_amd/csrc/fpmul.hip"),

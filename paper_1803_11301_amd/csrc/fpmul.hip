@@ -465,16 +465,33 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
             if (rc) return rc;
         }
     }
-    const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - R), persist_bot);
-    if (mode == BF_PRODUCT)
-        KLAUNCH_LDS(ctx, s, "butterfly_bottom_product", k_bfly_bottom<BF_PRODUCT>, bt, blk, bf_bottom_lds(R, true), A,
-                    B, l, R, ctx->tables);
-    else if (mode == BF_FWD)
-        KLAUNCH_LDS(ctx, s, "butterfly_bottom", k_bfly_bottom<BF_FWD>, bt, blk, bf_bottom_lds(R, false), A, B, l, R,
-                    ctx->tables);
-    else
-        KLAUNCH_LDS(ctx, s, "ibutterfly_bottom", k_bfly_bottom<BF_INV>, bt, blk, bf_bottom_lds(R, false), A, B, l, R,
-                    ctx->tables);
+    if (l >= B2_TILE_LG) {
+        // register-resident bottom passes; the pointwise step in between
+        const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - B2_TILE_LG), (uint64_t)ctx->num_cu * 2);
+        if (mode == BF_PRODUCT) {
+            KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD2>, bt, B2_THREADS, A, B, l, ctx->tables);
+            const uint64_t n = 1ull << l;
+            KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
+                                                                                   (uint64_t)ctx->num_cu * 2),
+                    1024, A, B, n, ctx->tables);
+            KLAUNCH(ctx, s, "ibutterfly_bottom", k_bf2_bottom<BF_INV>, bt, B2_THREADS, A, B, l, ctx->tables);
+        } else if (mode == BF_FWD) {
+            KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD>, bt, B2_THREADS, A, B, l, ctx->tables);
+        } else {
+            KLAUNCH(ctx, s, "ibutterfly_bottom", k_bf2_bottom<BF_INV>, bt, B2_THREADS, A, B, l, ctx->tables);
+        }
+    } else {
+        const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - R), persist_bot);
+        if (mode == BF_PRODUCT)
+            KLAUNCH_LDS(ctx, s, "butterfly_bottom_product", k_bfly_bottom<BF_PRODUCT>, bt, blk, bf_bottom_lds(R, true),
+                        A, B, l, R, ctx->tables);
+        else if (mode == BF_FWD)
+            KLAUNCH_LDS(ctx, s, "butterfly_bottom", k_bfly_bottom<BF_FWD>, bt, blk, bf_bottom_lds(R, false), A, B, l,
+                        R, ctx->tables);
+        else
+            KLAUNCH_LDS(ctx, s, "ibutterfly_bottom", k_bfly_bottom<BF_INV>, bt, blk, bf_bottom_lds(R, false), A, B, l,
+                        R, ctx->tables);
+    }
     if (mode != BF_FWD) {
         for (auto it = groups.begin(); it != groups.end(); ++it) {
             const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
@@ -832,8 +849,7 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
         for (int e = 0; e < 256; ++e) D.c15[p][e] = tw.m16(tw.v15, (uint16_t)(e << (8 * p)));
     for (int p = 0; p < 4; ++p)
         for (int e = 0; e < 256; ++e) D.c31[p][e] = tw.m32(tw.v31, (uint32_t)e << (8 * p));
-    for (int bl = 0; bl < 128; ++bl) {
-        const uint64_t beta = H.iota[0][2 * bl];   // iota(2 bl) lies in V_8: one tower byte
+    auto permtab = [&](uint8_t beta, uint32_t *pt) {
         uint8_t g0[8], g1[8], g2[4];
         for (int e = 0; e < 8; ++e) {
             g0[e] = tw.mul8[beta][e];
@@ -843,14 +859,15 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
         auto pack = [](const uint8_t *b) {
             return (uint32_t)b[0] | ((uint32_t)b[1] << 8) | ((uint32_t)b[2] << 16) | ((uint32_t)b[3] << 24);
         };
-        uint32_t *pt = D.pt_beta8[bl];
         pt[0] = pack(g0);
         pt[1] = pack(g0 + 4);
         pt[2] = pack(g1);
         pt[3] = pack(g1 + 4);
         pt[4] = pack(g2);
         pt[5] = pt[6] = pt[7] = 0;
-    }
+    };
+    for (int bl = 0; bl < 128; ++bl) permtab((uint8_t)H.iota[0][2 * bl], D.pt_beta8[bl]);   // iota(2 bl) is in V_8
+    for (int e = 0; e < 256; ++e) permtab((uint8_t)e, D.pt8[e]);
 }
 
 // ---------------------------------------------------------------------------

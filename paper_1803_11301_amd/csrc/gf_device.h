@@ -27,6 +27,7 @@ struct DevTables {
     // v_perm byte tables of beta = iota(2 bl), bl < 128, on the bit groups
     // {0,1,2}, {3,4,5}, {6,7} of a byte: t0lo t0hi t1lo t1hi t2 (3 words pad)
     uint32_t pt_beta8[128][8];
+    uint32_t pt8[256][8];        // the same tables for every byte of V_8
 };
 
 // ----------------------------------------------------------------- tmul ----

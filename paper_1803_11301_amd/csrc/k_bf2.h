@@ -300,3 +300,264 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restric
         }
     }
 }
+
+// ----------------------------------------------------------- bottom pass ---
+//
+// Layers 10 .. 0 on contiguous tiles of 2^11 values (tile bits = global bits
+// 0 .. 10).  Groups of register bits, forward order: {8,9,10}, {5,6,7},
+// {2,3,4}, {0,1} with bit 10 carried.  In layers 0, 1, 2 the 1024 blocks of
+// a tile would need several K tables with beta in V_8, so there the split is
+// K16 + beta16 with beta16 = iota(2 (b mod 2^15)) in V_16:
+//   x * beta16 = beta0 * x + beta1 * (x * v8)   (beta16 = beta1 v8 + beta0),
+// and x * v8 acts on each tower pair (y1 v8 + y0) as
+//   (y0 + y1) v8 + v7 y1      (v8^2 = v8 + v7, Eq. 2).
+
+struct B2Bottom {
+    static constexpr int NC = 4;
+};
+
+__device__ __forceinline__ B2Group b2_bottom_group(int c)
+{
+    B2Group g;
+    if (c < 3) {
+        const int lo = 8 - 3 * c;
+        g.s[0] = lo;
+        g.s[1] = lo + 1;
+        g.s[2] = lo + 2;
+        g.layer[0] = g.layer[1] = g.layer[2] = 1;
+    } else {
+        g.s[0] = 0;
+        g.s[1] = 1;
+        g.s[2] = 10;
+        g.layer[0] = g.layer[1] = 1;
+        g.layer[2] = 0;
+    }
+    return g;
+}
+
+// layers below 3 use the V_16 split
+__device__ __forceinline__ bool b2_wide(int i) { return i < 3; }
+
+// v_perm multiply of the four bytes of w by the byte with tables P
+__device__ __forceinline__ uint32_t b2_pmul32(const uint4 &t01, uint32_t t2, uint32_t w)
+{
+    const uint32_t s0 = w & 0x07070707u, s1 = (w >> 3) & 0x07070707u, s2 = (w >> 6) & 0x03030303u;
+    return xor3(__builtin_amdgcn_perm(t01.y, t01.x, s0), __builtin_amdgcn_perm(t01.w, t01.z, s1),
+                __builtin_amdgcn_perm(t2, t2, s2));
+}
+
+// x * v8 on the two tower pairs of a 32-bit word (tables of v7 in q01, q2)
+__device__ __forceinline__ uint32_t b2_mulv8(const uint4 &q01, uint32_t q2, uint32_t w)
+{
+    const uint32_t sw = __builtin_amdgcn_perm(w, w, 0x02030001u);   // swap the bytes of each pair
+    const uint32_t t = b2_pmul32(q01, q2, sw);                      // v7 * y1 in the low byte of each pair
+    const uint32_t m = 0xFF00FF00u;
+    return (m & (w ^ sw)) | (~m & t);
+}
+
+// acc XOR x * (K16 + beta16): P0, P1 = tables of beta0, beta1; Q = tables of v7
+__device__ __forceinline__ uint64_t b2_mul_acc16(const uint64_t *__restrict__ tab, const uint4 &p0, uint32_t p02,
+                                                 const uint4 &p1, uint32_t p12, const uint4 &q01, uint32_t q2,
+                                                 uint64_t x, uint64_t acc)
+{
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const uint64_t v0 = tab[lo & 255u], v1 = tab[256 + ((lo >> 8) & 255u)];
+    const uint64_t v2 = tab[512 + ((lo >> 16) & 255u)], v3 = tab[768 + (lo >> 24)];
+    const uint64_t v4 = tab[1024 + (hi & 255u)], v5 = tab[1280 + ((hi >> 8) & 255u)];
+    const uint64_t v6 = tab[1536 + ((hi >> 16) & 255u)], v7 = tab[1792 + (hi >> 24)];
+    const uint32_t al = b2_pmul32(p0, p02, lo), ah = b2_pmul32(p0, p02, hi);
+    const uint32_t bl = b2_pmul32(p1, p12, b2_mulv8(q01, q2, lo)), bh = b2_pmul32(p1, p12, b2_mulv8(q01, q2, hi));
+    const uint32_t rl = xor3(xor3((uint32_t)v0, (uint32_t)v1, (uint32_t)v2), xor3((uint32_t)v3, (uint32_t)v4,
+                             (uint32_t)v5), xor3((uint32_t)v6, (uint32_t)v7, al)) ^ bl ^ (uint32_t)acc;
+    const uint32_t rh = xor3(xor3((uint32_t)(v0 >> 32), (uint32_t)(v1 >> 32), (uint32_t)(v2 >> 32)),
+                             xor3((uint32_t)(v3 >> 32), (uint32_t)(v4 >> 32), (uint32_t)(v5 >> 32)),
+                             xor3((uint32_t)(v6 >> 32), (uint32_t)(v7 >> 32), ah)) ^ bh ^ (uint32_t)(acc >> 32);
+    return (uint64_t)rl | ((uint64_t)rh << 32);
+}
+
+// one V_16 layer on register bit M: block of a pair = b_t | register bits
+// above M times bw; beta16 = iota(2 (b mod 2^15)) through the iota tables of
+// the low two bytes (s_io16), then the byte tables of its two tower bytes
+template <int M, bool INV, bool TWO>
+__device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], uint64_t (&xb)[8], const uint64_t *__restrict__ tab,
+                                           const PermTab *__restrict__ s_pt8, const uint16_t (*s_io16)[256],
+                                           const uint4 &q01, uint32_t q2, uint32_t b_t, uint32_t bw1, uint32_t bw2)
+{
+#pragma unroll
+    for (int u = 0; u < (1 << (2 - M)); ++u) {
+        uint32_t b = b_t;
+        if (M == 0) {
+            if (u & 1) b ^= bw1;
+            if (u & 2) b ^= bw2;
+        } else if (M == 1) {
+            if (u & 1) b ^= bw2;
+        }
+        const uint32_t v = (2u * b) & 0xFFFFu;
+        const uint32_t beta = (uint32_t)s_io16[0][v & 255u] ^ (uint32_t)s_io16[1][v >> 8];
+        const PermTab *P0 = s_pt8 + (beta & 255u), *P1 = s_pt8 + (beta >> 8);
+        const uint4 p0 = *reinterpret_cast<const uint4 *>(P0), p1 = *reinterpret_cast<const uint4 *>(P1);
+        const uint32_t p02 = P0->t2, p12 = P1->t2;
+#pragma unroll
+        for (int low = 0; low < (1 << M); ++low) {
+            const int r0 = low | (u << (M + 1)), r1 = r0 | (1 << M);
+            if (!INV) {
+                const uint64_t h0 = b2_mul_acc16(tab, p0, p02, p1, p12, q01, q2, xa[r1], xa[r0]);
+                xa[r1] ^= h0;
+                xa[r0] = h0;
+                if (TWO) {
+                    const uint64_t g0 = b2_mul_acc16(tab, p0, p02, p1, p12, q01, q2, xb[r1], xb[r0]);
+                    xb[r1] ^= g0;
+                    xb[r0] = g0;
+                }
+            } else {
+                const uint64_t p = xa[r0] ^ xa[r1];
+                xa[r0] = b2_mul_acc16(tab, p0, p02, p1, p12, q01, q2, p, xa[r0]);
+                xa[r1] = p;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void b2_bottom_basis(const B2Group &g, uint64_t (*s_basis)[64], uint64_t gbase, int l,
+                                                const DevTables *__restrict__ T, int tid)
+{
+    const int m = tid >> 6;
+    if (m < 3 && g.layer[m]) {
+        const int i = g.s[m];
+        // K = 2^(32+d) + (b >> 7) << 8 (V_8 split) or 2^(32+d) + (b >> 15) << 16 (V_16 split)
+        const uint32_t bh = b2_wide(i) ? (uint32_t)(gbase >> (i + 16)) << 8 : (uint32_t)(gbase >> (i + 8));
+        ktable_basis(s_basis[m], l - i, bh, T, tid & 63);
+    }
+}
+
+template <bool INV, bool TWO>
+__device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&xa)[8], uint64_t (&xb)[8],
+                                                  uint64_t (*s_tab)[2048], const PermTab *s_ptb,
+                                                  const PermTab *s_pt8, const uint16_t (*s_io16)[256],
+                                                  const uint4 &q01, uint32_t q2, uint64_t gb_t)
+{
+    auto run = [&](auto Mc) {
+        constexpr int M = decltype(Mc)::value;
+        if (!g.layer[M]) return;
+        const int i = g.s[M];
+        if (b2_wide(i)) {
+            const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
+            const uint32_t bw1 = (1u << g.s[1]) >> (i + 1), bw2 = (1u << g.s[2]) >> (i + 1);
+            b2_layer16<M, INV, TWO>(xa, xb, s_tab[M], s_pt8, s_io16, q01, q2, b_t, bw1 & 0x7FFFu, bw2 & 0x7FFFu);
+        } else {
+            const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
+            const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 127u, bw2 = ((1u << g.s[2]) >> (i + 1)) & 127u;
+            b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_ptb, bl_t, bw1, bw2);
+        }
+    };
+    if (!INV) {
+        run(std::integral_constant<int, 2>());
+        run(std::integral_constant<int, 1>());
+        run(std::integral_constant<int, 0>());
+    } else {
+        run(std::integral_constant<int, 0>());
+        run(std::integral_constant<int, 1>());
+        run(std::integral_constant<int, 2>());
+    }
+}
+
+// MODE: BF_FWD (A), BF_FWD2 (A and B), BF_INV (A); l >= 11; grid <= 2^(l-11)
+template <int MODE>
+__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
+                                                              int l, const DevTables *__restrict__ T)
+{
+    constexpr bool INV = MODE == BF_INV, TWO = MODE == BF_FWD2;
+    constexpr int NC = B2Bottom::NC;
+    __shared__ __align__(16) uint64_t s_tab[3][2048];   // K tables; the exchange area aliases them
+    __shared__ __align__(16) PermTab s_ptb[128];        // tables of iota(2 bl), bl < 128
+    __shared__ __align__(16) PermTab s_pt8[256];        // tables of every byte of V_8
+    __shared__ uint16_t s_io16[2][256];                 // iota of the low two Cantor bytes (V_16)
+    __shared__ uint64_t s_basis[3][64];
+    uint64_t *stA = &s_tab[0][0], *stB = stA + B2_STAGE_WORDS;
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    for (int q = tid; q < 128 * 8; q += nth)
+        reinterpret_cast<uint32_t *>(s_ptb)[q] = reinterpret_cast<const uint32_t *>(T->pt_beta8)[q];
+    for (int q = tid; q < 256 * 8; q += nth)
+        reinterpret_cast<uint32_t *>(s_pt8)[q] = reinterpret_cast<const uint32_t *>(T->pt8)[q];
+    for (int q = tid; q < 2 * 256; q += nth) (&s_io16[0][0])[q] = (uint16_t)(&T->iota[0][0])[q];
+    __syncthreads();
+    const PermTab *Q = s_pt8 + 0x80;   // v_7 = Cantor byte 0x80
+    const uint4 q01 = *reinterpret_cast<const uint4 *>(Q);
+    const uint32_t q2 = Q->t2;
+
+    const uint64_t ntiles = 1ull << (l - B2_TILE_LG);
+    uint64_t xa[8], xb[8];
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t gbase = tile << B2_TILE_LG;
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) {
+            const int c = INV ? NC - 1 - cc : cc;
+            const B2Group g = b2_bottom_group(c);
+            const int e_t = b2_thread_base(g, tid);
+            const uint64_t gb_t = gbase | (uint64_t)e_t;
+            if (cc == 0) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    xa[r] = A[gbase | (uint64_t)e];
+                    if (TWO) xb[r] = B[gbase | (uint64_t)e];
+                }
+                __syncthreads();   // the previous tile is done with the tables
+                b2_bottom_basis(g, s_basis, gbase, l, T, tid);
+                __syncthreads();
+            } else {
+                const B2Group gp = b2_bottom_group(INV ? c + 1 : c - 1);
+                const int ep = b2_thread_base(gp, tid);
+                __syncthreads();   // done with the previous tables (the exchange area aliases them)
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = ep | ((r & 1) << gp.s[0]) | (((r >> 1) & 1) << gp.s[1]) | ((r >> 2) << gp.s[2]);
+                    stA[b2_pad(e)] = xa[r];
+                    if (TWO) stB[b2_pad(e)] = xb[r];
+                }
+                b2_bottom_basis(g, s_basis, gbase, l, T, tid);
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    xa[r] = stA[b2_pad(e)];
+                    if (TWO) xb[r] = stB[b2_pad(e)];
+                }
+                __syncthreads();   // exchange area free for the tables
+            }
+            b2_fill(g, s_tab, s_basis, tid, nth);
+            __syncthreads();
+            b2_bottom_compute<INV, TWO>(g, xa, xb, s_tab, s_ptb, s_pt8, s_io16, q01, q2, gb_t);
+            if (cc == NC - 1) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    A[gbase | (uint64_t)e] = xa[r];
+                    if (TWO) B[gbase | (uint64_t)e] = xb[r];
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ pointwise ---
+// A[j] = A[j] * B[j] (Alg. 5, the pointwise step), tower Karatsuba with the
+// GF(2^8) table in LDS (Mul8View layout)
+__global__ __launch_bounds__(1024) void k_pointwise(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
+                                                    uint64_t n, const DevTables *__restrict__ T)
+{
+    __shared__ __align__(16) uint8_t s_m8[M8V_BYTES];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_m8);
+    for (int idx = tid; idx < 256 * 16; idx += nth) {
+        const int a = idx >> 4, c = idx & 15;   // row a, 16-byte column c
+        dst[((a & 1) << 11) | ((a >> 1) << 4) | c] = src[idx];
+    }
+    for (int q = tid; q < 512; q += nth) reinterpret_cast<uint16_t *>(s_m8 + M8V_OFF_C15)[q] = (&T->c15[0][0])[q];
+    for (int q = tid; q < 1024; q += nth) reinterpret_cast<uint32_t *>(s_m8 + M8V_OFF_C31)[q] = (&T->c31[0][0])[q];
+    __syncthreads();
+    const Mul8View mv{s_m8};
+    for (uint64_t j = (uint64_t)blockIdx.x * nth + tid; j < n; j += (uint64_t)gridDim.x * nth) A[j] = mv.m64(A[j], B[j]);
+}
