@@ -725,6 +725,18 @@ static int basiscvt_body(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int
 // batch
 // ---------------------------------------------------------------------------
 
+// the compile-time step table of the inner conversion must be the recursion's
+static int check_bc16_table()
+{
+    std::vector<BStep> v;
+    bcvt_steps(1ull << 16, 1, v);
+    if ((int)v.size() != BC16_NSTEPS) return fail(POLYMUL_EIO, "inner BasisCvt step table has the wrong length");
+    for (int k = 0; k < BC16_NSTEPS; ++k)
+        if (v[k].S != (1ull << bc16_lgs[k]) || v[k].d != (1ull << bc16_lgd[k]))
+            return fail(POLYMUL_EIO, "inner BasisCvt step table differs from the recursion at step " + std::to_string(k));
+    return 0;
+}
+
 static int batch_steps_upload(polymul_ctx *ctx)
 {
     if (ctx->bsteps) return 0;
@@ -889,6 +901,7 @@ int polymul_ctx_create(polymul_ctx **out, int device, size_t workspace_cap)
     if (device < 0 || device >= ndev) return fail(POLYMUL_EINVAL, "no such device");
     DeviceGuard g(device);
     HIP_TRY(g.err);
+    if (int rc = check_bc16_table()) return rc;
     std::unique_ptr<fpmul_host::Tables> H(new fpmul_host::Tables());
     std::unique_ptr<DevTables> D(new DevTables());
     try {

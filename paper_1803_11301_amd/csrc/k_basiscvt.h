@@ -129,6 +129,130 @@ __device__ void bc_row_steps(uint64_t *row, int nwords, const BcSteps &st, bool 
     }
 }
 
+// ---------------------------------------- BasisCvt(2^16) on rows, fixed ---
+//
+// The inner conversion always has 2^16 bits, so its 32 Taylor steps are
+// compile-time constants (log2 S, log2 d), in the order the recursion of
+// Alg. 1 produces them (the host checks this table against its generator).
+#define BC16_NSTEPS 32
+static constexpr uint8_t bc16_lgs[BC16_NSTEPS] = {16, 15, 14, 13, 12, 11, 10, 9, 16, 15, 14, 13, 16, 15, 16, 14,
+                                                      12, 11, 12, 10, 8,  7,  6,  5, 8,  7,  8,  6,  4,  3,  4,  2};
+static constexpr uint8_t bc16_lgd[BC16_NSTEPS] = {7,  6,  5,  4,  3, 2, 1, 0, 11, 10, 9, 8, 13, 12, 14, 12,
+                                                      9,  8,  10, 8,  3, 2, 1, 0, 5,  4,  6, 4, 1,  0,  2,  0};
+
+// masks of an in-word step: low half and low d bits of every S-bit segment
+__host__ __device__ constexpr uint64_t bc16_mask(int S, int m)
+{
+    uint64_t r = 0;
+    for (int b = 0; b < 64; ++b)
+        if (b % S < m) r |= 1ull << b;
+    return r;
+}
+
+template <int LGS, int LGD, bool INV>
+__device__ __forceinline__ uint64_t bc16_inword(uint64_t x)
+{
+    constexpr int S = 1 << LGS, H = S / 2, d = 1 << LGD;
+    constexpr uint64_t L = bc16_mask(S, H), D = bc16_mask(S, d);
+    uint64_t lo = x & L, hi = (x >> H) & L;
+    if (!INV) {
+        hi ^= (hi >> (H - d)) & D;
+        lo ^= (hi << d) & L;
+    } else {
+        lo ^= (hi << d) & L;
+        hi ^= (hi >> (H - d)) & D;
+    }
+    return lo | (hi << H);
+}
+
+// one cross-word step (S >= 128 bits) on nrows rows of 1024 words; phase A
+// fixes hi[0, d) from hi[H - d, H), phase B adds hi[0, H - d) into lo[d, H)
+template <int LGS, int LGD, int PHASE>
+__device__ __forceinline__ void bc16_cross_phase(uint64_t *rows, int nrows, int tid, int nth)
+{
+    constexpr int S = 1 << LGS, H = S / 2, d = 1 << LGD;
+    constexpr int SW = S / 64, HW = SW / 2, NSEG = 1024 / SW;
+    if (PHASE == 0) {
+        constexpr int NA = (d + 63) / 64;                 // hi words written
+        const int nt = nrows * NSEG * NA;
+        for (int t = tid; t < nt; t += nth) {
+            const int k = t % NA, sg = t / NA;
+            uint64_t *hp = rows + sg * SW + HW;
+            if (d % 64 == 0) {
+                hp[k] ^= hp[k + (H - d) / 64];
+            } else {
+                // d < 64: bits [H - d, H) of hi into hi[0, d)
+                hp[0] ^= (hp[HW - 1] >> (64 - d));
+            }
+        }
+    } else {
+        constexpr int dw = d / 64, ds = d % 64;
+        constexpr int NB = HW - dw;                        // lo words written
+        const int nt = nrows * NSEG * NB;
+        for (int t = tid; t < nt; t += nth) {
+            const int q = dw + t % NB, sg = t / NB;
+            uint64_t *lp = rows + sg * SW, *hp = lp + HW;
+            uint64_t v = hp[q - dw];
+            if (ds) {
+                v <<= ds;
+                if (q - dw - 1 >= 0) v |= hp[q - dw - 1] >> (64 - ds);
+            }
+            lp[q] ^= v;
+        }
+    }
+}
+
+template <int K, bool INV>
+__device__ __forceinline__ void bc16_step(uint64_t *rows, int nrows, int tid, int nth);
+
+// runs of in-word steps [K, KE) are applied to every word at once
+template <int K, int KE, bool INV>
+__device__ __forceinline__ uint64_t bc16_inword_run(uint64_t x)
+{
+    if constexpr (K < KE) {
+        constexpr int k = INV ? BC16_NSTEPS - 1 - K : K;
+        x = bc16_inword<bc16_lgs[k], bc16_lgd[k], INV>(x);
+        return bc16_inword_run<K + 1, KE, INV>(x);
+    } else {
+        return x;
+    }
+}
+
+__host__ __device__ constexpr int bc16_run_end(int K, bool inv)
+{
+    int e = K;
+    while (e < BC16_NSTEPS && bc16_lgs[inv ? BC16_NSTEPS - 1 - e : e] <= 6) ++e;
+    return e;
+}
+
+template <int K, bool INV>
+__device__ __forceinline__ void bc16_steps_from(uint64_t *rows, int nrows, int tid, int nth)
+{
+    if constexpr (K < BC16_NSTEPS) {
+        constexpr int k = INV ? BC16_NSTEPS - 1 - K : K;
+        constexpr int LGS = bc16_lgs[k], LGD = bc16_lgd[k];
+        if constexpr (LGS <= 6) {
+            constexpr int KE = bc16_run_end(K, INV);
+            for (int w = tid; w < nrows * 1024; w += nth) rows[w] = bc16_inword_run<K, KE, INV>(rows[w]);
+            __syncthreads();
+            bc16_steps_from<KE, INV>(rows, nrows, tid, nth);
+        } else {
+            bc16_cross_phase<LGS, LGD, INV ? 1 : 0>(rows, nrows, tid, nth);
+            __syncthreads();
+            bc16_cross_phase<LGS, LGD, INV ? 0 : 1>(rows, nrows, tid, nth);
+            __syncthreads();
+            bc16_steps_from<K + 1, INV>(rows, nrows, tid, nth);
+        }
+    }
+}
+
+// BasisCvt(2^16) (or its inverse) on nrows rows of 1024 words in LDS
+template <bool INV>
+__device__ __forceinline__ void bc16_rows(uint64_t *rows, int nrows, int tid, int nth)
+{
+    bc16_steps_from<0, INV>(rows, nrows, tid, nth);
+}
+
 // Alg. 1 steps with whole elements (the outer conversion on a column vector of
 // R = 2^lgR elements of type T in LDS), in place.
 template <typename T>
@@ -267,7 +391,7 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *
             rows[e] = v;
         }
         __syncthreads();
-        bc_row_steps(rows, T * BC_TAU_WORDS, inner, false, tid, nth);
+        bc16_rows<false>(rows, T, tid, nth);
         for (int e = tid; e < T * BC_TAU_WORDS; e += nth) {
             const int k = e % T, w = e / T;
             Y[(uint64_t)w * R + q0 + k] = rows[k * BC_TAU_WORDS + w];
@@ -397,7 +521,7 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *
             reinterpret_cast<uint32_t *>(rows)[k * 2 * BC_TAU_WORDS + c] = Y32[(uint64_t)c * R + q0 + k];
         }
         __syncthreads();
-        bc_row_steps(rows, T * BC_TAU_WORDS, inner, true, tid, nth);
+        bc16_rows<true>(rows, T, tid, nth);
         for (int e = tid; e < T * EW; e += nth) {
             const int k = e / EW, w = e % EW, q = q0 + k;
             X[(uint64_t)q * EW + w] = bc_bits(rows + k * BC_TAU_WORDS, BC_TAU_WORDS, 64L * w - q);
