@@ -591,8 +591,21 @@ static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t
         if ((1 << (nb + lgWc)) > BC_ZETA_LDS) return fail(POLYMUL_EINVAL, "zeta tile exceeds LDS");
         const uint64_t tiles = (1ull << (lgR - nb)) * (uint64_t)(EW >> lgWc);
         const unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->num_cu * 8);
-        KLAUNCH(ctx, s, skew_first ? "basiscvt_zeta" : "ibasiscvt_zeta", k_bc_zeta, grid, BC_THREADS, X, in, len,
-                lgR, EW, b0, nb, lgWc, (pass == 0 && skew_first && in) ? 1 : 0);
+        const char *name = skew_first ? "basiscvt_zeta" : "ibasiscvt_zeta";
+        const int skew = (pass == 0 && skew_first && in) ? 1 : 0;
+        if (nb >= 6 && nb <= 8 && (EW % (1 << (12 - nb))) == 0) {
+            // register-resident tiles of 2^12 words
+            const uint64_t rt = (1ull << (lgR - nb)) * (uint64_t)(EW >> (12 - nb));
+            const unsigned g = (unsigned)std::min<uint64_t>(rt, (uint64_t)ctx->num_cu * 8);
+            if (nb == 8)
+                KLAUNCH(ctx, s, name, k_bc_zeta_r<8>, g, 256, X, in, len, lgR, EW, b0, skew);
+            else if (nb == 7)
+                KLAUNCH(ctx, s, name, k_bc_zeta_r<7>, g, 256, X, in, len, lgR, EW, b0, skew);
+            else
+                KLAUNCH(ctx, s, name, k_bc_zeta_r<6>, g, 256, X, in, len, lgR, EW, b0, skew);
+            continue;
+        }
+        KLAUNCH(ctx, s, name, k_bc_zeta, grid, BC_THREADS, X, in, len, lgR, EW, b0, nb, lgWc, skew);
     }
     return 0;
 }

@@ -349,6 +349,121 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_zeta(uint64_t *__restrict__ X
     }
 }
 
+// The same superset sums with the values in registers: a tile of 2^12 words
+// (2^NB rows by 2^(12-NB) words, NB in 6..8); each of 256 threads holds 16
+// values spanning four tile bits.  Pass A sums over the low four row bits
+// in registers, the tile is exchanged through LDS, pass B sums over the
+// remaining NB - 4 row bits (its other register bits are the top column
+// bits).  Tile bits: words 0 .. 11-NB, rows 12-NB .. 11.
+template <int NB>
+struct BcZetaR {
+    static constexpr int LGW = 12 - NB;
+    // register tile bits of pass P (ascending)
+    static constexpr int reg(int P, int v)
+    {
+        if (P == 0) return LGW + v;
+        const int nrow = NB - 4;                       // row bits of pass B
+        const int ncarry = 4 - nrow;                   // top column bits as padding
+        return v < ncarry ? LGW - ncarry + v : LGW + 4 + (v - ncarry);
+    }
+    static constexpr bool is_row(int P, int v) { return reg(P, v) >= LGW; }
+};
+
+template <int NB, int P>
+__device__ __forceinline__ int bcz_base(int t)
+{
+    int e = 0, q = 0;
+#pragma unroll
+    for (int b = 0; b < 12; ++b) {
+        bool r = false;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) r |= BcZetaR<NB>::reg(P, v) == b;
+        if (r) continue;
+        e |= ((t >> q) & 1) << b;
+        ++q;
+    }
+    return e;
+}
+
+template <int NB, int P>
+__device__ __forceinline__ int bcz_elem(int base, int v)
+{
+    int e = base;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) e |= ((v >> m) & 1) << BcZetaR<NB>::reg(P, m);
+    return e;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_bc_zeta_r(uint64_t *__restrict__ X, const uint64_t *__restrict__ in,
+                                                   uint64_t len, int lgR, int EW, int b0, int skew_in)
+{
+    using Z = BcZetaR<NB>;
+    constexpr int LGW = Z::LGW;
+    __shared__ uint64_t s[4096 + 512];
+    const int tid = threadIdx.x;
+    const int ncolt = EW >> LGW;
+    const uint64_t ntiles = (1ull << (lgR - NB)) * (uint64_t)ncolt;
+    const uint64_t inwords = (len + 63) / 64;
+    const int eA = bcz_base<NB, 0>(tid), eB = bcz_base<NB, 1>(tid);
+    uint64_t x[16];
+    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int ct = (int)(tile % ncolt);
+        const uint64_t rt = tile / ncolt;
+        const uint64_t rlow = rt & ((1ull << b0) - 1), rhigh = rt >> b0;
+        const int w0 = ct << LGW;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int e = bcz_elem<NB, 0>(eA, v), k = e >> LGW, w = w0 + (e & ((1 << LGW) - 1));
+            const uint64_t r = (rhigh << (b0 + NB)) | ((uint64_t)k << b0) | rlow;
+            if (skew_in) {
+                // stored word w of row r = bits [64 w - r, 64 w - r + 64) of the input row r
+                const long off = 64L * w - (long)r;
+                const uint64_t rb = r * BC_TAU_WORDS;
+                const long i0 = off >> 6;
+                const int sh = (int)(off & 63);
+                uint64_t a = 0, b = 0;
+                if (i0 >= 0 && i0 < BC_TAU_WORDS && rb + i0 < inwords) a = in[rb + i0];
+                if (i0 + 1 >= 0 && i0 + 1 < BC_TAU_WORDS && rb + i0 + 1 < inwords) b = in[rb + i0 + 1];
+                if ((len & 63) && i0 >= 0 && rb + i0 == inwords - 1) a &= (~0ull) >> (64 - (len & 63));
+                if ((len & 63) && i0 + 1 >= 0 && rb + i0 + 1 == inwords - 1) b &= (~0ull) >> (64 - (len & 63));
+                x[v] = sh ? ((a >> sh) | (b << (64 - sh))) : a;
+            } else {
+                x[v] = X[r * EW + w];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+                if (!((v >> t) & 1)) x[v] ^= x[v | (1 << t)];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int e = bcz_elem<NB, 0>(eA, v);
+            s[e + (e >> 3)] = x[v];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int e = bcz_elem<NB, 1>(eB, v);
+            x[v] = s[e + (e >> 3)];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (Z::is_row(1, t))
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+                    if (!((v >> t) & 1)) x[v] ^= x[v | (1 << t)];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int e = bcz_elem<NB, 1>(eB, v), k = e >> LGW, w = w0 + (e & ((1 << LGW) - 1));
+            const uint64_t r = (rhigh << (b0 + NB)) | ((uint64_t)k << b0) | rlow;
+            X[r * EW + w] = x[v];
+        }
+        __syncthreads();   // the exchange area is reused by the next tile
+    }
+}
+
 // ------------------------------------ forward: unskew, carry, inner --------
 //
 // Rows q of X (skewed, superset-summed) -> digits h_q -> inner BasisCvt(2^16)
