@@ -747,6 +747,15 @@ static int check_bc16_table()
     for (int k = 0; k < BC16_NSTEPS; ++k)
         if (v[k].S != (1ull << bc16_lgs[k]) || v[k].d != (1ull << bc16_lgd[k]))
             return fail(POLYMUL_EIO, "inner BasisCvt step table differs from the recursion at step " + std::to_string(k));
+    for (int lg = 6; lg <= 15; ++lg) {
+        std::vector<BStep> w;
+        bcvt_steps(1ull << lg, 1, w);
+        const BcStepList L = bc_steps_of(lg);
+        if ((int)w.size() != L.n) return fail(POLYMUL_EIO, "element step list has the wrong length");
+        for (int k = 0; k < L.n; ++k)
+            if (w[k].S != (1ull << L.lgs[k]) || w[k].d != (1ull << L.lgd[k]))
+                return fail(POLYMUL_EIO, "element step list differs from the recursion");
+    }
     return 0;
 }
 

@@ -464,6 +464,113 @@ __global__ __launch_bounds__(256) void k_bc_zeta_r(uint64_t *__restrict__ X, con
     }
 }
 
+// ----------------------------- element steps with compile-time lengths ---
+//
+// The Taylor steps of BasisCvt(2^LGR) on whole elements, generated at compile
+// time by the recursion of Alg. 1 (the host checks them against its own
+// generator for every LGR used).
+struct BcStepList {
+    int n;
+    uint8_t lgs[64], lgd[64];
+};
+
+__host__ __device__ constexpr void bc_gen(BcStepList &L, int lgN, int lge)
+{
+    if (lgN <= 1) return;
+    int lgtau = 1;
+    while (2 * lgtau <= lgN - 1) lgtau *= 2;
+    for (int lgS = lgN; lgS >= lgtau + 1; --lgS) {
+        L.lgs[L.n] = (uint8_t)(lgS + lge);
+        L.lgd[L.n] = (uint8_t)(lgS - lgtau - 1 + lge);
+        L.n++;
+    }
+    bc_gen(L, lgN - lgtau, lgtau + lge);
+    bc_gen(L, lgtau, lge);
+}
+
+__host__ __device__ constexpr BcStepList bc_steps_of(int lgN)
+{
+    BcStepList L{};
+    L.n = 0;
+    bc_gen(L, lgN, 0);
+    return L;
+}
+
+template <int LGR>
+struct BcElemSteps {
+    static constexpr BcStepList L = bc_steps_of(LGR);
+};
+
+template <int LGS, int LGD, int PHASE, typename T>
+__device__ __forceinline__ void bc_elem_phase(T *v, int lgR, int tid, int nth)
+{
+    constexpr int H = 1 << (LGS - 1), d = 1 << LGD;
+    if (PHASE == 0) {
+        // hi[0, d) ^= hi[H - d, H) in every segment
+        const int nt = 1 << (lgR - LGS + LGD);
+        for (int t = tid; t < nt; t += nth) {
+            const int sg = t >> LGD, p = t & (d - 1);
+            T *hp = v + (sg << LGS) + H;
+            hp[p] ^= hp[p + H - d];
+        }
+    } else {
+        // lo[d, H) ^= hi[0, H - d)
+        constexpr int LGW = (LGS - 1) > LGD ? 0 : 0;
+        (void)LGW;
+        const int per = H - d;                                // elements per segment
+        const int nt = (1 << (lgR - LGS)) * per;
+        for (int t = tid; t < nt; t += nth) {
+            const int sg = t / per, p = d + t % per;
+            T *lp = v + (sg << LGS);
+            lp[p] ^= lp[H + p - d];
+        }
+    }
+}
+
+template <int LGR, int K, bool INV, typename T>
+__device__ __forceinline__ void bc_elem_steps_from(T *v, int tid, int nth)
+{
+    constexpr BcStepList L = BcElemSteps<LGR>::L;
+    if constexpr (K < L.n) {
+        constexpr int k = INV ? L.n - 1 - K : K;
+        constexpr int LGS = L.lgs[k], LGD = L.lgd[k];
+        bc_elem_phase<LGS, LGD, INV ? 1 : 0>(v, LGR, tid, nth);
+        __syncthreads();
+        bc_elem_phase<LGS, LGD, INV ? 0 : 1>(v, LGR, tid, nth);
+        __syncthreads();
+        bc_elem_steps_from<LGR, K + 1, INV>(v, tid, nth);
+    }
+}
+
+// BasisCvt(2^lgR) on the elements of a column in LDS; compile-time steps for
+// lgR in 6 .. 15, the run-time list otherwise
+template <typename T>
+__device__ __forceinline__ void bc_elem_steps_any(T *v, int lgR, const BcSteps &st, bool inverse, int tid, int nth)
+{
+#define BC_ELEM_CASE(R)                                                         \
+    case R:                                                                     \
+        if (inverse)                                                            \
+            bc_elem_steps_from<R, 0, true>(v, tid, nth);                        \
+        else                                                                    \
+            bc_elem_steps_from<R, 0, false>(v, tid, nth);                       \
+        return;
+    switch (lgR) {
+        BC_ELEM_CASE(6)
+        BC_ELEM_CASE(7)
+        BC_ELEM_CASE(8)
+        BC_ELEM_CASE(9)
+        BC_ELEM_CASE(10)
+        BC_ELEM_CASE(11)
+        BC_ELEM_CASE(12)
+        BC_ELEM_CASE(13)
+        BC_ELEM_CASE(14)
+        BC_ELEM_CASE(15)
+    default:
+        bc_elem_steps<T>(v, lgR, st, inverse, tid, nth);
+    }
+#undef BC_ELEM_CASE
+}
+
 // ------------------------------------ forward: unskew, carry, inner --------
 //
 // Rows q of X (skewed, superset-summed) -> digits h_q -> inner BasisCvt(2^16)
@@ -551,7 +658,7 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64
     for (int c = blockIdx.x; c < BC_TAU_WORDS; c += gridDim.x) {
         for (int r = tid; r < R; r += nth) col[r] = Y[(uint64_t)c * R + r];
         __syncthreads();
-        bc_elem_steps<uint64_t>(col, lgR, outer, false, tid, nth);
+        bc_elem_steps_any<uint64_t>(col, lgR, outer, false, tid, nth);
         for (int r0 = wave; r0 < rows_per_j; r0 += nwave) {
             const int rr = lane * rows_per_j + r0;         // row of Encode input row j = lane
             uint64_t x = rr < R ? col[rr] : 0ull;
@@ -616,7 +723,7 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
             }
         }
         __syncthreads();
-        bc_elem_steps<uint32_t>(col, lgR, outer, true, tid, nth);
+        bc_elem_steps_any<uint32_t>(col, lgR, outer, true, tid, nth);
         for (int r = tid; r < R; r += nth) Y32[(uint64_t)c * R + r] = col[r];
         __syncthreads();
     }
