@@ -63,20 +63,41 @@ __device__ __forceinline__ uint64_t b2_mul_acc(const uint64_t *__restrict__ tab,
 // index of a pair is b_t | (register bits above M) * bw, beta = iota(2 (b mod 128)).
 template <int M, bool INV, bool TWO>
 __device__ __forceinline__ void b2_layer(uint64_t (&xa)[8], uint64_t (&xb)[8], const uint64_t *__restrict__ tab,
-                                         const PermTab *__restrict__ s_pt, uint32_t bl_t, uint32_t bw1, uint32_t bw2)
+                                         const PermTab *__restrict__ s_pt, const DevTables *__restrict__ T,
+                                         uint32_t bl_t, uint32_t bw1, uint32_t bw2)
 {
+    // tables of the thread's beta from LDS; those of the blocks that differ in
+    // register bits above M follow by linearity: tab(beta + beta') = tab(beta) +
+    // tab(beta'), with beta' = iota(2 bw) the same for the whole workgroup
+    const PermTab *P = s_pt + (bl_t & 127u);
+    const uint4 b01 = *reinterpret_cast<const uint4 *>(P);
+    const uint32_t b2 = P->t2;
+    uint4 c01[2] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+    uint32_t c2[2] = {0, 0};
+    if (M == 0) {
+        const uint32_t *q1 = T->pt_beta8[bw1], *q2 = T->pt_beta8[bw2];
+        c01[0] = make_uint4(q1[0], q1[1], q1[2], q1[3]);
+        c2[0] = q1[4];
+        c01[1] = make_uint4(q2[0], q2[1], q2[2], q2[3]);
+        c2[1] = q2[4];
+    } else if (M == 1) {
+        const uint32_t *q2 = T->pt_beta8[bw2];
+        c01[0] = make_uint4(q2[0], q2[1], q2[2], q2[3]);
+        c2[0] = q2[4];
+    }
 #pragma unroll
     for (int u = 0; u < (1 << (2 - M)); ++u) {
-        uint32_t bl = bl_t;
-        if (M == 0) {
-            if (u & 1) bl ^= bw1;
-            if (u & 2) bl ^= bw2;
-        } else if (M == 1) {
-            if (u & 1) bl ^= bw2;
-        }
-        const PermTab *P = s_pt + (bl & 127u);
-        const uint4 t01 = *reinterpret_cast<const uint4 *>(P);
-        const uint32_t t2 = P->t2;
+        uint4 t01 = b01;
+        uint32_t t2 = b2;
+#pragma unroll
+        for (int q = 0; q < 2 - M; ++q)
+            if ((u >> q) & 1) {
+                t01.x ^= c01[q].x;
+                t01.y ^= c01[q].y;
+                t01.z ^= c01[q].z;
+                t01.w ^= c01[q].w;
+                t2 ^= c2[q];
+            }
 #pragma unroll
         for (int low = 0; low < (1 << M); ++low) {
             const int r0 = low | (u << (M + 1)), r1 = r0 | (1 << M);
@@ -200,7 +221,7 @@ __device__ __forceinline__ void b2_fill(const B2Group &g, uint64_t (*s_tab)[2048
 template <int K, bool INV, bool TWO>
 __device__ __forceinline__ void b2_upper_compute(const B2Group &g, uint64_t (&xa)[8], uint64_t (&xb)[8],
                                                  uint64_t (*s_tab)[2048], const PermTab *s_pt, uint64_t gb_t,
-                                                 int i_lo)
+                                                 int i_lo, const DevTables *__restrict__ T)
 {
     constexpr int LGW = B2Upper<K>::LGW;
     // global weights of the register bits
@@ -213,7 +234,7 @@ __device__ __forceinline__ void b2_upper_compute(const B2Group &g, uint64_t (&xa
         const int i = i_lo + g.s[M] - LGW;
         const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
         const uint32_t bw1 = (uint32_t)(gw[1] >> (i + 1)) & 127u, bw2 = (uint32_t)(gw[2] >> (i + 1)) & 127u;
-        b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_pt, bl_t, bw1, bw2);
+        b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_pt, T, bl_t, bw1, bw2);
     };
     if (!INV) {
         run(std::integral_constant<int, 2>());
@@ -228,8 +249,9 @@ __device__ __forceinline__ void b2_upper_compute(const B2Group &g, uint64_t (&xa
 
 // MODE: BF_FWD (A), BF_FWD2 (A and B, same multipliers), BF_INV (A)
 template <int MODE, int K>
-__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
-                                                             int l, int i_lo, const DevTables *__restrict__ T)
+__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restrict__ A,
+                                                                          uint64_t *__restrict__ B, int l, int i_lo,
+                                                                          const DevTables *__restrict__ T)
 {
     constexpr bool INV = MODE == BF_INV, TWO = MODE == BF_FWD2;
     constexpr int NC = B2Upper<K>::NC, LGW = B2Upper<K>::LGW;
@@ -287,7 +309,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restric
             }
             b2_fill(g, s_tab, s_basis, tid, nth);
             __syncthreads();
-            b2_upper_compute<K, INV, TWO>(g, xa, xb, s_tab, s_pt, gb_t, i_lo);
+            b2_upper_compute<K, INV, TWO>(g, xa, xb, s_tab, s_pt, gb_t, i_lo, T);
             if (cc == NC - 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
@@ -434,7 +456,8 @@ template <bool INV, bool TWO>
 __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&xa)[8], uint64_t (&xb)[8],
                                                   uint64_t (*s_tab)[2048], const PermTab *s_ptb,
                                                   const PermTab *s_pt8, const uint16_t (*s_io16)[256],
-                                                  const uint4 &q01, uint32_t q2, uint64_t gb_t)
+                                                  const uint4 &q01, uint32_t q2, uint64_t gb_t,
+                                                  const DevTables *__restrict__ T)
 {
     auto run = [&](auto Mc) {
         constexpr int M = decltype(Mc)::value;
@@ -447,7 +470,7 @@ __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&x
         } else {
             const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
             const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 127u, bw2 = ((1u << g.s[2]) >> (i + 1)) & 127u;
-            b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_ptb, bl_t, bw1, bw2);
+            b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_ptb, T, bl_t, bw1, bw2);
         }
     };
     if (!INV) {
@@ -463,8 +486,9 @@ __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&x
 
 // MODE: BF_FWD (A), BF_FWD2 (A and B), BF_INV (A); l >= 11; grid <= 2^(l-11)
 template <int MODE>
-__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
-                                                              int l, const DevTables *__restrict__ T)
+__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restrict__ A,
+                                                                           uint64_t *__restrict__ B, int l,
+                                                                           const DevTables *__restrict__ T)
 {
     constexpr bool INV = MODE == BF_INV, TWO = MODE == BF_FWD2;
     constexpr int NC = B2Bottom::NC;
@@ -528,7 +552,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
             }
             b2_fill(g, s_tab, s_basis, tid, nth);
             __syncthreads();
-            b2_bottom_compute<INV, TWO>(g, xa, xb, s_tab, s_ptb, s_pt8, s_io16, q01, q2, gb_t);
+            b2_bottom_compute<INV, TWO>(g, xa, xb, s_tab, s_ptb, s_pt8, s_io16, q01, q2, gb_t, T);
             if (cc == NC - 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
