@@ -61,10 +61,10 @@ KERNEL_BYTES = {
 # taken on: the sha256 of the listed files must match, else traffic is null.
 MEASURED_TRAFFIC = {
     "butterfly_upper": {
-        "bytes": (262568 * 2 + 262144) * 1024,
-        "sources": ("paper_1803_11301_amd/csrc/k_butterfly.h", "paper_1803_11301_amd/csrc/gf_device.h",
-                    "paper_1803_11301_amd/csrc/fpmul.hip"),
-        "sha256": "2cbb0404ed505a0023a64ae4f537858ed0668488376bad61e99e2615440598c0",
+        "bytes": (262472 * 2 + 524288) * 1024,
+        "sources": ("paper_1803_11301_amd/csrc/k_bf2.h", "paper_1803_11301_amd/csrc/k_butterfly.h",
+                    "paper_1803_11301_amd/csrc/gf_device.h"),
+        "sha256": "ff4bbf991719f25e1a3c770f5921940776cfb791312ba0b9f3e6dd27606e6c8c",
     },
 }
 
@@ -325,6 +325,18 @@ def main():
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom), "bytes_per_launch": int(bytes_per_launch),
                 "avg_launch_us": round(avg_s * 1e6, 3)}
+    # the butterfly kernels are bound by LDS table lookups rather than HBM:
+    # report their rate of multiplications by constants (l/2 * n_p per transform,
+    # three transforms) per CU per clock at 2.4 GHz
+    bfly = [n for n in prof if "butterfly" in n]
+    bfly_ms = sum(prof[n][1] for n in bfly) / args.steps
+    l = log2n - 6
+    mults = 3 * (l * (1 << l) // 2)
+    bfly_rate = None
+    if bfly_ms > 0:
+        bfly_rate = {"multiplications_per_product": mults, "ms_per_product": round(bfly_ms, 4),
+                     "per_cu_per_clock": round(mults / (bfly_ms / 1e3) / (256 * 2.4e9), 3),
+                     "lookups_per_multiplication": 8}
     product_gbs = nominal / (ms / 1e3) / 1e9
     log(f"[bench] {ms:.3f} ms/product; nominal {nominal / 1e9:.3f} GB -> {product_gbs:.1f} GB/s "
         f"({100 * product_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
@@ -353,6 +365,7 @@ def main():
         "config": {"workload": desc, "len_a": L, "len_b": L, "transform_bits": 1 << log2n,
                    "seed": hex(seed), "field": "GF(2^64)"},
         "roofline": roof,
+        "butterfly_rate": bfly_rate,
         "product_roofline": {"nominal_bytes": nominal, "achieved": round(product_gbs, 2), "peak": HBM_PEAK_GBS,
                              "unit": "GB/s", "frac": round(product_gbs / HBM_PEAK_GBS, 5)},
         "kernels": per_kernel,
