@@ -138,14 +138,10 @@ __device__ __forceinline__ void ktable_fill_item(uint64_t *tab, const uint64_t *
     for (int v = 0; v < 5; ++v)
         if ((m >> v) & 1) base ^= bs[3 + v];
     const uint64_t b0 = bs[0], b1 = bs[1], b2 = bs[2];
-    uint64_t *t = tab + k * 256 + m * 8;
-    const uint64_t x01 = b0 ^ b1;
-    t[0] = base;
-    t[1] = base ^ b0;
-    t[2] = base ^ b1;
-    t[3] = base ^ x01;
-    t[4] = base ^ b2;
-    t[5] = base ^ b2 ^ b0;
-    t[6] = base ^ b2 ^ b1;
-    t[7] = base ^ b2 ^ x01;
+    ulonglong2 *t = reinterpret_cast<ulonglong2 *>(tab + k * 256 + m * 8);   // 16-byte LDS writes
+    const uint64_t x01 = b0 ^ b1, c = base ^ b2;
+    t[0] = make_ulonglong2(base, base ^ b0);
+    t[1] = make_ulonglong2(base ^ b1, base ^ x01);
+    t[2] = make_ulonglong2(c, c ^ b0);
+    t[3] = make_ulonglong2(c ^ b1, c ^ x01);
 }

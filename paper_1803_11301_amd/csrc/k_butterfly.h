@@ -185,7 +185,7 @@ __global__ __launch_bounds__(BF_UP_THREADS) void k_bfly_upper(uint64_t *__restri
                                                               int l, int i_lo, int k, int lgW,
                                                               const DevTables *__restrict__ T)
 {
-    __shared__ uint64_t s_tab[2048];                                 // the K table of the current layer
+    __shared__ __align__(16) uint64_t s_tab[2048];                   // the K table of the current layer
     __shared__ __align__(16) uint8_t s_mul8e[128 * 256];             // even rows of the GF(2^8) table
     __shared__ uint64_t s_basis[64];
     __shared__ uint64_t s_A[1 << (BF_UPPER_MAXK + BF_UPPER_LGW)];
