@@ -197,24 +197,50 @@ __device__ __forceinline__ uint64_t b2_upper_global(int e, uint64_t gbase, int i
     return gbase | (uint64_t)(e & ((1 << LGW) - 1)) | ((uint64_t)(e >> LGW) << i_lo);
 }
 
-// basis images of the K tables of group g's layers (threads 64 m .. 64 m + 63 for register bit m)
-template <int K>
-__device__ __forceinline__ void b2_upper_basis(const B2Group &g, uint64_t (*s_basis)[64], uint64_t gbase, int l,
-                                               int i_lo, const DevTables *__restrict__ T, int tid)
+// The 64 basis images of a K table: K = 2^(32+d) + bh << 8 in Cantor
+// coordinates, so the images are those of v_{32+d} plus the rows of the set
+// bits of bh (gf_device.h); the rows come from an LDS copy of the table.
+__device__ __forceinline__ void b2_basis(uint64_t *img, int d, uint32_t bh, const uint64_t (*s_pb)[64],
+                                         const DevTables *__restrict__ T, int t64)
 {
-    const int m = tid >> 6;
-    if (m < 3 && g.layer[m]) {
-        const int i = i_lo + g.s[m] - B2Upper<K>::LGW;
-        ktable_basis(s_basis[m], l - i, (uint32_t)(gbase >> (i + 8)), T, tid & 63);
-    }
+    uint64_t v = T->gbasis[d][t64];
+#pragma unroll
+    for (int b = 0; b < 24; ++b)
+        if ((bh >> b) & 1u) v ^= s_pb[b][t64];
+    img[t64] = v;
 }
 
-__device__ __forceinline__ void b2_fill(const B2Group &g, uint64_t (*s_tab)[2048], const uint64_t (*s_basis)[64],
-                                        int tid, int nth)
+__device__ __forceinline__ void b2_load_pbasis(uint64_t (*s_pb)[64], const DevTables *__restrict__ T, int tid, int nth)
+{
+    for (int q = tid; q < 24 * 64; q += nth) (&s_pb[0][0])[q] = (&T->pbasis[0][0])[q];
+}
+
+// the images of register bit m's layer are cached in slot[m] of s_img; they
+// are recomputed (threads 64 m .. 64 m + 63) only when that layer's K changes
+__device__ __forceinline__ void b2_fill(const B2Group &g, uint64_t (*s_tab)[2048], const uint64_t (*s_img)[64],
+                                        const int (&slot)[3], int tid, int nth)
 {
     for (int item = tid; item < 3 * 256; item += nth) {
         const int m = item >> 8;
-        if (g.layer[m]) ktable_fill_item(s_tab[m], s_basis[m], item & 255);
+        if (g.layer[m]) ktable_fill_item(s_tab[m], s_img[slot[m]], item & 255);
+    }
+}
+
+// images for the layers of group g: slot = row of the layer, key = its bh
+template <int K>
+__device__ __forceinline__ void b2_upper_images(const B2Group &g, uint64_t (*s_img)[64], uint32_t (&key)[K],
+                                                const uint64_t (*s_pb)[64], uint64_t gbase, int l, int i_lo,
+                                                const DevTables *__restrict__ T, int tid)
+{
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        if (!g.layer[m]) continue;
+        const int row = g.s[m] - B2Upper<K>::LGW, i = i_lo + row;
+        const uint32_t bh = (uint32_t)(gbase >> (i + 8));
+        if (key[row] != bh) {
+            if ((tid >> 6) == m) b2_basis(s_img[row], l - i, bh, s_pb, T, tid & 63);
+            key[row] = bh;
+        }
     }
 }
 
@@ -257,17 +283,27 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restric
     constexpr int NC = B2Upper<K>::NC, LGW = B2Upper<K>::LGW;
     __shared__ __align__(16) uint64_t s_tab[3][2048];   // K tables; the exchange area aliases them
     __shared__ __align__(16) PermTab s_pt[128];
-    __shared__ uint64_t s_basis[3][64];
+    __shared__ uint64_t s_pb[24][64];                   // basis rows of the bits of bh
+    __shared__ uint64_t s_img[K][64];                   // basis images of each layer's K, cached
     uint64_t *stA = &s_tab[0][0], *stB = stA + B2_STAGE_WORDS;
     const int tid = threadIdx.x, nth = blockDim.x;
 
     for (int q = tid; q < 128 * 8; q += nth)
         reinterpret_cast<uint32_t *>(s_pt)[q] = reinterpret_cast<const uint32_t *>(T->pt_beta8)[q];
+    b2_load_pbasis(s_pb, T, tid, nth);
+    __syncthreads();
 
     const int nlo = i_lo - LGW;
     const uint64_t ntiles = 1ull << (l - B2_TILE_LG);
+    // each workgroup takes a contiguous run of tiles: K changes only with the
+    // tile bits above the rows, so the cached images stay valid for long runs
+    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t_beg = (uint64_t)blockIdx.x * per, t_end = t_beg + per < ntiles ? t_beg + per : ntiles;
+    uint32_t key[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) key[r] = 0xFFFFFFFFu;
     uint64_t xa[8], xb[8];
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint64_t tile = t_beg; tile < t_end; ++tile) {
         const uint64_t gbase = ((tile >> nlo) << (i_lo + K)) | ((tile & ((1ull << nlo) - 1)) << LGW);
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
@@ -284,7 +320,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restric
                     if (TWO) xb[r] = B[j];
                 }
                 __syncthreads();   // the previous tile is done with the tables
-                b2_upper_basis<K>(g, s_basis, gbase, l, i_lo, T, tid);
+                b2_upper_images<K>(g, s_img, key, s_pb, gbase, l, i_lo, T, tid);
                 __syncthreads();
             } else {
                 // values out in the previous group's arrangement, in again in this one's
@@ -297,7 +333,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restric
                     stA[b2_pad(e)] = xa[r];
                     if (TWO) stB[b2_pad(e)] = xb[r];
                 }
-                b2_upper_basis<K>(g, s_basis, gbase, l, i_lo, T, tid);
+                b2_upper_images<K>(g, s_img, key, s_pb, gbase, l, i_lo, T, tid);
                 __syncthreads();
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
@@ -307,7 +343,10 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restric
                 }
                 __syncthreads();   // exchange area free for the tables
             }
-            b2_fill(g, s_tab, s_basis, tid, nth);
+            int slot[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) slot[m] = g.layer[m] ? g.s[m] - LGW : 0;
+            b2_fill(g, s_tab, s_img, slot, tid, nth);
             __syncthreads();
             b2_upper_compute<K, INV, TWO>(g, xa, xb, s_tab, s_pt, gb_t, i_lo, T);
             if (cc == NC - 1) {
@@ -440,15 +479,21 @@ __device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], uint64_t (&xb)[8],
     }
 }
 
-__device__ __forceinline__ void b2_bottom_basis(const B2Group &g, uint64_t (*s_basis)[64], uint64_t gbase, int l,
-                                                const DevTables *__restrict__ T, int tid)
+// images for the layers of group g: slot = layer index i, key = its bh
+__device__ __forceinline__ void b2_bottom_images(const B2Group &g, uint64_t (*s_img)[64], uint32_t (&key)[11],
+                                                 const uint64_t (*s_pb)[64], uint64_t gbase, int l,
+                                                 const DevTables *__restrict__ T, int tid)
 {
-    const int m = tid >> 6;
-    if (m < 3 && g.layer[m]) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        if (!g.layer[m]) continue;
         const int i = g.s[m];
         // K = 2^(32+d) + (b >> 7) << 8 (V_8 split) or 2^(32+d) + (b >> 15) << 16 (V_16 split)
         const uint32_t bh = b2_wide(i) ? (uint32_t)(gbase >> (i + 16)) << 8 : (uint32_t)(gbase >> (i + 8));
-        ktable_basis(s_basis[m], l - i, bh, T, tid & 63);
+        if (key[i] != bh) {
+            if ((tid >> 6) == m) b2_basis(s_img[i], l - i, bh, s_pb, T, tid & 63);
+            key[i] = bh;
+        }
     }
 }
 
@@ -496,7 +541,8 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
     __shared__ __align__(16) PermTab s_ptb[128];        // tables of iota(2 bl), bl < 128
     __shared__ __align__(16) PermTab s_pt8[256];        // tables of every byte of V_8
     __shared__ uint16_t s_io16[2][256];                 // iota of the low two Cantor bytes (V_16)
-    __shared__ uint64_t s_basis[3][64];
+    __shared__ uint64_t s_pb[24][64];                   // basis rows of the bits of bh
+    __shared__ uint64_t s_img[B2_TILE_LG][64];          // basis images of each layer's K, cached
     uint64_t *stA = &s_tab[0][0], *stB = stA + B2_STAGE_WORDS;
     const int tid = threadIdx.x, nth = blockDim.x;
 
@@ -505,14 +551,21 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
     for (int q = tid; q < 256 * 8; q += nth)
         reinterpret_cast<uint32_t *>(s_pt8)[q] = reinterpret_cast<const uint32_t *>(T->pt8)[q];
     for (int q = tid; q < 2 * 256; q += nth) (&s_io16[0][0])[q] = (uint16_t)(&T->iota[0][0])[q];
+    b2_load_pbasis(s_pb, T, tid, nth);
     __syncthreads();
     const PermTab *Q = s_pt8 + 0x80;   // v_7 = Cantor byte 0x80
     const uint4 q01 = *reinterpret_cast<const uint4 *>(Q);
     const uint32_t q2 = Q->t2;
 
     const uint64_t ntiles = 1ull << (l - B2_TILE_LG);
+    // contiguous runs of tiles keep most layers' K (and the cached images) unchanged
+    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t_beg = (uint64_t)blockIdx.x * per, t_end = t_beg + per < ntiles ? t_beg + per : ntiles;
+    uint32_t key[B2_TILE_LG];
+#pragma unroll
+    for (int i = 0; i < B2_TILE_LG; ++i) key[i] = 0xFFFFFFFFu;
     uint64_t xa[8], xb[8];
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (uint64_t tile = t_beg; tile < t_end; ++tile) {
         const uint64_t gbase = tile << B2_TILE_LG;
 #pragma unroll
         for (int cc = 0; cc < NC; ++cc) {
@@ -528,7 +581,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
                     if (TWO) xb[r] = B[gbase | (uint64_t)e];
                 }
                 __syncthreads();   // the previous tile is done with the tables
-                b2_bottom_basis(g, s_basis, gbase, l, T, tid);
+                b2_bottom_images(g, s_img, key, s_pb, gbase, l, T, tid);
                 __syncthreads();
             } else {
                 const B2Group gp = b2_bottom_group(INV ? c + 1 : c - 1);
@@ -540,7 +593,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
                     stA[b2_pad(e)] = xa[r];
                     if (TWO) stB[b2_pad(e)] = xb[r];
                 }
-                b2_bottom_basis(g, s_basis, gbase, l, T, tid);
+                b2_bottom_images(g, s_img, key, s_pb, gbase, l, T, tid);
                 __syncthreads();
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
@@ -550,7 +603,10 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
                 }
                 __syncthreads();   // exchange area free for the tables
             }
-            b2_fill(g, s_tab, s_basis, tid, nth);
+            int slot[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) slot[m] = g.layer[m] ? g.s[m] : 0;
+            b2_fill(g, s_tab, s_img, slot, tid, nth);
             __syncthreads();
             b2_bottom_compute<INV, TWO>(g, xa, xb, s_tab, s_ptb, s_pt8, s_io16, q01, q2, gb_t, T);
             if (cc == NC - 1) {
