@@ -622,24 +622,65 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *
     }
 }
 
+// Lane exchanges without the LDS: the value of lane (lane ^ J) for J < 64,
+// through DPP row operations (J <= 8; row_ror:N delivers lane (i - N) mod 16
+// of each 16-lane row) and the gfx950 half-row / half-wave swaps (J = 16, 32).
+template <int J>
+__device__ __forceinline__ uint32_t bc_xor_lane(uint32_t v, int lane)
+{
+    if constexpr (J == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    } else if constexpr (J == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    } else if constexpr (J == 4) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12C, 0xf, 0xf, false);   // i + 4
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false);   // i - 4
+        return (lane & 4) ? dn : up;
+    } else if constexpr (J == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);   // row_ror:8
+    } else if constexpr (J == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? r[0] : r[1];
+    }
+}
+
+// one stage of the transpose on a 32-bit word: lanes with bit J clear keep
+// the bits of mask m and take the partner's bits of m shifted up by J; the
+// others keep ~m and take the partner's bits of ~m shifted down by J
+template <int J>
+__device__ __forceinline__ uint32_t bc_tstage(uint32_t x, uint32_t m, int lane)
+{
+    const uint32_t y = bc_xor_lane<J>(x, lane);
+    return (lane & J) ? (((y & ~m) >> J) | (x & ~m)) : ((x & m) | ((y & m) << J));
+}
+
 // 64 x 64 bit transpose across a wavefront: lane i holds row i; afterwards
 // lane t holds column t (bit i = bit t of row i)
 __device__ __forceinline__ uint64_t bc_wave_transpose64(uint64_t x, int lane)
 {
-    const uint64_t masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                               0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int s = 0; s < 6; ++s) {
-        const int j = 32 >> s;
-        const uint64_t m = masks[s];
-        uint32_t lo = __shfl_xor((uint32_t)x, j, 64), hi = __shfl_xor((uint32_t)(x >> 32), j, 64);
-        const uint64_t y = (uint64_t)lo | ((uint64_t)hi << 32);
-        if (lane & j)
-            x = ((y & ~m) >> j) | (x & ~m);
-        else
-            x = (x & m) | ((y & m) << j);
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    {
+        // J = 32: lanes below 32 take the partner's low word as their high word,
+        // lanes from 32 up take the partner's high word as their low word: one
+        // swap of the upper half-wave of lo with the lower half-wave of hi
+        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        lo = r[0];
+        hi = r[1];
     }
-    return x;
+    lo = bc_tstage<16>(lo, 0x0000FFFFu, lane);
+    hi = bc_tstage<16>(hi, 0x0000FFFFu, lane);
+    lo = bc_tstage<8>(lo, 0x00FF00FFu, lane);
+    hi = bc_tstage<8>(hi, 0x00FF00FFu, lane);
+    lo = bc_tstage<4>(lo, 0x0F0F0F0Fu, lane);
+    hi = bc_tstage<4>(hi, 0x0F0F0F0Fu, lane);
+    lo = bc_tstage<2>(lo, 0x33333333u, lane);
+    hi = bc_tstage<2>(hi, 0x33333333u, lane);
+    lo = bc_tstage<1>(lo, 0x55555555u, lane);
+    hi = bc_tstage<1>(hi, 0x55555555u, lane);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
 // Outer BasisCvt(R) on one 64-bit column of Y, then Encode: element
@@ -701,20 +742,16 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
             // transpose the two 32 x 64 blocks (one per half-wave): afterwards lane
             // (half, j) holds bits j and j + 32 of the 32 decoded vectors
             uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
-            const uint32_t masks[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
-#pragma unroll
-            for (int s = 0; s < 5; ++s) {
-                const int j = 16 >> s;
-                const uint32_t m = masks[s];
-                uint32_t ylo = __shfl_xor(lo, j, 64), yhi = __shfl_xor(hi, j, 64);
-                if (t & j) {
-                    lo = ((ylo & ~m) >> j) | (lo & ~m);
-                    hi = ((yhi & ~m) >> j) | (hi & ~m);
-                } else {
-                    lo = (lo & m) | ((ylo & m) << j);
-                    hi = (hi & m) | ((yhi & m) << j);
-                }
-            }
+            lo = bc_tstage<16>(lo, 0x0000FFFFu, lane);
+            hi = bc_tstage<16>(hi, 0x0000FFFFu, lane);
+            lo = bc_tstage<8>(lo, 0x00FF00FFu, lane);
+            hi = bc_tstage<8>(hi, 0x00FF00FFu, lane);
+            lo = bc_tstage<4>(lo, 0x0F0F0F0Fu, lane);
+            hi = bc_tstage<4>(hi, 0x0F0F0F0Fu, lane);
+            lo = bc_tstage<2>(lo, 0x33333333u, lane);
+            hi = bc_tstage<2>(hi, 0x33333333u, lane);
+            lo = bc_tstage<1>(lo, 0x55555555u, lane);
+            hi = bc_tstage<1>(hi, 0x55555555u, lane);
             if (r0 < rows_per_j) {
                 // lane t now holds bit t of vector s at bit s: that is row j = t (lo) and j = t + 32 (hi)
                 const int rlo = t * rows_per_j + r0, rhi = (t + 32) * rows_per_j + r0;
