@@ -225,13 +225,89 @@ __host__ __device__ constexpr int bc16_run_end(int K, bool inv)
     return e;
 }
 
+// a cross-word step with S <= 1024 bits on one aligned block of 16 words in
+// registers (every segment lies inside the block)
+template <int LGS, int LGD, int PHASE>
+__device__ __forceinline__ void bc16_block_phase(uint64_t (&w)[16])
+{
+    constexpr int S = 1 << LGS, H = S / 2, d = 1 << LGD;
+    constexpr int SW = S / 64, HW = SW / 2, NSEG = 16 / SW;
+#pragma unroll
+    for (int sg = 0; sg < NSEG; ++sg) {
+        uint64_t *lo = w + sg * SW, *hi = lo + HW;
+        if (PHASE == 0) {
+            if (d % 64 == 0) {
+#pragma unroll
+                for (int k = 0; k < d / 64; ++k) hi[k] ^= hi[k + (H - d) / 64];
+            } else {
+                hi[0] ^= hi[HW - 1] >> (64 - d);
+            }
+        } else {
+            constexpr int dw = d / 64, ds = d % 64;
+#pragma unroll
+            for (int q = HW - 1; q >= dw; --q) {
+                uint64_t v = hi[q - dw];
+                if (ds) {
+                    v <<= ds;
+                    if (q - dw - 1 >= 0) v |= hi[q - dw - 1] >> (64 - ds);
+                }
+                lo[q] ^= v;
+            }
+        }
+    }
+}
+
+__host__ __device__ constexpr int bc16_block_run_end(int K, bool inv)
+{
+    int e = K;
+    while (e < BC16_NSTEPS && bc16_lgs[inv ? BC16_NSTEPS - 1 - e : e] <= 10) ++e;
+    return e;
+}
+
+template <int K, int KE, bool INV>
+__device__ __forceinline__ void bc16_block_run(uint64_t (&w)[16])
+{
+    if constexpr (K < KE) {
+        constexpr int k = INV ? BC16_NSTEPS - 1 - K : K;
+        constexpr int LGS = bc16_lgs[k], LGD = bc16_lgd[k];
+        if constexpr (LGS <= 6) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) w[i] = bc16_inword<LGS, LGD, INV>(w[i]);
+        } else {
+            bc16_block_phase<LGS, LGD, INV ? 1 : 0>(w);
+            bc16_block_phase<LGS, LGD, INV ? 0 : 1>(w);
+        }
+        bc16_block_run<K + 1, KE, INV>(w);
+    }
+}
+
 template <int K, bool INV>
 __device__ __forceinline__ void bc16_steps_from(uint64_t *rows, int nrows, int tid, int nth)
 {
     if constexpr (K < BC16_NSTEPS) {
         constexpr int k = INV ? BC16_NSTEPS - 1 - K : K;
         constexpr int LGS = bc16_lgs[k], LGD = bc16_lgd[k];
-        if constexpr (LGS <= 6) {
+        if constexpr (LGS <= 10 && bc16_block_run_end(K, INV) - K >= 2) {
+            // a run of steps inside 1024-bit segments: each thread applies it to
+            // whole 16-word blocks in registers
+            constexpr int KE = bc16_block_run_end(K, INV);
+            for (int blk = tid; blk < nrows * 64; blk += nth) {
+                uint64_t w[16];
+                const ulonglong2 *src = reinterpret_cast<const ulonglong2 *>(rows + blk * 16);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const ulonglong2 v = src[i];
+                    w[2 * i] = v.x;
+                    w[2 * i + 1] = v.y;
+                }
+                bc16_block_run<K, KE, INV>(w);
+                ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(rows + blk * 16);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) dst[i] = make_ulonglong2(w[2 * i], w[2 * i + 1]);
+            }
+            __syncthreads();
+            bc16_steps_from<KE, INV>(rows, nrows, tid, nth);
+        } else if constexpr (LGS <= 6) {
             constexpr int KE = bc16_run_end(K, INV);
             for (int w = tid; w < nrows * 1024; w += nth) rows[w] = bc16_inword_run<K, KE, INV>(rows[w]);
             __syncthreads();
@@ -582,7 +658,7 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *
                                                             const uint64_t *__restrict__ in, uint64_t len, int lgR,
                                                             int EW, uint64_t *__restrict__ Y, BcSteps inner)
 {
-    __shared__ uint64_t rows[BC_ROWS * BC_TAU_WORDS];
+    __shared__ __align__(16) uint64_t rows[BC_ROWS * BC_TAU_WORDS];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
     const uint64_t inwords = (len + 63) / 64;
@@ -771,7 +847,7 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
 __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *__restrict__ Y32, int lgR, int EW,
                                                             uint64_t *__restrict__ X, BcSteps inner)
 {
-    __shared__ uint64_t rows[BC_ROWS * BC_TAU_WORDS];
+    __shared__ __align__(16) uint64_t rows[BC_ROWS * BC_TAU_WORDS];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
     for (int q0 = blockIdx.x * T; q0 < R; q0 += gridDim.x * T) {
