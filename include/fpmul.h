@@ -159,8 +159,12 @@ int polymul_ticket_times(polymul_server *srv, uint64_t ticket, uint64_t *submit_
  * (len_a bits, len_a <= 2^log2n) at the n/64 points of the Frobenius
  * partition Sigma = v_{l+32} + V_l, l = log2n - 6 (Eq. 6, Eq. 8).
  * values: device, 2^(log2n-6) words; word j is A(v_{l+32} + j) with j read
- * as Cantor coordinates, each value a GF(2^64) element written in the
- * polynomial basis modulo x^64 + x^4 + x^3 + x + 1 (Sec. 4.3).
+ * as Cantor coordinates.  Each value is a GF(2^64) element in the library's
+ * multiplication representation: the tower over V_8 = span(v_0 .. v_7)
+ * (a subfield, Sec. 2.2) by v_8, v_16 and v_32, where bit 8k + u is the
+ * coefficient of v_u * W_k and W_k is the product of v_8, v_16, v_32 for
+ * the set bits 0, 1, 2 of k.  (Any representation gives the same product;
+ * this one is chosen for the device, see polymul_pointwise.)
  * 6 <= log2n <= 37.
  */
 int polymul_addfft(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a, int log2n,
@@ -175,6 +179,18 @@ int polymul_addfft(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a, int
  */
 int polymul_iaddfft(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_t *out,
                     uint64_t out_bits, void *stream);
+
+/*
+ * polymul_pointwise -- fc[j] = fa[j] * fb[j] in GF(2^64) for the
+ * 2^(log2n-6) values of two transforms of the same log2n (the pointwise step
+ * of Alg. 5), in the representation polymul_addfft writes.  With it a
+ * transform can be computed once and reused: A * B_k for several B_k is
+ * addfft(A) once, addfft(B_k), pointwise, iaddfft; A^2 is addfft(A),
+ * pointwise(fa, fa), iaddfft.  fc may be fa or fb; otherwise it must not
+ * overlap them.  6 <= log2n <= 37.
+ */
+int polymul_pointwise(polymul_ctx *ctx, const uint64_t *fa, const uint64_t *fb, int log2n, uint64_t *fc,
+                      void *stream);
 
 /*
  * polymul_basiscvt -- Alg. 1 alone: monomial -> novelpoly coefficients of a

@@ -1026,6 +1026,31 @@ int polymul_addfft(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, int log2
     return addfft_body(ctx, a, len_a, log2n, values, (hipStream_t)stream);
 }
 
+int polymul_pointwise(polymul_ctx *ctx, const uint64_t *fa, const uint64_t *fb, int log2n, uint64_t *fc,
+                      void *stream)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (log2n < 6 || log2n > 37) return fail(POLYMUL_EINVAL, "log2n must be in [6, 37]");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(g.err);
+    int rc;
+    if ((rc = check_dev_ptr(fa, "fa")) || (rc = check_dev_ptr(fb, "fb")) || (rc = check_dev_ptr(fc, "fc"))) return rc;
+    const uint64_t n = 1ull << (log2n - 6);
+    const size_t bytes = (size_t)n * 8;
+    if ((fc != fa && ranges_overlap(fc, bytes, fa, bytes)) || (fc != fb && ranges_overlap(fc, bytes, fb, bytes)))
+        return fail(POLYMUL_EINVAL, "fc overlaps an input without being it");
+    hipStream_t s = (hipStream_t)stream;
+    const uint64_t *other = fb;
+    if (fc == fb) {
+        other = fa;   // the product commutes: multiply fb in place by fa
+    } else if (fc != fa) {
+        HIP_TRY(hipMemcpyAsync(fc, fa, bytes, hipMemcpyDeviceToDevice, s));
+    }
+    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu * 2),
+            1024, fc, other, n, ctx->tables);
+    return 0;
+}
+
 int polymul_iaddfft(polymul_ctx *ctx, const uint64_t *values, int log2n, uint64_t *out, uint64_t out_bits,
                     void *stream)
 {

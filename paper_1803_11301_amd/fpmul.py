@@ -33,6 +33,7 @@ SIGNATURES = {
     "polymul_ticket_times": (_I, [_V, _U64, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "polymul_addfft": (_I, [_V, _P, _U64, _I, _P, _V]),
     "polymul_iaddfft": (_I, [_V, _P, _I, _P, _U64, _V]),
+    "polymul_pointwise": (_I, [_V, _P, _P, _I, _P, _V]),
     "polymul_basiscvt": (_I, [_V, _P, _U64, _I, _I, _P, _V]),
     "polymul_profile_enable": (_I, [_V, _I]),
     "polymul_profile_report": (_I, [_V, ctypes.c_char_p, _SZ]),
@@ -166,6 +167,14 @@ class Context:
             out = torch.empty(max(1, nwords(out_bits)), dtype=torch.int64, device=values.device)
         _check(lib().polymul_iaddfft(self.handle, _dptr(values), log2n, _dptr(out), out_bits, _stream(stream)))
         return out
+
+    def pointwise(self, fa, fb, log2n: int, fc=None, stream=None):
+        """fc[j] = fa[j] * fb[j] on two transforms of the same log2n; fc may be fa or fb."""
+        import torch
+        if fc is None:   # the library checks log2n; size the output only when it is valid
+            fc = torch.empty(1 << max(0, log2n - 6), dtype=torch.int64, device=fa.device)
+        _check(lib().polymul_pointwise(self.handle, _dptr(fa), _dptr(fb), log2n, _dptr(fc), _stream(stream)))
+        return fc
 
     def basiscvt(self, x, length: int, log2n: int, inverse: bool = False, out=None, stream=None):
         import torch

@@ -245,3 +245,60 @@ def test_error_codes(ctx):
     assert L.polymul_ex(small.handle, big.data_ptr(), 100000, big.data_ptr(), 100000, big_out.data_ptr(), None) \
         == fpmul.ENOMEM
     small.close()
+
+
+# --------------------------------------------------------------------------
+# transform reuse and squaring (pointwise on transforms)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("log2n", [12, 20, 24])
+def test_transform_reuse_one_operand_many_products(ctx, log2n):
+    rng = random.Random(log2n)
+    n = 1 << log2n
+    la = n // 2 - 7
+    say("transform reuse", log2n)
+    a = rand_words(rng, la)
+    fa = ctx.addfft(dev(a), la, log2n)
+    for k in range(3):
+        lb = rng.randint(1, n // 2)
+        b = rand_words(rng, lb)
+        fb = ctx.addfft(dev(b), lb, log2n)
+        fc = ctx.pointwise(fa, fb, log2n)
+        got = host(ctx.iaddfft(fc, log2n, la + lb - 1))[: O.nwords(la + lb - 1)]
+        if log2n <= 20:
+            assert np.array_equal(got, O.polymul(a, la, b, lb)), k
+        else:
+            nw = O.nwords(la + lb - 1)
+            idx = np.array(sorted({0, nw - 1, nw // 2} | {rng.randrange(nw) for _ in range(5)}), dtype=np.uint64)
+            assert np.array_equal(got[idx.astype(np.int64)], O.product_words(a, la, b, lb, idx)), k
+    # fa is still the transform of A
+    assert np.array_equal(host(ctx.iaddfft(fa, log2n, la)), a)
+
+
+@pytest.mark.parametrize("log2n", [7, 16, 23])
+def test_squaring_through_one_transform_is_bit_spread(ctx, log2n):
+    # A^2 in GF(2)[x] spreads bit i to bit 2i (Frobenius); computed as
+    # addfft(A), pointwise(fa, fa) in place, iaddfft
+    rng = random.Random(100 + log2n)
+    n = 1 << log2n
+    la = n // 2
+    say("squaring", log2n)
+    a = rand_words(rng, la)
+    fa = ctx.addfft(dev(a), la, log2n)
+    ctx.pointwise(fa, fa, log2n, fc=fa)
+    got = host(ctx.iaddfft(fa, log2n, 2 * la - 1))[: O.nwords(2 * la - 1)]
+    bits = np.unpackbits(a.view(np.uint8), bitorder="little")[:la]
+    spread = np.zeros(2 * la - 1 + 1, dtype=np.uint8)
+    spread[0:2 * la:2] = bits
+    want = np.packbits(spread[: 64 * O.nwords(2 * la - 1)], bitorder="little")
+    want = np.frombuffer(np.pad(want, (0, 8 * O.nwords(2 * la - 1) - want.size)).tobytes(), dtype=np.uint64)
+    assert np.array_equal(got, want)
+
+
+def test_pointwise_rejects_bad_arguments(ctx):
+    from paper_1803_11301_amd import fpmul
+    t = torch.zeros(64, dtype=torch.int64, device="cuda")
+    with pytest.raises(fpmul.FpmulError):
+        ctx.pointwise(t, t, 5)
+    with pytest.raises(fpmul.FpmulError):
+        ctx.pointwise(t[:32], t[16:48], 11, fc=t[8:40])   # overlapping output that is neither input
