@@ -170,7 +170,8 @@ def bench_batch(ctx, steps: int):
     return rec
 
 
-def bench_serve(ctx, count: int, warmup: int, rho: float):
+def bench_serve(ctx, count: int, warmup: int, rho: float, slots: int = 8, batch_limit_bits: int = 1 << 20,
+                max_batch: int = 512):
     """Poisson stream of products, operands log-uniform in [2^12, 2^24] bits
     (seed 0x5EED05E5), through the continuous-batching server: first the
     saturated throughput X (every request submitted at once), then arrivals
@@ -195,7 +196,7 @@ def bench_serve(ctx, count: int, warmup: int, rho: float):
     args = [(ab + 8 * int(offa[k]), int(la[k]), bb + 8 * int(offb[k]), int(lb[k]), ob + 8 * int(oofs[k]))
             for k in range(total)]
     torch.cuda.synchronize()
-    srv = fpmul.Server(ctx, hbm_budget=8 << 30, slots=4)
+    srv = fpmul.Server(ctx, hbm_budget=8 << 30, slots=slots, batch_limit_bits=batch_limit_bits, max_batch=max_batch)
     # saturation: the warm-up requests plus the first measured ones all at once
     nsat = max(warmup, 1)
     t0 = time.perf_counter()
@@ -228,7 +229,8 @@ def bench_serve(ctx, count: int, warmup: int, rho: float):
            "offered_per_s": round(rate, 1), "achieved_products_per_s": round(count / wall, 1),
            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
            "mean_ms": round(float(lat.mean()), 3), "p99_queue_ms": round(float(np.percentile(queue, 99)), 3),
-           "slots": 4, "hbm_budget_bytes": 8 << 30}
+           "slots": slots, "batch_limit_bits": batch_limit_bits, "max_batch": max_batch,
+           "hbm_budget_bytes": 8 << 30}
     log(f"[bench] serve: saturated {X:.0f}/s; at {rho:.2f}: {count / wall:.0f}/s, p50 {rec['p50_ms']} ms, "
         f"p99 {rec['p99_ms']} ms")
     return rec

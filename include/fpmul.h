@@ -125,9 +125,9 @@ int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, cons
  *   and nothing afterwards, and runs max_slots (1..64) launch slots, each a
  *   HIP stream.  A scheduler thread admits waiting requests whenever a slot
  *   is free and the request's workspace fits in what is left of the arena:
- *   all waiting products of at most POLYMUL_BATCH_MAX_PRODUCT_BITS bits go
- *   out together as one batched launch (as polymul_batch), a larger product
- *   runs alone (as polymul_ex).  A later request may pass an earlier one that
+ *   waiting products of at most 2^20 bits (up to 512 of them) go out
+ *   together as one batched launch (as polymul_batch), a larger product runs
+ *   alone (as polymul_ex); polymul_server_set_policy changes both limits.  A later request may pass an earlier one that
  *   does not fit yet; one passed 64 times blocks later ones until it fits.
  *   Launches on different slots overlap on the device.
  * polymul_submit -- queues C = A * B (same arguments and rules as polymul;
@@ -146,6 +146,14 @@ int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, cons
 typedef struct polymul_server polymul_server;
 int polymul_server_create(polymul_server **srv, polymul_ctx *ctx, size_t hbm_budget_bytes, uint32_t max_slots);
 int polymul_server_destroy(polymul_server *srv);
+/*
+ * polymul_server_set_policy -- before the first submit: products of at most
+ * batch_limit_bits bits (<= POLYMUL_BATCH_MAX_PRODUCT_BITS) are grouped into
+ * batched launches of at most max_batch requests (1..4096); larger products
+ * run alone.  Defaults: 2^20 bits, 512 requests.  POLYMUL_EINVAL after the
+ * first submit or for values out of range.
+ */
+int polymul_server_set_policy(polymul_server *srv, uint64_t batch_limit_bits, uint32_t max_batch);
 int polymul_submit(polymul_server *srv, const uint64_t *a_bits, uint64_t len_a, const uint64_t *b_bits,
                    uint64_t len_b, uint64_t *out, uint64_t *ticket);
 int polymul_poll(polymul_server *srv, uint64_t ticket, int *done);

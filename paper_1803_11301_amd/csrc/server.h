@@ -4,9 +4,9 @@
 // One scheduler thread per server owns every launch.  Requests are queued by
 // polymul_submit; whenever a launch slot (a stream with its own workspace
 // view) is free, the admission policy of server_policy.h picks the next
-// launch: all waiting small products (product at most 2^22 bits) together
-// as one batched launch of k_batch, or one large product through the
-// single-product path.  Its workspace is carved out of the server's arena,
+// launch: waiting small products (by default at most 2^20 bits, up to 512 of
+// them) together as one batched launch of k_batch, or one larger product
+// through the single-product path.  Its workspace is carved out of the server's arena,
 // one device allocation made at creation, so memory use never exceeds the
 // budget and nothing is allocated while serving.  Launches on different
 // slots overlap on the device; a slot is freed, and its arena range
@@ -181,7 +181,6 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
     if ((rc = batch_steps_upload(ctx)) || (rc = set_lds_limits())) return rc;
     std::unique_ptr<polymul_server> S(new polymul_server());
     S->ctx = ctx;
-    S->policy.batch_limit_bits = POLYMUL_BATCH_MAX_PRODUCT_BITS;
     polymul_ctx *parent = ctx;
     S->fp.single = [](uint64_t lc) { return srv_single_bytes(lc); };
     S->fp.batch = [parent](uint32_t count, uint64_t max_lc) {
@@ -196,8 +195,7 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
         e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
         if (e == hipSuccess)
-            e = hipHostMalloc((void **)&slot.host_desc, (size_t)S->policy.max_batch * sizeof(BtDesc),
-                              hipHostMallocDefault);
+            e = hipHostMalloc((void **)&slot.host_desc, (size_t)4096 * sizeof(BtDesc), hipHostMallocDefault);
         if (e != hipSuccess) break;
         slot.view = new polymul_ctx();
         slot.view->device = ctx->device;
@@ -240,6 +238,18 @@ int polymul_server_destroy(polymul_server *S)
     }
     if (S->arena_base) (void)hipFree(S->arena_base);
     delete S;
+    return 0;
+}
+
+int polymul_server_set_policy(polymul_server *S, uint64_t batch_limit_bits, uint32_t max_batch)
+{
+    if (!S) return fail(POLYMUL_EINVAL, "server is null");
+    if (batch_limit_bits > POLYMUL_BATCH_MAX_PRODUCT_BITS || max_batch < 1 || max_batch > 4096)
+        return fail(POLYMUL_EINVAL, "policy out of range");
+    std::lock_guard<std::mutex> lk(S->m);
+    if (S->next_ticket != 1) return fail(POLYMUL_EINVAL, "policy must be set before the first submit");
+    S->policy.batch_limit_bits = batch_limit_bits;
+    S->policy.max_batch = max_batch;
     return 0;
 }
 

@@ -86,8 +86,8 @@ struct Req {
 };
 
 struct Policy {
-    uint64_t batch_limit_bits = 1ull << 22;   // products at or below go to batched launches
-    uint32_t max_batch = 4096;                // requests per batched launch
+    uint64_t batch_limit_bits = 1ull << 20;   // products at or below go to batched launches
+    uint32_t max_batch = 512;                 // requests per batched launch
     uint32_t starve_after = 64;               // passes before a waiting request blocks later ones
 };
 

@@ -27,6 +27,7 @@ SIGNATURES = {
     "polymul_batch": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _V]),
     "polymul_server_create": (_I, [ctypes.POINTER(_V), _V, _SZ, ctypes.c_uint32]),
     "polymul_server_destroy": (_I, [_V]),
+    "polymul_server_set_policy": (_I, [_V, _U64, ctypes.c_uint32]),
     "polymul_submit": (_I, [_V, _P, _U64, _P, _U64, _P, ctypes.POINTER(_U64)]),
     "polymul_poll": (_I, [_V, _U64, ctypes.POINTER(_I)]),
     "polymul_wait": (_I, [_V, _U64]),
@@ -55,6 +56,10 @@ def lib():
     """Load libfpmul.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch first: the library and torch share one HIP runtime, and the
+        # first libamdhip64 loaded into the process is the one both use; torch
+        # initialises only with the runtime it ships with
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise FileNotFoundError(
                 f"{LIB_PATH} is missing: build it with paper_1803_11301_amd/build.py "
@@ -201,11 +206,17 @@ class Server:
     Operands and outputs are CUDA int64 tensors (or raw device addresses) the
     caller keeps alive until the ticket is done."""
 
-    def __init__(self, ctx: Context, hbm_budget: int = 4 << 30, slots: int = 4):
+    def __init__(self, ctx: Context, hbm_budget: int = 4 << 30, slots: int = 8, batch_limit_bits: int = 1 << 20,
+                 max_batch: int = 512):
         h = ctypes.c_void_p()
         _check(lib().polymul_server_create(ctypes.byref(h), ctx.handle, hbm_budget, slots))
         self.handle = h
         self.ctx = ctx
+        try:
+            _check(lib().polymul_server_set_policy(self.handle, batch_limit_bits, max_batch))
+        except FpmulError:
+            self.close()
+            raise
 
     def close(self):
         if self.handle:

@@ -136,3 +136,37 @@ def test_empty_and_errors(ctx):
     with pytest.raises(fpmul.FpmulError):
         srv.wait(123456789)                  # unknown ticket
     srv.close()
+
+
+@pytest.mark.parametrize("limit,max_batch", [(0, 1), (1 << 22, 4096), (1 << 16, 3)])
+def test_policy_changes_routing_not_results(ctx, limit, max_batch):
+    from paper_1803_11301_amd import fpmul
+    lens = [(1000, 3000), (1 << 15, 1 << 15), (1 << 19, 1 << 19), ((1 << 21) - 7, 1 << 20), (64, 64), (65, 1)]
+    lens += [(200 + 97 * k, 5000 - 131 * k) for k in range(12)]
+    say("policy", limit, max_batch, len(lens), "requests")
+    ops = []
+    for k, (x, y) in enumerate(lens):
+        a, b = synth.dense_poly(0x9011C700 + 2 * k, x), synth.dense_poly(0x9011C701 + 2 * k, y)
+        out = torch.zeros(O.nwords(x + y - 1), dtype=torch.int64, device="cuda")
+        ops.append((a, x, b, y, dev64(a), dev64(b), out))
+    torch.cuda.synchronize()
+    srv = fpmul.Server(ctx, hbm_budget=1 << 30, slots=3, batch_limit_bits=limit, max_batch=max_batch)
+    tickets = [srv.submit(ta, x, tb, y, out) for a, x, b, y, ta, tb, out in ops]
+    with pytest.raises(fpmul.FpmulError):
+        fpmul._check(fpmul.lib().polymul_server_set_policy(srv.handle, 1 << 20, 512))
+    for tk in tickets:
+        srv.wait(tk)
+    srv.close()
+    rng = random.Random(limit + max_batch)
+    for a, x, b, y, ta, tb, out in ops:
+        n = O.nwords(x + y - 1)
+        got = host(out, n)
+        assert np.array_equal(got, host(ctx.polymul(ta, x, tb, y), n)), (x, y)
+        check_against_oracle(a, x, b, y, got, rng)
+
+
+def test_policy_rejects_out_of_range(ctx):
+    from paper_1803_11301_amd import fpmul
+    for limit, mb in [((1 << 22) + 1, 16), (1 << 20, 0), (1 << 20, 4097)]:
+        with pytest.raises(fpmul.FpmulError):
+            fpmul.Server(ctx, hbm_budget=16 << 20, slots=1, batch_limit_bits=limit, max_batch=mb)
