@@ -63,6 +63,7 @@ static int fail(int code, const std::string &msg)
 #include "k_steps.h"
 #include "k_batch.h"
 #include "k_bf2.h"
+#include "k_bf3.h"
 
 // ---------------------------------------------------------------------------
 // elementary kernels
@@ -445,6 +446,32 @@ static int launch_bf2_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
     return 0;
 }
 
+// upper pass of K = k layers with resident tables: one workgroup per CU, the
+// grid split between the operands when B is given
+template <bool INV>
+static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l,
+                            int i_lo, int k)
+{
+    const uint64_t nops = B ? 2 : 1, ntiles = 1ull << (l - B3_TILE_LG);
+    const uint64_t per_op = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)ctx->num_cu / nops));
+    const unsigned grid = (unsigned)(per_op * nops);
+    void (*kern)(uint64_t *, uint64_t *, int, int, const DevTables *) = nullptr;
+    switch (k) {
+    case 1: kern = k_bf3_upper<INV, 1>; break;
+    case 2: kern = k_bf3_upper<INV, 2>; break;
+    case 3: kern = k_bf3_upper<INV, 3>; break;
+    case 4: kern = k_bf3_upper<INV, 4>; break;
+    case 5: kern = k_bf3_upper<INV, 5>; break;
+    case 6: kern = k_bf3_upper<INV, 6>; break;
+    case 7: kern = k_bf3_upper<INV, 7>; break;
+    default: return fail(POLYMUL_EINVAL, "upper layer group of more than 7 layers");
+    }
+    if (l < B3_TILE_LG || i_lo + k > l || i_lo < B3_TILE_LG - k)
+        return fail(POLYMUL_EINVAL, "upper pass does not fit the tile geometry");
+    KLAUNCH(ctx, s, name, kern, grid, B3_THREADS, A, B, l, i_lo, ctx->tables);
+    return 0;
+}
+
 // Butterflies of one transform (mode BF_FWD or BF_INV) or of a product
 // (BF_PRODUCT: forward A and B, pointwise, inverse; result in A)
 static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B, int l, hipStream_t s)
@@ -459,9 +486,8 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
             (void)lgW;
             (void)persist_up;
             (void)ublk;
-            const int rc = mode == BF_PRODUCT
-                               ? launch_bf2_upper<BF_FWD2>(ctx, s, "butterfly_upper", A, B, l, i_lo, k)
-                               : launch_bf2_upper<BF_FWD>(ctx, s, "butterfly_upper", A, B, l, i_lo, k);
+            const int rc = launch_bf3_upper<false>(ctx, s, "butterfly_upper", A, mode == BF_PRODUCT ? B : nullptr,
+                                                   l, i_lo, k);
             if (rc) return rc;
         }
     }
@@ -496,7 +522,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         for (auto it = groups.begin(); it != groups.end(); ++it) {
             const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
             (void)lgW;
-            const int rc = launch_bf2_upper<BF_INV>(ctx, s, "ibutterfly_upper", A, B, l, i_lo, k);
+            const int rc = launch_bf3_upper<true>(ctx, s, "ibutterfly_upper", A, nullptr, l, i_lo, k);
             if (rc) return rc;
         }
     }

@@ -128,7 +128,10 @@ __device__ __forceinline__ void ktable_basis(uint64_t *basis, int d, uint32_t bh
     }
 }
 
-// fill entries [32 * item, 32 * item + 32) ... one work item = 8 consecutive entries
+// one work item = 8 entries of window k = item / 32: with m = item mod 32 the
+// entry pairs 32 j + m, j < 4 (entries 64 j + 2 m and 64 j + 2 m + 1).  Work
+// items m, m + 1 write adjacent 16-byte pairs, so the lanes of a wave store one
+// contiguous run and the LDS writes are free of bank conflicts.
 __device__ __forceinline__ void ktable_fill_item(uint64_t *tab, const uint64_t *basis, int item)
 {
     const int k = item >> 5, m = item & 31;
@@ -136,12 +139,12 @@ __device__ __forceinline__ void ktable_fill_item(uint64_t *tab, const uint64_t *
     uint64_t base = 0;
 #pragma unroll
     for (int v = 0; v < 5; ++v)
-        if ((m >> v) & 1) base ^= bs[3 + v];
-    const uint64_t b0 = bs[0], b1 = bs[1], b2 = bs[2];
-    ulonglong2 *t = reinterpret_cast<ulonglong2 *>(tab + k * 256 + m * 8);   // 16-byte LDS writes
-    const uint64_t x01 = b0 ^ b1, c = base ^ b2;
+        if ((m >> v) & 1) base ^= bs[1 + v];
+    const uint64_t b0 = bs[0], b6 = bs[6], b7 = bs[7];
+    ulonglong2 *t = reinterpret_cast<ulonglong2 *>(tab + k * 256) + m;
+    const uint64_t c1 = base ^ b6, c2 = base ^ b7, c3 = c1 ^ b7;
     t[0] = make_ulonglong2(base, base ^ b0);
-    t[1] = make_ulonglong2(base ^ b1, base ^ x01);
-    t[2] = make_ulonglong2(c, c ^ b0);
-    t[3] = make_ulonglong2(c ^ b1, c ^ x01);
+    t[32] = make_ulonglong2(c1, c1 ^ b0);
+    t[64] = make_ulonglong2(c2, c2 ^ b0);
+    t[96] = make_ulonglong2(c3, c3 ^ b0);
 }

@@ -127,9 +127,9 @@ __device__ __forceinline__ void b2_layer(uint64_t (&xa)[8], uint64_t (&xb)[8], c
 // or from the bottom (inverse); a group of fewer than three rows is padded
 // with the highest other tile bits, on which no layer runs.
 
-template <int K>
+template <int K, int TLG = B2_TILE_LG>
 struct B2Upper {
-    static constexpr int LGW = B2_TILE_LG - K;
+    static constexpr int LGW = TLG - K;
     static constexpr int NC = (K + 2) / 3;
     // rows of group c (forward order): [lo, hi]
     static constexpr int lo_row(int c) { return K - 3 * c - 3 < 0 ? 0 : K - 3 * c - 3; }
@@ -142,17 +142,17 @@ struct B2Group {
     int layer[3];   // 1 if a layer runs on register bit m
 };
 
-template <int K>
+template <int K, int TLG = B2_TILE_LG>
 __device__ __forceinline__ B2Group b2_upper_group(int c)
 {
-    using U = B2Upper<K>;
+    using U = B2Upper<K, TLG>;
     const int lo = U::lo_row(c), hi = U::hi_row(c), n = hi - lo + 1;
     int bits[3], lay[3], cnt = 0;
     for (int r = lo; r <= hi; ++r) {
         bits[cnt] = U::LGW + r;
         lay[cnt++] = 1;
     }
-    for (int b = B2_TILE_LG - 1; cnt < 3 && b >= 0; --b) {
+    for (int b = TLG - 1; cnt < 3 && b >= 0; --b) {
         if (b >= U::LGW + lo && b <= U::LGW + hi) continue;
         bits[cnt] = b;
         lay[cnt++] = 0;
@@ -177,12 +177,13 @@ __device__ __forceinline__ B2Group b2_upper_group(int c)
     return g;
 }
 
-// tile index of thread t's value with register bits zero: the 8 thread bits
+// tile index of thread t's value with register bits zero: the thread bits
 // fill the tile bits outside the group, lowest first
+template <int TLG = B2_TILE_LG>
 __device__ __forceinline__ int b2_thread_base(const B2Group &g, int t)
 {
     int e = 0, q = 0;
-    for (int b = 0; b < B2_TILE_LG; ++b) {
+    for (int b = 0; b < TLG; ++b) {
         if (b == g.s[0] || b == g.s[1] || b == g.s[2]) continue;
         e |= ((t >> q) & 1) << b;
         ++q;
@@ -190,10 +191,10 @@ __device__ __forceinline__ int b2_thread_base(const B2Group &g, int t)
     return e;
 }
 
-template <int K>
+template <int K, int TLG = B2_TILE_LG>
 __device__ __forceinline__ uint64_t b2_upper_global(int e, uint64_t gbase, int i_lo)
 {
-    constexpr int LGW = B2Upper<K>::LGW;
+    constexpr int LGW = B2Upper<K, TLG>::LGW;
     return gbase | (uint64_t)(e & ((1 << LGW) - 1)) | ((uint64_t)(e >> LGW) << i_lo);
 }
 
