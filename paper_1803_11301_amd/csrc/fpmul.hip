@@ -472,20 +472,61 @@ static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
     return 0;
 }
 
+#define BF3_WIDE 6      // bottom layers below this use the V_16 split
+#define BF3_MIN_L 20    // resident-table bottom pass from 2^20 transform values
+
+template <bool INV>
+static int launch_bf3_bottom(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l)
+{
+    const uint64_t nops = B ? 2 : 1, ntiles = 1ull << (l - B3_TILE_LG);
+    const uint64_t per_op = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)ctx->num_cu / nops));
+    if (l < B3_TILE_LG) return fail(POLYMUL_EINVAL, "bottom pass needs at least one tile");
+    KLAUNCH(ctx, s, name, (k_bf3_bottom<INV, BF3_WIDE>), (unsigned)(per_op * nops), B3_THREADS, A, B, l,
+            ctx->tables);
+    return 0;
+}
+
 // Butterflies of one transform (mode BF_FWD or BF_INV) or of a product
-// (BF_PRODUCT: forward A and B, pointwise, inverse; result in A)
+// (BF_PRODUCT: forward A and B, pointwise, inverse; result in A).  Large
+// transforms: upper passes down to layer 6, then the bottom pass of layers
+// 0 .. 5, all with resident K tables.  Smaller ones: upper passes down to
+// layer 11 and the 2^11-value bottom pass (more tiles to spread).
 static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B, int l, hipStream_t s)
 {
+    const uint64_t n = 1ull << l;
+    if (l >= BF3_MIN_L) {
+        // the lowest upper pass starts at layer 6 and so needs 7 layers
+        // (i_lo >= 12 - K); the layers above it are split evenly
+        auto groups = upper_groups(l, B3_BOT_LAYERS + BF_UPPER_MAXK);
+        groups.insert(groups.begin(), {B3_BOT_LAYERS, BF_UPPER_MAXK});
+        int rc;
+        if (mode != BF_INV) {
+            for (auto it = groups.rbegin(); it != groups.rend(); ++it)
+                if ((rc = launch_bf3_upper<false>(ctx, s, "butterfly_upper", A, mode == BF_PRODUCT ? B : nullptr, l,
+                                                  it->first, it->second)))
+                    return rc;
+            if ((rc = launch_bf3_bottom<false>(ctx, s, "butterfly_bottom", A, mode == BF_PRODUCT ? B : nullptr, l)))
+                return rc;
+        }
+        if (mode == BF_PRODUCT)
+            KLAUNCH(ctx, s, "pointwise", k_pointwise,
+                    (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu * 2), 1024, A, B, n,
+                    ctx->tables);
+        if (mode != BF_FWD) {
+            if ((rc = launch_bf3_bottom<true>(ctx, s, "ibutterfly_bottom", A, nullptr, l))) return rc;
+            for (auto it = groups.begin(); it != groups.end(); ++it)
+                if ((rc = launch_bf3_upper<true>(ctx, s, "ibutterfly_upper", A, nullptr, l, it->first, it->second)))
+                    return rc;
+        }
+        return 0;
+    }
     const int R = std::min(l, BF_BOTTOM_R);
     const auto groups = upper_groups(l, R);
-    const dim3 blk(BF_THREADS), ublk(BF_UP_THREADS);
-    const uint64_t persist_up = (uint64_t)ctx->num_cu * 2, persist_bot = (uint64_t)ctx->num_cu;
+    const dim3 blk(BF_THREADS);
+    const uint64_t persist_bot = (uint64_t)ctx->num_cu;
     if (mode != BF_INV) {
         for (auto it = groups.rbegin(); it != groups.rend(); ++it) {
-            const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
-            (void)lgW;
-            (void)persist_up;
-            (void)ublk;
+            const int i_lo = it->first, k = it->second;
             const int rc = launch_bf3_upper<false>(ctx, s, "butterfly_upper", A, mode == BF_PRODUCT ? B : nullptr,
                                                    l, i_lo, k);
             if (rc) return rc;
@@ -496,7 +537,6 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - B2_TILE_LG), (uint64_t)ctx->num_cu * 2);
         if (mode == BF_PRODUCT) {
             KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD2>, bt, B2_THREADS, A, B, l, ctx->tables);
-            const uint64_t n = 1ull << l;
             KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
                                                                                    (uint64_t)ctx->num_cu * 2),
                     1024, A, B, n, ctx->tables);
@@ -520,9 +560,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
     }
     if (mode != BF_FWD) {
         for (auto it = groups.begin(); it != groups.end(); ++it) {
-            const int i_lo = it->first, k = it->second, lgW = std::min(BF_UPPER_LGW, i_lo);
-            (void)lgW;
-            const int rc = launch_bf3_upper<true>(ctx, s, "ibutterfly_upper", A, nullptr, l, i_lo, k);
+            const int rc = launch_bf3_upper<true>(ctx, s, "ibutterfly_upper", A, nullptr, l, it->first, it->second);
             if (rc) return rc;
         }
     }

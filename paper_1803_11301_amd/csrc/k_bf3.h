@@ -162,3 +162,169 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_upper(uint64_t *__restric
         }
     }
 }
+
+// ----------------------------------------------------------- bottom pass ---
+//
+// Layers 0 .. 5 on contiguous tiles of 2^12 values, all six K tables
+// resident.  Register groups (forward order) {3,4,5} then {0,1,2}; one
+// exchange per tile.  Layers below WIDE use the V_16 split of k_bf2.h
+// (K16 + beta16, K16 changes once per 2^(i+4) tiles); the others use the V_8
+// split.  Within a 2^12 tile, K of the V_8 split is constant only from layer
+// 4 up, so WIDE >= 4.
+
+#define B3_BOT_LAYERS 6
+
+__device__ __forceinline__ B2Group bf3_bottom_group(int c)
+{
+    B2Group g;
+    const int lo = c == 0 ? 3 : 0;
+    g.s[0] = lo;
+    g.s[1] = lo + 1;
+    g.s[2] = lo + 2;
+    g.layer[0] = g.layer[1] = g.layer[2] = 1;
+    return g;
+}
+
+template <int WIDE>
+__device__ __forceinline__ uint32_t bf3_bottom_key(uint64_t gbase, int i)
+{
+    return i < WIDE ? (uint32_t)(gbase >> (i + 16)) << 8 : (uint32_t)(gbase >> (i + 8));
+}
+
+template <bool INV, int WIDE>
+__device__ __forceinline__ void bf3_bottom_compute(const B2Group &g, uint64_t (&x)[8], uint64_t (*s_tab)[2048],
+                                                   const PermTab *s_ptb, const PermTab *s_pt8,
+                                                   const uint16_t (*s_io16)[256], const uint4 &q01, uint32_t q2,
+                                                   uint64_t gb_t, const DevTables *__restrict__ T)
+{
+    auto run = [&](auto Mc) {
+        constexpr int M = decltype(Mc)::value;
+        const int i = g.s[M];
+        if (i < WIDE) {
+            const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
+            const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 0x7FFFu, bw2 = ((1u << g.s[2]) >> (i + 1)) & 0x7FFFu;
+            b2_layer16<M, INV, false>(x, x, s_tab[i], s_pt8, s_io16, q01, q2, b_t, bw1, bw2);
+        } else {
+            const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
+            const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 127u, bw2 = ((1u << g.s[2]) >> (i + 1)) & 127u;
+            b2_layer<M, INV, false>(x, x, s_tab[i], s_ptb, T, bl_t, bw1, bw2);
+        }
+    };
+    if (!INV) {
+        run(std::integral_constant<int, 2>());
+        run(std::integral_constant<int, 1>());
+        run(std::integral_constant<int, 0>());
+    } else {
+        run(std::integral_constant<int, 0>());
+        run(std::integral_constant<int, 1>());
+        run(std::integral_constant<int, 2>());
+    }
+}
+
+// Layers 0 .. 5 of A (and of B when B is not null: the second half of the
+// grid takes B; the grid is then even).  l >= 12.
+template <bool INV, int WIDE>
+__global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
+                                                                int l, const DevTables *__restrict__ T)
+{
+    static_assert(WIDE >= 4 && WIDE <= B3_BOT_LAYERS, "the V_8 split needs a constant K over the tile");
+    __shared__ __align__(16) uint64_t s_tab[B3_BOT_LAYERS][2048];   // K table of layer i
+    __shared__ __align__(16) uint64_t s_x[B3_STAGE_WORDS];
+    __shared__ __align__(16) PermTab s_ptb[128];        // tables of iota(2 bl), bl < 128
+    __shared__ __align__(16) PermTab s_pt8[256];        // tables of every byte of V_8
+    __shared__ uint16_t s_io16[2][256];                 // iota of the low two Cantor bytes
+    __shared__ uint64_t s_pb[24][64];                   // basis rows of the bits of bh
+    __shared__ uint64_t s_img[64];
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    for (int q = tid; q < 128 * 8; q += nth)
+        reinterpret_cast<uint32_t *>(s_ptb)[q] = reinterpret_cast<const uint32_t *>(T->pt_beta8)[q];
+    for (int q = tid; q < 256 * 8; q += nth)
+        reinterpret_cast<uint32_t *>(s_pt8)[q] = reinterpret_cast<const uint32_t *>(T->pt8)[q];
+    for (int q = tid; q < 2 * 256; q += nth) (&s_io16[0][0])[q] = (uint16_t)(&T->iota[0][0])[q];
+    b2_load_pbasis(s_pb, T, tid, nth);
+    __syncthreads();
+    const PermTab *Q = s_pt8 + 0x80;   // v_7 = Cantor byte 0x80
+    const uint4 q01 = *reinterpret_cast<const uint4 *>(Q);
+    const uint32_t q2 = Q->t2;
+
+    const unsigned nops = B ? 2u : 1u, per_op = gridDim.x / nops;
+    const unsigned op = blockIdx.x / per_op;
+    if (op >= nops) return;   // uniform per workgroup
+    uint64_t *__restrict__ X = op ? B : A;
+    const uint64_t bid = blockIdx.x - (uint64_t)op * per_op;
+    const uint64_t ntiles = 1ull << (l - B3_TILE_LG);
+    const uint64_t per = (ntiles + per_op - 1) / per_op;
+    const uint64_t t_beg = bid * per, t_end = t_beg + per < ntiles ? t_beg + per : ntiles;
+    if (t_beg >= t_end) return;   // uniform per workgroup
+
+    const B2Group g0 = bf3_bottom_group(INV ? 1 : 0);
+    const int e0 = b2_thread_base<B3_TILE_LG>(g0, tid);
+    auto load = [&](uint64_t tile, uint64_t(&v)[8]) {
+        const uint64_t gbase = tile << B3_TILE_LG;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int e = e0 | ((r & 1) << g0.s[0]) | (((r >> 1) & 1) << g0.s[1]) | ((r >> 2) << g0.s[2]);
+            v[r] = X[gbase | (uint64_t)e];
+        }
+    };
+
+    uint32_t key[B3_BOT_LAYERS];
+#pragma unroll
+    for (int i = 0; i < B3_BOT_LAYERS; ++i) key[i] = 0xFFFFFFFFu;
+    uint64_t x[8], nx[8];
+    load(t_beg, nx);
+    for (uint64_t tile = t_beg; tile < t_end; ++tile) {
+        const uint64_t gbase = tile << B3_TILE_LG;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) x[r] = nx[r];
+        if (tile + 1 < t_end) load(tile + 1, nx);   // in flight during this tile
+
+        // rebuild the tables whose K changed; uniform over the workgroup
+        bool changed = false;
+#pragma unroll
+        for (int i = 0; i < B3_BOT_LAYERS; ++i) {
+            const uint32_t bh = bf3_bottom_key<WIDE>(gbase, i);
+            if (key[i] != bh) {
+                key[i] = bh;
+                changed = true;
+                __syncthreads();   // s_tab[i] and s_img no longer read
+                if (tid < 64) b2_basis(s_img, l - i, bh, s_pb, T, tid);
+                __syncthreads();
+                for (int item = tid; item < 256; item += nth) ktable_fill_item(s_tab[i], s_img, item);
+            }
+        }
+        if (changed) __syncthreads();
+
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int c = INV ? 1 - cc : cc;
+            const B2Group g = bf3_bottom_group(c);
+            const int e_t = b2_thread_base<B3_TILE_LG>(g, tid);
+            if (cc > 0) {
+                const B2Group gp = bf3_bottom_group(1 - c);
+                const int ep = b2_thread_base<B3_TILE_LG>(gp, tid);
+                __syncthreads();   // the previous exchange has been read
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = ep | ((r & 1) << gp.s[0]) | (((r >> 1) & 1) << gp.s[1]) | ((r >> 2) << gp.s[2]);
+                    s_x[b2_pad(e)] = x[r];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    x[r] = s_x[b2_pad(e)];
+                }
+            }
+            bf3_bottom_compute<INV, WIDE>(g, x, s_tab, s_ptb, s_pt8, s_io16, q01, q2, gbase | (uint64_t)e_t, T);
+            if (cc == 1) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
+                    X[gbase | (uint64_t)e] = x[r];
+                }
+            }
+        }
+    }
+}

@@ -74,7 +74,7 @@ def test_basiscvt_against_definition(ctx, log2n):
         assert O.words_to_int(back, n) == f
 
 
-@pytest.mark.parametrize("log2n", [6, 7, 8, 9, 12, 13, 16, 17, 18, 19, 24])
+@pytest.mark.parametrize("log2n", [6, 7, 8, 9, 12, 13, 16, 17, 18, 19, 24, 26, 27])
 def test_addfft_is_evaluation_at_sigma(ctx, log2n):
     say("addfft", log2n)
     rng = random.Random(100 + log2n)
@@ -206,9 +206,9 @@ def test_mid_config_exact(ctx):
     assert int(got[-1]) >> 62 == 1   # degree 2^25 - 2 is present
 
 
-def test_large_config_sampled(ctx):
-    L = 1 << 30
-    say("2^30 x 2^30 sampled", hex(synth.SEED_LARGE))
+@pytest.mark.parametrize("L", [1 << 25, (1 << 26) - 5, 1 << 30])
+def test_large_config_sampled(ctx, L):
+    say(L, "x", L, "sampled", hex(synth.SEED_LARGE))
     a, b = synth.single_pair(synth.SEED_LARGE, L)
     got = gpu_product(ctx, a, L, b, L)
     rng = random.Random(30)
