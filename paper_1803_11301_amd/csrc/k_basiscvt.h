@@ -577,43 +577,105 @@ struct BcElemSteps {
     static constexpr BcStepList L = bc_steps_of(LGR);
 };
 
+// V consecutive column elements as one LDS access (up to 16 bytes)
+template <typename T, int V>
+struct BcVec;
+template <> struct BcVec<uint32_t, 1> { using type = uint32_t; };
+template <> struct BcVec<uint32_t, 2> { using type = uint2; };
+template <> struct BcVec<uint32_t, 4> { using type = uint4; };
+template <> struct BcVec<uint64_t, 1> { using type = uint64_t; };
+template <> struct BcVec<uint64_t, 2> { using type = ulonglong2; };
+
+__device__ __forceinline__ void bc_xorv(uint32_t &a, uint32_t b) { a ^= b; }
+__device__ __forceinline__ void bc_xorv(uint64_t &a, uint64_t b) { a ^= b; }
+__device__ __forceinline__ void bc_xorv(uint2 &a, uint2 b) { a.x ^= b.x; a.y ^= b.y; }
+__device__ __forceinline__ void bc_xorv(uint4 &a, uint4 b) { a.x ^= b.x; a.y ^= b.y; a.z ^= b.z; a.w ^= b.w; }
+__device__ __forceinline__ void bc_xorv(ulonglong2 &a, ulonglong2 b) { a.x ^= b.x; a.y ^= b.y; }
+
+// one phase of step (2^LGS, 2^LGD) on the column, V consecutive elements per
+// access (V divides d, so both operands of every access are V-aligned)
 template <int LGS, int LGD, int PHASE, typename T>
 __device__ __forceinline__ void bc_elem_phase(T *v, int lgR, int tid, int nth)
 {
-    constexpr int H = 1 << (LGS - 1), d = 1 << LGD;
+    constexpr int LGH = LGS - 1, H = 1 << LGH, d = 1 << LGD;
+    constexpr int VMAX = 16 / (int)sizeof(T), V = d < VMAX ? d : VMAX, LGV = V == 4 ? 2 : V == 2 ? 1 : 0;
+    using VT = typename BcVec<T, V>::type;
+    VT *vv = reinterpret_cast<VT *>(v);
     if (PHASE == 0) {
         // hi[0, d) ^= hi[H - d, H) in every segment
-        const int nt = 1 << (lgR - LGS + LGD);
+        const int nt = 1 << (lgR - LGS + LGD - LGV);
         for (int t = tid; t < nt; t += nth) {
-            const int sg = t >> LGD, p = t & (d - 1);
-            T *hp = v + (sg << LGS) + H;
-            hp[p] ^= hp[p + H - d];
+            const int sg = t >> (LGD - LGV), q = t & ((d >> LGV) - 1);
+            const int a = (sg << (LGS - LGV)) + ((H >> LGV) + q);
+            VT x = vv[a];
+            bc_xorv(x, vv[a + ((H - d) >> LGV)]);
+            vv[a] = x;
+        }
+    } else if (2 * d == H) {
+        // lo[d, H) ^= hi[0, H - d): H - d = d chunks of a power-of-two count
+        const int nt = 1 << (lgR - LGS + LGD - LGV);
+        for (int t = tid; t < nt; t += nth) {
+            const int sg = t >> (LGD - LGV), q = t & ((d >> LGV) - 1);
+            const int a = (sg << (LGS - LGV)) + ((d >> LGV) + q);
+            VT x = vv[a];
+            bc_xorv(x, vv[a + ((H - d) >> LGV)]);
+            vv[a] = x;
         }
     } else {
-        // lo[d, H) ^= hi[0, H - d)
-        constexpr int LGW = (LGS - 1) > LGD ? 0 : 0;
-        (void)LGW;
-        const int per = H - d;                                // elements per segment
-        const int nt = (1 << (lgR - LGS)) * per;
+        // lo[d, H) ^= hi[0, H - d): all of lo, the first d elements left alone
+        const int nt = 1 << (lgR - 1 - LGV);
         for (int t = tid; t < nt; t += nth) {
-            const int sg = t / per, p = d + t % per;
-            T *lp = v + (sg << LGS);
-            lp[p] ^= lp[H + p - d];
+            const int sg = t >> (LGH - LGV), q = t & ((H >> LGV) - 1);
+            if (q < (d >> LGV)) continue;
+            const int a = (sg << (LGS - LGV)) + q;
+            VT x = vv[a];
+            bc_xorv(x, vv[a + ((H - d) >> LGV)]);
+            vv[a] = x;
         }
     }
 }
 
+// LDS accesses of the lanes of one wave are made visible to the wave's other
+// lanes (DS instructions of a wave complete in order; the fences keep the
+// compiler from moving accesses across)
+__device__ __forceinline__ void bc_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Steps [K, L.n) of BasisCvt(2^LGR) on a column of a BC_COL_THREADS
+// workgroup.  A step whose segments (2^LGS elements) fit in one wave's share
+// of 2^(LGR - 4) consecutive elements runs on that share alone, ordered by
+// wave-level syncs instead of workgroup barriers.
 template <int LGR, int K, bool INV, typename T>
 __device__ __forceinline__ void bc_elem_steps_from(T *v, int tid, int nth)
 {
     constexpr BcStepList L = BcElemSteps<LGR>::L;
+    constexpr int LGL = LGR - 4;   // log2 elements per wave (16 waves)
+    static_assert(BC_COL_THREADS == 1024, "16 waves per column workgroup");
     if constexpr (K < L.n) {
         constexpr int k = INV ? L.n - 1 - K : K;
         constexpr int LGS = L.lgs[k], LGD = L.lgd[k];
-        bc_elem_phase<LGS, LGD, INV ? 1 : 0>(v, LGR, tid, nth);
-        __syncthreads();
-        bc_elem_phase<LGS, LGD, INV ? 0 : 1>(v, LGR, tid, nth);
-        __syncthreads();
+        constexpr bool LOCAL = LGS <= LGL;
+        if constexpr (LOCAL) {
+            constexpr int kn = INV ? L.n - 2 - K : K + 1;   // the next step, if any
+            constexpr bool NEXT_LOCAL = K + 1 < L.n && L.lgs[kn < 0 ? 0 : kn] <= LGL;
+            T *w = v + ((tid >> 6) << LGL);
+            bc_elem_phase<LGS, LGD, INV ? 1 : 0>(w, LGL, tid & 63, 64);
+            bc_wave_sync();
+            bc_elem_phase<LGS, LGD, INV ? 0 : 1>(w, LGL, tid & 63, 64);
+            if constexpr (NEXT_LOCAL)
+                bc_wave_sync();
+            else
+                __syncthreads();
+        } else {
+            bc_elem_phase<LGS, LGD, INV ? 1 : 0>(v, LGR, tid, nth);
+            __syncthreads();
+            bc_elem_phase<LGS, LGD, INV ? 0 : 1>(v, LGR, tid, nth);
+            __syncthreads();
+        }
         bc_elem_steps_from<LGR, K + 1, INV>(v, tid, nth);
     }
 }
