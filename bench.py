@@ -61,10 +61,10 @@ KERNEL_BYTES = {
 # taken on: the sha256 of the listed files must match, else traffic is null.
 MEASURED_TRAFFIC = {
     "butterfly_upper": {
-        "bytes": (262472 * 2 + 524288) * 1024,
-        "sources": ("paper_1803_11301_amd/csrc/k_bf2.h", "paper_1803_11301_amd/csrc/k_butterfly.h",
+        "bytes": ((2 * 262398 + 263198) * 2 // 3 + 524288) * 1024,
+        "sources": ("paper_1803_11301_amd/csrc/k_bf3.h", "paper_1803_11301_amd/csrc/k_bf2.h",
                     "paper_1803_11301_amd/csrc/gf_device.h"),
-        "sha256": "ff4bbf991719f25e1a3c770f5921940776cfb791312ba0b9f3e6dd27606e6c8c",
+        "sha256": "ca334ca4cd1d52ff2c7f949b20f2143f7151fbdbfef819d0713ba3f159e6b559",
     },
 }
 

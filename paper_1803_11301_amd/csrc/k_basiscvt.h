@@ -35,6 +35,7 @@
 #define BC_ZETA_LDS 4096              // words of a zeta tile (2^nb rows x 2^lgWc words)
 #define BC_ROW_THREADS 512            // row kernels (two workgroups per CU)
 #define BC_COL_THREADS 1024           // column kernels (one workgroup per CU)
+#define BC_XCDS 8                     // accelerator complex dies (separate L2 caches)
 #define BC_MAX_STEPS 96
 
 struct BcSteps {
@@ -912,7 +913,12 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *
     __shared__ __align__(16) uint64_t rows[BC_ROWS * BC_TAU_WORDS];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
-    for (int q0 = blockIdx.x * T; q0 < R; q0 += gridDim.x * T) {
+    // workgroups go to the 8 XCDs round robin; those of one XCD take
+    // consecutive row groups, so that each 128-byte line of a column (32
+    // rows) is fetched once into that XCD's L2 rather than into four
+    const unsigned G = gridDim.x, b = blockIdx.x;
+    const unsigned w = G % BC_XCDS == 0 ? (b % BC_XCDS) * (G / BC_XCDS) + b / BC_XCDS : b;
+    for (int q0 = (int)w * T; q0 < R; q0 += (int)G * T) {
         for (int e = tid; e < T * 2 * BC_TAU_WORDS; e += nth) {
             const int k = e % T, c = e / T;                 // 32-bit column c of row q0 + k
             reinterpret_cast<uint32_t *>(rows)[k * 2 * BC_TAU_WORDS + c] = Y32[(uint64_t)c * R + q0 + k];
