@@ -474,6 +474,7 @@ static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
 
 #define BF3_WIDE 6      // bottom layers below this use the V_16 split
 #define BF3_MIN_L 20    // resident-table bottom pass from 2^20 transform values
+#define SINGLE_VIA_BATCH_LOG2N 17   // polymul_ex of products up to 2^17 bits runs as a one-item batch
 
 template <bool INV>
 static int launch_bf3_bottom(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l)
@@ -885,10 +886,12 @@ static size_t batch_ws_bytes(const polymul_ctx *ctx, uint32_t count, uint64_t ma
     return batch_layout(ctx, count, max_bits).total;
 }
 
+// one_host: a single product given on the host; its descriptor goes into
+// the workspace (the 256-byte tail beside the queue counter)
 static int batch_body(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, const uint64_t *a_off,
                       const uint64_t *len_a, const uint64_t *b_pool, const uint64_t *b_off, const uint64_t *len_b,
                       uint64_t *out_pool, const uint64_t *out_off, const BtDesc *desc, uint64_t max_bits,
-                      int32_t *status, hipStream_t s)
+                      int32_t *status, hipStream_t s, const BtDesc *one_host = nullptr)
 {
     int rc;
     if ((rc = batch_steps_upload(ctx)) || (rc = set_lds_limits())) return rc;
@@ -916,6 +919,11 @@ static int batch_body(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, 
     uint64_t *slab = static_cast<uint64_t *>(ctx->bws);
     uint32_t *order = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + slab_bytes);
     uint32_t *counter = reinterpret_cast<uint32_t *>(static_cast<char *>(ctx->bws) + slab_bytes + order_bytes);
+    if (one_host) {
+        BtDesc *d1 = reinterpret_cast<BtDesc *>(static_cast<char *>(ctx->bws) + slab_bytes + order_bytes + 64);
+        KLAUNCH(ctx, s, "batch_desc", k_bt_put_desc, 1, 64, *one_host, d1);
+        desc = d1;
+    }
     KLAUNCH(ctx, s, "batch_plan", k_batch_plan, 1, 1024, count, len_a, len_b, desc, max_bits, order, counter);
     KLAUNCH_LDS(ctx, s, "batch", k_batch, grid, BT_THREADS, bf_bottom_lds(BF_BOTTOM_R, true), a_pool, a_off, len_a,
                 b_pool, b_off, len_b, out_pool, out_off, desc, status, count, max_bits, order, counter, slab,
@@ -1052,6 +1060,14 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
     if (ranges_overlap(out, ob, a, (size_t)((len_a + 63) / 64) * 8) ||
         ranges_overlap(out, ob, b, (size_t)((len_b + 63) / 64) * 8))
         return fail(POLYMUL_EINVAL, "out overlaps an input");
+    const int log2n = transform_log2(len_a, len_b);
+    if (log2n <= SINGLE_VIA_BATCH_LOG2N) {
+        // a small product is one workgroup's work: the batch kernel takes it in
+        // three launches instead of one launch per BasisCvt step
+        const BtDesc one{a, b, out, len_a, len_b};
+        return batch_body(ctx, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                          1ull << log2n, nullptr, (hipStream_t)stream, &one);
+    }
     return product_body(ctx, a, len_a, b, len_b, out, (hipStream_t)stream);
 }
 

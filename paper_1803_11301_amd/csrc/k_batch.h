@@ -43,6 +43,12 @@ struct BtDesc {
     uint64_t la, lb;
 };
 
+// writes a descriptor passed by value (a single product through the batch path)
+__global__ void k_bt_put_desc(BtDesc d, BtDesc *__restrict__ dst)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
+}
+
 __device__ __forceinline__ int bt_ceil_log2(uint64_t x) { return x <= 1 ? 0 : 64 - __clzll(x - 1); }
 
 // transform log2 of a product, or -1 if it has no bits, or BT_MAX_LOG2N + 1
