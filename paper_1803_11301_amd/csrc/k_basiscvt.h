@@ -31,7 +31,7 @@
 #include "gf_device.h"
 
 #define BC_TAU_WORDS 1024            // tau = 2^16 bits
-#define BC_THREADS 256                // zeta tiles, final store
+#define BC_THREADS 256                // zeta tiles, final store (divides BC_TAU_WORDS)
 #define BC_ZETA_LDS 4096              // words of a zeta tile (2^nb rows x 2^lgWc words)
 #define BC_ROW_THREADS 512            // row kernels (two workgroups per CU)
 #define BC_COL_THREADS 1024           // column kernels (one workgroup per CU)
@@ -941,13 +941,25 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_inv_store(const uint64_t *__r
     const int tid = threadIdx.x, nth = blockDim.x;
     const int R = 1 << lgR;
     const uint64_t outw = (len + 63) / 64;
+    // the loads of the row's words a thread handles go out together
+    constexpr int PER = BC_TAU_WORDS / BC_THREADS;
     for (int r = blockIdx.x; r < R; r += gridDim.x) {
         const uint64_t *xr = X + (uint64_t)r * EW;
         const uint64_t *xp = r ? X + (uint64_t)(r - 1) * EW : nullptr;
-        for (int w = tid; w < BC_TAU_WORDS; w += nth) {
+        const int sh = r & 63, wr = r >> 6;   // output word w = bits [64 (w + wr) + sh, + 64) of row r
+        uint64_t a[PER], b[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid + k * nth + wr;
+            a[k] = i < EW ? xr[i] : 0ull;
+            b[k] = i + 1 < EW ? xr[i + 1] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int w = tid + k * nth;
             const uint64_t ow = (uint64_t)r * BC_TAU_WORDS + w;
             if (ow >= outw) continue;
-            uint64_t v = bc_bits(xr, EW, 64L * w + r);
+            uint64_t v = sh ? ((a[k] >> sh) | (b[k] << (64 - sh))) : a[k];
             if (xp && 64 * w < R) {
                 uint64_t h = bc_bits(xp, EW, 64L * (BC_TAU_WORDS + w) + (r - 1));
                 if (64 * (w + 1) > R) h &= bc_lowmask(R - 64 * w);
