@@ -117,6 +117,22 @@ int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, cons
                   uint64_t *out_pool, const uint64_t *out_word_off, uint64_t max_product_bits, int32_t *status,
                   void *stream);
 
+/* Largest transform (log2 of its bits) that the m = 32 field supports. */
+#define POLYMUL_SMALL_FIELD_MAX_LOG2N 20
+
+/*
+ * polymul_set_small_field -- the m = 32 variant of Sec. 3 for small products
+ * (the field size limit n < (m/2) 2^(m/2) gives 2^20 bits for m = 32):
+ * batch items whose transform has at most 2^max_log2n bits (polymul_batch,
+ * the batched launches of the server, and polymul_ex products of at most
+ * 2^17 bits, which run as one-item batches) are computed over GF(2^32)
+ * instead of GF(2^64).  The product is the same either way.  0 keeps every
+ * item on GF(2^64).  Default: 20.  Affects launches enqueued afterwards (a
+ * server created later on ctx takes the value at its creation).
+ * Returns 0, or POLYMUL_EINVAL for a null ctx or max_log2n outside [0, 20].
+ */
+int polymul_set_small_field(polymul_ctx *ctx, int max_log2n);
+
 /*
  * Product server: continuous batching of product requests on one GPU.
  *

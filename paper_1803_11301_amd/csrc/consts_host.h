@@ -193,6 +193,8 @@ struct Tables {
     uint64_t iota[8][256];
     uint64_t enc[64];
     uint64_t dec[64];
+    uint32_t enc32[32];         // m = 32: Encode rows r_j = prod over set bits k of j (k < 5) of v_{16-k}
+    uint32_t dec32[32];         // m = 32: inverse of the Encode matrix
     Tower tw;
 };
 
@@ -262,6 +264,25 @@ static inline void build_tables(Tables &T)
         T.enc[j] = r;
     }
     invert64(T.enc, T.dec);
+    // the same for m = 32 (Sec. 3, Eq. 9 with l_m = 5): the elements lie in
+    // GF(2^32), the low half of the tower representation
+    uint64_t e64[64], d64[64];
+    for (int j = 0; j < 32; ++j) {
+        uint32_t r = 1;
+        for (int k = 0; k < 5; ++k)
+            if ((j >> k) & 1) {
+                if (T.cantor[16 - k] >> 32) throw std::runtime_error("v_{16-k} outside GF(2^32)");
+                r = T.tw.m32(r, (uint32_t)T.cantor[16 - k]);
+            }
+        T.enc32[j] = r;
+    }
+    // invert the 32 x 32 matrix inside a 64 x 64 one (identity on the top half)
+    for (int j = 0; j < 64; ++j) e64[j] = j < 32 ? (uint64_t)T.enc32[j] : 1ull << j;
+    invert64(e64, d64);
+    for (int j = 0; j < 32; ++j) {
+        if (d64[j] >> 32) throw std::runtime_error("m = 32 Encode inverse leaves GF(2^32)");
+        T.dec32[j] = (uint32_t)d64[j];
+    }
 }
 
 // 8-bit window tables of multiplication by c: tab[k*256 + e] = c * (e at byte k)

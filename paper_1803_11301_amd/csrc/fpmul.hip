@@ -201,6 +201,8 @@ struct ProfRec {
     hipEvent_t start, stop;
 };
 
+#define SMALL_FIELD_DEFAULT_LOG2N 20   // m = 32 batch items: transforms up to 2^20 bits
+
 struct polymul_ctx {
     int device = 0;
     size_t cap = 0;
@@ -213,6 +215,9 @@ struct polymul_ctx {
     BatchSteps *bsteps = nullptr;
     void *bws = nullptr;
     size_t bws_bytes = 0;
+    // batch items with transforms of at most 2^small_field_log2n bits run over
+    // GF(2^32) (m = 32); 0 keeps every item on m = 64
+    int small_field_log2n = SMALL_FIELD_DEFAULT_LOG2N;
     // per-kernel timing with HIP events on the launch stream (off by default)
     bool prof = false;
     std::vector<ProfRec> prof_live;       // recorded, not yet read
@@ -927,7 +932,7 @@ static int batch_body(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, 
     KLAUNCH(ctx, s, "batch_plan", k_batch_plan, 1, 1024, count, len_a, len_b, desc, max_bits, order, counter);
     KLAUNCH_LDS(ctx, s, "batch", k_batch, grid, BT_THREADS, bf_bottom_lds(BF_BOTTOM_R, true), a_pool, a_off, len_a,
                 b_pool, b_off, len_b, out_pool, out_off, desc, status, count, max_bits, order, counter, slab,
-                slab_words, ctx->tables, ctx->bsteps);
+                slab_words, ctx->tables, ctx->bsteps, ctx->small_field_log2n);
     return 0;
 }
 
@@ -974,6 +979,21 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
     };
     for (int bl = 0; bl < 128; ++bl) permtab((uint8_t)H.iota[0][2 * bl], D.pt_beta8[bl]);   // iota(2 bl) is in V_8
     for (int e = 0; e < 256; ++e) permtab((uint8_t)e, D.pt8[e]);
+    for (int k = 0; k < 4; ++k)
+        for (int e = 0; e < 256; ++e) {
+            uint32_t f = 0, a = 0;
+            for (int u = 0; u < 8; ++u)
+                if ((e >> u) & 1) {
+                    f ^= H.enc32[8 * k + u];
+                    a ^= H.dec32[8 * k + u];
+                }
+            D.enc32_win[k][e] = f;
+            D.dec32_win[k][e] = a;
+        }
+    for (int d = 0; d < 16; ++d)
+        for (int k = 0; k < 4; ++k)
+            for (int e = 0; e < 256; ++e)
+                D.kt32[d][256 * k + e] = tw.m32((uint32_t)H.cantor[16 + d], (uint32_t)e << (8 * k));
 }
 
 // ---------------------------------------------------------------------------
@@ -1069,6 +1089,15 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
                           1ull << log2n, nullptr, (hipStream_t)stream, &one);
     }
     return product_body(ctx, a, len_a, b, len_b, out, (hipStream_t)stream);
+}
+
+int polymul_set_small_field(polymul_ctx *ctx, int max_log2n)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (max_log2n < 0 || max_log2n > POLYMUL_SMALL_FIELD_MAX_LOG2N)
+        return fail(POLYMUL_EINVAL, "small-field limit must be in [0, 20]");
+    ctx->small_field_log2n = max_log2n;
+    return 0;
 }
 
 int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, const uint64_t *a_word_off,

@@ -28,6 +28,10 @@ struct DevTables {
     // {0,1,2}, {3,4,5}, {6,7} of a byte: t0lo t0hi t1lo t1hi t2 (3 words pad)
     uint32_t pt_beta8[128][8];
     uint32_t pt8[256][8];        // the same tables for every byte of V_8
+    // m = 32 (GF(2^32), the low half of the tower representation)
+    uint32_t enc32_win[4][256];  // Encode: byte window k of the 32-bit column -> sum of r_j
+    uint32_t dec32_win[4][256];  // Decode: byte window k of the value -> bits
+    uint32_t kt32[16][1024];     // window tables of v_{16+d}: [d][256 k + e] = v_{16+d} * (e at byte k)
 };
 
 // ----------------------------------------------------------------- tmul ----

@@ -12,6 +12,7 @@
 
 #include "gf_device.h"
 #include "k_basiscvt.h"
+#include "k_bf2.h"
 #include "k_butterfly.h"
 #include "k_steps.h"
 
@@ -247,6 +248,178 @@ __device__ void bt_upper_layer(uint64_t *__restrict__ X, uint64_t *__restrict__ 
     __syncthreads();
 }
 
+// ------------------------------------------------------------ m = 32 -----
+//
+// Small products over GF(2^32) (Sec. 3 with m = 32): n = 2^log2n <= 2^20 bits
+// ((m/2) 2^(m/2) = 2^20), n_p = n/32 values of 32 bits, l = log2n - 5 < 16.
+// GF(2^32) is the low half of the tower representation, so its elements are
+// 32-bit words.  Encode and Decode use 32 x 32 half-wave transposes and the
+// 32 x 32 matrix R (rows r_j = product of v_{16-k} over the set bits k of
+// j).  Butterfly layer i of block b multiplies by the element with Cantor
+// vector 2^(16+d) XOR 2b, d = l - i; since 2b < 2^15 this is
+//   x * v_{16+d}  (four 8-bit window lookups in its fixed table)
+// + x * beta16    (beta16 = iota(2b) in V_16: v_perm byte products as in the
+//                  V_16 split of the large passes).
+#define BT32_MAX_LOG2N 20
+#define BT32_OFF_K BF_OFF_DATA                        // window table of v_{16+d}, 4 KiB
+#define BT32_OFF_PT8 (BF_OFF_DATA + 4096)              // v_perm tables of every byte of V_8, 8 KiB
+#define BT32_OFF_IO16 (BF_OFF_DATA + 4096 + 8192)      // iota of the low two Cantor bytes, 1 KiB
+
+__device__ __forceinline__ uint32_t bt32_enc(const DevTables *__restrict__ T, uint32_t x)
+{
+    return T->enc32_win[0][x & 255u] ^ T->enc32_win[1][(x >> 8) & 255u] ^ T->enc32_win[2][(x >> 16) & 255u] ^
+           T->enc32_win[3][x >> 24];
+}
+
+__device__ __forceinline__ uint32_t bt32_dec(const DevTables *__restrict__ T, uint32_t h)
+{
+    return T->dec32_win[0][h & 255u] ^ T->dec32_win[1][(h >> 8) & 255u] ^ T->dec32_win[2][(h >> 16) & 255u] ^
+           T->dec32_win[3][h >> 24];
+}
+
+// 32 x 32 bit transpose in each half-wave: lane i holds row i, afterwards
+// lane t holds column t (bit i = bit t of row i); every lane takes part
+__device__ __forceinline__ uint32_t bt32_transpose(uint32_t x, int lane)
+{
+    x = bc_tstage<16>(x, 0x0000FFFFu, lane);
+    x = bc_tstage<8>(x, 0x00FF00FFu, lane);
+    x = bc_tstage<4>(x, 0x0F0F0F0Fu, lane);
+    x = bc_tstage<2>(x, 0x33333333u, lane);
+    return bc_tstage<1>(x, 0x55555555u, lane);
+}
+
+// Encode, m = 32: vals[i] = sum over j < 32 of bit (j n_p + i) of `bits` times r_j
+__device__ void bt_encode32(const uint64_t *__restrict__ bits, int l, uint32_t *__restrict__ vals,
+                            const DevTables *__restrict__ T, int tid, int nth)
+{
+    const uint32_t n_p = 1u << l;
+    if (l >= 5) {
+        const uint32_t *b32 = reinterpret_cast<const uint32_t *>(bits);
+        const int lane = tid & 63, t = lane & 31, half = lane >> 5, wave = tid >> 6, nwave = nth >> 6;
+        const uint32_t groups = n_p >> 5;
+        for (uint32_t g0 = 2 * wave; g0 < groups; g0 += 2 * nwave) {
+            // lane (half, j): bits j n_p + 32 g .. + 31 of row j, one 32-bit word
+            const uint32_t g = g0 + half;
+            uint32_t x = g < groups ? b32[((uint32_t)t << (l - 5)) + g] : 0u;
+            x = bt32_transpose(x, lane);
+            if (g < groups) vals[32 * g + t] = bt32_enc(T, x);
+        }
+    } else {
+        for (uint32_t i = tid; i < n_p; i += nth) {
+            uint32_t col = 0;
+            for (int j = 0; j < 32; ++j) {
+                const uint32_t p = ((uint32_t)j << l) + i;
+                col |= (uint32_t)((bits[p >> 6] >> (p & 63)) & 1ull) << j;
+            }
+            vals[i] = bt32_enc(T, col);
+        }
+    }
+}
+
+// Decode, m = 32: bit j of R^-1 vals[i] goes to bit j n_p + i of `bits` (n/64
+// words); tmp (n_p words of 32 bits) is scratch for l < 5
+__device__ void bt_decode32(const uint32_t *__restrict__ vals, int l, uint64_t *__restrict__ bits,
+                            uint32_t *__restrict__ tmp, const DevTables *__restrict__ T, int tid, int nth)
+{
+    const uint32_t n_p = 1u << l;
+    uint32_t *b32 = reinterpret_cast<uint32_t *>(bits);
+    if (l >= 5) {
+        const int lane = tid & 63, t = lane & 31, half = lane >> 5, wave = tid >> 6, nwave = nth >> 6;
+        const uint32_t groups = n_p >> 5;
+        for (uint32_t g0 = 2 * wave; g0 < groups; g0 += 2 * nwave) {
+            const uint32_t g = g0 + half;
+            uint32_t a = g < groups ? bt32_dec(T, vals[32 * g + t]) : 0u;
+            // lane (half, j) then holds bit j of the 32 vectors: bits j n_p + 32 g .. + 31
+            a = bt32_transpose(a, lane);
+            if (g < groups) b32[((uint32_t)t << (l - 5)) + g] = a;
+        }
+    } else {
+        for (uint32_t i = tid; i < n_p; i += nth) tmp[i] = bt32_dec(T, vals[i]);
+        __syncthreads();
+        // 32 n_p bits, i.e. n_p words of 32 bits: bit p is bit (p >> l) of tmp[p mod n_p]
+        for (uint32_t W = tid; W < n_p; W += nth) {
+            uint32_t r = 0;
+            for (int t = 0; t < 32; ++t) {
+                const uint32_t p = 32 * W + t;
+                r |= ((tmp[p & (n_p - 1)] >> (p >> l)) & 1u) << t;
+            }
+            b32[W] = r;
+        }
+    }
+}
+
+// v_perm tables and iota tables of the m = 32 layers into LDS
+__device__ __forceinline__ void bt32_load_tables(uint8_t *smem, const DevTables *__restrict__ T, int tid, int nth)
+{
+    uint32_t *s_pt8 = reinterpret_cast<uint32_t *>(smem + BT32_OFF_PT8);
+    uint16_t *s_io16 = reinterpret_cast<uint16_t *>(smem + BT32_OFF_IO16);
+    for (int q = tid; q < 256 * 8; q += nth) s_pt8[q] = (&T->pt8[0][0])[q];
+    for (int q = tid; q < 2 * 256; q += nth) s_io16[q] = (uint16_t)(&T->iota[0][0])[q];
+}
+
+// one butterfly layer, m = 32, streamed through X (and Y with the same
+// multipliers, forward only)
+__device__ void bt_bfly32_layer(uint32_t *__restrict__ X, uint32_t *__restrict__ Y, int l, int i, bool inverse,
+                                uint8_t *smem, const DevTables *__restrict__ T, int tid, int nth)
+{
+    uint32_t *s_k = reinterpret_cast<uint32_t *>(smem + BT32_OFF_K);
+    const PermTab *s_pt8 = reinterpret_cast<const PermTab *>(smem + BT32_OFF_PT8);
+    const uint16_t *s_io16 = reinterpret_cast<const uint16_t *>(smem + BT32_OFF_IO16);
+    const int d = l - i;
+    for (int q = tid; q < 1024; q += nth) s_k[q] = T->kt32[d][q];
+    __syncthreads();
+    const uint4 q01 = *reinterpret_cast<const uint4 *>(s_pt8 + 0x80);   // v_7 = Cantor byte 0x80
+    const uint32_t q2 = s_pt8[0x80].t2;
+    const uint32_t half = 1u << (l - 1);
+    for (uint32_t q = tid; q < half; q += nth) {
+        const uint32_t tb = q >> i, off = q & ((1u << i) - 1u);
+        const uint32_t p0 = (tb << (i + 1)) | off, p1 = p0 | (1u << i);
+        const uint32_t v = 2u * tb;   // below 2^15
+        const uint32_t beta = (uint32_t)s_io16[v & 255u] ^ (uint32_t)s_io16[256 + (v >> 8)];
+        const PermTab *P0 = s_pt8 + (beta & 255u), *P1 = s_pt8 + (beta >> 8);
+        const uint4 t0 = *reinterpret_cast<const uint4 *>(P0), t1 = *reinterpret_cast<const uint4 *>(P1);
+        const uint32_t t02 = P0->t2, t12 = P1->t2;
+        auto mul = [&](uint32_t x) {
+            const uint32_t k = s_k[x & 255u] ^ s_k[256 + ((x >> 8) & 255u)] ^ s_k[512 + ((x >> 16) & 255u)] ^
+                               s_k[768 + (x >> 24)];
+            return k ^ b2_pmul32(t0, t02, x) ^ b2_pmul32(t1, t12, b2_mulv8(q01, q2, x));
+        };
+        if (!inverse) {
+            const uint32_t b = X[p1], h0 = X[p0] ^ mul(b);
+            X[p0] = h0;
+            X[p1] = h0 ^ b;
+            if (Y) {
+                const uint32_t bb = Y[p1], g0 = Y[p0] ^ mul(bb);
+                Y[p0] = g0;
+                Y[p1] = g0 ^ bb;
+            }
+        } else {
+            const uint32_t h0 = X[p0], pp = h0 ^ X[p1];
+            X[p0] = h0 ^ mul(pp);
+            X[p1] = pp;
+        }
+    }
+    __syncthreads();
+}
+
+// A[i] = A[i] * B[i] in GF(2^32) for i < n_p (Mul8View tables set up in LDS)
+__device__ void bt_pointwise32(uint32_t *__restrict__ A, const uint32_t *__restrict__ B, uint32_t n_p, uint8_t *smem,
+                               const DevTables *__restrict__ T, int tid, int nth)
+{
+    static_assert(BF_OFF_TAB == BF_OFF_MUL8 + 32768, "odd rows must follow the even rows");
+    static_assert(BT32_OFF_K - BF_OFF_MUL8 >= M8V_BYTES, "m = 32 tables overlap the product tables");
+    uint8_t *s_odd = smem + BF_OFF_TAB;
+    uint16_t *s_c15 = reinterpret_cast<uint16_t *>(smem + BF_OFF_MUL8 + M8V_OFF_C15);
+    const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_odd);
+    for (int idx = tid; idx < 128 * 16; idx += nth) dst[idx] = src[(2 * (idx >> 4) + 1) * 16 + (idx & 15)];
+    for (int idx = tid; idx < 512; idx += nth) s_c15[idx] = (&T->c15[0][0])[idx];
+    __syncthreads();
+    const Mul8View mv{smem + BF_OFF_MUL8};
+    for (uint32_t e = tid; e < n_p; e += nth) A[e] = mv.m32(A[e], B[e]);
+    __syncthreads();
+}
+
 // grid: persistent workgroups; slab: 4 buffers of slab_words per workgroup.
 // Items come from the pools and offset arrays, or from `desc` when it is set.
 __global__ __launch_bounds__(BT_THREADS) void k_batch(
@@ -256,7 +429,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
     int32_t *__restrict__ status,
     uint32_t count, uint64_t max_bits, const uint32_t *__restrict__ order, uint32_t *__restrict__ counter,
     uint64_t *__restrict__ slab, uint64_t slab_words, const DevTables *__restrict__ T,
-    const BatchSteps *__restrict__ BS)
+    const BatchSteps *__restrict__ BS, int m32_max_log2n)
 {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_next;
@@ -281,6 +454,9 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
         }
         const int l = log2n - 6;
         const uint64_t n_p = 1ull << l, lc = la + lb - 1;
+        // m = 32 for small transforms (GF(2^32) values), else m = 64
+        const bool m32 = log2n <= m32_max_log2n && log2n <= BT32_MAX_LOG2N;
+        const int l32 = log2n - 5;
 
         // BasisCvt and Encode of both operands: A -> TA, B -> TB
         for (int side = 0; side < 2; ++side) {
@@ -293,18 +469,31 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
             uint64_t *cur = bt_basiscvt(X, Y, lgN, false, BS, tid, nth);
             for (uint64_t w = (1ull << lgN) / 64 + tid; w < n_p; w += nth) cur[w] = 0;
             __syncthreads();
-            bt_encode(cur, l, side ? TB : TA, T, tid, nth);
+            if (m32)
+                bt_encode32(cur, l32, reinterpret_cast<uint32_t *>(side ? TB : TA), T, tid, nth);
+            else
+                bt_encode(cur, l, side ? TB : TA, T, tid, nth);
             __syncthreads();
         }
 
-        // Butterfly of A and B, pointwise, iButterfly: result in TA
-        const int R = l < BF_BOTTOM_R ? l : BF_BOTTOM_R;
-        for (int i = l - 1; i >= R; --i) bt_upper_layer(TA, TB, l, i, false, smem, T, tid, nth);
-        for (uint64_t H = 0; H < (1ull << (l - R)); ++H) bf_bottom_tile<BF_PRODUCT>(TA, TB, l, R, H, smem, T, tid, nth);
-        for (int i = R; i < l; ++i) bt_upper_layer(TA, nullptr, l, i, true, smem, T, tid, nth);
-
-        // Decode and iBasisCvt(2^log2n), then the first lc bits to out
-        bt_decode(TA, l, X, TB, T, tid, nth);
+        if (m32) {
+            // Butterfly of A and B, pointwise, iButterfly over GF(2^32); Decode
+            uint32_t *A32 = reinterpret_cast<uint32_t *>(TA), *B32 = reinterpret_cast<uint32_t *>(TB);
+            bt32_load_tables(smem, T, tid, nth);
+            for (int i = l32 - 1; i >= 0; --i) bt_bfly32_layer(A32, B32, l32, i, false, smem, T, tid, nth);
+            bt_pointwise32(A32, B32, 1u << l32, smem, T, tid, nth);
+            for (int i = 0; i < l32; ++i) bt_bfly32_layer(A32, nullptr, l32, i, true, smem, T, tid, nth);
+            bt_decode32(A32, l32, X, B32, T, tid, nth);
+        } else {
+            // Butterfly of A and B, pointwise, iButterfly: result in TA
+            const int R = l < BF_BOTTOM_R ? l : BF_BOTTOM_R;
+            for (int i = l - 1; i >= R; --i) bt_upper_layer(TA, TB, l, i, false, smem, T, tid, nth);
+            for (uint64_t H = 0; H < (1ull << (l - R)); ++H)
+                bf_bottom_tile<BF_PRODUCT>(TA, TB, l, R, H, smem, T, tid, nth);
+            for (int i = R; i < l; ++i) bt_upper_layer(TA, nullptr, l, i, true, smem, T, tid, nth);
+            bt_decode(TA, l, X, TB, T, tid, nth);
+        }
+        // iBasisCvt(2^log2n), then the first lc bits to out
         __syncthreads();
         const uint64_t *res = bt_basiscvt(X, Y, log2n, true, BS, tid, nth);
         uint64_t *out = desc ? desc[q].out : out_pool + out_off[q];

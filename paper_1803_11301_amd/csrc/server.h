@@ -202,6 +202,7 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
         slot.view->tables = ctx->tables;
         slot.view->bsteps = ctx->bsteps;
         slot.view->num_cu = ctx->num_cu;
+        slot.view->small_field_log2n = ctx->small_field_log2n;
     }
     if (e != hipSuccess) {
         for (SrvSlot &slot : S->slots) {

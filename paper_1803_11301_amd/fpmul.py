@@ -25,6 +25,7 @@ SIGNATURES = {
     "polymul_ctx_destroy": (_I, [_V]),
     "polymul_ex": (_I, [_V, _P, _U64, _P, _U64, _P, _V]),
     "polymul_batch": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _V]),
+    "polymul_set_small_field": (_I, [_V, _I]),
     "polymul_server_create": (_I, [ctypes.POINTER(_V), _V, _SZ, ctypes.c_uint32]),
     "polymul_server_destroy": (_I, [_V]),
     "polymul_server_set_policy": (_I, [_V, _U64, ctypes.c_uint32]),
@@ -158,6 +159,11 @@ class Context:
                                    max_product_bits, status.data_ptr() if status is not None else None,
                                    _stream(stream)))
         return out_pool
+
+    def set_small_field(self, max_log2n: int):
+        """Batch items (and polymul_ex products up to 2^17 bits) with transforms of
+        at most 2^max_log2n bits run over GF(2^32); 0 keeps GF(2^64)."""
+        _check(lib().polymul_set_small_field(self.handle, max_log2n))
 
     def addfft(self, a, len_a: int, log2n: int, values=None, stream=None):
         import torch

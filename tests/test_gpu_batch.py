@@ -173,3 +173,40 @@ def test_full_mixed_batch_4096(ctx):
         lhs = O.gf64_mul(O.eval_at(As[k], la, z), O.eval_at(Bs[k], lb, z))
         assert lhs == O.eval_at(outs[k], la + lb - 1, z), (k, la, lb)
     assert exact > 600
+
+
+@pytest.mark.parametrize("limit", [0, 12, 20])
+def test_small_field_limit_changes_field_not_products(ctx, limit):
+    """Items up to 2^limit transform bits run over GF(2^32), the rest over
+    GF(2^64); the products equal the oracle's for every limit."""
+    rng = random.Random(4000 + limit)
+    lens = [(1, 1), (1, 64), (33, 31), (64, 64), (65, 65), (500, 700), (2048, 2049), (4095, 4097), (9000, 70),
+            (1 << 13, 1 << 13), ((1 << 16) - 3, 1 << 16), (1 << 18, 1 << 18), ((1 << 19) - 1, (1 << 19) + 2),
+            (1 << 20, 1 << 20)]
+    for _ in range(20):
+        lens.append((rng.randint(1, 40000), rng.randint(1, 40000)))
+    say("small-field limit", limit, len(lens), "items")
+    As = [words(rng, la) for la, _ in lens]
+    Bs = [words(rng, lb) for _, lb in lens]
+    ctx.set_small_field(limit)
+    try:
+        outs, st = run_batch(ctx, As, Bs, [x for x, _ in lens], [y for _, y in lens])
+    finally:
+        ctx.set_small_field(20)
+    assert (st == 0).all()
+    for (la, lb), a, b, got in zip(lens, As, Bs, outs):
+        n = O.nwords(la + lb - 1)
+        if la + lb <= (1 << 17):
+            assert np.array_equal(got[:n], O.polymul(a, la, b, lb)), (la, lb)
+        else:
+            idx = np.array(sorted({0, n - 1, n // 2} | {rng.randrange(n) for _ in range(5)}), dtype=np.uint64)
+            assert np.array_equal(got[idx.astype(np.int64)], O.product_words(a, la, b, lb, idx)), (la, lb)
+            z = rng.getrandbits(64) | 1
+            assert O.gf64_mul(O.eval_at(a, la, z), O.eval_at(b, lb, z)) == O.eval_at(got[:n], la + lb - 1, z)
+
+
+def test_small_field_limit_rejects_out_of_range(ctx):
+    from paper_1803_11301_amd import fpmul
+    for bad in (-1, 21, 64):
+        with pytest.raises(fpmul.FpmulError):
+            ctx.set_small_field(bad)
