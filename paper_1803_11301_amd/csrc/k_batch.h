@@ -151,6 +151,110 @@ __device__ uint64_t *bt_basiscvt(uint64_t *X, uint64_t *Y, int lgN, bool inverse
     return X;
 }
 
+// Steps [k0, k1) in execution order of BasisCvt(2^lgN) (steps st0[0, cnt),
+// reversed for the inverse) on nw words held in LDS, in place.  Every step
+// must have segments of at most 64 nw bits.  A wide step (S >= 128) runs as
+// its two updates with a barrier between them (hi[0, d) ^= hi[H-d, H) and
+// lo[d, H) ^= hi[0, H-d), in that order forward and the other order
+// inverse); consecutive in-word steps run together in one pass.
+__device__ void bt_lds_steps(uint64_t *v, int nw, const BatchStep *__restrict__ st0, int cnt, bool inverse, int k0,
+                             int k1, int tid, int nth)
+{
+    auto step = [&](int k) { return st0[inverse ? cnt - 1 - k : k]; };
+    for (int k = k0; k < k1;) {
+        const BatchStep s = step(k);
+        if (s.S <= 64) {
+            int e = k + 1;
+            while (e < k1 && step(e).S <= 64) ++e;
+            for (int w = tid; w < nw; w += nth) {
+                uint64_t x = v[w];
+                for (int j = k; j < e; ++j) {
+                    const BatchStep t = step(j);
+                    x = bcvt_in_word(x, (int)(t.S / 2), (int)t.d, t.L, t.D, inverse ? 1 : 0);
+                }
+                v[w] = x;
+            }
+            __syncthreads();
+            k = e;
+            continue;
+        }
+        const int SW = (int)(s.S / 64), HW = SW / 2, lgHW = 31 - __clz(HW), nseg = nw / SW;
+        const int d = (int)s.d;
+        for (int ph = 0; ph < 2; ++ph) {
+            const bool fix_hi = (ph == 0) != inverse;
+            if (fix_hi) {
+                if (d >= 64) {
+                    // hi word k ^= hi word k + HW - dw, k < dw
+                    const int dw = d / 64, lgdw = 31 - __clz(dw);
+                    for (int t = tid; t < nseg * dw; t += nth) {
+                        uint64_t *hp = v + (t >> lgdw) * SW + HW;
+                        const int k2 = t & (dw - 1);
+                        hp[k2] ^= hp[k2 + HW - dw];
+                    }
+                } else {
+                    for (int sg = tid; sg < nseg; sg += nth) {
+                        uint64_t *hp = v + sg * SW + HW;
+                        hp[0] ^= hp[HW - 1] >> (64 - d);
+                    }
+                }
+            } else {
+                for (int t = tid; t < nseg * HW; t += nth) {
+                    const int q = t & (HW - 1);
+                    uint64_t *lp = v + (t >> lgHW) * SW, *hp = lp + HW;
+                    if (d >= 64) {
+                        const int dw = d / 64;
+                        if (q >= dw) lp[q] ^= hp[q - dw];
+                    } else {
+                        lp[q] ^= (hp[q] << d) | (q ? hp[q - 1] >> (64 - d) : 0ull);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        ++k;
+    }
+}
+
+#define BT_LDS_WORDS (1 << 14)   // 2^20 bits of BasisCvt in LDS at a time (128 KiB)
+static_assert(BF_OFF_DATA + (2 << BF_BOTTOM_R) * 8 >= BT_LDS_WORDS * 8, "the batch kernel's LDS holds the chunk");
+
+// BasisCvt(2^lgN) (or its inverse) on words [0, 2^lgN / 64) of X, ping-pong
+// with Y for the steps whose segments exceed LDS; runs of the other steps
+// are applied chunk by chunk in LDS (lds: BT_LDS_WORDS words).  Returns the
+// buffer that holds the result.
+__device__ uint64_t *bt_basiscvt_lds(uint64_t *X, uint64_t *Y, int lgN, bool inverse, const BatchSteps *__restrict__ BS,
+                                     uint64_t *lds, int tid, int nth)
+{
+    const int nw = (int)((1ull << lgN) / 64);
+    const int first = BS->first[lgN], cnt = BS->count[lgN];
+    const BatchStep *st0 = BS->st + first;
+    auto step = [&](int k) { return st0[inverse ? cnt - 1 - k : k]; };
+    for (int k = 0; k < cnt;) {
+        const BatchStep s = step(k);
+        if (s.S <= 64ull * BT_LDS_WORDS) {
+            int e = k + 1;
+            while (e < cnt && step(e).S <= 64ull * BT_LDS_WORDS) ++e;
+            const int chw = nw < BT_LDS_WORDS ? nw : BT_LDS_WORDS;
+            for (int c0 = 0; c0 < nw; c0 += chw) {
+                for (int w = tid; w < chw; w += nth) lds[w] = X[c0 + w];
+                __syncthreads();
+                bt_lds_steps(lds, chw, st0, cnt, inverse, k, e, tid, nth);
+                for (int w = tid; w < chw; w += nth) X[c0 + w] = lds[w];
+                __syncthreads();
+            }
+            k = e;
+        } else {
+            for (int w = tid; w < nw; w += nth) Y[w] = bcvt_wide_word(X, w, s.S, s.d, inverse ? 1 : 0);
+            __syncthreads();
+            uint64_t *t = X;
+            X = Y;
+            Y = t;
+            ++k;
+        }
+    }
+    return X;
+}
+
 // Encode (Alg. 4): vals[i] = sum_j bit (j n_p + i) of `bits` times r_j, n_p = 2^l
 __device__ void bt_encode(const uint64_t *__restrict__ bits, int l, uint64_t *__restrict__ vals,
                           const DevTables *__restrict__ T, int tid, int nth)
@@ -466,7 +570,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
             if (lgN < BT_MIN_LOG2N) lgN = BT_MIN_LOG2N;
             bt_load(src, len, X, n_p, tid, nth);
             __syncthreads();
-            uint64_t *cur = bt_basiscvt(X, Y, lgN, false, BS, tid, nth);
+            uint64_t *cur = bt_basiscvt_lds(X, Y, lgN, false, BS, reinterpret_cast<uint64_t *>(smem), tid, nth);
             for (uint64_t w = (1ull << lgN) / 64 + tid; w < n_p; w += nth) cur[w] = 0;
             __syncthreads();
             if (m32)
@@ -476,6 +580,9 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
             __syncthreads();
         }
 
+        // BasisCvt used all of LDS: the even rows of the GF(2^8) table back
+        bf_load_mul8_even(smem + BF_OFF_MUL8, T, tid, nth);
+        __syncthreads();
         if (m32) {
             // Butterfly of A and B, pointwise, iButterfly over GF(2^32); Decode
             uint32_t *A32 = reinterpret_cast<uint32_t *>(TA), *B32 = reinterpret_cast<uint32_t *>(TB);
@@ -495,7 +602,7 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
         }
         // iBasisCvt(2^log2n), then the first lc bits to out
         __syncthreads();
-        const uint64_t *res = bt_basiscvt(X, Y, log2n, true, BS, tid, nth);
+        const uint64_t *res = bt_basiscvt_lds(X, Y, log2n, true, BS, reinterpret_cast<uint64_t *>(smem), tid, nth);
         uint64_t *out = desc ? desc[q].out : out_pool + out_off[q];
         const uint64_t ow = (lc + 63) / 64;
         for (uint64_t w = tid; w < ow; w += nth) {
