@@ -218,6 +218,8 @@ struct polymul_ctx {
     // batch items with transforms of at most 2^small_field_log2n bits run over
     // GF(2^32) (m = 32); 0 keeps every item on m = 64
     int small_field_log2n = SMALL_FIELD_DEFAULT_LOG2N;
+    // workspaces lent by a server's arena: never freed or grown here
+    bool borrowed = false;
     // per-kernel timing with HIP events on the launch stream (off by default)
     bool prof = false;
     std::vector<ProfRec> prof_live;       // recorded, not yet read
@@ -284,6 +286,7 @@ static unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 
 static int ensure_ws(polymul_ctx *ctx, uint64_t words)
 {
     if (words <= ctx->ws_words) return 0;
+    if (ctx->borrowed) return fail(POLYMUL_EIO, "borrowed workspace smaller than the launch needs");
     size_t bytes = (size_t)words * 8;
     if (ctx->cap && 4 * bytes > ctx->cap)
         return fail(POLYMUL_ENOMEM, "workspace of " + std::to_string(4 * bytes) + " bytes exceeds the cap of " +
@@ -416,6 +419,10 @@ static int set_lds_limits()
     // k_batch also has static LDS, so its dynamic limit is exactly what it uses
     HIP_TRY(hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)bf_bottom_lds(BF_BOTTOM_R, true)));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_mid_encode, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                MID_LDS_BYTES));
+    HIP_TRY(hipFuncSetAttribute((const void *)k_mid_decode, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                MID_LDS_BYTES));
     done = 1;
     return 0;
 }
@@ -480,6 +487,8 @@ static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
 #define BF3_WIDE 6      // bottom layers below this use the V_16 split
 #define BF3_MIN_L 20    // resident-table bottom pass from 2^20 transform values
 #define SINGLE_VIA_BATCH_LOG2N 17   // polymul_ex of products up to 2^17 bits runs as a one-item batch
+#define MID_MIN_LOG2N 18            // mid-size path (LDS BasisCvt in one workgroup per operand) ...
+#define MID_MAX_LOG2N 20            // ... up to 2^20-bit transforms
 
 template <bool INV>
 static int launch_bf3_bottom(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l)
@@ -573,11 +582,17 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
     return 0;
 }
 
-static int transform_log2(uint64_t len_a, uint64_t len_b)
+// log2 of the transform length of a product of lc bits: n = max(64,
+// 2^ceil(log2 lc)), except that a 2^21-bit transform is taken as 2^22 bits,
+// which the fused path (from 2^22) computes faster than the per-step path
+// (0.28 against 0.50 ms); any n >= lc gives the same product
+static int product_log2n(uint64_t lc)
 {
-    uint64_t lc = len_a + len_b - 1;
-    return std::max(6, ilog2(lc));
+    const int k = std::max(6, ilog2(lc));
+    return k == 21 ? 22 : k;
 }
+
+static int transform_log2(uint64_t len_a, uint64_t len_b) { return product_log2n(len_a + len_b - 1); }
 
 static int ranges_overlap(const void *a, size_t an, const void *b, size_t bn)
 {
@@ -720,6 +735,8 @@ static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, ui
     return 0;
 }
 
+static int batch_steps_upload(polymul_ctx *ctx);
+
 static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
                         uint64_t *out, hipStream_t s)
 {
@@ -730,6 +747,17 @@ static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, con
     if ((rc = set_lds_limits())) return rc;
     uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2], *W3 = ctx->ws[3];
     uint64_t *pa, *pb;
+    if (log2n >= MID_MIN_LOG2N && log2n <= MID_MAX_LOG2N && ilog2(std::max<uint64_t>(len_a, 1)) <= 20 &&
+        ilog2(std::max<uint64_t>(len_b, 1)) <= 20) {
+        // each operand's BasisCvt whole in one workgroup's LDS (2^20 bits)
+        if ((rc = batch_steps_upload(ctx))) return rc;
+        KLAUNCH_LDS(ctx, s, "mid_encode", k_mid_encode, 2, BT_THREADS, MID_LDS_BYTES, a, len_a, b, len_b, log2n, W0,
+                    W1, ctx->tables, ctx->bsteps);
+        if ((rc = run_butterflies(ctx, BF_PRODUCT, W0, W1, log2n - 6, s))) return rc;
+        KLAUNCH_LDS(ctx, s, "mid_decode", k_mid_decode, 1, BT_THREADS, MID_LDS_BYTES, W0, log2n, out, lc, W2, W3,
+                    ctx->tables, ctx->bsteps);
+        return 0;
+    }
     // forward transforms of A into W0, of B into W1 (W2, W3 scratch)
     for (int side = 0; side < 2; ++side) {
         const uint64_t *src = side ? b : a;
@@ -905,6 +933,7 @@ static int batch_body(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, 
     const uint64_t slab_words = BL.slab_words;
     const size_t slab_bytes = BL.slab_bytes, order_bytes = BL.order_bytes, need = BL.total;
     if (need > ctx->bws_bytes) {
+        if (ctx->borrowed) return fail(POLYMUL_EIO, "borrowed batch workspace smaller than the launch needs");
         if (ctx->cap && need > ctx->cap)
             return fail(POLYMUL_ENOMEM, "batch workspace of " + std::to_string(need) + " bytes exceeds the cap of " +
                                             std::to_string(ctx->cap));

@@ -256,8 +256,9 @@ __device__ uint64_t *bt_basiscvt_lds(uint64_t *X, uint64_t *Y, int lgN, bool inv
 }
 
 // Encode (Alg. 4): vals[i] = sum_j bit (j n_p + i) of `bits` times r_j, n_p = 2^l
+// (bits: n_p words, or only the first nwv of them with the rest zero)
 __device__ void bt_encode(const uint64_t *__restrict__ bits, int l, uint64_t *__restrict__ vals,
-                          const DevTables *__restrict__ T, int tid, int nth)
+                          const DevTables *__restrict__ T, int tid, int nth, uint64_t nwv = ~0ull)
 {
     const uint64_t n_p = 1ull << l;
     if (l >= 6) {
@@ -266,7 +267,8 @@ __device__ void bt_encode(const uint64_t *__restrict__ bits, int l, uint64_t *__
         for (uint64_t g = wave; g < groups; g += nwave) {
             // lane j: bits j n_p + 64 g .. + 63, one word; after the transpose lane t
             // holds the column of element 64 g + t
-            uint64_t x = bits[((uint64_t)lane << (l - 6)) + g];
+            const uint64_t iw = ((uint64_t)lane << (l - 6)) + g;
+            uint64_t x = iw < nwv ? bits[iw] : 0ull;
             x = bc_wave_transpose64(x, lane);
             uint64_t f = 0;
 #pragma unroll
@@ -278,7 +280,7 @@ __device__ void bt_encode(const uint64_t *__restrict__ bits, int l, uint64_t *__
             uint64_t col = 0;
             for (int j = 0; j < 64; ++j) {
                 const uint64_t p = ((uint64_t)j << l) + i;
-                col |= ((bits[p >> 6] >> (p & 63)) & 1ull) << j;
+                if ((p >> 6) < nwv) col |= ((bits[p >> 6] >> (p & 63)) & 1ull) << j;
             }
             uint64_t f = 0;
 #pragma unroll
@@ -612,5 +614,63 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
         }
         if (tid == 0 && status) status[q] = 0;
         __syncthreads();
+    }
+}
+
+// ------------------------------------------------------ mid-size products --
+//
+// Products with transforms of 2^18 .. 2^21 bits and operands of at most
+// 2^20 bits (polymul_ex): each operand's BasisCvt runs whole in the LDS of
+// one workgroup and Encode reads it from there (k_mid_encode, one workgroup
+// per operand); the butterflies are the multi-workgroup passes; Decode and
+// the inverse BasisCvt run in one workgroup (k_mid_decode).  Three launches
+// plus the butterflies, instead of one launch per BasisCvt step.
+#define MID_LDS_BYTES (BT_LDS_WORDS * 8)
+
+__global__ __launch_bounds__(BT_THREADS) void k_mid_encode(const uint64_t *__restrict__ a, uint64_t la,
+                                                           const uint64_t *__restrict__ b, uint64_t lb, int log2n,
+                                                           uint64_t *__restrict__ ta, uint64_t *__restrict__ tb,
+                                                           const DevTables *__restrict__ T,
+                                                           const BatchSteps *__restrict__ BS)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint64_t *v = reinterpret_cast<uint64_t *>(smem);
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const bool side = blockIdx.x != 0;
+    const uint64_t *src = side ? b : a;
+    const uint64_t len = side ? lb : la;
+    int lgN = bt_ceil_log2(len);
+    if (lgN < BT_MIN_LOG2N) lgN = BT_MIN_LOG2N;
+    const int nw = (int)((1ull << lgN) / 64);   // at most BT_LDS_WORDS (checked on the host)
+    const uint64_t inw = (len + 63) / 64;
+    for (int w = tid; w < nw; w += nth) {
+        uint64_t x = 0;
+        if ((uint64_t)w < inw) {
+            x = src[w];
+            if ((uint64_t)w == inw - 1 && (len & 63)) x &= (~0ull) >> (64 - (len & 63));
+        }
+        v[w] = x;
+    }
+    __syncthreads();
+    bt_lds_steps(v, nw, BS->st + BS->first[lgN], BS->count[lgN], false, 0, BS->count[lgN], tid, nth);
+    bt_encode(v, log2n - 6, side ? tb : ta, T, tid, nth, (uint64_t)nw);
+}
+
+__global__ __launch_bounds__(BT_THREADS) void k_mid_decode(const uint64_t *__restrict__ vals, int log2n,
+                                                           uint64_t *__restrict__ out, uint64_t lc,
+                                                           uint64_t *__restrict__ X, uint64_t *__restrict__ Y,
+                                                           const DevTables *__restrict__ T,
+                                                           const BatchSteps *__restrict__ BS)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    bt_decode(vals, log2n - 6, X, Y, T, tid, nth);
+    __syncthreads();
+    const uint64_t *res = bt_basiscvt_lds(X, Y, log2n, true, BS, reinterpret_cast<uint64_t *>(smem), tid, nth);
+    const uint64_t ow = (lc + 63) / 64;
+    for (uint64_t w = tid; w < ow; w += nth) {
+        uint64_t x = res[w];
+        if (w == ow - 1 && (lc & 63)) x &= (~0ull) >> (64 - (lc & 63));
+        out[w] = x;
     }
 }

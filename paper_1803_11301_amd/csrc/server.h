@@ -50,8 +50,7 @@ uint64_t srv_now_ns(std::chrono::steady_clock::time_point t0)
 // device bytes of one single-product launch (the four workspace buffers)
 uint64_t srv_single_bytes(uint64_t lc)
 {
-    const int log2n = std::max(6, ilog2(lc));
-    return 4 * ws_words_for(log2n) * 8;
+    return 4 * ws_words_for(product_log2n(lc)) * 8;
 }
 
 }  // namespace
@@ -100,8 +99,8 @@ static int srv_launch(polymul_server *S, SrvSlot &slot)
     int rc;
     if (!p.batch) {
         const fpmul_srv::Req &r = p.reqs[0];
-        const int log2n = std::max(6, ilog2(fpmul_srv::product_bits(r)));
-        const uint64_t words = ws_words_for(log2n);
+        // the transform product_body will use, so that the borrowed buffers fit
+        const uint64_t words = ws_words_for(product_log2n(fpmul_srv::product_bits(r)));
         for (int k = 0; k < 4; ++k) v->ws[k] = reinterpret_cast<uint64_t *>(base + (size_t)k * words * 8);
         v->ws_words = words;
         rc = product_body(v, r.a, r.la, r.b, r.lb, r.out, s);
@@ -203,6 +202,7 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
         slot.view->bsteps = ctx->bsteps;
         slot.view->num_cu = ctx->num_cu;
         slot.view->small_field_log2n = ctx->small_field_log2n;
+        slot.view->borrowed = true;
     }
     if (e != hipSuccess) {
         for (SrvSlot &slot : S->slots) {

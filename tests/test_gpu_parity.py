@@ -302,3 +302,16 @@ def test_pointwise_rejects_bad_arguments(ctx):
         ctx.pointwise(t, t, 5)
     with pytest.raises(fpmul.FpmulError):
         ctx.pointwise(t[:32], t[16:48], 11, fc=t[8:40])   # overlapping output that is neither input
+
+
+@pytest.mark.parametrize("la,lb", [(1 << 17, 1 << 17), ((1 << 18) + 3, (1 << 18) - 7), (1 << 19, 1 << 19),
+                                   ((1 << 20) - 10, 5), ((1 << 19) - 1, (1 << 19) + 5), (1 << 20, 1 << 20),
+                                   (1000, (1 << 20) - 1), ((1 << 20) + 1, 1 << 10)])
+def test_mid_size_products_exact(ctx, la, lb):
+    """Products with transforms of 2^18..2^20 bits (each operand's BasisCvt in
+    one workgroup's LDS) and of 2^21 bits (computed with 2^22-bit transforms
+    on the fused path)."""
+    say("mid size", la, lb)
+    rng = random.Random(la * 3 + lb)
+    a, b = rand_words(rng, la), rand_words(rng, lb)
+    assert np.array_equal(gpu_product(ctx, a, la, b, lb), O.polymul(a, la, b, lb, threads=8))
