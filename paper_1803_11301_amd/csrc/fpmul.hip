@@ -484,7 +484,6 @@ static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
     return 0;
 }
 
-#define BF3_WIDE 6      // bottom layers below this use the V_16 split
 #define BF3_MIN_L 20    // resident-table bottom pass from 2^20 transform values
 #define SINGLE_VIA_BATCH_LOG2N 17   // polymul_ex of products up to 2^17 bits runs as a one-item batch
 #define MID_MIN_LOG2N 18            // mid-size path (LDS BasisCvt in one workgroup per operand) ...
@@ -496,24 +495,24 @@ static int launch_bf3_bottom(polymul_ctx *ctx, hipStream_t s, const char *name, 
     const uint64_t nops = B ? 2 : 1, ntiles = 1ull << (l - B3_TILE_LG);
     const uint64_t per_op = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)ctx->num_cu / nops));
     if (l < B3_TILE_LG) return fail(POLYMUL_EINVAL, "bottom pass needs at least one tile");
-    KLAUNCH(ctx, s, name, (k_bf3_bottom<INV, BF3_WIDE>), (unsigned)(per_op * nops), B3_THREADS, A, B, l,
+    KLAUNCH(ctx, s, name, k_bf3_bottom<INV>, (unsigned)(per_op * nops), B3_THREADS, A, B, l,
             ctx->tables);
     return 0;
 }
 
 // Butterflies of one transform (mode BF_FWD or BF_INV) or of a product
 // (BF_PRODUCT: forward A and B, pointwise, inverse; result in A).  Large
-// transforms: upper passes down to layer 6, then the bottom pass of layers
-// 0 .. 5, all with resident K tables.  Smaller ones: upper passes down to
+// transforms: upper passes down to layer 7, then the bottom pass of layers
+// 0 .. 6, all with resident K tables.  Smaller ones: upper passes down to
 // layer 11 and the 2^11-value bottom pass (more tiles to spread).
 static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B, int l, hipStream_t s)
 {
     const uint64_t n = 1ull << l;
     if (l >= BF3_MIN_L) {
-        // the lowest upper pass starts at layer 6 and so needs 7 layers
-        // (i_lo >= 12 - K); the layers above it are split evenly
-        auto groups = upper_groups(l, B3_BOT_LAYERS + BF_UPPER_MAXK);
-        groups.insert(groups.begin(), {B3_BOT_LAYERS, BF_UPPER_MAXK});
+        // the layers above the bottom pass split evenly into passes of at most
+        // 7; the lowest starts at layer 7 and needs K >= 5 (i_lo >= 12 - K),
+        // which every split for l >= 20 gives
+        const auto groups = upper_groups(l, B3_BOT_LAYERS);
         int rc;
         if (mode != BF_INV) {
             for (auto it = groups.rbegin(); it != groups.rend(); ++it)

@@ -1,5 +1,6 @@
-// k_bf3.h -- upper butterfly passes (Alg. 2 and its inverse, layers at or
-// above 11) with every layer's K table resident in LDS.
+// k_bf3.h -- butterfly passes (Alg. 2 and its inverse) with every layer's K
+// table resident in LDS: upper passes (layers from 7, or from 11 for
+// transforms below 2^20 values) and the bottom pass of layers 0 .. 6.
 //
 // A workgroup of 512 threads owns a tile of 2^12 values: the K <= 7 layers of
 // the pass (tile rows) times 2^(12-K) consecutive columns.  Each thread holds
@@ -165,50 +166,62 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_upper(uint64_t *__restric
 
 // ----------------------------------------------------------- bottom pass ---
 //
-// Layers 0 .. 5 on contiguous tiles of 2^12 values, all six K tables
-// resident.  Register groups (forward order) {3,4,5} then {0,1,2}; one
-// exchange per tile.  Layers below WIDE use the V_16 split of k_bf2.h
-// (K16 + beta16, K16 changes once per 2^(i+4) tiles); the others use the V_8
-// split.  Within a 2^12 tile, K of the V_8 split is constant only from layer
-// 4 up, so WIDE >= 4.
+// Layers 0 .. 6 on contiguous tiles of 2^12 values, all seven K tables
+// resident.  Register groups (forward order) {4,5,6}, {1,2,3} and {0} (with
+// two tile bits on which no layer runs); an exchange between groups.  Every
+// layer uses the V_16 split of k_bf2.h: K16 = 2^(32+d) + (b >> 15) << 16
+// changes once per 2^(i+4) tiles, so the tables are rebuilt almost never
+// (with the V_8 split, K of the lowest layers would change every tile or two
+// and vary inside a 2^12 tile below layer 4).
 
-#define B3_BOT_LAYERS 6
+#define B3_BOT_LAYERS 7
+#define B3_BOT_GROUPS 3
 
 __device__ __forceinline__ B2Group bf3_bottom_group(int c)
 {
+    // layers hi .. lo of group c, counted from the top, then padding bits from
+    // the highest tile bits outside the group
+    const int hi = B3_BOT_LAYERS - 1 - 3 * c, lo = hi - 2 < 0 ? 0 : hi - 2;
+    int bits[3], lay[3], cnt = 0;
+    for (int r = lo; r <= hi; ++r) {
+        bits[cnt] = r;
+        lay[cnt++] = 1;
+    }
+    for (int b = B3_TILE_LG - 1; cnt < 3; --b) {
+        if (b >= lo && b <= hi) continue;
+        bits[cnt] = b;
+        lay[cnt++] = 0;
+    }
+    for (int x = 0; x < 3; ++x)
+        for (int y = x + 1; y < 3; ++y)
+            if (bits[y] < bits[x]) {
+                int t = bits[x];
+                bits[x] = bits[y];
+                bits[y] = t;
+                t = lay[x];
+                lay[x] = lay[y];
+                lay[y] = t;
+            }
     B2Group g;
-    const int lo = c == 0 ? 3 : 0;
-    g.s[0] = lo;
-    g.s[1] = lo + 1;
-    g.s[2] = lo + 2;
-    g.layer[0] = g.layer[1] = g.layer[2] = 1;
+    for (int m = 0; m < 3; ++m) {
+        g.s[m] = bits[m];
+        g.layer[m] = lay[m];
+    }
     return g;
 }
 
-template <int WIDE>
-__device__ __forceinline__ uint32_t bf3_bottom_key(uint64_t gbase, int i)
-{
-    return i < WIDE ? (uint32_t)(gbase >> (i + 16)) << 8 : (uint32_t)(gbase >> (i + 8));
-}
-
-template <bool INV, int WIDE>
+template <bool INV>
 __device__ __forceinline__ void bf3_bottom_compute(const B2Group &g, uint64_t (&x)[8], uint64_t (*s_tab)[2048],
-                                                   const PermTab *s_ptb, const PermTab *s_pt8,
-                                                   const uint16_t (*s_io16)[256], const uint4 &q01, uint32_t q2,
-                                                   uint64_t gb_t, const DevTables *__restrict__ T)
+                                                   const PermTab *s_pt8, const uint16_t (*s_io16)[256],
+                                                   const uint4 &q01, uint32_t q2, uint64_t gb_t)
 {
     auto run = [&](auto Mc) {
         constexpr int M = decltype(Mc)::value;
+        if (!g.layer[M]) return;
         const int i = g.s[M];
-        if (i < WIDE) {
-            const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
-            const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 0x7FFFu, bw2 = ((1u << g.s[2]) >> (i + 1)) & 0x7FFFu;
-            b2_layer16<M, INV, false>(x, x, s_tab[i], s_pt8, s_io16, q01, q2, b_t, bw1, bw2);
-        } else {
-            const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
-            const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 127u, bw2 = ((1u << g.s[2]) >> (i + 1)) & 127u;
-            b2_layer<M, INV, false>(x, x, s_tab[i], s_ptb, T, bl_t, bw1, bw2);
-        }
+        const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
+        const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 0x7FFFu, bw2 = ((1u << g.s[2]) >> (i + 1)) & 0x7FFFu;
+        b2_layer16<M, INV, false>(x, x, s_tab[i], s_pt8, s_io16, q01, q2, b_t, bw1, bw2);
     };
     if (!INV) {
         run(std::integral_constant<int, 2>());
@@ -221,28 +234,22 @@ __device__ __forceinline__ void bf3_bottom_compute(const B2Group &g, uint64_t (&
     }
 }
 
-// Layers 0 .. 5 of A (and of B when B is not null: the second half of the
+// Layers 0 .. 6 of A (and of B when B is not null: the second half of the
 // grid takes B; the grid is then even).  l >= 12.
-template <bool INV, int WIDE>
+template <bool INV>
 __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
                                                                 int l, const DevTables *__restrict__ T)
 {
-    static_assert(WIDE >= 4 && WIDE <= B3_BOT_LAYERS, "the V_8 split needs a constant K over the tile");
-    __shared__ __align__(16) uint64_t s_tab[B3_BOT_LAYERS][2048];   // K table of layer i
+    __shared__ __align__(16) uint64_t s_tab[B3_BOT_LAYERS][2048];   // K16 table of layer i
     __shared__ __align__(16) uint64_t s_x[B3_STAGE_WORDS];
-    __shared__ __align__(16) PermTab s_ptb[128];        // tables of iota(2 bl), bl < 128
     __shared__ __align__(16) PermTab s_pt8[256];        // tables of every byte of V_8
     __shared__ uint16_t s_io16[2][256];                 // iota of the low two Cantor bytes
-    __shared__ uint64_t s_pb[24][64];                   // basis rows of the bits of bh
     __shared__ uint64_t s_img[64];
     const int tid = threadIdx.x, nth = blockDim.x;
 
-    for (int q = tid; q < 128 * 8; q += nth)
-        reinterpret_cast<uint32_t *>(s_ptb)[q] = reinterpret_cast<const uint32_t *>(T->pt_beta8)[q];
     for (int q = tid; q < 256 * 8; q += nth)
         reinterpret_cast<uint32_t *>(s_pt8)[q] = reinterpret_cast<const uint32_t *>(T->pt8)[q];
     for (int q = tid; q < 2 * 256; q += nth) (&s_io16[0][0])[q] = (uint16_t)(&T->iota[0][0])[q];
-    b2_load_pbasis(s_pb, T, tid, nth);
     __syncthreads();
     const PermTab *Q = s_pt8 + 0x80;   // v_7 = Cantor byte 0x80
     const uint4 q01 = *reinterpret_cast<const uint4 *>(Q);
@@ -258,7 +265,7 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
     const uint64_t t_beg = bid * per, t_end = t_beg + per < ntiles ? t_beg + per : ntiles;
     if (t_beg >= t_end) return;   // uniform per workgroup
 
-    const B2Group g0 = bf3_bottom_group(INV ? 1 : 0);
+    const B2Group g0 = bf3_bottom_group(INV ? B3_BOT_GROUPS - 1 : 0);
     const int e0 = b2_thread_base<B3_TILE_LG>(g0, tid);
     auto load = [&](uint64_t tile, uint64_t(&v)[8]) {
         const uint64_t gbase = tile << B3_TILE_LG;
@@ -280,16 +287,16 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
         for (int r = 0; r < 8; ++r) x[r] = nx[r];
         if (tile + 1 < t_end) load(tile + 1, nx);   // in flight during this tile
 
-        // rebuild the tables whose K changed; uniform over the workgroup
+        // rebuild the tables whose K16 changed; uniform over the workgroup
         bool changed = false;
 #pragma unroll
         for (int i = 0; i < B3_BOT_LAYERS; ++i) {
-            const uint32_t bh = bf3_bottom_key<WIDE>(gbase, i);
+            const uint32_t bh = (uint32_t)(gbase >> (i + 16)) << 8;
             if (key[i] != bh) {
                 key[i] = bh;
                 changed = true;
                 __syncthreads();   // s_tab[i] and s_img no longer read
-                if (tid < 64) b2_basis(s_img, l - i, bh, s_pb, T, tid);
+                ktable_basis(s_img, l - i, bh, T, tid);
                 __syncthreads();
                 for (int item = tid; item < 256; item += nth) ktable_fill_item(s_tab[i], s_img, item);
             }
@@ -297,12 +304,12 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
         if (changed) __syncthreads();
 
 #pragma unroll
-        for (int cc = 0; cc < 2; ++cc) {
-            const int c = INV ? 1 - cc : cc;
+        for (int cc = 0; cc < B3_BOT_GROUPS; ++cc) {
+            const int c = INV ? B3_BOT_GROUPS - 1 - cc : cc;
             const B2Group g = bf3_bottom_group(c);
             const int e_t = b2_thread_base<B3_TILE_LG>(g, tid);
             if (cc > 0) {
-                const B2Group gp = bf3_bottom_group(1 - c);
+                const B2Group gp = bf3_bottom_group(INV ? c + 1 : c - 1);
                 const int ep = b2_thread_base<B3_TILE_LG>(gp, tid);
                 __syncthreads();   // the previous exchange has been read
 #pragma unroll
@@ -317,8 +324,8 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
                     x[r] = s_x[b2_pad(e)];
                 }
             }
-            bf3_bottom_compute<INV, WIDE>(g, x, s_tab, s_ptb, s_pt8, s_io16, q01, q2, gbase | (uint64_t)e_t, T);
-            if (cc == 1) {
+            bf3_bottom_compute<INV>(g, x, s_tab, s_pt8, s_io16, q01, q2, gbase | (uint64_t)e_t);
+            if (cc == B3_BOT_GROUPS - 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
