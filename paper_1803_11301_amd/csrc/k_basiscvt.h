@@ -171,34 +171,86 @@ __device__ __forceinline__ uint64_t bc16_inword(uint64_t x)
 template <int LGS, int LGD, int PHASE>
 __device__ __forceinline__ void bc16_cross_phase(uint64_t *rows, int nrows, int tid, int nth)
 {
-    constexpr int S = 1 << LGS, H = S / 2, d = 1 << LGD;
-    constexpr int SW = S / 64, HW = SW / 2, NSEG = 1024 / SW;
+    constexpr int S = 1 << LGS, d = 1 << LGD;
+    constexpr int SW = S / 64, HW = SW / 2, NSEG = 1024 / SW, LGHW = LGS - 7;
+    constexpr int dw = d / 64, ds = d % 64;
+    static_assert(HW >= 2 && HW % 2 == 0, "cross-word steps have segments of at least 256 bits");
+    ulonglong2 *rows2 = reinterpret_cast<ulonglong2 *>(rows);
     if (PHASE == 0) {
-        constexpr int NA = (d + 63) / 64;                 // hi words written
-        const int nt = nrows * NSEG * NA;
-        for (int t = tid; t < nt; t += nth) {
-            const int k = t % NA, sg = t / NA;
-            uint64_t *hp = rows + sg * SW + HW;
-            if (d % 64 == 0) {
-                hp[k] ^= hp[k + (H - d) / 64];
-            } else {
-                // d < 64: bits [H - d, H) of hi into hi[0, d)
-                hp[0] ^= (hp[HW - 1] >> (64 - d));
+        // hi[0, d) ^= hi[H - d, H)
+        if constexpr (ds != 0) {
+            const int nt = nrows * NSEG;
+            for (int t = tid; t < nt; t += nth) {
+                uint64_t *hp = rows + t * SW + HW;
+                hp[0] ^= hp[HW - 1] >> (64 - d);
+            }
+        } else if constexpr (dw >= 2) {
+            // 16-byte pairs of words
+            constexpr int NA2 = dw / 2, LGNA2 = LGD - 7;
+            const int nt = nrows * NSEG * NA2;
+            for (int t = tid; t < nt; t += nth) {
+                ulonglong2 *hp = rows2 + (t >> LGNA2) * (SW / 2) + HW / 2;
+                const int k = t & (NA2 - 1);
+                ulonglong2 x = hp[k];
+                const ulonglong2 y = hp[k + (HW - dw) / 2];
+                x.x ^= y.x;
+                x.y ^= y.y;
+                hp[k] = x;
+            }
+        } else {
+            const int nt = nrows * NSEG;
+            for (int t = tid; t < nt; t += nth) {
+                uint64_t *hp = rows + t * SW + HW;
+                hp[0] ^= hp[HW - 1];
             }
         }
     } else {
-        constexpr int dw = d / 64, ds = d % 64;
-        constexpr int NB = HW - dw;                        // lo words written
-        const int nt = nrows * NSEG * NB;
-        for (int t = tid; t < nt; t += nth) {
-            const int q = dw + t % NB, sg = t / NB;
-            uint64_t *lp = rows + sg * SW, *hp = lp + HW;
-            uint64_t v = hp[q - dw];
-            if (ds) {
-                v <<= ds;
-                if (q - dw - 1 >= 0) v |= hp[q - dw - 1] >> (64 - ds);
+        // lo[d, H) ^= hi[0, H - d)
+        if constexpr (ds != 0) {
+            const int nt = nrows * NSEG * HW;
+            for (int t = tid; t < nt; t += nth) {
+                const int q = t & (HW - 1);
+                uint64_t *lp = rows + (t >> LGHW) * SW, *hp = lp + HW;
+                uint64_t v = hp[q] << ds;
+                if (q) v |= hp[q - 1] >> (64 - ds);
+                lp[q] ^= v;
             }
-            lp[q] ^= v;
+        } else if constexpr (dw % 2 == 0) {
+            constexpr int HW2 = HW / 2, DW2 = dw / 2, LGHW2 = LGHW - 1;
+            if constexpr (2 * dw == HW) {
+                // H - d = d: DW2 pairs per segment, a power of two
+                constexpr int LGDW2 = LGD - 7;
+                const int nt = nrows * NSEG * DW2;
+                for (int t = tid; t < nt; t += nth) {
+                    ulonglong2 *lp = rows2 + (t >> LGDW2) * (SW / 2), *hp = lp + HW2;
+                    const int qv = DW2 + (t & (DW2 - 1));
+                    ulonglong2 x = lp[qv];
+                    const ulonglong2 y = hp[qv - DW2];
+                    x.x ^= y.x;
+                    x.y ^= y.y;
+                    lp[qv] = x;
+                }
+            } else {
+                const int nt = nrows * NSEG * HW2;
+                for (int t = tid; t < nt; t += nth) {
+                    const int qv = t & (HW2 - 1);
+                    if (qv < DW2) continue;
+                    ulonglong2 *lp = rows2 + (t >> LGHW2) * (SW / 2), *hp = lp + HW2;
+                    ulonglong2 x = lp[qv];
+                    const ulonglong2 y = hp[qv - DW2];
+                    x.x ^= y.x;
+                    x.y ^= y.y;
+                    lp[qv] = x;
+                }
+            }
+        } else {
+            const int nt = nrows * NSEG * HW;
+            for (int t = tid; t < nt; t += nth) {
+                const int q = t & (HW - 1);
+                if (q < dw) continue;
+                uint64_t *lp = rows + (t >> LGHW) * SW, *hp = lp + HW;
+                lp[q] ^= hp[q - dw];
+            }
         }
     }
 }
