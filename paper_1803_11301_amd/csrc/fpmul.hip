@@ -438,25 +438,6 @@ static int set_lds_limits()
     } while (0)
 
 // upper layer group [i_lo, i_lo + k) with the register-resident passes
-template <int MODE>
-static int launch_bf2_upper(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l,
-                            int i_lo, int k)
-{
-    const unsigned grid = (unsigned)std::min<uint64_t>(1ull << (l - B2_TILE_LG), (uint64_t)ctx->num_cu * 2);
-    void (*kern)(uint64_t *, uint64_t *, int, int, const DevTables *) = nullptr;
-    switch (k) {
-    case 1: kern = k_bf2_upper<MODE, 1>; break;
-    case 2: kern = k_bf2_upper<MODE, 2>; break;
-    case 3: kern = k_bf2_upper<MODE, 3>; break;
-    case 4: kern = k_bf2_upper<MODE, 4>; break;
-    case 5: kern = k_bf2_upper<MODE, 5>; break;
-    case 6: kern = k_bf2_upper<MODE, 6>; break;
-    case 7: kern = k_bf2_upper<MODE, 7>; break;
-    default: return fail(POLYMUL_EINVAL, "upper layer group of more than 7 layers");
-    }
-    KLAUNCH(ctx, s, name, kern, grid, B2_THREADS, A, B, l, i_lo, ctx->tables);
-    return 0;
-}
 
 // upper pass of K = k layers with resident tables: one workgroup per CU, the
 // grid split between the operands when B is given

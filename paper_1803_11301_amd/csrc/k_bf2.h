@@ -227,142 +227,6 @@ __device__ __forceinline__ void b2_fill(const B2Group &g, uint64_t (*s_tab)[2048
     }
 }
 
-// images for the layers of group g: slot = row of the layer, key = its bh
-template <int K>
-__device__ __forceinline__ void b2_upper_images(const B2Group &g, uint64_t (*s_img)[64], uint32_t (&key)[K],
-                                                const uint64_t (*s_pb)[64], uint64_t gbase, int l, int i_lo,
-                                                const DevTables *__restrict__ T, int tid)
-{
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        if (!g.layer[m]) continue;
-        const int row = g.s[m] - B2Upper<K>::LGW, i = i_lo + row;
-        const uint32_t bh = (uint32_t)(gbase >> (i + 8));
-        if (key[row] != bh) {
-            if ((tid >> 6) == m) b2_basis(s_img[row], l - i, bh, s_pb, T, tid & 63);
-            key[row] = bh;
-        }
-    }
-}
-
-template <int K, bool INV, bool TWO>
-__device__ __forceinline__ void b2_upper_compute(const B2Group &g, uint64_t (&xa)[8], uint64_t (&xb)[8],
-                                                 uint64_t (*s_tab)[2048], const PermTab *s_pt, uint64_t gb_t,
-                                                 int i_lo, const DevTables *__restrict__ T)
-{
-    constexpr int LGW = B2Upper<K>::LGW;
-    // global weights of the register bits
-    uint64_t gw[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) gw[m] = b2_upper_global<K>(1 << g.s[m], 0, i_lo);
-    auto run = [&](auto Mc) {
-        constexpr int M = decltype(Mc)::value;
-        if (!g.layer[M]) return;
-        const int i = i_lo + g.s[M] - LGW;
-        const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
-        const uint32_t bw1 = (uint32_t)(gw[1] >> (i + 1)) & 127u, bw2 = (uint32_t)(gw[2] >> (i + 1)) & 127u;
-        b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_pt, T, bl_t, bw1, bw2);
-    };
-    if (!INV) {
-        run(std::integral_constant<int, 2>());
-        run(std::integral_constant<int, 1>());
-        run(std::integral_constant<int, 0>());
-    } else {
-        run(std::integral_constant<int, 0>());
-        run(std::integral_constant<int, 1>());
-        run(std::integral_constant<int, 2>());
-    }
-}
-
-// MODE: BF_FWD (A), BF_FWD2 (A and B, same multipliers), BF_INV (A)
-template <int MODE, int K>
-__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_upper(uint64_t *__restrict__ A,
-                                                                          uint64_t *__restrict__ B, int l, int i_lo,
-                                                                          const DevTables *__restrict__ T)
-{
-    constexpr bool INV = MODE == BF_INV, TWO = MODE == BF_FWD2;
-    constexpr int NC = B2Upper<K>::NC, LGW = B2Upper<K>::LGW;
-    __shared__ __align__(16) uint64_t s_tab[3][2048];   // K tables; the exchange area aliases them
-    __shared__ __align__(16) PermTab s_pt[128];
-    __shared__ uint64_t s_pb[24][64];                   // basis rows of the bits of bh
-    __shared__ uint64_t s_img[K][64];                   // basis images of each layer's K, cached
-    uint64_t *stA = &s_tab[0][0], *stB = stA + B2_STAGE_WORDS;
-    const int tid = threadIdx.x, nth = blockDim.x;
-
-    for (int q = tid; q < 128 * 8; q += nth)
-        reinterpret_cast<uint32_t *>(s_pt)[q] = reinterpret_cast<const uint32_t *>(T->pt_beta8)[q];
-    b2_load_pbasis(s_pb, T, tid, nth);
-    __syncthreads();
-
-    const int nlo = i_lo - LGW;
-    const uint64_t ntiles = 1ull << (l - B2_TILE_LG);
-    // each workgroup takes a contiguous run of tiles: K changes only with the
-    // tile bits above the rows, so the cached images stay valid for long runs
-    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
-    const uint64_t t_beg = (uint64_t)blockIdx.x * per, t_end = t_beg + per < ntiles ? t_beg + per : ntiles;
-    uint32_t key[K];
-#pragma unroll
-    for (int r = 0; r < K; ++r) key[r] = 0xFFFFFFFFu;
-    uint64_t xa[8], xb[8];
-    for (uint64_t tile = t_beg; tile < t_end; ++tile) {
-        const uint64_t gbase = ((tile >> nlo) << (i_lo + K)) | ((tile & ((1ull << nlo) - 1)) << LGW);
-#pragma unroll
-        for (int cc = 0; cc < NC; ++cc) {
-            const int c = INV ? NC - 1 - cc : cc;
-            const B2Group g = b2_upper_group<K>(c);
-            const int e_t = b2_thread_base(g, tid);
-            const uint64_t gb_t = b2_upper_global<K>(e_t, gbase, i_lo);
-            if (cc == 0) {
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
-                    const uint64_t j = b2_upper_global<K>(e, gbase, i_lo);
-                    xa[r] = A[j];
-                    if (TWO) xb[r] = B[j];
-                }
-                __syncthreads();   // the previous tile is done with the tables
-                b2_upper_images<K>(g, s_img, key, s_pb, gbase, l, i_lo, T, tid);
-                __syncthreads();
-            } else {
-                // values out in the previous group's arrangement, in again in this one's
-                const B2Group gp = b2_upper_group<K>(INV ? c + 1 : c - 1);
-                const int ep = b2_thread_base(gp, tid);
-                __syncthreads();   // done with the previous tables (the exchange area aliases them)
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int e = ep | ((r & 1) << gp.s[0]) | (((r >> 1) & 1) << gp.s[1]) | ((r >> 2) << gp.s[2]);
-                    stA[b2_pad(e)] = xa[r];
-                    if (TWO) stB[b2_pad(e)] = xb[r];
-                }
-                b2_upper_images<K>(g, s_img, key, s_pb, gbase, l, i_lo, T, tid);
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
-                    xa[r] = stA[b2_pad(e)];
-                    if (TWO) xb[r] = stB[b2_pad(e)];
-                }
-                __syncthreads();   // exchange area free for the tables
-            }
-            int slot[3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) slot[m] = g.layer[m] ? g.s[m] - LGW : 0;
-            b2_fill(g, s_tab, s_img, slot, tid, nth);
-            __syncthreads();
-            b2_upper_compute<K, INV, TWO>(g, xa, xb, s_tab, s_pt, gb_t, i_lo, T);
-            if (cc == NC - 1) {
-#pragma unroll
-                for (int r = 0; r < 8; ++r) {
-                    const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
-                    const uint64_t j = b2_upper_global<K>(e, gbase, i_lo);
-                    A[j] = xa[r];
-                    if (TWO) B[j] = xb[r];
-                }
-            }
-        }
-    }
-}
-
 // ----------------------------------------------------------- bottom pass ---
 //
 // Layers 10 .. 0 on contiguous tiles of 2^11 values (tile bits = global bits

@@ -8,11 +8,11 @@
 // (the arrangement of the k_bf2.h passes), and the multiplications are the
 // same tmul + pmul of x * (K + beta).
 //
-// What differs from k_bf2_upper: the K tables of all layers of the pass stay
-// in LDS for the whole run of tiles (up to 7 x 16 KiB) beside a separate
-// exchange area, so a table is rebuilt only when its K changes -- once per
-// 2^(r + 1 + i_lo - 5) tiles for row r, i.e. almost never -- instead of for
-// every layer group of every tile.  The price is one workgroup per CU, so
+// Unlike the 2^11-value passes of k_bf2.h, the K tables of all layers of the
+// pass stay in LDS for the whole run of tiles (up to 7 x 16 KiB) beside a
+// separate exchange area, so a table is rebuilt only when its K changes
+// (layer i: once per 2^(i-4) tiles or less) instead of for every layer group
+// of every tile.  The price is one workgroup per CU, so
 // the next tile's values are loaded into registers while the current tile
 // is computed.  The two operands of a product are taken by the two halves of
 // the grid.

@@ -1,32 +1,27 @@
-// k_butterfly.h -- Butterfly (Alg. 2) and its inverse as LDS-resident passes.
+// k_butterfly.h -- Butterfly (Alg. 2) and its inverse as LDS-resident tile
+// passes, for small transforms (l < 11) and the batch kernel.
 //
-// The n_p = 2^l values of one transform are processed in passes over groups
-// of layers.  Layer i pairs indices j and j + 2^i inside blocks of 2^(i+1); the
-// block b = j >> (i+1) fixes the multiplier s_i(v_{l+32} + b 2^(i+1)) whose
-// Cantor vector is 2^(32+d) XOR 2b, d = l - i.
+// Layer i pairs indices j and j + 2^i inside blocks of 2^(i+1); the block
+// b = j >> (i+1) fixes the multiplier s_i(v_{l+32} + b 2^(i+1)) whose Cantor
+// vector is 2^(32+d) XOR 2b, d = l - i.
 //
-//  * bottom pass: layers R-1 .. 0 on contiguous tiles of 2^R values.  For a
-//    product it runs the forward layers of A and B, the pointwise products and
-//    the inverse layers of C on the same tile (the low layers of the forward
-//    transforms, the pointwise step and the low layers of the inverse
-//    transform of Alg. 5), so those steps cost one HBM round trip.
-//  * upper pass: k <= 7 consecutive layers i_lo .. i_hi on tiles of 2^k rows
-//    (the index bits i_lo .. i_hi) by W contiguous columns (low index bits).
+// The bottom pass runs layers R-1 .. 0 on contiguous tiles of 2^R values.
+// For a product it runs the forward layers of A and B, the pointwise
+// products and the inverse layers of C on the same tile (the low layers of
+// the forward transforms, the pointwise step and the low layers of the
+// inverse transform of Alg. 5), so those steps cost one HBM round trip.
 //
 // Each multiplication is x * (K + beta) = tmul(T_K, x) ^ bmul(beta, x) with K
 // shared by 128 consecutive blocks (window table built in LDS) and beta in V_8
-// (gf_device.h).  In an upper pass with k <= 7 one K serves a whole layer of
-// the tile; in the bottom pass the low layers need up to 2^(R-8) of them.
+// (gf_device.h); the low layers of a tile need up to 2^(R-8) tables.
 #pragma once
 
 #include "gf_device.h"
 
 #define BF_THREADS 1024       // bottom pass (one workgroup per CU)
-#define BF_UP_THREADS 512     // upper pass (two workgroups per CU)
 #define BF_SLOTS 4            // K tables resident in LDS at once (16 KiB each)
 #define BF_BOTTOM_R 11        // log2 of the bottom tile
 #define BF_UPPER_MAXK 7       // layers per upper pass
-#define BF_UPPER_LGW 3        // log2 of the columns of an upper tile
 
 enum { BF_FWD = 0, BF_INV = 1, BF_PRODUCT = 2, BF_FWD2 = 3 };
 
@@ -175,68 +170,6 @@ __global__ __launch_bounds__(BF_THREADS) void k_bfly_bottom(uint64_t *__restrict
     const uint64_t ntiles = 1ull << (l - R);
     bf_load_mul8_even(smem + BF_OFF_MUL8, T, tid, nth);
     for (uint64_t H = blockIdx.x; H < ntiles; H += gridDim.x) bf_bottom_tile<MODE>(A, B, l, R, H, smem, T, tid, nth);
-}
-
-// Upper pass: layers i_lo .. i_lo+k-1 (k <= 7), tiles of 2^k rows x 2^lgW columns
-// (lgW <= BF_UPPER_LGW), persistent over the tiles.
-// MODE: BF_FWD (A), BF_FWD2 (A and B, same multipliers), BF_INV (A).
-template <int MODE>
-__global__ __launch_bounds__(BF_UP_THREADS) void k_bfly_upper(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
-                                                              int l, int i_lo, int k, int lgW,
-                                                              const DevTables *__restrict__ T)
-{
-    __shared__ __align__(16) uint64_t s_tab[2048];                   // the K table of the current layer
-    __shared__ __align__(16) uint8_t s_mul8e[128 * 256];             // even rows of the GF(2^8) table
-    __shared__ uint64_t s_basis[64];
-    __shared__ uint64_t s_A[1 << (BF_UPPER_MAXK + BF_UPPER_LGW)];
-    __shared__ uint64_t s_B[MODE == BF_FWD2 ? (1 << (BF_UPPER_MAXK + BF_UPPER_LGW)) : 1];
-    const int rows = 1 << k, W = 1 << lgW, nel = rows << lgW;
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const int i_hi = i_lo + k - 1;
-    const int lgchunks = i_lo - lgW;
-    const uint64_t ntiles = 1ull << (l - k - lgW);
-
-    bf_load_mul8_even(s_mul8e, T, tid, nth);
-    for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const uint64_t H = tile >> lgchunks, c0 = (tile & ((1ull << lgchunks) - 1)) << lgW;
-        const uint64_t gbase = (H << (i_hi + 1)) | c0;
-        for (int e = tid; e < nel; e += nth) {
-            const uint64_t j = gbase | ((uint64_t)(e >> lgW) << i_lo) | (uint64_t)(e & (W - 1));
-            s_A[e] = A[j];
-            if (MODE == BF_FWD2) s_B[e] = B[j];
-        }
-        for (int step = 0; step < k; ++step) {
-            const int i = (MODE == BF_INV) ? i_lo + step : i_hi - step;
-            const int s = i - i_lo;                        // row bit of this layer
-            const int d = l - i;
-            const uint64_t bfirst = H << (i_hi - i);       // global block of row pair 0
-            // (the barrier inside bf_build also orders the tile load / previous layer)
-            __syncthreads();
-            bf_build(s_tab, s_basis, d, (uint32_t)(bfirst >> 7), 1, T, tid, nth);
-            const int total = (rows >> 1) << lgW;
-            for (int q = tid; q < total; q += nth) {
-                const int c = q & (W - 1), pr = q >> lgW;
-                const int t0 = ((pr >> s) << (s + 1)) | (pr & ((1 << s) - 1));
-                const int t1 = t0 | (1 << s);
-                const uint32_t bl = (uint32_t)((bfirst + (uint64_t)(t0 >> (s + 1))) & 127u);
-                const uint8_t *row = s_mul8e + bl * 256;
-                const uint32_t p0 = (uint32_t)((t0 << lgW) | c), p1 = (uint32_t)((t1 << lgW) | c);
-                if (MODE == BF_INV) {
-                    bf_inv_pair(s_A, p0, p1, s_tab, row);
-                } else {
-                    bf_fwd_pair(s_A, p0, p1, s_tab, row);
-                    if (MODE == BF_FWD2) bf_fwd_pair(s_B, p0, p1, s_tab, row);
-                }
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < nel; e += nth) {
-            const uint64_t j = gbase | ((uint64_t)(e >> lgW) << i_lo) | (uint64_t)(e & (W - 1));
-            A[j] = s_A[e];
-            if (MODE == BF_FWD2) B[j] = s_B[e];
-        }
-        __syncthreads();
-    }
 }
 
 static inline size_t bf_bottom_lds(int R, bool product)
