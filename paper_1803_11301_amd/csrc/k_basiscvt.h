@@ -971,9 +971,27 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *
     const unsigned G = gridDim.x, b = blockIdx.x;
     const unsigned w = G % BC_XCDS == 0 ? (b % BC_XCDS) * (G / BC_XCDS) + b / BC_XCDS : b;
     for (int q0 = (int)w * T; q0 < R; q0 += (int)G * T) {
-        for (int e = tid; e < T * 2 * BC_TAU_WORDS; e += nth) {
-            const int k = e % T, c = e / T;                 // 32-bit column c of row q0 + k
-            reinterpret_cast<uint32_t *>(rows)[k * 2 * BC_TAU_WORDS + c] = Y32[(uint64_t)c * R + q0 + k];
+        uint32_t *rows32 = reinterpret_cast<uint32_t *>(rows);
+        if (T == BC_ROWS) {
+            // one 32-bit column c per thread: a 32-byte run of Y32 in, LDS writes
+            // of consecutive words per wave (no bank conflicts)
+            for (int c = tid; c < 2 * BC_TAU_WORDS; c += nth) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(Y32 + (uint64_t)c * R + q0);
+                const uint4 v0 = src[0], v1 = src[1];
+                rows32[0 * 2 * BC_TAU_WORDS + c] = v0.x;
+                rows32[1 * 2 * BC_TAU_WORDS + c] = v0.y;
+                rows32[2 * 2 * BC_TAU_WORDS + c] = v0.z;
+                rows32[3 * 2 * BC_TAU_WORDS + c] = v0.w;
+                rows32[4 * 2 * BC_TAU_WORDS + c] = v1.x;
+                rows32[5 * 2 * BC_TAU_WORDS + c] = v1.y;
+                rows32[6 * 2 * BC_TAU_WORDS + c] = v1.z;
+                rows32[7 * 2 * BC_TAU_WORDS + c] = v1.w;
+            }
+        } else {
+            for (int e = tid; e < T * 2 * BC_TAU_WORDS; e += nth) {
+                const int k = e % T, c = e / T;                 // 32-bit column c of row q0 + k
+                rows32[k * 2 * BC_TAU_WORDS + c] = Y32[(uint64_t)c * R + q0 + k];
+            }
         }
         __syncthreads();
         bc16_rows<true>(rows, T, tid, nth);
