@@ -43,9 +43,19 @@ extern "C" {
 #define POLYMUL_ENOMEM (-12)
 #define POLYMUL_EINVAL (-22)
 
-/* Largest supported product length in bits: n <= (m/2) 2^(m/2) with m = 64
- * (Sec. 3.1, the bound that follows Prop. 2; the partition needs l < m/2). */
-#define POLYMUL_MAX_PRODUCT_BITS (1ull << 37)
+/* Largest product length in bits over GF(2^64): n <= (m/2) 2^(m/2) with
+ * m = 64 (Sec. 3.1, the bound that follows Prop. 2; the partition needs
+ * l < m/2).  Longer products run over GF(2^128) (m = 128, whose bound
+ * 64 * 2^64 no length reaches). */
+#define POLYMUL_M64_MAX_PRODUCT_BITS (1ull << 37)
+/* Largest product length polymul and polymul_ex accept.  Device memory is
+ * the practical limit: a product with a transform of n bits holds a
+ * workspace of four buffers of at least n/8 bytes each besides its operands
+ * and output (on one MI355X, 288 GB, n = 2^38 is the largest that fits), and
+ * a workspace that cannot be allocated gives POLYMUL_ENOMEM. */
+#define POLYMUL_MAX_PRODUCT_BITS (1ull << 62)
+/* Largest product length the product server accepts. */
+#define POLYMUL_SERVER_MAX_PRODUCT_BITS POLYMUL_M64_MAX_PRODUCT_BITS
 
 typedef struct polymul_ctx polymul_ctx;
 
@@ -133,6 +143,23 @@ int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, cons
  */
 int polymul_set_small_field(polymul_ctx *ctx, int max_log2n);
 
+/* Smallest transform (log2 of its bits) of the m = 128 field: n_p = n / 128
+ * values need n >= 128. */
+#define POLYMUL_LARGE_FIELD_MIN_LOG2N 7
+
+/*
+ * polymul_set_large_field -- the m = 128 variant of Sec. 3 (GF(2^128), l_m = 7):
+ * products of polymul_ex / polymul whose transform has at least 2^min_log2n
+ * bits are computed over GF(2^128).  Transforms above 2^37 bits always are,
+ * since GF(2^64) cannot hold them.  The product is the same either way; a
+ * smaller threshold exists to run the m = 128 path on products of any size.
+ * Default: 38.  Products of the server (which admits at most 2^37 bits) and
+ * batch items are not affected.  The first m = 128 product on a context
+ * builds and uploads its constant tables (2 MiB, synchronously).
+ * Returns 0, or POLYMUL_EINVAL for a null ctx or min_log2n outside [7, 38].
+ */
+int polymul_set_large_field(polymul_ctx *ctx, int min_log2n);
+
 /*
  * Product server: continuous batching of product requests on one GPU.
  *
@@ -146,7 +173,8 @@ int polymul_set_small_field(polymul_ctx *ctx, int max_log2n);
  *   alone (as polymul_ex); polymul_server_set_policy changes both limits.  A later request may pass an earlier one that
  *   does not fit yet; one passed 64 times blocks later ones until it fits.
  *   Launches on different slots overlap on the device.
- * polymul_submit -- queues C = A * B (same arguments and rules as polymul;
+ * polymul_submit -- queues C = A * B (same arguments and rules as polymul,
+ *   with products of at most POLYMUL_SERVER_MAX_PRODUCT_BITS bits;
  *   device pointers the caller keeps alive and unmodified until the ticket is
  *   done; the server copies nothing) and returns its ticket.  A product whose
  *   workspace exceeds the whole arena is refused with POLYMUL_ENOMEM.

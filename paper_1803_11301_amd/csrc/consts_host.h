@@ -292,4 +292,116 @@ static inline void window_table(const Tables &T, uint64_t c, uint64_t *tab)
         for (int e = 0; e < 256; ++e) tab[k * 256 + e] = T.tw.m64(c, (uint64_t)e << (8 * k));
 }
 
+// ------------------------------------------------------- m = 128 field --
+//
+// GF(2^128) = GF(2^64)[y] / (y^2 + y + v_63).  v_63 lies outside the image
+// of x -> x^2 + x on GF(2^64) (its equation has no root there: checked
+// below), so the quadratic is irreducible, and y is a root of the next
+// Cantor equation, v_64 = y (of the two roots y and y + 1 it is the one
+// whose low half has bit 0 clear, the same rule as below 64).  An element
+// is (x0, x1) = x0 + x1 y with both halves in the tower representation:
+//   (a0 + a1 y)(b0 + b1 y) = (a0 b0 + a1 b1 v_63) + ((a0 + a1)(b0 + b1) + a0 b0) y.
+// The Cantor basis continues with v_i^2 + v_i = v_{i-1} for 64 < i < 128,
+// solved in GF(2^128).
+
+struct E128 {
+    uint64_t lo, hi;
+};
+
+static inline E128 mul128(const Tables &T, E128 a, E128 b)
+{
+    const uint64_t p0 = T.tw.m64(a.lo, b.lo), p2 = T.tw.m64(a.hi, b.hi);
+    const uint64_t p1 = T.tw.m64(a.lo ^ a.hi, b.lo ^ b.hi);
+    return {p0 ^ T.tw.m64(p2, T.cantor[63]), p1 ^ p0};
+}
+
+// root of x^2 + x = c in GF(2^128) with bit 0 of the low half clear
+// (Gaussian elimination on the GF(2)-linear map x -> x^2 + x, kernel {0, 1})
+static inline E128 solve_x2_plus_x_128(const Tables &T, E128 c)
+{
+    typedef unsigned __int128 u128;
+    auto pack = [](E128 e) { return (u128)e.lo | ((u128)e.hi << 64); };
+    u128 col[128];
+    for (int t = 0; t < 128; ++t) {
+        E128 e{t < 64 ? 1ull << t : 0, t < 64 ? 0 : 1ull << (t - 64)};
+        E128 q = mul128(T, e, e);
+        col[t] = pack(q) ^ pack(e);
+    }
+    u128 rowm[128];
+    int rhs[128];
+    const u128 cv = pack(c);
+    for (int r = 0; r < 128; ++r) {
+        u128 m = 0;
+        for (int t = 0; t < 128; ++t)
+            if ((col[t] >> r) & 1u) m |= (u128)1 << t;
+        rowm[r] = m;
+        rhs[r] = (int)((cv >> r) & 1u);
+    }
+    int pivrow[128];
+    for (int t = 0; t < 128; ++t) pivrow[t] = -1;
+    int rank = 0;
+    for (int t = 0; t < 128 && rank < 128; ++t) {
+        int p = -1;
+        for (int r = rank; r < 128; ++r)
+            if ((rowm[r] >> t) & 1u) { p = r; break; }
+        if (p < 0) continue;
+        std::swap(rowm[p], rowm[rank]);
+        std::swap(rhs[p], rhs[rank]);
+        for (int r = 0; r < 128; ++r)
+            if (r != rank && ((rowm[r] >> t) & 1u)) {
+                rowm[r] ^= rowm[rank];
+                rhs[r] ^= rhs[rank];
+            }
+        pivrow[t] = rank++;
+    }
+    for (int r = rank; r < 128; ++r)
+        if (rhs[r]) throw std::runtime_error("x^2 + x = c has no root in GF(2^128)");
+    u128 x = 0;
+    for (int t = 0; t < 128; ++t)
+        if (pivrow[t] >= 0 && rhs[pivrow[t]]) x |= (u128)1 << t;
+    if (x & 1u) x ^= 1u;
+    E128 r{(uint64_t)x, (uint64_t)(x >> 64)};
+    E128 chk = mul128(T, r, r);
+    if ((chk.lo ^ r.lo) != c.lo || (chk.hi ^ r.hi) != c.hi) throw std::runtime_error("GF(2^128) root check failed");
+    return r;
+}
+
+#define M128_MAXD 64
+
+struct Tables128 {
+    E128 v[128];                 // Cantor basis of GF(2^128), v_i for i < 64 in the low half
+    uint64_t enc[64];            // P_t = prod over set bits k of t (k < 6) of v_{63-k}
+    uint64_t dec[64];            // inverse of the P matrix
+    uint64_t ktab[M128_MAXD][2][2048];   // window tables of H_d and H_d v_63 (v_{64+d} = L_d + H_d y)
+};
+
+// T128 must be heap-allocated (2 MiB of window tables)
+static inline void build_tables128(const Tables &T, Tables128 &U)
+{
+    // x^2 + x = v_63 has no root in GF(2^64): the GF(2)-linear map x -> x^2 + x
+    // has rank 63 there and v_63 lies outside its image
+    bool has_root = true;
+    try {
+        (void)solve_x2_plus_x(T.cantor_poly[63]);
+    } catch (const std::exception &) {
+        has_root = false;
+    }
+    if (has_root) throw std::runtime_error("y^2 + y + v_63 is reducible over GF(2^64)");
+    for (int i = 0; i < 64; ++i) U.v[i] = {T.cantor[i], 0};
+    for (int i = 64; i < 128; ++i) U.v[i] = solve_x2_plus_x_128(T, U.v[i - 1]);
+    if (U.v[64].lo != 0 || U.v[64].hi != 1) throw std::runtime_error("v_64 is not the tower generator");
+    for (int t = 0; t < 64; ++t) {
+        uint64_t r = 1;
+        for (int k = 0; k < 6; ++k)
+            if ((t >> k) & 1) r = T.tw.m64(r, T.cantor[63 - k]);
+        U.enc[t] = r;
+    }
+    invert64(U.enc, U.dec);
+    for (int d = 0; d < M128_MAXD; ++d) {
+        const uint64_t h = U.v[64 + d].hi;
+        window_table(T, h, U.ktab[d][0]);
+        window_table(T, T.tw.m64(h, T.cantor[63]), U.ktab[d][1]);
+    }
+}
+
 }  // namespace fpmul_host

@@ -64,37 +64,43 @@ static int fail(int code, const std::string &msg)
 #include "k_batch.h"
 #include "k_bf2.h"
 #include "k_bf3.h"
+#include "k_m128.h"
 
 // ---------------------------------------------------------------------------
 // elementary kernels
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint64_t gid() { return (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ uint64_t gstride() { return (uint64_t)gridDim.x * blockDim.x; }
+
+// The elementary kernels below loop over their index range with the grid's
+// stride, so one launch of a capped grid covers any length (a launch of more
+// than 2^32 work items does not exist).
 
 // dst[0 .. dst_words) = src bits [0, len) zero-padded
 __global__ void k_load_mask(const uint64_t *__restrict__ src, uint64_t len, uint64_t *__restrict__ dst,
                             uint64_t dst_words)
 {
-    uint64_t w = gid();
-    if (w >= dst_words) return;
-    uint64_t nw = (len + 63) / 64;
-    uint64_t v = 0;
-    if (w < nw) {
-        v = src[w];
-        if (w == nw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+    const uint64_t nw = (len + 63) / 64;
+    for (uint64_t w = gid(); w < dst_words; w += gstride()) {
+        uint64_t v = 0;
+        if (w < nw) {
+            v = src[w];
+            if (w == nw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+        }
+        dst[w] = v;
     }
-    dst[w] = v;
 }
 
 // out[0 .. ceil(len/64)) = src bits [0, len), tail zeroed
 __global__ void k_store_mask(const uint64_t *__restrict__ src, uint64_t len, uint64_t *__restrict__ out)
 {
-    uint64_t w = gid();
-    uint64_t nw = (len + 63) / 64;
-    if (w >= nw) return;
-    uint64_t v = src[w];
-    if (w == nw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
-    out[w] = v;
+    const uint64_t nw = (len + 63) / 64;
+    for (uint64_t w = gid(); w < nw; w += gstride()) {
+        uint64_t v = src[w];
+        if (w == nw - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+        out[w] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -130,18 +136,14 @@ static void bcvt_steps(uint64_t N, uint64_t e, std::vector<BStep> &out)
 __global__ void k_bcvt_step_wide(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t nw,
                                  uint64_t S, uint64_t d, int inverse)
 {
-    uint64_t w = gid();
-    if (w >= nw) return;
-    out[w] = bcvt_wide_word(in, w, S, d, inverse);
+    for (uint64_t w = gid(); w < nw; w += gstride()) out[w] = bcvt_wide_word(in, w, S, d, inverse);
 }
 
 // one step with S <= 64 inside each word (L: low-half mask, D: low-d mask per segment)
 __global__ void k_bcvt_step_word(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t nw,
                                  int H, int d, uint64_t L, uint64_t D, int inverse)
 {
-    uint64_t w = gid();
-    if (w >= nw) return;
-    out[w] = bcvt_in_word(in[w], H, d, L, D, inverse);
+    for (uint64_t w = gid(); w < nw; w += gstride()) out[w] = bcvt_in_word(in[w], H, d, L, D, inverse);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,44 +154,45 @@ __global__ void k_bcvt_step_word(const uint64_t *__restrict__ in, uint64_t *__re
 __global__ void k_encode(const uint64_t *__restrict__ bits, int l, const DevTables *__restrict__ T,
                          uint64_t *__restrict__ vals)
 {
-    uint64_t i = gid();
-    uint64_t n_p = 1ull << l;
-    if (i >= n_p) return;
-    uint64_t col = 0;
-    for (int j = 0; j < 64; ++j) {
-        uint64_t p = ((uint64_t)j << l) + i;
-        col |= ((bits[p >> 6] >> (p & 63)) & 1ull) << j;
-    }
-    uint64_t f = 0;
+    const uint64_t n_p = 1ull << l;
+    for (uint64_t i = gid(); i < n_p; i += gstride()) {
+        uint64_t col = 0;
+        for (int j = 0; j < 64; ++j) {
+            uint64_t p = ((uint64_t)j << l) + i;
+            col |= ((bits[p >> 6] >> (p & 63)) & 1ull) << j;
+        }
+        uint64_t f = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(col >> (8 * k)) & 255u];
-    vals[i] = f;
+        for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(col >> (8 * k)) & 255u];
+        vals[i] = f;
+    }
 }
 
 // Decode part 1: each value -> its 64 bits, in place
 __global__ void k_decode_vec(uint64_t *__restrict__ vals, int l, const DevTables *__restrict__ T)
 {
-    uint64_t i = gid();
-    if (i >= (1ull << l)) return;
-    uint64_t h = vals[i], a = 0;
+    for (uint64_t i = gid(); i < (1ull << l); i += gstride()) {
+        uint64_t h = vals[i], a = 0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) a ^= T->dec_win[k][(h >> (8 * k)) & 255u];
-    vals[i] = a;
+        for (int k = 0; k < 8; ++k) a ^= T->dec_win[k][(h >> (8 * k)) & 255u];
+        vals[i] = a;
+    }
 }
 
 // Decode part 2: bit j of vector i goes to bit j n_p + i
 __global__ void k_decode_scatter(const uint64_t *__restrict__ vecs, int l, uint64_t *__restrict__ bits)
 {
-    uint64_t W = gid();
-    uint64_t nw = 1ull << l;   // n / 64 words
-    if (W >= nw) return;
-    uint64_t mask = (1ull << l) - 1, r = 0;
-    for (int t = 0; t < 64; ++t) {
-        uint64_t p = 64 * W + t;
-        uint64_t j = p >> l, i = p & mask;
-        r |= ((vecs[i] >> j) & 1ull) << t;
+    const uint64_t nw = 1ull << l;   // n / 64 words
+    const uint64_t mask = (1ull << l) - 1;
+    for (uint64_t W = gid(); W < nw; W += gstride()) {
+        uint64_t r = 0;
+        for (int t = 0; t < 64; ++t) {
+            uint64_t p = 64 * W + t;
+            uint64_t j = p >> l, i = p & mask;
+            r |= ((vecs[i] >> j) & 1ull) << t;
+        }
+        bits[W] = r;
     }
-    bits[W] = r;
 }
 
 // ---------------------------------------------------------------------------
@@ -202,6 +205,8 @@ struct ProfRec {
 };
 
 #define SMALL_FIELD_DEFAULT_LOG2N 20   // m = 32 batch items: transforms up to 2^20 bits
+#define M64_MAX_LOG2N 37               // m = 64 field bound: n <= (m/2) 2^(m/2) = 2^37
+#define LARGE_FIELD_DEFAULT_LOG2N 38   // m = 128 from the first transform m = 64 cannot take
 
 struct polymul_ctx {
     int device = 0;
@@ -220,6 +225,10 @@ struct polymul_ctx {
     int small_field_log2n = SMALL_FIELD_DEFAULT_LOG2N;
     // workspaces lent by a server's arena: never freed or grown here
     bool borrowed = false;
+    // products whose transform has at least 2^large_field_log2n bits run over
+    // GF(2^128) (m = 128); above 2^37 bits m = 64 cannot take them
+    int large_field_log2n = LARGE_FIELD_DEFAULT_LOG2N;
+    DevTables128 *tables128 = nullptr;   // built on the first m = 128 product
     // per-kernel timing with HIP events on the launch stream (off by default)
     bool prof = false;
     std::vector<ProfRec> prof_live;       // recorded, not yet read
@@ -281,7 +290,13 @@ static void prof_collect(polymul_ctx *c)
             return fail(POLYMUL_EIO, std::string("launch ") + (name) + ": " + hipGetErrorString(_le)); \
     } while (0)
 
-static unsigned grid_for(uint64_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+// grid of the grid-stride elementary kernels: one item per thread up to
+// 2^16 workgroups, at least one workgroup
+#define GRID_CAP (1u << 16)
+static unsigned grid_for(uint64_t n, unsigned bs)
+{
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + bs - 1) / bs, GRID_CAP));
+}
 
 static int ensure_ws(polymul_ctx *ctx, uint64_t words)
 {
@@ -363,15 +378,22 @@ static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *&cur, 
     return 0;
 }
 
+// The forward steps of an operand of N = 2^k >= len bits touch its first N
+// bits only (every segment of a step lies inside them), so they run on those
+// words; the rest of both buffers is zero.
+static uint64_t bcvt_active_words(uint64_t N, uint64_t nw) { return std::max<uint64_t>(1, std::min(nw, N / 64)); }
+
 // A (len bits) -> BasisCvt -> Encode: n_p values in *cur (cur/spare swapped as needed)
 static int run_encode_in(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int log2n, uint64_t *&cur,
                          uint64_t *&spare, hipStream_t s)
 {
     const int l = log2n - 6;
-    const uint64_t nw = 1ull << l, n_p = 1ull << l;
+    const uint64_t nw = 1ull << l, n_p = 1ull << l, N = next_pow2(std::max<uint64_t>(len, 1));
+    const uint64_t nwa = bcvt_active_words(N, nw);
     const unsigned bs = 256;
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, bs), bs, a, len, cur, nw);
-    int rc = run_bcvt(ctx, next_pow2(std::max<uint64_t>(len, 1)), false, cur, spare, nw, s);
+    if (nwa < nw) KLAUNCH(ctx, s, "zero", k_load_mask, grid_for(nw - nwa, bs), bs, a, 0, spare + nwa, nw - nwa);
+    int rc = run_bcvt(ctx, N, false, cur, spare, nwa, s);
     if (rc) return rc;
     KLAUNCH(ctx, s, "encode", k_encode, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
     std::swap(cur, spare);
@@ -717,11 +739,119 @@ static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, ui
 
 static int batch_steps_upload(polymul_ctx *ctx);
 
+// ---------------------------------------------------------------------------
+// m = 128 products (k_m128.h): per-step BasisCvt, Encode over GF(2^128), one
+// launch per butterfly layer (both operands together), pointwise, the inverse
+// layers, Decode, per-step iBasisCvt
+// ---------------------------------------------------------------------------
+
+static int ensure_tables128(polymul_ctx *ctx)
+{
+    if (ctx->tables128) return 0;
+    std::unique_ptr<fpmul_host::Tables> H(new fpmul_host::Tables());
+    std::unique_ptr<fpmul_host::Tables128> H2(new fpmul_host::Tables128());
+    std::unique_ptr<DevTables128> D(new DevTables128());
+    try {
+        fpmul_host::build_tables(*H);
+        fpmul_host::build_tables128(*H, *H2);
+    } catch (const std::exception &ex) {
+        return fail(POLYMUL_EIO, std::string("m = 128 constant tables: ") + ex.what());
+    }
+    for (int k = 0; k < 8; ++k)
+        for (int e = 0; e < 256; ++e) {
+            uint64_t f = 0, a = 0;
+            for (int t = 0; t < 8; ++t)
+                if ((e >> t) & 1) {
+                    f ^= H2->enc[8 * k + t];
+                    a ^= H2->dec[8 * k + t];
+                }
+            D->enc_win[k][e] = f;
+            D->dec_win[k][e] = a;
+        }
+    for (int d = 0; d < M128_MAXD; ++d) D->lo[d] = H2->v[64 + d].lo;
+    D->v63 = H->cantor[63];
+    static_assert(sizeof(D->ktab) == sizeof(H2->ktab), "window table layout");
+    std::memcpy(D->ktab, H2->ktab, sizeof(D->ktab));
+    DevTables128 *dev = nullptr;
+    hipError_t e = hipMalloc(&dev, sizeof(DevTables128));
+    if (e == hipSuccess) e = hipMemcpy(dev, D.get(), sizeof(DevTables128), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (dev) (void)hipFree(dev);
+        return fail(POLYMUL_EIO, std::string("upload m = 128 tables: ") + hipGetErrorString(e));
+    }
+    ctx->tables128 = dev;
+    return 0;
+}
+
+static size_t bcvt_nsteps(uint64_t N)
+{
+    std::vector<BStep> steps;
+    bcvt_steps(N, 1, steps);
+    return steps.size();
+}
+
+// A (len bits) -> BasisCvt -> Encode over GF(2^128): 2^(log2n-7) values in dst
+static int run_encode128(polymul_ctx *ctx, const uint64_t *src, uint64_t len, int log2n, uint64_t *dst,
+                         uint64_t *spare, hipStream_t s)
+{
+    const int l = log2n - 7;
+    const uint64_t nw = 1ull << (log2n - 6), n_p = 1ull << l, N = next_pow2(std::max<uint64_t>(len, 1));
+    // the steps alternate between the two buffers; start where Encode then
+    // writes into dst
+    uint64_t *cur = (bcvt_nsteps(N) & 1) ? dst : spare, *sp = cur == dst ? spare : dst;
+    const uint64_t nwa = bcvt_active_words(N, nw);
+    KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, src, len, cur, nw);
+    if (nwa < nw) KLAUNCH(ctx, s, "zero", k_load_mask, grid_for(nw - nwa, 256), 256, src, 0, sp + nwa, nw - nwa);
+    int rc = run_bcvt(ctx, N, false, cur, sp, nwa, s);
+    if (rc) return rc;
+    if (sp != dst) return fail(POLYMUL_EIO, "m = 128 encode buffer order");
+    KLAUNCH(ctx, s, "encode128", k_encode128, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
+    return 0;
+}
+
+// forward layers of A and B, pointwise, inverse layers: the product's values in A
+static int run_product128(polymul_ctx *ctx, uint64_t *A, uint64_t *B, int l, hipStream_t s)
+{
+    const uint64_t n_p = 1ull << l;
+    const uint64_t wgs = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->num_cu, (n_p + 1023) / 1024));
+    for (int i = l - 1; i >= 0; --i)
+        KLAUNCH(ctx, s, "butterfly128", k_bfly128_layer<false>, (unsigned)wgs, 1024, A, B, l, i, ctx->tables,
+                ctx->tables128);
+    KLAUNCH(ctx, s, "pointwise128", k_pointwise128, (unsigned)wgs, 1024, A, B, n_p, ctx->tables, ctx->tables128);
+    for (int i = 0; i < l; ++i)
+        KLAUNCH(ctx, s, "ibutterfly128", k_bfly128_layer<true>, (unsigned)wgs, 1024, A, nullptr, l, i, ctx->tables,
+                ctx->tables128);
+    return 0;
+}
+
+static int product128_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
+                           uint64_t *out, hipStream_t s)
+{
+    const uint64_t lc = len_a + len_b - 1;
+    const int log2n = std::max(7, ilog2(lc)), l = log2n - 7;
+    const uint64_t nw = 1ull << (log2n - 6);
+    int rc = ensure_ws(ctx, nw);
+    if (rc) return rc;
+    if ((rc = ensure_tables128(ctx))) return rc;
+    uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2];
+    if ((rc = run_encode128(ctx, a, len_a, log2n, W0, W2, s))) return rc;
+    if ((rc = run_encode128(ctx, b, len_b, log2n, W1, W2, s))) return rc;
+    if ((rc = run_product128(ctx, W0, W1, l, s))) return rc;
+    KLAUNCH(ctx, s, "decode128_vec", k_decode128_vec, grid_for(nw, 256), 256, W0, nw, ctx->tables128);
+    KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
+    uint64_t *cur = W1, *spare = W2;
+    if ((rc = run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s))) return rc;
+    KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, cur, lc, out);
+    return 0;
+}
+
 static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
                         uint64_t *out, hipStream_t s)
 {
     const uint64_t lc = len_a + len_b - 1;
     const int log2n = transform_log2(len_a, len_b);
+    if (log2n >= ctx->large_field_log2n || log2n > M64_MAX_LOG2N)
+        return product128_body(ctx, a, len_a, b, len_b, out, s);
     int rc = ensure_ws(ctx, ws_words_for(log2n));
     if (rc) return rc;
     if ((rc = set_lds_limits())) return rc;
@@ -1060,6 +1190,7 @@ int polymul_ctx_destroy(polymul_ctx *ctx)
     for (int k = 0; k < 4; ++k)
         if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
     if (ctx->tables) (void)hipFree(ctx->tables);
+    if (ctx->tables128) (void)hipFree(ctx->tables128);
     if (ctx->bsteps) (void)hipFree(ctx->bsteps);
     if (ctx->bws) (void)hipFree(ctx->bws);
     for (ProfRec &r : ctx->prof_live) {
@@ -1078,7 +1209,7 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
     if (len_a == 0 || len_b == 0) return 0;
     if (len_a > POLYMUL_MAX_PRODUCT_BITS || len_b > POLYMUL_MAX_PRODUCT_BITS ||
         len_a + len_b - 1 > POLYMUL_MAX_PRODUCT_BITS)
-        return fail(POLYMUL_EINVAL, "product length exceeds 2^37 bits");
+        return fail(POLYMUL_EINVAL, "product length exceeds 2^62 bits");
     const uint64_t lc = len_a + len_b - 1;
     DeviceGuard g(ctx->device);
     HIP_TRY(g.err);
@@ -1090,7 +1221,7 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
         ranges_overlap(out, ob, b, (size_t)((len_b + 63) / 64) * 8))
         return fail(POLYMUL_EINVAL, "out overlaps an input");
     const int log2n = transform_log2(len_a, len_b);
-    if (log2n <= SINGLE_VIA_BATCH_LOG2N) {
+    if (log2n <= SINGLE_VIA_BATCH_LOG2N && log2n < ctx->large_field_log2n) {
         // a small product is one workgroup's work: the batch kernel takes it in
         // three launches instead of one launch per BasisCvt step
         const BtDesc one{a, b, out, len_a, len_b};
@@ -1098,6 +1229,15 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
                           1ull << log2n, nullptr, (hipStream_t)stream, &one);
     }
     return product_body(ctx, a, len_a, b, len_b, out, (hipStream_t)stream);
+}
+
+int polymul_set_large_field(polymul_ctx *ctx, int min_log2n)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (min_log2n < POLYMUL_LARGE_FIELD_MIN_LOG2N || min_log2n > M64_MAX_LOG2N + 1)
+        return fail(POLYMUL_EINVAL, "large-field threshold must be in [7, 38]");
+    ctx->large_field_log2n = min_log2n;
+    return 0;
 }
 
 int polymul_set_small_field(polymul_ctx *ctx, int max_log2n)

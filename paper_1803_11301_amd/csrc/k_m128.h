@@ -1,0 +1,167 @@
+// k_m128.h -- the m = 128 variant of the method (Sec. 3 with m = 128, l_m = 7;
+// the field-size bound after Prop. 2 then allows transforms far beyond the
+// 2^37 bits of m = 64).
+//
+// Field: GF(2^128) = GF(2^64)[y] / (y^2 + y + v_63), y = v_64 (the Cantor
+// equation of v_64).  A value is two words (x0, x1) = x0 + x1 y, each half in
+// the tower representation of gf_device.h, stored at words 2i and 2i + 1 of
+// the transform buffer: n_p = n / 128 values take n bits, as for m = 64.
+//
+// Encode (Alg. 4, Eq. 9 with m = 128): row j of the m x n_p bit matrix goes
+// to r_j = prod over set bits k of j (k < 7) of v_{64-k}.  Bit 0 of j selects
+// v_64 = y, so r_j = y^(j & 1) P_{j >> 1} with P_t = prod over set bits k of t
+// of v_{63-k} in GF(2^64): the even rows give the low half and the odd rows
+// the high half, each through the same 64 x 64 map P.  Decode applies P^-1 to
+// both halves and returns the bits to their rows.
+//
+// Butterfly (Alg. 2 at alpha = v_{l+64}): layer i, block b multiplies by the
+// element with Cantor vector 2^(64+d) XOR 2b, d = l - i.  With
+// v_{64+d} = L_d + H_d y and A = L_d + iota(2b) (2b < 2^63 stays in the low
+// half):
+//   (x0 + x1 y) (A + H_d y) = (x0 A + x1 (H_d v_63)) + ((x0 + x1) H_d + x1 A) y,
+// two general GF(2^64) products by A and two by the layer constants H_d and
+// H_d v_63 through their 8-bit window tables.
+#pragma once
+
+#include "gf_device.h"
+
+#define M128_MAXD 64
+
+struct DevTables128 {
+    uint64_t enc_win[8][256];            // Encode: byte window k of a 64-row column -> sum of P_t
+    uint64_t dec_win[8][256];            // Decode: byte window k of a half -> its 64 row bits
+    uint64_t lo[M128_MAXD];              // L_d
+    uint64_t v63;                        // v_63, tower representation
+    uint64_t ktab[M128_MAXD][2][2048];   // window tables of H_d and H_d v_63
+};
+
+// the GF(2^8) table and the two reduction tables into LDS (Mul8View layout)
+__device__ __forceinline__ void m128_load_mul8(uint8_t *s_m8, const DevTables *__restrict__ T, int tid, int nth)
+{
+    const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_m8);
+    for (int idx = tid; idx < 256 * 16; idx += nth) {
+        const int a = idx >> 4, c = idx & 15;   // row a, 16-byte column c
+        dst[((a & 1) << 11) | ((a >> 1) << 4) | c] = src[idx];
+    }
+    for (int q = tid; q < 512; q += nth) reinterpret_cast<uint16_t *>(s_m8 + M8V_OFF_C15)[q] = (&T->c15[0][0])[q];
+    for (int q = tid; q < 1024; q += nth) reinterpret_cast<uint32_t *>(s_m8 + M8V_OFF_C31)[q] = (&T->c31[0][0])[q];
+}
+
+__device__ __forceinline__ uint64_t m128_win(const uint64_t (*__restrict__ win)[256], uint64_t x)
+{
+    uint64_t r = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) r ^= win[k][(x >> (8 * k)) & 255u];
+    return r;
+}
+
+// Encode: value i gathers bit i of each of the 128 rows of n_p bits
+__global__ void k_encode128(const uint64_t *__restrict__ bits, int l, const DevTables128 *__restrict__ U,
+                            uint64_t *__restrict__ vals)
+{
+    const uint64_t n_p = 1ull << l, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_p; i += stride) {
+        uint64_t c0 = 0, c1 = 0;
+        for (int t = 0; t < 64; ++t) {
+            const uint64_t p0 = ((uint64_t)(2 * t) << l) + i, p1 = p0 + n_p;
+            c0 |= ((bits[p0 >> 6] >> (p0 & 63)) & 1ull) << t;
+            c1 |= ((bits[p1 >> 6] >> (p1 & 63)) & 1ull) << t;
+        }
+        vals[2 * i] = m128_win(U->enc_win, c0);
+        vals[2 * i + 1] = m128_win(U->enc_win, c1);
+    }
+}
+
+// Decode part 1: both halves of every value -> their row bits, in place
+__global__ void k_decode128_vec(uint64_t *__restrict__ vals, uint64_t nwords, const DevTables128 *__restrict__ U)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < nwords; w += stride)
+        vals[w] = m128_win(U->dec_win, vals[w]);
+}
+
+// Decode part 2: bit t of half e of value i is row 2t + e, column i
+__global__ void k_decode128_scatter(const uint64_t *__restrict__ vecs, int l, uint64_t *__restrict__ bits)
+{
+    const uint64_t nw = 2ull << l, mask = (1ull << l) - 1, stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t W = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; W < nw; W += stride) {
+        uint64_t r = 0;
+        for (int t = 0; t < 64; ++t) {
+            const uint64_t p = 64 * W + t, j = p >> l, i = p & mask;
+            r |= ((vecs[2 * i + (j & 1)] >> (j >> 1)) & 1ull) << t;
+        }
+        bits[W] = r;
+    }
+}
+
+// (x0 + x1 y) (A + H y) with tab0 = window table of H, tab1 = of H v_63
+__device__ __forceinline__ void m128_mulc(const Mul8View &mv, const uint64_t *__restrict__ tab0,
+                                          const uint64_t *__restrict__ tab1, uint64_t A, uint64_t x0, uint64_t x1,
+                                          uint64_t &r0, uint64_t &r1)
+{
+    r0 = mv.m64(x0, A) ^ tmul(tab1, x1);
+    r1 = tmul(tab0, x0 ^ x1) ^ mv.m64(x1, A);
+}
+
+// One butterfly layer i of the transforms of A (and of B when given):
+// forward h0 = p0 + c p1, h1 = h0 + p1; inverse p1 = h0 + h1, p0 = h0 + c p1.
+// One work item per pair, grid-stride over the pairs of both operands.
+template <bool INV>
+__global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A, uint64_t *__restrict__ B, int l,
+                                                        int i, const DevTables *__restrict__ T,
+                                                        const DevTables128 *__restrict__ U)
+{
+    __shared__ __align__(16) uint8_t s_m8[M8V_BYTES];
+    __shared__ __align__(16) uint64_t s_tab[2][2048];
+    const int tid = threadIdx.x, nth = blockDim.x, d = l - i;
+    m128_load_mul8(s_m8, T, tid, nth);
+    for (int q = tid; q < 2 * 2048; q += nth) (&s_tab[0][0])[q] = (&U->ktab[d][0][0])[q];
+    __syncthreads();
+    const Mul8View mv{s_m8};
+    const uint64_t Ld = U->lo[d];
+    const uint64_t half = 1ull << (l - 1), total = B ? 2 * half : half;
+    const uint64_t stride = (uint64_t)gridDim.x * nth, omask = (1ull << i) - 1;
+    for (uint64_t q = (uint64_t)blockIdx.x * nth + tid; q < total; q += stride) {
+        uint64_t *X = q < half ? A : B;
+        const uint64_t r = q & (half - 1), b = r >> i;
+        const uint64_t j0 = (b << (i + 1)) | (r & omask), j1 = j0 + (1ull << i);
+        const uint64_t cb = 2 * b;
+        uint64_t Ab = Ld;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) Ab ^= T->iota[k][(cb >> (8 * k)) & 255u];
+        const ulonglong2 u = reinterpret_cast<const ulonglong2 *>(X)[j0];
+        const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(X)[j1];
+        uint64_t m0, m1;
+        if (!INV) {
+            m128_mulc(mv, s_tab[0], s_tab[1], Ab, v.x, v.y, m0, m1);
+            const uint64_t h0 = u.x ^ m0, h1 = u.y ^ m1;
+            reinterpret_cast<ulonglong2 *>(X)[j0] = make_ulonglong2(h0, h1);
+            reinterpret_cast<ulonglong2 *>(X)[j1] = make_ulonglong2(h0 ^ v.x, h1 ^ v.y);
+        } else {
+            const uint64_t p10 = u.x ^ v.x, p11 = u.y ^ v.y;
+            m128_mulc(mv, s_tab[0], s_tab[1], Ab, p10, p11, m0, m1);
+            reinterpret_cast<ulonglong2 *>(X)[j0] = make_ulonglong2(u.x ^ m0, u.y ^ m1);
+            reinterpret_cast<ulonglong2 *>(X)[j1] = make_ulonglong2(p10, p11);
+        }
+    }
+}
+
+// A[j] = A[j] B[j] over GF(2^128) (Alg. 5, the pointwise step)
+__global__ __launch_bounds__(1024) void k_pointwise128(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
+                                                       uint64_t n_p, const DevTables *__restrict__ T,
+                                                       const DevTables128 *__restrict__ U)
+{
+    __shared__ __align__(16) uint8_t s_m8[M8V_BYTES];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    m128_load_mul8(s_m8, T, tid, nth);
+    __syncthreads();
+    const Mul8View mv{s_m8};
+    const uint64_t v63 = U->v63, stride = (uint64_t)gridDim.x * nth;
+    for (uint64_t j = (uint64_t)blockIdx.x * nth + tid; j < n_p; j += stride) {
+        const ulonglong2 a = reinterpret_cast<const ulonglong2 *>(A)[j];
+        const ulonglong2 b = reinterpret_cast<const ulonglong2 *>(B)[j];
+        const uint64_t p0 = mv.m64(a.x, b.x), p2 = mv.m64(a.y, b.y), p1 = mv.m64(a.x ^ a.y, b.x ^ b.y);
+        reinterpret_cast<ulonglong2 *>(A)[j] = make_ulonglong2(p0 ^ mv.m64(p2, v63), p1 ^ p0);
+    }
+}

@@ -202,6 +202,7 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
         slot.view->bsteps = ctx->bsteps;
         slot.view->num_cu = ctx->num_cu;
         slot.view->small_field_log2n = ctx->small_field_log2n;
+        slot.view->large_field_log2n = M64_MAX_LOG2N + 1;   // the server admits m = 64 products only
         slot.view->borrowed = true;
     }
     if (e != hipSuccess) {
@@ -261,8 +262,8 @@ int polymul_submit(polymul_server *S, const uint64_t *a, uint64_t len_a, const u
     *ticket = 0;
     const bool empty = len_a == 0 || len_b == 0;
     if (!empty) {
-        if (len_a > POLYMUL_MAX_PRODUCT_BITS || len_b > POLYMUL_MAX_PRODUCT_BITS ||
-            len_a + len_b - 1 > POLYMUL_MAX_PRODUCT_BITS)
+        if (len_a > POLYMUL_SERVER_MAX_PRODUCT_BITS || len_b > POLYMUL_SERVER_MAX_PRODUCT_BITS ||
+            len_a + len_b - 1 > POLYMUL_SERVER_MAX_PRODUCT_BITS)
             return fail(POLYMUL_EINVAL, "product length exceeds 2^37 bits");
         DeviceGuard g(S->ctx->device);
         HIP_TRY(g.err);

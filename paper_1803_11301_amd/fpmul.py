@@ -14,7 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfpmul.so")
 
 EIO, ENOMEM, EINVAL = -5, -12, -22
-MAX_PRODUCT_BITS = 1 << 37
+M64_MAX_PRODUCT_BITS = 1 << 37
+MAX_PRODUCT_BITS = 1 << 62
+SERVER_MAX_PRODUCT_BITS = M64_MAX_PRODUCT_BITS
 BATCH_MAX_PRODUCT_BITS = 1 << 22
 
 # (name, restype, argtypes) of every symbol include/fpmul.h declares
@@ -26,6 +28,7 @@ SIGNATURES = {
     "polymul_ex": (_I, [_V, _P, _U64, _P, _U64, _P, _V]),
     "polymul_batch": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _V]),
     "polymul_set_small_field": (_I, [_V, _I]),
+    "polymul_set_large_field": (_I, [_V, _I]),
     "polymul_server_create": (_I, [ctypes.POINTER(_V), _V, _SZ, ctypes.c_uint32]),
     "polymul_server_destroy": (_I, [_V]),
     "polymul_server_set_policy": (_I, [_V, _U64, ctypes.c_uint32]),
@@ -164,6 +167,11 @@ class Context:
         """Batch items (and polymul_ex products up to 2^17 bits) with transforms of
         at most 2^max_log2n bits run over GF(2^32); 0 keeps GF(2^64)."""
         _check(lib().polymul_set_small_field(self.handle, max_log2n))
+
+    def set_large_field(self, min_log2n: int):
+        """Products (polymul_ex) with transforms of at least 2^min_log2n bits run
+        over GF(2^128); transforms above 2^37 bits always do."""
+        _check(lib().polymul_set_large_field(self.handle, min_log2n))
 
     def addfft(self, a, len_a: int, log2n: int, values=None, stream=None):
         import torch

@@ -83,6 +83,40 @@ def dense_poly(seed: int, length: int, top_bit: bool = False) -> np.ndarray:
     return w[: nwords(length)]
 
 
+def _as_i64(v: int) -> int:
+    v &= MASK64
+    return v - (1 << 64) if v >> 63 else v
+
+
+def dense_poly_device(seed: int, length: int, device, chunk_words: int = 1 << 26):
+    """``dense_poly(seed, length)`` generated on a torch device (int64 words of
+    the same bits), for operands too large to draw on the host.  int64
+    products wrap modulo 2^64, and a logical shift is an arithmetic shift
+    masked to the low 64 - k bits."""
+    import torch
+    n = max(nwords(length), 1)
+    out = torch.empty(n, dtype=torch.int64, device=device)
+
+    def shr(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    golden, m1, m2 = _as_i64(int(GOLDEN)), _as_i64(int(_M1)), _as_i64(int(_M2))
+    for off in range(0, n, chunk_words):
+        cnt = min(chunk_words, n - off)
+        z = torch.arange(off + 1, off + cnt + 1, dtype=torch.int64, device=device)
+        z.mul_(golden).add_(_as_i64(seed))
+        z.bitwise_xor_(shr(z, 30)).mul_(m1)
+        z.bitwise_xor_(shr(z, 27)).mul_(m2)
+        z.bitwise_xor_(shr(z, 31))
+        out[off:off + cnt] = z
+        del z
+    if length % 64 and length:
+        out[n - 1] &= (1 << (length % 64)) - 1
+    if length == 0:
+        out.zero_()
+    return out
+
+
 def unit_floats(seed: int, count: int, start: int = 0) -> np.ndarray:
     """Uniform doubles in [0, 1) from the 53 high bits of each output."""
     x = splitmix64(seed, count, start) >> np.uint64(11)

@@ -235,9 +235,11 @@ def test_error_codes(ctx):
     # host memory is not accepted
     host_buf = np.zeros(4, np.uint64)
     assert L.polymul_ex(ctx.handle, host_buf.ctypes.data, 64, a.data_ptr(), 64, out.data_ptr(), None) == fpmul.EINVAL
-    # beyond the 2^37-bit limit (rejected before any launch)
-    assert L.polymul_ex(ctx.handle, a.data_ptr(), 1 << 37, a.data_ptr(), 2, out.data_ptr(), None) == fpmul.EINVAL
-    assert "2^37" in L.polymul_last_error().decode()
+    # beyond the 2^62-bit limit (rejected before any launch)
+    assert L.polymul_ex(ctx.handle, a.data_ptr(), 1 << 62, a.data_ptr(), 2, out.data_ptr(), None) == fpmul.EINVAL
+    assert "2^62" in L.polymul_last_error().decode()
+    assert L.polymul_ex(ctx.handle, a.data_ptr(), (1 << 62) + 1, a.data_ptr(), 1, out.data_ptr(), None) \
+        == fpmul.EINVAL
     # workspace above the context cap
     big = dev(np.zeros(2000, np.uint64))
     big_out = dev(np.zeros(4000, np.uint64))
