@@ -139,13 +139,6 @@ __global__ void k_bcvt_step_wide(const uint64_t *__restrict__ in, uint64_t *__re
     for (uint64_t w = gid(); w < nw; w += gstride()) out[w] = bcvt_wide_word(in, w, S, d, inverse);
 }
 
-// one step with S <= 64 inside each word (L: low-half mask, D: low-d mask per segment)
-__global__ void k_bcvt_step_word(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t nw,
-                                 int H, int d, uint64_t L, uint64_t D, int inverse)
-{
-    for (uint64_t w = gid(); w < nw; w += gstride()) out[w] = bcvt_in_word(in[w], H, d, L, D, inverse);
-}
-
 // ---------------------------------------------------------------------------
 // Encode (Alg. 4): f_i = sum_j a_{j n_p + i} r_j, the 64-bit column of bits
 // (a_{j n_p + i})_j multiplied into the rows r_j by 8-bit windows
@@ -165,6 +158,30 @@ __global__ void k_encode(const uint64_t *__restrict__ bits, int l, const DevTabl
 #pragma unroll
         for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(col >> (8 * k)) & 255u];
         vals[i] = f;
+    }
+}
+
+// Encode with the bit transpose done by wave ballots (n_p >= 64): one wave
+// per 64 consecutive values; lane t loads the word of row t over their
+// columns, and value k's column is the ballot of bit k of those words
+__global__ __launch_bounds__(256) void k_encode_w(const uint64_t *__restrict__ bits, int l,
+                                                  const DevTables *__restrict__ T, uint64_t *__restrict__ vals)
+{
+    const uint64_t rw = 1ull << (l - 6);   // words per row = blocks of 64 values
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = gstride() >> 6;
+    for (uint64_t blk = gid() >> 6; blk < rw; blk += nwaves) {
+        const uint64_t w = bits[(uint64_t)lane * rw + blk];
+        uint64_t col = 0;
+#pragma unroll 8
+        for (int k = 0; k < 64; ++k) {
+            const uint64_t m = __ballot((int)((w >> k) & 1u));
+            col = lane == k ? m : col;
+        }
+        uint64_t f = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(col >> (8 * k)) & 255u];
+        vals[blk * 64 + lane] = f;
     }
 }
 
@@ -195,6 +212,26 @@ __global__ void k_decode_scatter(const uint64_t *__restrict__ vecs, int l, uint6
     }
 }
 
+// Decode part 2 with ballots (n_p >= 64): lane k holds vector i0 + k; the
+// word of row t over columns i0 .. i0 + 63 is the ballot of bit t, kept by lane t
+__global__ __launch_bounds__(256) void k_decode_scatter_w(const uint64_t *__restrict__ vecs, int l,
+                                                          uint64_t *__restrict__ bits)
+{
+    const uint64_t rw = 1ull << (l - 6);
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = gstride() >> 6;
+    for (uint64_t blk = gid() >> 6; blk < rw; blk += nwaves) {
+        const uint64_t h = vecs[blk * 64 + lane];
+        uint64_t r = 0;
+#pragma unroll 8
+        for (int t = 0; t < 64; ++t) {
+            const uint64_t m = __ballot((int)((h >> t) & 1u));
+            r = lane == t ? m : r;
+        }
+        bits[(uint64_t)lane * rw + blk] = r;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
@@ -207,6 +244,8 @@ struct ProfRec {
 #define SMALL_FIELD_DEFAULT_LOG2N 20   // m = 32 batch items: transforms up to 2^20 bits
 #define M64_MAX_LOG2N 37               // m = 64 field bound: n <= (m/2) 2^(m/2) = 2^37
 #define LARGE_FIELD_DEFAULT_LOG2N 38   // m = 128 from the first transform m = 64 cannot take
+
+struct PStepTable;
 
 struct polymul_ctx {
     int device = 0;
@@ -229,6 +268,7 @@ struct polymul_ctx {
     // GF(2^128) (m = 128); above 2^37 bits m = 64 cannot take them
     int large_field_log2n = LARGE_FIELD_DEFAULT_LOG2N;
     DevTables128 *tables128 = nullptr;   // built on the first m = 128 product
+    PStepTable *psteps = nullptr;        // BasisCvt step lists of the per-step path
     // per-kernel timing with HIP events on the launch stream (off by default)
     bool prof = false;
     std::vector<ProfRec> prof_live;       // recorded, not yet read
@@ -350,30 +390,117 @@ static int ilog2(uint64_t x)
     return r;
 }
 
+// Step lists of BasisCvt(2^k) for every k <= PSTEP_MAX_LOG2N, in one device
+// table built once per context: entries first[k] .. first[k] + count[k] - 1,
+// with the in-word masks of the steps of at most 64 bits (BatchStep)
+#define PSTEP_MAX_LOG2N 62
+#define PSTEP_MAX 5120
+struct PStepTable {
+    BatchStep st[PSTEP_MAX];
+};
+
+struct PStepIndex {
+    int first[PSTEP_MAX_LOG2N + 1];
+    int count[PSTEP_MAX_LOG2N + 1];
+};
+
+static const PStepIndex &pstep_index()
+{
+    static const PStepIndex idx = [] {
+        PStepIndex r{};
+        int at = 0;
+        for (int k = 0; k <= PSTEP_MAX_LOG2N; ++k) {
+            std::vector<BStep> v;
+            bcvt_steps(1ull << k, 1, v);
+            r.first[k] = at;
+            r.count[k] = (int)v.size();
+            at += (int)v.size();
+        }
+        return r;
+    }();
+    return idx;
+}
+
+static int build_psteps(PStepTable &P)
+{
+    const PStepIndex &ix = pstep_index();
+    if (ix.first[PSTEP_MAX_LOG2N] + ix.count[PSTEP_MAX_LOG2N] > PSTEP_MAX)
+        return fail(POLYMUL_EIO, "BasisCvt step table overflow");
+    for (int k = 0; k <= PSTEP_MAX_LOG2N; ++k) {
+        std::vector<BStep> v;
+        bcvt_steps(1ull << k, 1, v);
+        for (size_t j = 0; j < v.size(); ++j) {
+            BatchStep b{v[j].S, v[j].d, 0, 0};
+            if (v[j].S <= 64) {
+                const int S = (int)v[j].S, H = S / 2, d = (int)v[j].d;
+                for (int t = 0; t < 64; ++t) {
+                    if (t % S < H) b.L |= 1ull << t;
+                    if (t % S < d) b.D |= 1ull << t;
+                }
+            }
+            P.st[ix.first[k] + j] = b;
+        }
+    }
+    return 0;
+}
+
+// Runs of consecutive steps whose segments fit BT_LDS_WORDS words, applied
+// chunk by chunk in LDS in place (each chunk holds whole segments)
+__global__ __launch_bounds__(1024) void k_bcvt_lds_run(uint64_t *__restrict__ X, uint64_t nw, int chw,
+                                                       const BatchStep *__restrict__ st0, int cnt, int inverse, int k0,
+                                                       int k1)
+{
+    __shared__ __align__(16) uint64_t lds[BT_LDS_WORDS];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (uint64_t c0 = (uint64_t)blockIdx.x * chw; c0 < nw; c0 += (uint64_t)gridDim.x * chw) {
+        for (int w = tid; w < chw; w += nth) lds[w] = X[c0 + w];
+        __syncthreads();
+        bt_lds_steps(lds, chw, st0, cnt, inverse != 0, k0, k1, tid, nth);
+        for (int w = tid; w < chw; w += nth) X[c0 + w] = lds[w];
+        __syncthreads();
+    }
+}
+
+// steps with segments beyond LDS, which run out of place (one buffer swap each)
+static size_t bcvt_swaps(uint64_t N)
+{
+    std::vector<BStep> steps;
+    bcvt_steps(N, 1, steps);
+    size_t c = 0;
+    for (const BStep &st : steps) c += st.S > 64ull * BT_LDS_WORDS;
+    return c;
+}
+
 // run the BasisCvt steps for N bits (or their inverse) on buffers of nw words
+// (nw >= N / 64): every run of steps with segments of at most 2^20 bits in
+// one LDS pass, each larger step out of place
 static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *&cur, uint64_t *&spare, uint64_t nw,
                     hipStream_t s)
 {
     std::vector<BStep> steps;
     bcvt_steps(N, 1, steps);
-    if (inverse) std::reverse(steps.begin(), steps.end());
-    const unsigned bs = 256;
-    for (const BStep &st : steps) {
-        if (st.S >= 128) {
-            KLAUNCH(ctx, s, inverse ? "ibasiscvt_wide" : "basiscvt_wide", k_bcvt_step_wide, grid_for(nw, bs), bs,
-                    cur, spare, nw, st.S, st.d, inverse ? 1 : 0);
+    const int cnt = (int)steps.size(), lg = ilog2(N);
+    if (!cnt) return 0;
+    if (lg > PSTEP_MAX_LOG2N || pstep_index().count[lg] != cnt || !ctx->psteps)
+        return fail(POLYMUL_EIO, "BasisCvt step table");
+    const BatchStep *st0 = ctx->psteps->st + pstep_index().first[lg];
+    const uint64_t lds_bits = 64ull * BT_LDS_WORDS, chw = std::min<uint64_t>(nw, BT_LDS_WORDS);
+    auto S_of = [&](int k) { return steps[inverse ? cnt - 1 - k : k].S; };
+    for (int k = 0; k < cnt;) {
+        if (S_of(k) <= lds_bits) {
+            int e = k + 1;
+            while (e < cnt && S_of(e) <= lds_bits) ++e;
+            const unsigned grid = (unsigned)std::min<uint64_t>(nw / chw, GRID_CAP);
+            KLAUNCH(ctx, s, inverse ? "ibasiscvt_lds" : "basiscvt_lds", k_bcvt_lds_run, grid, 1024, cur, nw,
+                    (int)chw, st0, cnt, inverse ? 1 : 0, k, e);
+            k = e;
         } else {
-            int H = (int)(st.S / 2), d = (int)st.d;
-            uint64_t L = 0, D = 0;
-            for (int b = 0; b < 64; ++b) {
-                int r = b % (int)st.S;
-                if (r < H) L |= 1ull << b;
-                if (r < d) D |= 1ull << b;
-            }
-            KLAUNCH(ctx, s, inverse ? "ibasiscvt_word" : "basiscvt_word", k_bcvt_step_word, grid_for(nw, bs), bs,
-                    cur, spare, nw, H, d, L, D, inverse ? 1 : 0);
+            const BStep &st = steps[inverse ? cnt - 1 - k : k];
+            KLAUNCH(ctx, s, inverse ? "ibasiscvt_wide" : "basiscvt_wide", k_bcvt_step_wide, grid_for(nw, 256), 256,
+                    cur, spare, nw, st.S, st.d, inverse ? 1 : 0);
+            std::swap(cur, spare);
+            ++k;
         }
-        std::swap(cur, spare);
     }
     return 0;
 }
@@ -395,7 +522,10 @@ static int run_encode_in(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int 
     if (nwa < nw) KLAUNCH(ctx, s, "zero", k_load_mask, grid_for(nw - nwa, bs), bs, a, 0, spare + nwa, nw - nwa);
     int rc = run_bcvt(ctx, N, false, cur, spare, nwa, s);
     if (rc) return rc;
-    KLAUNCH(ctx, s, "encode", k_encode, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
+    if (l >= 6)
+        KLAUNCH(ctx, s, "encode", k_encode_w, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
+    else
+        KLAUNCH(ctx, s, "encode", k_encode, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
     std::swap(cur, spare);
     return 0;
 }
@@ -407,7 +537,10 @@ static int run_decode_out(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t 
     const uint64_t nw = 1ull << l, n_p = 1ull << l;
     const unsigned bs = 256;
     KLAUNCH(ctx, s, "decode_vec", k_decode_vec, grid_for(n_p, bs), bs, cur, l, ctx->tables);
-    KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
+    if (l >= 6)
+        KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter_w, grid_for(nw, bs), bs, cur, l, spare);
+    else
+        KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
     std::swap(cur, spare);
     return run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s);
 }
@@ -769,6 +902,8 @@ static int ensure_tables128(polymul_ctx *ctx)
             D->dec_win[k][e] = a;
         }
     for (int d = 0; d < M128_MAXD; ++d) D->lo[d] = H2->v[64 + d].lo;
+    for (int d = 0; d <= 32; ++d)
+        for (int t = 0; t < 64; ++t) D->gbase[d][t] = H->tw.m64(H2->v[64 + d].lo, 1ull << t);
     D->v63 = H->cantor[63];
     static_assert(sizeof(D->ktab) == sizeof(H2->ktab), "window table layout");
     std::memcpy(D->ktab, H2->ktab, sizeof(D->ktab));
@@ -783,13 +918,6 @@ static int ensure_tables128(polymul_ctx *ctx)
     return 0;
 }
 
-static size_t bcvt_nsteps(uint64_t N)
-{
-    std::vector<BStep> steps;
-    bcvt_steps(N, 1, steps);
-    return steps.size();
-}
-
 // A (len bits) -> BasisCvt -> Encode over GF(2^128): 2^(log2n-7) values in dst
 static int run_encode128(polymul_ctx *ctx, const uint64_t *src, uint64_t len, int log2n, uint64_t *dst,
                          uint64_t *spare, hipStream_t s)
@@ -798,14 +926,17 @@ static int run_encode128(polymul_ctx *ctx, const uint64_t *src, uint64_t len, in
     const uint64_t nw = 1ull << (log2n - 6), n_p = 1ull << l, N = next_pow2(std::max<uint64_t>(len, 1));
     // the steps alternate between the two buffers; start where Encode then
     // writes into dst
-    uint64_t *cur = (bcvt_nsteps(N) & 1) ? dst : spare, *sp = cur == dst ? spare : dst;
+    uint64_t *cur = (bcvt_swaps(N) & 1) ? dst : spare, *sp = cur == dst ? spare : dst;
     const uint64_t nwa = bcvt_active_words(N, nw);
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, src, len, cur, nw);
     if (nwa < nw) KLAUNCH(ctx, s, "zero", k_load_mask, grid_for(nw - nwa, 256), 256, src, 0, sp + nwa, nw - nwa);
     int rc = run_bcvt(ctx, N, false, cur, sp, nwa, s);
     if (rc) return rc;
     if (sp != dst) return fail(POLYMUL_EIO, "m = 128 encode buffer order");
-    KLAUNCH(ctx, s, "encode128", k_encode128, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
+    if (l >= 6)
+        KLAUNCH(ctx, s, "encode128", k_encode128_w, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
+    else
+        KLAUNCH(ctx, s, "encode128", k_encode128, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
     return 0;
 }
 
@@ -838,7 +969,10 @@ static int product128_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, 
     if ((rc = run_encode128(ctx, b, len_b, log2n, W1, W2, s))) return rc;
     if ((rc = run_product128(ctx, W0, W1, l, s))) return rc;
     KLAUNCH(ctx, s, "decode128_vec", k_decode128_vec, grid_for(nw, 256), 256, W0, nw, ctx->tables128);
-    KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
+    if (l >= 6)
+        KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter_w, grid_for(nw / 2, 256), 256, W0, l, W1);
+    else
+        KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
     uint64_t *cur = W1, *spare = W2;
     if ((rc = run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s))) return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, cur, lc, out);
@@ -1171,10 +1305,18 @@ int polymul_ctx_create(polymul_ctx **out, int device, size_t workspace_cap)
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
             ctx->num_cu = cus;
     }
+    std::unique_ptr<PStepTable> P(new PStepTable());
+    if (int rc = build_psteps(*P)) {
+        delete ctx;
+        return rc;
+    }
     hipError_t e = hipMalloc(&ctx->tables, sizeof(DevTables));
     if (e == hipSuccess) e = hipMemcpy(ctx->tables, D.get(), sizeof(DevTables), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&ctx->psteps, sizeof(PStepTable));
+    if (e == hipSuccess) e = hipMemcpy(ctx->psteps, P.get(), sizeof(PStepTable), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         if (ctx->tables) (void)hipFree(ctx->tables);
+        if (ctx->psteps) (void)hipFree(ctx->psteps);
         delete ctx;
         return fail(POLYMUL_EIO, std::string("upload tables: ") + hipGetErrorString(e));
     }
@@ -1191,6 +1333,7 @@ int polymul_ctx_destroy(polymul_ctx *ctx)
         if (ctx->ws[k]) (void)hipFree(ctx->ws[k]);
     if (ctx->tables) (void)hipFree(ctx->tables);
     if (ctx->tables128) (void)hipFree(ctx->tables128);
+    if (ctx->psteps) (void)hipFree(ctx->psteps);
     if (ctx->bsteps) (void)hipFree(ctx->bsteps);
     if (ctx->bws) (void)hipFree(ctx->bws);
     for (ProfRec &r : ctx->prof_live) {

@@ -19,8 +19,8 @@
 // v_{64+d} = L_d + H_d y and A = L_d + iota(2b) (2b < 2^63 stays in the low
 // half):
 //   (x0 + x1 y) (A + H_d y) = (x0 A + x1 (H_d v_63)) + ((x0 + x1) H_d + x1 A) y,
-// two general GF(2^64) products by A and two by the layer constants H_d and
-// H_d v_63 through their 8-bit window tables.
+// two GF(2^64) products by A and two by the layer constants H_d and H_d v_63
+// through their 8-bit window tables.
 #pragma once
 
 #include "gf_device.h"
@@ -33,6 +33,7 @@ struct DevTables128 {
     uint64_t lo[M128_MAXD];              // L_d
     uint64_t v63;                        // v_63, tower representation
     uint64_t ktab[M128_MAXD][2][2048];   // window tables of H_d and H_d v_63
+    uint64_t gbase[33][64];              // L_d unit_t (basis images of L_d), d <= 32
 };
 
 // the GF(2^8) table and the two reduction tables into LDS (Mul8View layout)
@@ -73,6 +74,30 @@ __global__ void k_encode128(const uint64_t *__restrict__ bits, int l, const DevT
     }
 }
 
+// The same with the bit transpose done by wave ballots (n_p >= 64): one wave
+// per 64 consecutive values i0 .. i0 + 63.  Lane t loads the words of rows 2t
+// and 2t + 1 that hold those columns; bit t of value k's halves is bit k of
+// lane t's words, which the ballot over the lanes of bit k collects.
+__global__ __launch_bounds__(256) void k_encode128_w(const uint64_t *__restrict__ bits, int l,
+                                                     const DevTables128 *__restrict__ U, uint64_t *__restrict__ vals)
+{
+    const uint64_t rw = 1ull << (l - 6);   // words per row = blocks of 64 values
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t blk = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; blk < rw; blk += nwaves) {
+        const uint64_t we = bits[(uint64_t)(2 * lane) * rw + blk], wo = bits[(uint64_t)(2 * lane + 1) * rw + blk];
+        uint64_t c0 = 0, c1 = 0;
+#pragma unroll 8
+        for (int k = 0; k < 64; ++k) {
+            const uint64_t m0 = __ballot((int)((we >> k) & 1u)), m1 = __ballot((int)((wo >> k) & 1u));
+            c0 = lane == k ? m0 : c0;
+            c1 = lane == k ? m1 : c1;
+        }
+        const uint64_t i = blk * 64 + lane;
+        reinterpret_cast<ulonglong2 *>(vals)[i] = make_ulonglong2(m128_win(U->enc_win, c0), m128_win(U->enc_win, c1));
+    }
+}
+
 // Decode part 1: both halves of every value -> their row bits, in place
 __global__ void k_decode128_vec(uint64_t *__restrict__ vals, uint64_t nwords, const DevTables128 *__restrict__ U)
 {
@@ -95,18 +120,43 @@ __global__ void k_decode128_scatter(const uint64_t *__restrict__ vecs, int l, ui
     }
 }
 
-// (x0 + x1 y) (A + H y) with tab0 = window table of H, tab1 = of H v_63
-__device__ __forceinline__ void m128_mulc(const Mul8View &mv, const uint64_t *__restrict__ tab0,
-                                          const uint64_t *__restrict__ tab1, uint64_t A, uint64_t x0, uint64_t x1,
-                                          uint64_t &r0, uint64_t &r1)
+// Decode part 2 with ballots (n_p >= 64): lane k holds value i0 + k; the
+// word of row 2t + e over columns i0 .. i0 + 63 is the ballot of bit t of
+// half e, kept by lane t
+__global__ __launch_bounds__(256) void k_decode128_scatter_w(const uint64_t *__restrict__ vecs, int l,
+                                                             uint64_t *__restrict__ bits)
 {
-    r0 = mv.m64(x0, A) ^ tmul(tab1, x1);
-    r1 = tmul(tab0, x0 ^ x1) ^ mv.m64(x1, A);
+    const uint64_t rw = 1ull << (l - 6);
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t blk = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; blk < rw; blk += nwaves) {
+        const ulonglong2 h = reinterpret_cast<const ulonglong2 *>(vecs)[blk * 64 + lane];
+        uint64_t r0 = 0, r1 = 0;
+#pragma unroll 8
+        for (int t = 0; t < 64; ++t) {
+            const uint64_t m0 = __ballot((int)((h.x >> t) & 1u)), m1 = __ballot((int)((h.y >> t) & 1u));
+            r0 = lane == t ? m0 : r0;
+            r1 = lane == t ? m1 : r1;
+        }
+        bits[(uint64_t)(2 * lane) * rw + blk] = r0;
+        bits[(uint64_t)(2 * lane + 1) * rw + blk] = r1;
+    }
 }
 
 // One butterfly layer i of the transforms of A (and of B when given):
 // forward h0 = p0 + c p1, h1 = h0 + p1; inverse p1 = h0 + h1, p0 = h0 + c p1.
-// One work item per pair, grid-stride over the pairs of both operands.
+// The pairs of both operands form one range of 1024-pair tiles, one pair per
+// thread; each workgroup takes a contiguous run of tiles.
+//
+// The products by A = L_d + iota(2b) split as for m = 64: with b = 128 bh + bl,
+// A = K + beta, K = L_d + iota(bh << 8) and beta = iota(2 bl) in V_8, so
+// x A = tmul(T_K, x) + bmul(beta, x).  T_K is rebuilt in LDS whenever bh
+// changes (every 2^(i+7) pairs) from its basis images K unit_t =
+// L_d unit_t + the v_{8+v} unit_t of the set bits v of bh.  This needs a
+// tile inside one block range of bh (i >= 3, whole tiles: l >= 11) and
+// bh < 2^24 (d <= 32); other layers take general products by A.
+#define M128_TILE 1024
+
 template <bool INV>
 __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A, uint64_t *__restrict__ B, int l,
                                                         int i, const DevTables *__restrict__ T,
@@ -114,35 +164,74 @@ __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A
 {
     __shared__ __align__(16) uint8_t s_m8[M8V_BYTES];
     __shared__ __align__(16) uint64_t s_tab[2][2048];
+    __shared__ __align__(16) uint64_t s_k[2048];
+    __shared__ uint64_t s_img[64];
     const int tid = threadIdx.x, nth = blockDim.x, d = l - i;
     m128_load_mul8(s_m8, T, tid, nth);
     for (int q = tid; q < 2 * 2048; q += nth) (&s_tab[0][0])[q] = (&U->ktab[d][0][0])[q];
     __syncthreads();
     const Mul8View mv{s_m8};
     const uint64_t Ld = U->lo[d];
-    const uint64_t half = 1ull << (l - 1), total = B ? 2 * half : half;
-    const uint64_t stride = (uint64_t)gridDim.x * nth, omask = (1ull << i) - 1;
-    for (uint64_t q = (uint64_t)blockIdx.x * nth + tid; q < total; q += stride) {
+    const uint64_t half = 1ull << (l - 1), total = B ? 2 * half : half, omask = (1ull << i) - 1;
+    const bool tabled = i >= 3 && l >= 11 && d <= 32;
+    const uint64_t ntiles = (total + M128_TILE - 1) / M128_TILE;
+    const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t_end = min(ntiles, (uint64_t)(blockIdx.x + 1) * per);
+    uint64_t key = ~0ull;
+    for (uint64_t tile = (uint64_t)blockIdx.x * per; tile < t_end; ++tile) {
+        if (tabled) {
+            const uint64_t bh = ((tile * M128_TILE) & (half - 1)) >> (i + 7);
+            if (bh != key) {   // uniform: one tile lies in one block range of bh
+                __syncthreads();   // the previous tile is done with T_K
+                if (tid < 64) {
+                    uint64_t v = U->gbase[d][tid];
+#pragma unroll
+                    for (int k = 0; k < 24; ++k) v ^= ((bh >> k) & 1u) ? T->pbasis[k][tid] : 0ull;
+                    s_img[tid] = v;
+                }
+                __syncthreads();
+                if (tid < 256) ktable_fill_item(s_k, s_img, tid);
+                __syncthreads();
+                key = bh;
+            }
+        }
+        const uint64_t q = tile * M128_TILE + tid;
+        if (q >= total) continue;
         uint64_t *X = q < half ? A : B;
         const uint64_t r = q & (half - 1), b = r >> i;
         const uint64_t j0 = (b << (i + 1)) | (r & omask), j1 = j0 + (1ull << i);
-        const uint64_t cb = 2 * b;
-        uint64_t Ab = Ld;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) Ab ^= T->iota[k][(cb >> (8 * k)) & 255u];
         const ulonglong2 u = reinterpret_cast<const ulonglong2 *>(X)[j0];
         const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(X)[j1];
-        uint64_t m0, m1;
+        uint64_t x0, x1;
         if (!INV) {
-            m128_mulc(mv, s_tab[0], s_tab[1], Ab, v.x, v.y, m0, m1);
+            x0 = v.x;
+            x1 = v.y;
+        } else {
+            x0 = u.x ^ v.x;
+            x1 = u.y ^ v.y;
+        }
+        uint64_t a0, a1;   // x0 A, x1 A
+        if (tabled) {
+            const uint8_t *row = s_m8 + ((b & 127u) << 8);   // GF(2^8) row of beta = 2 bl (even)
+            a0 = tmul(s_k, x0) ^ bmul(row, x0);
+            a1 = tmul(s_k, x1) ^ bmul(row, x1);
+        } else {
+            const uint64_t cb = 2 * b;
+            uint64_t Ab = Ld;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) Ab ^= T->iota[k][(cb >> (8 * k)) & 255u];
+            a0 = mv.m64(x0, Ab);
+            a1 = mv.m64(x1, Ab);
+        }
+        // (x0 + x1 y)(A + H_d y) = (x0 A + x1 H_d v_63) + ((x0 + x1) H_d + x1 A) y
+        const uint64_t m0 = a0 ^ tmul(s_tab[1], x1), m1 = tmul(s_tab[0], x0 ^ x1) ^ a1;
+        if (!INV) {
             const uint64_t h0 = u.x ^ m0, h1 = u.y ^ m1;
             reinterpret_cast<ulonglong2 *>(X)[j0] = make_ulonglong2(h0, h1);
             reinterpret_cast<ulonglong2 *>(X)[j1] = make_ulonglong2(h0 ^ v.x, h1 ^ v.y);
         } else {
-            const uint64_t p10 = u.x ^ v.x, p11 = u.y ^ v.y;
-            m128_mulc(mv, s_tab[0], s_tab[1], Ab, p10, p11, m0, m1);
             reinterpret_cast<ulonglong2 *>(X)[j0] = make_ulonglong2(u.x ^ m0, u.y ^ m1);
-            reinterpret_cast<ulonglong2 *>(X)[j1] = make_ulonglong2(p10, p11);
+            reinterpret_cast<ulonglong2 *>(X)[j1] = make_ulonglong2(x0, x1);
         }
     }
 }

@@ -199,6 +199,7 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
         slot.view = new polymul_ctx();
         slot.view->device = ctx->device;
         slot.view->tables = ctx->tables;
+        slot.view->psteps = ctx->psteps;
         slot.view->bsteps = ctx->bsteps;
         slot.view->num_cu = ctx->num_cu;
         slot.view->small_field_log2n = ctx->small_field_log2n;
