@@ -186,6 +186,74 @@ def bench_batch(ctx, steps: int):
     return rec
 
 
+def _time_product(ctx, A, la, B, lb, out, steps: int):
+    import torch
+    stream = torch.cuda.current_stream()
+    ctx.polymul(A, la, B, lb, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        ctx.polymul(A, la, B, lb, out=out, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def bench_m128(steps: int, log2_len: int = 37):
+    """The m = 128 variant: a 2^37 x 2^37-bit product, whose 2^38-bit transform
+    is past the m = 64 bound and runs over GF(2^128) (operands drawn on the
+    device from seeds 0x5eed0037 and 0x5eed0038), timed with its per-kernel
+    table; and the 2^30 x 2^30 workload forced onto GF(2^128) for the cost of
+    the field at equal size.  (The GPU tests check the products of this path
+    against the definition, at this transform size too.)"""
+    import numpy as np
+    import torch
+    from paper_1803_11301_amd import fpmul, synth
+    L = 1 << log2_len
+    seed = 0x5EED0037
+    A = synth.dense_poly_device(seed, L, "cuda")
+    B = synth.dense_poly_device(seed + 1, L, "cuda")
+    lc = 2 * L - 1
+    out = torch.empty((lc + 63) // 64, dtype=torch.int64, device="cuda")
+    torch.cuda.empty_cache()
+    ctx = fpmul.Context(0)
+    log(f"[bench] m128: 2^{log2_len} x 2^{log2_len} bits over GF(2^128), {steps} steps")
+    ms = _time_product(ctx, A, L, B, L, out, steps)
+    ctx.profile(True)
+    ctx.polymul(A, L, B, L, out=out, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    prof = ctx.profile_report()
+    ctx.profile(False)
+    kernels = {name: {"launches": cnt, "ms": round(tot, 3)}
+               for name, (cnt, tot) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    for name, k in kernels.items():
+        log(f"[bench] m128 {name:22s} {k['launches']:5d} launches {k['ms']:10.2f} ms")
+    ctx.close()
+    del A, B, out
+    torch.cuda.empty_cache()
+    # the large workload over GF(2^128), against its GF(2^64) time in the headline
+    a_np, b_np = synth.single_pair(0x5EED0030, 1 << 30)
+    a = torch.from_numpy(a_np.view(np.int64)).cuda()
+    b = torch.from_numpy(b_np.view(np.int64)).cuda()
+    o = torch.empty(((2 << 30) - 1 + 63) // 64, dtype=torch.int64, device="cuda")
+    c2 = fpmul.Context(0)
+    c2.set_large_field(31)
+    ms30 = _time_product(c2, a, 1 << 30, b, 1 << 30, o, 3)
+    c2.close()
+    nominal = nominal_bytes(L // 8, L // 8, (1 << (log2_len + 1)) // 8)
+    rec = {"workload": f"single product 2^{log2_len} x 2^{log2_len} bits, uniform random, seeds 0x5eed0037/8, "
+                       f"2^{log2_len + 1}-bit transform over GF(2^128)",
+           "ms_per_product": round(ms, 2), "steps": steps,
+           "product_roofline": {"nominal_bytes": nominal, "achieved": round(nominal / (ms / 1e3) / 1e9, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(nominal / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+           "ms_2e30_product_over_gf2_128": round(ms30, 3),
+           "kernels": kernels}
+    log(f"[bench] m128: {ms:.1f} ms per 2^{log2_len}-bit product; 2^30 over GF(2^128) {ms30:.2f} ms")
+    return rec
+
+
 def bench_serve(ctx, count: int, warmup: int, rho: float, slots: int = 8, batch_limit_bits: int = 1 << 20,
                 max_batch: int = 512):
     """Poisson stream of products, operands log-uniform in [2^12, 2^24] bits
@@ -266,6 +334,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--serve-rho", type=float, default=0.8, help="offered load as a fraction of saturation")
+    ap.add_argument("--no-m128", action="store_true", help="skip the GF(2^128) measurement")
+    ap.add_argument("--m128-steps", type=int, default=2)
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -378,6 +448,10 @@ def main():
     if not args.no_serve and args.workload == "large":
         serve = bench_serve(ctx, args.serve_requests, args.serve_warmup, args.serve_rho)
 
+    m128 = None
+    if not args.no_m128 and args.workload == "large":
+        m128 = bench_m128(args.m128_steps)
+
     cpu = None
     if not args.no_cpu:
         log(f"[bench] oracle sample 2^{args.cpu_log2} on the host")
@@ -401,6 +475,7 @@ def main():
         "kernels": per_kernel,
         "batch": batch,
         "serve": serve,
+        "m128": m128,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -223,3 +223,41 @@ def test_m128_beyond_the_m64_bound():
     if free < (200 << 30):
         pytest.skip("needs 200 GiB of free device memory")
     _full_size_case((1 << 37) + 1, 4096, 0x5EED0038)
+
+
+def test_m128_balanced_2e37_end_words():
+    """The bench shape, 2^37 x 2^37 bits over GF(2^128): the lowest and highest
+    output words, which the definition computes from the lowest (highest)
+    words of A and B alone."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    free, total = torch.cuda.mem_get_info()
+    if free < (230 << 30):
+        pytest.skip("needs 230 GiB of free device memory")
+    from paper_1803_11301_amd import fpmul
+    L, seed = 1 << 37, 0x5EED0037
+    say("balanced 2^37 x 2^37 end words, seeds", hex(seed), hex(seed + 1))
+    A = synth.dense_poly_device(seed, L, "cuda")
+    B = synth.dense_poly_device(seed + 1, L, "cuda")
+    torch.cuda.empty_cache()
+    c = fpmul.Context(0)
+    try:
+        out = c.polymul(A, L, B, L)
+        torch.cuda.synchronize()
+        nc, na = out.numel(), A.numel()
+        for w in list(range(16)) + list(range(nc - 16, nc)):
+            if w < na:
+                a_w = A[: w + 1].cpu().numpy().view(np.uint64)
+                b_w = B[: w + 1].cpu().numpy().view(np.uint64)
+                ref = O.product_words(a_w, 64 * (w + 1), b_w, 64 * (w + 1), np.array([w], np.uint64))[0]
+            else:
+                s0 = w - na   # only words s0 .. of A and B reach word w
+                a_w = A[s0:].cpu().numpy().view(np.uint64)
+                b_w = B[s0:].cpu().numpy().view(np.uint64)
+                ref = O.product_words(a_w, L - 64 * s0, b_w, L - 64 * s0, np.array([w - 2 * s0], np.uint64))[0]
+            assert int(out[w].item()) & ((1 << 64) - 1) == int(ref), ("word", w)
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+        del A, B
+        torch.cuda.empty_cache()
