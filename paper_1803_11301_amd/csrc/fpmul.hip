@@ -945,13 +945,35 @@ static int run_product128(polymul_ctx *ctx, uint64_t *A, uint64_t *B, int l, hip
 {
     const uint64_t n_p = 1ull << l;
     const uint64_t wgs = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->num_cu, (n_p + 1023) / 1024));
-    for (int i = l - 1; i >= 0; --i)
-        KLAUNCH(ctx, s, "butterfly128", k_bfly128_layer<false>, (unsigned)wgs, 1024, A, B, l, i, ctx->tables,
-                ctx->tables128);
+    // layer groups from the top: pairs (i + 1, i) in one pass where the
+    // two-layer kernel applies (i >= 3, l >= 11, l - i <= 32), else single layers
+    std::vector<std::pair<int, int>> plan;   // (lowest layer, layers)
+    for (int i = l - 1; i >= 0;) {
+        if (i - 1 >= 3 && l >= 11 && l - (i - 1) <= 32) {
+            plan.push_back({i - 1, 2});
+            i -= 2;
+        } else {
+            plan.push_back({i, 1});
+            i -= 1;
+        }
+    }
+    for (const auto &p : plan) {
+        if (p.second == 2)
+            KLAUNCH(ctx, s, "butterfly128", k_bfly128_2layer<false>, (unsigned)ctx->num_cu, M128_TILE2, A, B, l,
+                    p.first, ctx->tables, ctx->tables128);
+        else
+            KLAUNCH(ctx, s, "butterfly128", k_bfly128_layer<false>, (unsigned)wgs, 1024, A, B, l, p.first,
+                    ctx->tables, ctx->tables128);
+    }
     KLAUNCH(ctx, s, "pointwise128", k_pointwise128, (unsigned)wgs, 1024, A, B, n_p, ctx->tables, ctx->tables128);
-    for (int i = 0; i < l; ++i)
-        KLAUNCH(ctx, s, "ibutterfly128", k_bfly128_layer<true>, (unsigned)wgs, 1024, A, nullptr, l, i, ctx->tables,
-                ctx->tables128);
+    for (auto it = plan.rbegin(); it != plan.rend(); ++it) {
+        if (it->second == 2)
+            KLAUNCH(ctx, s, "ibutterfly128", k_bfly128_2layer<true>, (unsigned)ctx->num_cu, M128_TILE2, A, nullptr,
+                    l, it->first, ctx->tables, ctx->tables128);
+        else
+            KLAUNCH(ctx, s, "ibutterfly128", k_bfly128_layer<true>, (unsigned)wgs, 1024, A, nullptr, l, it->first,
+                    ctx->tables, ctx->tables128);
+    }
     return 0;
 }
 

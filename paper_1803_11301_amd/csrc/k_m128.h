@@ -157,6 +157,35 @@ __global__ __launch_bounds__(256) void k_decode128_scatter_w(const uint64_t *__r
 // bh < 2^24 (d <= 32); other layers take general products by A.
 #define M128_TILE 1024
 
+// x beta for beta in V_8, every byte by byte permutes (b2_pmul32 with the
+// v_perm tables t01, t2 of beta) instead of GF(2^8) table lookups
+__device__ __forceinline__ uint64_t m128_pmul(const uint4 &t01, uint32_t t2, uint64_t x)
+{
+    return (uint64_t)b2_pmul32(t01, t2, (uint32_t)x) | ((uint64_t)b2_pmul32(t01, t2, (uint32_t)(x >> 32)) << 32);
+}
+
+// forward butterfly on (u, v): u += c v, v += u; inverse: v += u, u += c v,
+// for c = A + H_d y with A = K + beta (T_K = tk; beta's v_perm tables t01,
+// t2), th / thv the window tables of H_d and H_d v_63:
+// (x0 + x1 y)(A + H_d y) = (x0 A + x1 H_d v_63) + ((x0 + x1) H_d + x1 A) y
+template <bool INV>
+__device__ __forceinline__ void m128_bfly(const uint64_t *__restrict__ tk, const uint4 &t01, uint32_t t2,
+                                          const uint64_t *__restrict__ th, const uint64_t *__restrict__ thv,
+                                          ulonglong2 &u, ulonglong2 &v)
+{
+    if (INV) {
+        v.x ^= u.x;
+        v.y ^= u.y;
+    }
+    const uint64_t a0 = tmul(tk, v.x) ^ m128_pmul(t01, t2, v.x), a1 = tmul(tk, v.y) ^ m128_pmul(t01, t2, v.y);
+    u.x ^= a0 ^ tmul(thv, v.y);
+    u.y ^= tmul(th, v.x ^ v.y) ^ a1;
+    if (!INV) {
+        v.x ^= u.x;
+        v.y ^= u.y;
+    }
+}
+
 template <bool INV>
 __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A, uint64_t *__restrict__ B, int l,
                                                         int i, const DevTables *__restrict__ T,
@@ -233,6 +262,113 @@ __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A
             reinterpret_cast<ulonglong2 *>(X)[j0] = make_ulonglong2(u.x ^ m0, u.y ^ m1);
             reinterpret_cast<ulonglong2 *>(X)[j1] = make_ulonglong2(x0, x1);
         }
+    }
+}
+
+// Layers i + 1 and i in one pass (forward: i + 1 first), one group of four
+// values j + k 2^i (k < 4) per thread.  Layer i + 1 pairs (0, 2) and (1, 3) in
+// block b1 = j >> (i + 2); layer i pairs (0, 1) in block 2 b1 and (2, 3) in
+// block 2 b1 + 1, which share K (2 b1 is even) and differ in beta by 2.
+// With 512 groups per tile (one per thread) both K keys are uniform over a
+// tile when i >= 3; needs l >= 11 (whole tiles) and d = l - i <= 32.  512
+// threads keep the four values and the products in registers (256 VGPRs).
+// LDS: the v_perm tables of
+// the betas, the window tables of H and H v_63 of both layers and the two K
+// tables.
+#define M128_TILE2 512
+
+template <bool INV>
+__global__ __launch_bounds__(M128_TILE2) void k_bfly128_2layer(uint64_t *__restrict__ A, uint64_t *__restrict__ B, int l,
+                                                         int i, const DevTables *__restrict__ T,
+                                                         const DevTables128 *__restrict__ U)
+{
+    __shared__ __align__(16) uint32_t s_ptb[128][8];
+    __shared__ __align__(16) uint64_t s_h[4][2048];
+    __shared__ __align__(16) uint64_t s_k[2][2048];
+    __shared__ uint64_t s_img[2][64];
+    const int tid = threadIdx.x, nth = blockDim.x, d0 = l - i, d1 = d0 - 1;
+    {
+        for (int q = tid; q < 128 * 8; q += nth) (&s_ptb[0][0])[q] = (&T->pt_beta8[0][0])[q];
+        for (int q = tid; q < 2 * 2048; q += nth) {
+            (&s_h[0][0])[q] = (&U->ktab[d1][0][0])[q];
+            (&s_h[2][0])[q] = (&U->ktab[d0][0][0])[q];
+        }
+    }
+    __syncthreads();
+    const uint64_t quarter = 1ull << (l - 2), total = B ? 2 * quarter : quarter, imask = (1ull << i) - 1;
+    const uint64_t ntiles = total / M128_TILE2, per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t_end = min(ntiles, (uint64_t)(blockIdx.x + 1) * per);
+    uint64_t key1 = ~0ull, key0 = ~0ull;
+    // group of this thread in a tile: operand, first value j, block b1
+    auto where = [&](uint64_t tile, ulonglong2 *&P, uint64_t &j, uint64_t &b1) {
+        const uint64_t q = tile * M128_TILE2 + tid, g = q & (quarter - 1);
+        P = reinterpret_cast<ulonglong2 *>(q < quarter ? A : B);
+        b1 = g >> i;
+        j = (b1 << (i + 2)) | (g & imask);
+    };
+    const uint64_t s = 1ull << i;
+    uint64_t tile = (uint64_t)blockIdx.x * per;
+    ulonglong2 *P = nullptr;
+    uint64_t j = 0, b1 = 0;
+    ulonglong2 x0{}, x1{}, x2{}, x3{};
+    if (tile < t_end) {
+        where(tile, P, j, b1);
+        x0 = P[j], x1 = P[j + s], x2 = P[j + 2 * s], x3 = P[j + 3 * s];
+    }
+    for (; tile < t_end; ++tile) {
+        // the next tile's values are loaded while this one computes
+        ulonglong2 *Pn = P;
+        uint64_t jn = j, b1n = b1;
+        ulonglong2 y0{}, y1{}, y2{}, y3{};
+        if (tile + 1 < t_end) {
+            where(tile + 1, Pn, jn, b1n);
+            y0 = Pn[jn], y1 = Pn[jn + s], y2 = Pn[jn + 2 * s], y3 = Pn[jn + 3 * s];
+        }
+        const uint64_t g0 = (tile * M128_TILE2) & (quarter - 1);
+        const uint64_t bh1 = g0 >> (i + 7), bh0 = g0 >> (i + 6);
+        if (bh1 != key1 || bh0 != key0) {   // uniform over the tile
+            __syncthreads();   // the previous tile is done with the K tables
+            if (tid < 128) {
+                const int t = tid & 63, which = tid >> 6;
+                const uint64_t bh = which ? bh0 : bh1;
+                uint64_t v = U->gbase[which ? d0 : d1][t];
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v ^= ((bh >> k) & 1u) ? T->pbasis[k][t] : 0ull;
+                s_img[which][t] = v;
+            }
+            __syncthreads();
+            for (int it = tid; it < 512; it += nth) ktable_fill_item(s_k[it >> 8], s_img[it >> 8], it & 255);
+            __syncthreads();
+            key1 = bh1;
+            key0 = bh0;
+        }
+        const int r1 = (int)(b1 & 127u), r0 = (int)((2 * b1) & 127u);   // beta = 2 r (r0 even)
+        const uint4 p1 = *reinterpret_cast<const uint4 *>(s_ptb[r1]);
+        const uint4 p0a = *reinterpret_cast<const uint4 *>(s_ptb[r0]);
+        const uint4 p0b = *reinterpret_cast<const uint4 *>(s_ptb[r0 + 1]);
+        const uint32_t p1e = s_ptb[r1][4], p0ae = s_ptb[r0][4], p0be = s_ptb[r0 + 1][4];
+        if (!INV) {
+            m128_bfly<false>(s_k[0], p1, p1e, s_h[0], s_h[1], x0, x2);
+            m128_bfly<false>(s_k[0], p1, p1e, s_h[0], s_h[1], x1, x3);
+            m128_bfly<false>(s_k[1], p0a, p0ae, s_h[2], s_h[3], x0, x1);
+            m128_bfly<false>(s_k[1], p0b, p0be, s_h[2], s_h[3], x2, x3);
+        } else {
+            m128_bfly<true>(s_k[1], p0a, p0ae, s_h[2], s_h[3], x0, x1);
+            m128_bfly<true>(s_k[1], p0b, p0be, s_h[2], s_h[3], x2, x3);
+            m128_bfly<true>(s_k[0], p1, p1e, s_h[0], s_h[1], x0, x2);
+            m128_bfly<true>(s_k[0], p1, p1e, s_h[0], s_h[1], x1, x3);
+        }
+        P[j] = x0;
+        P[j + s] = x1;
+        P[j + 2 * s] = x2;
+        P[j + 3 * s] = x3;
+        P = Pn;
+        j = jn;
+        b1 = b1n;
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
     }
 }
 
