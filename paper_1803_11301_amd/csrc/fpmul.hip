@@ -132,11 +132,32 @@ static void bcvt_steps(uint64_t N, uint64_t e, std::vector<BStep> &out)
     bcvt_steps(tau, e, out);             // inner conversion of each block
 }
 
-// one step on words [0, nw); segments of S >= 128 bits; out-of-place
-__global__ void k_bcvt_step_wide(const uint64_t *__restrict__ in, uint64_t *__restrict__ out, uint64_t nw,
-                                 uint64_t S, uint64_t d, int inverse)
+// One step with S >= 128 bits in place, as its two updates (forward: the hi
+// fix first; inverse: the lo update first).  d = S / (2 tau) <= H / 2, so
+// the fix writes hi[0, d) from hi[H-d, H), bits it does not write, and the
+// lo update reads hi only: every word is written by one thread from words
+// no thread writes in the same launch.
+// hi[0, d) ^= hi[H-d, H) on every segment of words [0, nw)
+__global__ void k_bcvt_wide_hi(uint64_t *__restrict__ X, uint64_t nw, uint64_t S, uint64_t d)
 {
-    for (uint64_t w = gid(); w < nw; w += gstride()) out[w] = bcvt_wide_word(in, w, S, d, inverse);
+    const uint64_t SW = S / 64, HW = SW / 2, H = S / 2, dw = (d + 63) / 64, n = (nw / SW) * dw;
+    for (uint64_t t = gid(); t < n; t += gstride()) {
+        const uint64_t seg = t / dw, k = t - seg * dw;
+        uint64_t *hp = X + seg * SW + HW;
+        const int64_t rem = (int64_t)d - 64 * (int64_t)k;
+        hp[k] ^= bits_at(hp, (int64_t)HW, 64 * (int64_t)k + (int64_t)(H - d)) & lowmask(rem);
+    }
+}
+
+// lo[d, H) ^= hi[0, H-d) on every segment of words [0, nw)
+__global__ void k_bcvt_wide_lo(uint64_t *__restrict__ X, uint64_t nw, uint64_t S, uint64_t d)
+{
+    const uint64_t SW = S / 64, HW = SW / 2, n = (nw / SW) * HW;
+    for (uint64_t t = gid(); t < n; t += gstride()) {
+        const uint64_t seg = t / HW, q = t - seg * HW;
+        uint64_t *lp = X + seg * SW;
+        lp[q] ^= bits_at(lp + HW, (int64_t)HW, 64 * (int64_t)q - (int64_t)d);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -461,21 +482,10 @@ __global__ __launch_bounds__(1024) void k_bcvt_lds_run(uint64_t *__restrict__ X,
     }
 }
 
-// steps with segments beyond LDS, which run out of place (one buffer swap each)
-static size_t bcvt_swaps(uint64_t N)
-{
-    std::vector<BStep> steps;
-    bcvt_steps(N, 1, steps);
-    size_t c = 0;
-    for (const BStep &st : steps) c += st.S > 64ull * BT_LDS_WORDS;
-    return c;
-}
-
-// run the BasisCvt steps for N bits (or their inverse) on buffers of nw words
-// (nw >= N / 64): every run of steps with segments of at most 2^20 bits in
-// one LDS pass, each larger step out of place
-static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *&cur, uint64_t *&spare, uint64_t nw,
-                    hipStream_t s)
+// run the BasisCvt steps for N bits (or their inverse) in place on the nw
+// words of cur (nw >= N / 64): every run of steps with segments of at most
+// 2^20 bits in one LDS pass, each larger step as its two updates
+static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *cur, uint64_t nw, hipStream_t s)
 {
     std::vector<BStep> steps;
     bcvt_steps(N, 1, steps);
@@ -496,9 +506,13 @@ static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *&cur, 
             k = e;
         } else {
             const BStep &st = steps[inverse ? cnt - 1 - k : k];
-            KLAUNCH(ctx, s, inverse ? "ibasiscvt_wide" : "basiscvt_wide", k_bcvt_step_wide, grid_for(nw, 256), 256,
-                    cur, spare, nw, st.S, st.d, inverse ? 1 : 0);
-            std::swap(cur, spare);
+            const uint64_t nhi = (nw / (st.S / 64)) * ((st.d + 63) / 64), nlo = nw / 2;
+            if (!inverse)
+                KLAUNCH(ctx, s, "basiscvt_wide_hi", k_bcvt_wide_hi, grid_for(nhi, 256), 256, cur, nw, st.S, st.d);
+            KLAUNCH(ctx, s, inverse ? "ibasiscvt_wide" : "basiscvt_wide", k_bcvt_wide_lo, grid_for(nlo, 256), 256,
+                    cur, nw, st.S, st.d);
+            if (inverse)
+                KLAUNCH(ctx, s, "ibasiscvt_wide_hi", k_bcvt_wide_hi, grid_for(nhi, 256), 256, cur, nw, st.S, st.d);
             ++k;
         }
     }
@@ -519,8 +533,7 @@ static int run_encode_in(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int 
     const uint64_t nwa = bcvt_active_words(N, nw);
     const unsigned bs = 256;
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, bs), bs, a, len, cur, nw);
-    if (nwa < nw) KLAUNCH(ctx, s, "zero", k_load_mask, grid_for(nw - nwa, bs), bs, a, 0, spare + nwa, nw - nwa);
-    int rc = run_bcvt(ctx, N, false, cur, spare, nwa, s);
+    int rc = run_bcvt(ctx, N, false, cur, nwa, s);
     if (rc) return rc;
     if (l >= 6)
         KLAUNCH(ctx, s, "encode", k_encode_w, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
@@ -542,7 +555,7 @@ static int run_decode_out(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t 
     else
         KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
     std::swap(cur, spare);
-    return run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s);
+    return run_bcvt(ctx, 1ull << log2n, true, cur, nw, s);
 }
 
 // the layers above the bottom tile, as (i_lo, k) groups of at most BF_UPPER_MAXK, lowest first
@@ -924,15 +937,10 @@ static int run_encode128(polymul_ctx *ctx, const uint64_t *src, uint64_t len, in
 {
     const int l = log2n - 7;
     const uint64_t nw = 1ull << (log2n - 6), n_p = 1ull << l, N = next_pow2(std::max<uint64_t>(len, 1));
-    // the steps alternate between the two buffers; start where Encode then
-    // writes into dst
-    uint64_t *cur = (bcvt_swaps(N) & 1) ? dst : spare, *sp = cur == dst ? spare : dst;
-    const uint64_t nwa = bcvt_active_words(N, nw);
+    uint64_t *cur = spare;
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, src, len, cur, nw);
-    if (nwa < nw) KLAUNCH(ctx, s, "zero", k_load_mask, grid_for(nw - nwa, 256), 256, src, 0, sp + nwa, nw - nwa);
-    int rc = run_bcvt(ctx, N, false, cur, sp, nwa, s);
+    int rc = run_bcvt(ctx, N, false, cur, bcvt_active_words(N, nw), s);
     if (rc) return rc;
-    if (sp != dst) return fail(POLYMUL_EIO, "m = 128 encode buffer order");
     if (l >= 6)
         KLAUNCH(ctx, s, "encode128", k_encode128_w, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
     else
@@ -995,9 +1003,8 @@ static int product128_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, 
         KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter_w, grid_for(nw / 2, 256), 256, W0, l, W1);
     else
         KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
-    uint64_t *cur = W1, *spare = W2;
-    if ((rc = run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s))) return rc;
-    KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, cur, lc, out);
+    if ((rc = run_bcvt(ctx, 1ull << log2n, true, W1, nw, s))) return rc;
+    KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, W1, lc, out);
     return 0;
 }
 
@@ -1089,9 +1096,9 @@ static int basiscvt_body(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int
     const uint64_t nbits = 1ull << log2n, nw = (nbits + 63) / 64;
     int rc = ensure_ws(ctx, nw);
     if (rc) return rc;
-    uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+    uint64_t *cur = ctx->ws[0];
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, in, inverse ? nbits : len, cur, nw);
-    if ((rc = run_bcvt(ctx, inverse ? nbits : next_pow2(std::max<uint64_t>(len, 1)), inverse != 0, cur, spare, nw,
+    if ((rc = run_bcvt(ctx, inverse ? nbits : next_pow2(std::max<uint64_t>(len, 1)), inverse != 0, cur, nw,
                        s)))
         return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for(nw, 256), 256, cur, nbits, out);
