@@ -154,7 +154,10 @@ __global__ __launch_bounds__(256) void k_decode128_scatter_w(const uint64_t *__r
 // changes (every 2^(i+7) pairs) from its basis images K unit_t =
 // L_d unit_t + the v_{8+v} unit_t of the set bits v of bh.  This needs a
 // tile inside one block range of bh (i >= 3, whole tiles: l >= 11) and
-// bh < 2^24 (d <= 32); other layers take general products by A.
+// bh < 2^24 (d <= 32).  The layers below 3 split b at bit 11 instead:
+// beta = iota(2 (b mod 2^11)) lies in V_16 and is applied as
+// beta0 x + beta1 (x v_8) with byte permutes.  Transforms with l < 11 or
+// d > 32 take general products by A.
 #define M128_TILE 1024
 
 // x beta for beta in V_8, every byte by byte permutes (b2_pmul32 with the
@@ -194,28 +197,37 @@ __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A
     __shared__ __align__(16) uint8_t s_m8[M8V_BYTES];
     __shared__ __align__(16) uint64_t s_tab[2][2048];
     __shared__ __align__(16) uint64_t s_k[2048];
+    __shared__ __align__(16) uint32_t s_pt8[256][8];
     __shared__ uint64_t s_img[64];
     const int tid = threadIdx.x, nth = blockDim.x, d = l - i;
     m128_load_mul8(s_m8, T, tid, nth);
     for (int q = tid; q < 2 * 2048; q += nth) (&s_tab[0][0])[q] = (&U->ktab[d][0][0])[q];
+    for (int q = tid; q < 256 * 8; q += nth) (&s_pt8[0][0])[q] = (&T->pt8[0][0])[q];
     __syncthreads();
     const Mul8View mv{s_m8};
     const uint64_t Ld = U->lo[d];
     const uint64_t half = 1ull << (l - 1), total = B ? 2 * half : half, omask = (1ull << i) - 1;
-    const bool tabled = i >= 3 && l >= 11 && d <= 32;
+    // tabled: K from the bits of b above 7 (beta in V_8); for i < 3 a tile
+    // spans more than 128 blocks, so K takes the bits above 11 and beta the
+    // 12-bit rest, an element of V_16 applied as beta0 x + beta1 (x v_8)
+    const bool tabled = l >= 11 && d <= 32;
+    const int kshift = i >= 3 ? 7 : 11;
+    const uint4 q01 = *reinterpret_cast<const uint4 *>(s_pt8[0x80]);   // v_7 (Cantor byte 0x80)
+    const uint32_t q2 = s_pt8[0x80][4];
     const uint64_t ntiles = (total + M128_TILE - 1) / M128_TILE;
     const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
     const uint64_t t_end = min(ntiles, (uint64_t)(blockIdx.x + 1) * per);
     uint64_t key = ~0ull;
     for (uint64_t tile = (uint64_t)blockIdx.x * per; tile < t_end; ++tile) {
         if (tabled) {
-            const uint64_t bh = ((tile * M128_TILE) & (half - 1)) >> (i + 7);
+            const uint64_t bh = ((tile * M128_TILE) & (half - 1)) >> (i + kshift);
             if (bh != key) {   // uniform: one tile lies in one block range of bh
                 __syncthreads();   // the previous tile is done with T_K
                 if (tid < 64) {
+                    // K = L_d + iota(bh << (kshift + 1)); pbasis[k] is v_{8+k} unit_t
+                    const int off = kshift - 7;
                     uint64_t v = U->gbase[d][tid];
-#pragma unroll
-                    for (int k = 0; k < 24; ++k) v ^= ((bh >> k) & 1u) ? T->pbasis[k][tid] : 0ull;
+                    for (int k = 0; k + off < 24; ++k) v ^= ((bh >> k) & 1u) ? T->pbasis[k + off][tid] : 0ull;
                     s_img[tid] = v;
                 }
                 __syncthreads();
@@ -240,10 +252,24 @@ __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A
             x1 = u.y ^ v.y;
         }
         uint64_t a0, a1;   // x0 A, x1 A
-        if (tabled) {
+        if (tabled && i >= 3) {
             const uint8_t *row = s_m8 + ((b & 127u) << 8);   // GF(2^8) row of beta = 2 bl (even)
             a0 = tmul(s_k, x0) ^ bmul(row, x0);
             a1 = tmul(s_k, x1) ^ bmul(row, x1);
+        } else if (tabled) {
+            const uint64_t cb = 2 * (b & 2047u);   // beta = iota(cb), cb < 2^12: V_16
+            const uint32_t b16 = (uint32_t)(T->iota[0][cb & 255u] ^ T->iota[1][cb >> 8]);
+            const uint4 p0 = *reinterpret_cast<const uint4 *>(s_pt8[b16 & 255u]);
+            const uint4 p1 = *reinterpret_cast<const uint4 *>(s_pt8[b16 >> 8]);
+            const uint32_t p02 = s_pt8[b16 & 255u][4], p12 = s_pt8[b16 >> 8][4];
+            auto mul16 = [&](uint64_t x) {
+                const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+                const uint32_t rl = b2_pmul32(p0, p02, lo) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, lo));
+                const uint32_t rh = b2_pmul32(p0, p02, hi) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, hi));
+                return (uint64_t)rl | ((uint64_t)rh << 32);
+            };
+            a0 = tmul(s_k, x0) ^ mul16(x0);
+            a1 = tmul(s_k, x1) ^ mul16(x1);
         } else {
             const uint64_t cb = 2 * b;
             uint64_t Ab = Ld;
