@@ -206,6 +206,42 @@ __global__ __launch_bounds__(256) void k_encode_w(const uint64_t *__restrict__ b
     }
 }
 
+// The same for 8 consecutive blocks per wave (l >= 9): every row is read as
+// one 64-byte run; rows at or above nzrows are zero and are not read
+#define ENC_NB 8
+__global__ __launch_bounds__(256) void k_encode_w8(const uint64_t *__restrict__ bits, int l, int nzrows,
+                                                   const DevTables *__restrict__ T, uint64_t *__restrict__ vals)
+{
+    __shared__ uint64_t s_win[8][256];
+    for (int q = threadIdx.x; q < 8 * 256; q += blockDim.x) (&s_win[0][0])[q] = (&T->enc_win[0][0])[q];
+    __syncthreads();
+    const uint64_t rw = 1ull << (l - 6), ngrp = rw / ENC_NB;
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = gstride() >> 6;
+    const bool live = lane < nzrows;
+    for (uint64_t grp = gid() >> 6; grp < ngrp; grp += nwaves) {
+        const uint64_t b0 = grp * ENC_NB;
+        ulonglong2 w[ENC_NB / 2];
+        const ulonglong2 *r = reinterpret_cast<const ulonglong2 *>(bits + (uint64_t)lane * rw + b0);
+#pragma unroll
+        for (int h = 0; h < ENC_NB / 2; ++h) w[h] = live ? r[h] : make_ulonglong2(0, 0);
+#pragma unroll
+        for (int bb = 0; bb < ENC_NB; ++bb) {
+            const uint64_t x = (bb & 1) ? w[bb / 2].y : w[bb / 2].x;
+            uint64_t col = 0;
+#pragma unroll 8
+            for (int k = 0; k < 64; ++k) {
+                const uint64_t m = __ballot((int)((x >> k) & 1u));
+                col = lane == k ? m : col;
+            }
+            uint64_t f = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) f ^= s_win[k][(col >> (8 * k)) & 255u];
+            vals[(b0 + bb) * 64 + lane] = f;
+        }
+    }
+}
+
 // Decode part 1: each value -> its 64 bits, in place
 __global__ void k_decode_vec(uint64_t *__restrict__ vals, int l, const DevTables *__restrict__ T)
 {
@@ -250,6 +286,40 @@ __global__ __launch_bounds__(256) void k_decode_scatter_w(const uint64_t *__rest
             r = lane == t ? m : r;
         }
         bits[(uint64_t)lane * rw + blk] = r;
+    }
+}
+
+// Decode, both parts, for 8 consecutive blocks per wave (l >= 9): R^-1 on
+// every value, then the transpose; every row is written as one 64-byte run
+__global__ __launch_bounds__(256) void k_decode_w8(const uint64_t *__restrict__ vecs, int l,
+                                                   const DevTables *__restrict__ T, uint64_t *__restrict__ bits)
+{
+    __shared__ uint64_t s_win[8][256];
+    for (int q = threadIdx.x; q < 8 * 256; q += blockDim.x) (&s_win[0][0])[q] = (&T->dec_win[0][0])[q];
+    __syncthreads();
+    const uint64_t rw = 1ull << (l - 6), ngrp = rw / ENC_NB;
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = gstride() >> 6;
+    for (uint64_t grp = gid() >> 6; grp < ngrp; grp += nwaves) {
+        const uint64_t b0 = grp * ENC_NB;
+        uint64_t r[ENC_NB];
+#pragma unroll
+        for (int bb = 0; bb < ENC_NB; ++bb) {
+            const uint64_t v = vecs[(b0 + bb) * 64 + lane];
+            uint64_t h = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) h ^= s_win[k][(v >> (8 * k)) & 255u];
+            uint64_t a = 0;
+#pragma unroll 8
+            for (int t = 0; t < 64; ++t) {
+                const uint64_t m = __ballot((int)((h >> t) & 1u));
+                a = lane == t ? m : a;
+            }
+            r[bb] = a;
+        }
+        ulonglong2 *w = reinterpret_cast<ulonglong2 *>(bits + (uint64_t)lane * rw + b0);
+#pragma unroll
+        for (int h = 0; h < ENC_NB / 2; ++h) w[h] = make_ulonglong2(r[2 * h], r[2 * h + 1]);
     }
 }
 
@@ -535,7 +605,11 @@ static int run_encode_in(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int 
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, bs), bs, a, len, cur, nw);
     int rc = run_bcvt(ctx, N, false, cur, nwa, s);
     if (rc) return rc;
-    if (l >= 6)
+    if (l >= 9) {
+        // rows at or above ceil(N / n_p) hold no bit of the operand
+        const int nz = (int)std::min<uint64_t>(64, (N + n_p - 1) / n_p);
+        KLAUNCH(ctx, s, "encode", k_encode_w8, grid_for(n_p / ENC_NB, bs), bs, cur, l, nz, ctx->tables, spare);
+    } else if (l >= 6)
         KLAUNCH(ctx, s, "encode", k_encode_w, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
     else
         KLAUNCH(ctx, s, "encode", k_encode, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
@@ -549,11 +623,15 @@ static int run_decode_out(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t 
     const int l = log2n - 6;
     const uint64_t nw = 1ull << l, n_p = 1ull << l;
     const unsigned bs = 256;
-    KLAUNCH(ctx, s, "decode_vec", k_decode_vec, grid_for(n_p, bs), bs, cur, l, ctx->tables);
-    if (l >= 6)
-        KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter_w, grid_for(nw, bs), bs, cur, l, spare);
-    else
-        KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
+    if (l >= 9) {
+        KLAUNCH(ctx, s, "decode", k_decode_w8, grid_for(nw / ENC_NB, bs), bs, cur, l, ctx->tables, spare);
+    } else {
+        KLAUNCH(ctx, s, "decode_vec", k_decode_vec, grid_for(n_p, bs), bs, cur, l, ctx->tables);
+        if (l >= 6)
+            KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter_w, grid_for(nw, bs), bs, cur, l, spare);
+        else
+            KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
+    }
     std::swap(cur, spare);
     return run_bcvt(ctx, 1ull << log2n, true, cur, nw, s);
 }
@@ -941,7 +1019,12 @@ static int run_encode128(polymul_ctx *ctx, const uint64_t *src, uint64_t len, in
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, src, len, cur, nw);
     int rc = run_bcvt(ctx, N, false, cur, bcvt_active_words(N, nw), s);
     if (rc) return rc;
-    if (l >= 6)
+    if (l >= 9) {
+        // rows at or above ceil(N / n_p) hold no bit of the operand
+        const int nz = (int)std::min<uint64_t>(128, (N + n_p - 1) / n_p);
+        KLAUNCH(ctx, s, "encode128", k_encode128_w8, grid_for(n_p / M128_NB, 256), 256, cur, l, nz,
+                ctx->tables128, dst);
+    } else if (l >= 6)
         KLAUNCH(ctx, s, "encode128", k_encode128_w, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
     else
         KLAUNCH(ctx, s, "encode128", k_encode128, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
@@ -998,11 +1081,15 @@ static int product128_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, 
     if ((rc = run_encode128(ctx, a, len_a, log2n, W0, W2, s))) return rc;
     if ((rc = run_encode128(ctx, b, len_b, log2n, W1, W2, s))) return rc;
     if ((rc = run_product128(ctx, W0, W1, l, s))) return rc;
-    KLAUNCH(ctx, s, "decode128_vec", k_decode128_vec, grid_for(nw, 256), 256, W0, nw, ctx->tables128);
-    if (l >= 6)
-        KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter_w, grid_for(nw / 2, 256), 256, W0, l, W1);
-    else
-        KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
+    if (l >= 9) {
+        KLAUNCH(ctx, s, "decode128", k_decode128_w8, grid_for(nw / 2 / M128_NB, 256), 256, W0, l, ctx->tables128, W1);
+    } else {
+        KLAUNCH(ctx, s, "decode128_vec", k_decode128_vec, grid_for(nw, 256), 256, W0, nw, ctx->tables128);
+        if (l >= 6)
+            KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter_w, grid_for(nw / 2, 256), 256, W0, l, W1);
+        else
+            KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
+    }
     if ((rc = run_bcvt(ctx, 1ull << log2n, true, W1, nw, s))) return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, W1, lc, out);
     return 0;

@@ -98,6 +98,46 @@ __global__ __launch_bounds__(256) void k_encode128_w(const uint64_t *__restrict_
     }
 }
 
+// The same for 8 consecutive blocks per wave (l >= 9): every row is read as
+// one 64-byte run.  Rows at or above nzrows are zero (the operand's bits end
+// below nzrows n_p) and are not read.
+#define M128_NB 8
+__global__ __launch_bounds__(256) void k_encode128_w8(const uint64_t *__restrict__ bits, int l, int nzrows,
+                                                      const DevTables128 *__restrict__ U, uint64_t *__restrict__ vals)
+{
+    __shared__ uint64_t s_win[8][256];
+    for (int q = threadIdx.x; q < 8 * 256; q += blockDim.x) (&s_win[0][0])[q] = (&U->enc_win[0][0])[q];
+    __syncthreads();
+    const uint64_t rw = 1ull << (l - 6), ngrp = rw / M128_NB;
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    const bool le = 2 * lane < nzrows, lo = 2 * lane + 1 < nzrows;
+    for (uint64_t grp = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; grp < ngrp; grp += nwaves) {
+        const uint64_t b0 = grp * M128_NB;
+        ulonglong2 we[M128_NB / 2], wo[M128_NB / 2];
+        const ulonglong2 *re = reinterpret_cast<const ulonglong2 *>(bits + (uint64_t)(2 * lane) * rw + b0);
+        const ulonglong2 *ro = reinterpret_cast<const ulonglong2 *>(bits + (uint64_t)(2 * lane + 1) * rw + b0);
+#pragma unroll
+        for (int h = 0; h < M128_NB / 2; ++h) {
+            we[h] = le ? re[h] : make_ulonglong2(0, 0);
+            wo[h] = lo ? ro[h] : make_ulonglong2(0, 0);
+        }
+#pragma unroll
+        for (int bb = 0; bb < M128_NB; ++bb) {
+            const uint64_t e = (bb & 1) ? we[bb / 2].y : we[bb / 2].x, o = (bb & 1) ? wo[bb / 2].y : wo[bb / 2].x;
+            uint64_t c0 = 0, c1 = 0;
+#pragma unroll 8
+            for (int k = 0; k < 64; ++k) {
+                const uint64_t m0 = __ballot((int)((e >> k) & 1u)), m1 = __ballot((int)((o >> k) & 1u));
+                c0 = lane == k ? m0 : c0;
+                c1 = lane == k ? m1 : c1;
+            }
+            reinterpret_cast<ulonglong2 *>(vals)[(b0 + bb) * 64 + lane] =
+                make_ulonglong2(m128_win(s_win, c0), m128_win(s_win, c1));
+        }
+    }
+}
+
 // Decode part 1: both halves of every value -> their row bits, in place
 __global__ void k_decode128_vec(uint64_t *__restrict__ vals, uint64_t nwords, const DevTables128 *__restrict__ U)
 {
@@ -165,6 +205,44 @@ __global__ __launch_bounds__(256) void k_decode128_scatter_w(const uint64_t *__r
 __device__ __forceinline__ uint64_t m128_pmul(const uint4 &t01, uint32_t t2, uint64_t x)
 {
     return (uint64_t)b2_pmul32(t01, t2, (uint32_t)x) | ((uint64_t)b2_pmul32(t01, t2, (uint32_t)(x >> 32)) << 32);
+}
+
+// Decode, both parts, for 8 consecutive blocks per wave (l >= 9): P^-1 on
+// both halves, then the transpose; every row is written as one 64-byte run
+__global__ __launch_bounds__(256) void k_decode128_w8(const uint64_t *__restrict__ vecs, int l,
+                                                      const DevTables128 *__restrict__ U, uint64_t *__restrict__ bits)
+{
+    __shared__ uint64_t s_win[8][256];
+    for (int q = threadIdx.x; q < 8 * 256; q += blockDim.x) (&s_win[0][0])[q] = (&U->dec_win[0][0])[q];
+    __syncthreads();
+    const uint64_t rw = 1ull << (l - 6), ngrp = rw / M128_NB;
+    const int lane = threadIdx.x & 63;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t grp = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; grp < ngrp; grp += nwaves) {
+        const uint64_t b0 = grp * M128_NB;
+        uint64_t r0[M128_NB], r1[M128_NB];
+#pragma unroll
+        for (int bb = 0; bb < M128_NB; ++bb) {
+            const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(vecs)[(b0 + bb) * 64 + lane];
+            const ulonglong2 h = make_ulonglong2(m128_win(s_win, v.x), m128_win(s_win, v.y));
+            uint64_t a0 = 0, a1 = 0;
+#pragma unroll 8
+            for (int t = 0; t < 64; ++t) {
+                const uint64_t m0 = __ballot((int)((h.x >> t) & 1u)), m1 = __ballot((int)((h.y >> t) & 1u));
+                a0 = lane == t ? m0 : a0;
+                a1 = lane == t ? m1 : a1;
+            }
+            r0[bb] = a0;
+            r1[bb] = a1;
+        }
+        ulonglong2 *we = reinterpret_cast<ulonglong2 *>(bits + (uint64_t)(2 * lane) * rw + b0);
+        ulonglong2 *wo = reinterpret_cast<ulonglong2 *>(bits + (uint64_t)(2 * lane + 1) * rw + b0);
+#pragma unroll
+        for (int h = 0; h < M128_NB / 2; ++h) {
+            we[h] = make_ulonglong2(r0[2 * h], r0[2 * h + 1]);
+            wo[h] = make_ulonglong2(r1[2 * h], r1[2 * h + 1]);
+        }
+    }
 }
 
 // forward butterfly on (u, v): u += c v, v += u; inverse: v += u, u += c v,
