@@ -182,32 +182,10 @@ __global__ void k_encode(const uint64_t *__restrict__ bits, int l, const DevTabl
     }
 }
 
-// Encode with the bit transpose done by wave ballots (n_p >= 64): one wave
-// per 64 consecutive values; lane t loads the word of row t over their
-// columns, and value k's column is the ballot of bit k of those words
-__global__ __launch_bounds__(256) void k_encode_w(const uint64_t *__restrict__ bits, int l,
-                                                  const DevTables *__restrict__ T, uint64_t *__restrict__ vals)
-{
-    const uint64_t rw = 1ull << (l - 6);   // words per row = blocks of 64 values
-    const int lane = threadIdx.x & 63;
-    const uint64_t nwaves = gstride() >> 6;
-    for (uint64_t blk = gid() >> 6; blk < rw; blk += nwaves) {
-        const uint64_t w = bits[(uint64_t)lane * rw + blk];
-        uint64_t col = 0;
-#pragma unroll 8
-        for (int k = 0; k < 64; ++k) {
-            const uint64_t m = __ballot((int)((w >> k) & 1u));
-            col = lane == k ? m : col;
-        }
-        uint64_t f = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) f ^= T->enc_win[k][(col >> (8 * k)) & 255u];
-        vals[blk * 64 + lane] = f;
-    }
-}
-
-// The same for 8 consecutive blocks per wave (l >= 9): every row is read as
-// one 64-byte run; rows at or above nzrows are zero and are not read
+// Encode with the bit transpose done by wave ballots (l >= 9): one wave per
+// 8 blocks of 64 consecutive values; lane t loads the words of row t over
+// their columns (one 64-byte run), and value k's column is the ballot of bit
+// k of those words.  Rows at or above nzrows are zero and are not read.
 #define ENC_NB 8
 __global__ __launch_bounds__(256) void k_encode_w8(const uint64_t *__restrict__ bits, int l, int nzrows,
                                                    const DevTables *__restrict__ T, uint64_t *__restrict__ vals)
@@ -269,28 +247,9 @@ __global__ void k_decode_scatter(const uint64_t *__restrict__ vecs, int l, uint6
     }
 }
 
-// Decode part 2 with ballots (n_p >= 64): lane k holds vector i0 + k; the
-// word of row t over columns i0 .. i0 + 63 is the ballot of bit t, kept by lane t
-__global__ __launch_bounds__(256) void k_decode_scatter_w(const uint64_t *__restrict__ vecs, int l,
-                                                          uint64_t *__restrict__ bits)
-{
-    const uint64_t rw = 1ull << (l - 6);
-    const int lane = threadIdx.x & 63;
-    const uint64_t nwaves = gstride() >> 6;
-    for (uint64_t blk = gid() >> 6; blk < rw; blk += nwaves) {
-        const uint64_t h = vecs[blk * 64 + lane];
-        uint64_t r = 0;
-#pragma unroll 8
-        for (int t = 0; t < 64; ++t) {
-            const uint64_t m = __ballot((int)((h >> t) & 1u));
-            r = lane == t ? m : r;
-        }
-        bits[(uint64_t)lane * rw + blk] = r;
-    }
-}
-
-// Decode, both parts, for 8 consecutive blocks per wave (l >= 9): R^-1 on
-// every value, then the transpose; every row is written as one 64-byte run
+// Decode, both parts, with ballots (l >= 9): R^-1 on every value, then the
+// word of row t over a block's 64 columns is the ballot of bit t, kept by
+// lane t; 8 blocks per wave, so every row is written as one 64-byte run
 __global__ __launch_bounds__(256) void k_decode_w8(const uint64_t *__restrict__ vecs, int l,
                                                    const DevTables *__restrict__ T, uint64_t *__restrict__ bits)
 {
@@ -609,9 +568,7 @@ static int run_encode_in(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int 
         // rows at or above ceil(N / n_p) hold no bit of the operand
         const int nz = (int)std::min<uint64_t>(64, (N + n_p - 1) / n_p);
         KLAUNCH(ctx, s, "encode", k_encode_w8, grid_for(n_p / ENC_NB, bs), bs, cur, l, nz, ctx->tables, spare);
-    } else if (l >= 6)
-        KLAUNCH(ctx, s, "encode", k_encode_w, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
-    else
+    } else
         KLAUNCH(ctx, s, "encode", k_encode, grid_for(n_p, bs), bs, cur, l, ctx->tables, spare);
     std::swap(cur, spare);
     return 0;
@@ -627,10 +584,7 @@ static int run_decode_out(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t 
         KLAUNCH(ctx, s, "decode", k_decode_w8, grid_for(nw / ENC_NB, bs), bs, cur, l, ctx->tables, spare);
     } else {
         KLAUNCH(ctx, s, "decode_vec", k_decode_vec, grid_for(n_p, bs), bs, cur, l, ctx->tables);
-        if (l >= 6)
-            KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter_w, grid_for(nw, bs), bs, cur, l, spare);
-        else
-            KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
+        KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
     }
     std::swap(cur, spare);
     return run_bcvt(ctx, 1ull << log2n, true, cur, nw, s);
@@ -1024,9 +978,7 @@ static int run_encode128(polymul_ctx *ctx, const uint64_t *src, uint64_t len, in
         const int nz = (int)std::min<uint64_t>(128, (N + n_p - 1) / n_p);
         KLAUNCH(ctx, s, "encode128", k_encode128_w8, grid_for(n_p / M128_NB, 256), 256, cur, l, nz,
                 ctx->tables128, dst);
-    } else if (l >= 6)
-        KLAUNCH(ctx, s, "encode128", k_encode128_w, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
-    else
+    } else
         KLAUNCH(ctx, s, "encode128", k_encode128, grid_for(n_p, 256), 256, cur, l, ctx->tables128, dst);
     return 0;
 }
@@ -1085,10 +1037,7 @@ static int product128_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, 
         KLAUNCH(ctx, s, "decode128", k_decode128_w8, grid_for(nw / 2 / M128_NB, 256), 256, W0, l, ctx->tables128, W1);
     } else {
         KLAUNCH(ctx, s, "decode128_vec", k_decode128_vec, grid_for(nw, 256), 256, W0, nw, ctx->tables128);
-        if (l >= 6)
-            KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter_w, grid_for(nw / 2, 256), 256, W0, l, W1);
-        else
-            KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
+        KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
     }
     if ((rc = run_bcvt(ctx, 1ull << log2n, true, W1, nw, s))) return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, W1, lc, out);

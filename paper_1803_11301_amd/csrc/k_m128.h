@@ -74,32 +74,11 @@ __global__ void k_encode128(const uint64_t *__restrict__ bits, int l, const DevT
     }
 }
 
-// The same with the bit transpose done by wave ballots (n_p >= 64): one wave
-// per 64 consecutive values i0 .. i0 + 63.  Lane t loads the words of rows 2t
-// and 2t + 1 that hold those columns; bit t of value k's halves is bit k of
-// lane t's words, which the ballot over the lanes of bit k collects.
-__global__ __launch_bounds__(256) void k_encode128_w(const uint64_t *__restrict__ bits, int l,
-                                                     const DevTables128 *__restrict__ U, uint64_t *__restrict__ vals)
-{
-    const uint64_t rw = 1ull << (l - 6);   // words per row = blocks of 64 values
-    const int lane = threadIdx.x & 63;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t blk = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; blk < rw; blk += nwaves) {
-        const uint64_t we = bits[(uint64_t)(2 * lane) * rw + blk], wo = bits[(uint64_t)(2 * lane + 1) * rw + blk];
-        uint64_t c0 = 0, c1 = 0;
-#pragma unroll 8
-        for (int k = 0; k < 64; ++k) {
-            const uint64_t m0 = __ballot((int)((we >> k) & 1u)), m1 = __ballot((int)((wo >> k) & 1u));
-            c0 = lane == k ? m0 : c0;
-            c1 = lane == k ? m1 : c1;
-        }
-        const uint64_t i = blk * 64 + lane;
-        reinterpret_cast<ulonglong2 *>(vals)[i] = make_ulonglong2(m128_win(U->enc_win, c0), m128_win(U->enc_win, c1));
-    }
-}
-
-// The same for 8 consecutive blocks per wave (l >= 9): every row is read as
-// one 64-byte run.  Rows at or above nzrows are zero (the operand's bits end
+// The same with the bit transpose done by wave ballots (l >= 9): one wave
+// per 8 blocks of 64 consecutive values.  Lane t loads the words of rows 2t
+// and 2t + 1 over those columns, each row as one 64-byte run; bit t of value
+// k's halves is bit k of lane t's words, which the ballot over the lanes of
+// bit k collects.  Rows at or above nzrows are zero (the operand's bits end
 // below nzrows n_p) and are not read.
 #define M128_NB 8
 __global__ __launch_bounds__(256) void k_encode128_w8(const uint64_t *__restrict__ bits, int l, int nzrows,
@@ -160,55 +139,10 @@ __global__ void k_decode128_scatter(const uint64_t *__restrict__ vecs, int l, ui
     }
 }
 
-// Decode part 2 with ballots (n_p >= 64): lane k holds value i0 + k; the
-// word of row 2t + e over columns i0 .. i0 + 63 is the ballot of bit t of
-// half e, kept by lane t
-__global__ __launch_bounds__(256) void k_decode128_scatter_w(const uint64_t *__restrict__ vecs, int l,
-                                                             uint64_t *__restrict__ bits)
-{
-    const uint64_t rw = 1ull << (l - 6);
-    const int lane = threadIdx.x & 63;
-    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-    for (uint64_t blk = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; blk < rw; blk += nwaves) {
-        const ulonglong2 h = reinterpret_cast<const ulonglong2 *>(vecs)[blk * 64 + lane];
-        uint64_t r0 = 0, r1 = 0;
-#pragma unroll 8
-        for (int t = 0; t < 64; ++t) {
-            const uint64_t m0 = __ballot((int)((h.x >> t) & 1u)), m1 = __ballot((int)((h.y >> t) & 1u));
-            r0 = lane == t ? m0 : r0;
-            r1 = lane == t ? m1 : r1;
-        }
-        bits[(uint64_t)(2 * lane) * rw + blk] = r0;
-        bits[(uint64_t)(2 * lane + 1) * rw + blk] = r1;
-    }
-}
-
-// One butterfly layer i of the transforms of A (and of B when given):
-// forward h0 = p0 + c p1, h1 = h0 + p1; inverse p1 = h0 + h1, p0 = h0 + c p1.
-// The pairs of both operands form one range of 1024-pair tiles, one pair per
-// thread; each workgroup takes a contiguous run of tiles.
-//
-// The products by A = L_d + iota(2b) split as for m = 64: with b = 128 bh + bl,
-// A = K + beta, K = L_d + iota(bh << 8) and beta = iota(2 bl) in V_8, so
-// x A = tmul(T_K, x) + bmul(beta, x).  T_K is rebuilt in LDS whenever bh
-// changes (every 2^(i+7) pairs) from its basis images K unit_t =
-// L_d unit_t + the v_{8+v} unit_t of the set bits v of bh.  This needs a
-// tile inside one block range of bh (i >= 3, whole tiles: l >= 11) and
-// bh < 2^24 (d <= 32).  The layers below 3 split b at bit 11 instead:
-// beta = iota(2 (b mod 2^11)) lies in V_16 and is applied as
-// beta0 x + beta1 (x v_8) with byte permutes.  Transforms with l < 11 or
-// d > 32 take general products by A.
-#define M128_TILE 1024
-
-// x beta for beta in V_8, every byte by byte permutes (b2_pmul32 with the
-// v_perm tables t01, t2 of beta) instead of GF(2^8) table lookups
-__device__ __forceinline__ uint64_t m128_pmul(const uint4 &t01, uint32_t t2, uint64_t x)
-{
-    return (uint64_t)b2_pmul32(t01, t2, (uint32_t)x) | ((uint64_t)b2_pmul32(t01, t2, (uint32_t)(x >> 32)) << 32);
-}
-
-// Decode, both parts, for 8 consecutive blocks per wave (l >= 9): P^-1 on
-// both halves, then the transpose; every row is written as one 64-byte run
+// Decode, both parts, with ballots (l >= 9): lane k holds value i0 + k of a
+// block of 64; P^-1 on both halves, then the word of row 2t + e over the
+// block's columns is the ballot of bit t of half e, kept by lane t.  8 blocks
+// per wave, so every row is written as one 64-byte run.
 __global__ __launch_bounds__(256) void k_decode128_w8(const uint64_t *__restrict__ vecs, int l,
                                                       const DevTables128 *__restrict__ U, uint64_t *__restrict__ bits)
 {
@@ -245,6 +179,13 @@ __global__ __launch_bounds__(256) void k_decode128_w8(const uint64_t *__restrict
     }
 }
 
+// x beta for beta in V_8, every byte by byte permutes (b2_pmul32 with the
+// v_perm tables t01, t2 of beta) instead of GF(2^8) table lookups
+__device__ __forceinline__ uint64_t m128_pmul(const uint4 &t01, uint32_t t2, uint64_t x)
+{
+    return (uint64_t)b2_pmul32(t01, t2, (uint32_t)x) | ((uint64_t)b2_pmul32(t01, t2, (uint32_t)(x >> 32)) << 32);
+}
+
 // forward butterfly on (u, v): u += c v, v += u; inverse: v += u, u += c v,
 // for c = A + H_d y with A = K + beta (T_K = tk; beta's v_perm tables t01,
 // t2), th / thv the window tables of H_d and H_d v_63:
@@ -266,6 +207,23 @@ __device__ __forceinline__ void m128_bfly(const uint64_t *__restrict__ tk, const
         v.y ^= u.y;
     }
 }
+
+// One butterfly layer i of the transforms of A (and of B when given):
+// forward h0 = p0 + c p1, h1 = h0 + p1; inverse p1 = h0 + h1, p0 = h0 + c p1.
+// The pairs of both operands form one range of 1024-pair tiles, one pair per
+// thread; each workgroup takes a contiguous run of tiles.
+//
+// The products by A = L_d + iota(2b) split as for m = 64: with b = 128 bh + bl,
+// A = K + beta, K = L_d + iota(bh << 8) and beta = iota(2 bl) in V_8, so
+// x A = tmul(T_K, x) + bmul(beta, x).  T_K is rebuilt in LDS whenever bh
+// changes (every 2^(i+7) pairs) from its basis images K unit_t =
+// L_d unit_t + the v_{8+v} unit_t of the set bits v of bh.  This needs a
+// tile inside one block range of bh (i >= 3, whole tiles: l >= 11) and
+// bh < 2^24 (d <= 32).  The layers below 3 split b at bit 11 instead:
+// beta = iota(2 (b mod 2^11)) lies in V_16 and is applied as
+// beta0 x + beta1 (x v_8) with byte permutes.  Transforms with l < 11 or
+// d > 32 take general products by A.
+#define M128_TILE 1024
 
 template <bool INV>
 __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A, uint64_t *__restrict__ B, int l,
