@@ -235,9 +235,20 @@ def bench_m128(steps: int, log2_len: int = 37, compare: bool = True):
     if compare:
         ms30 = _m128_at_2e30()
     nominal = nominal_bytes(L // 8, L // 8, (1 << (log2_len + 1)) // 8)
+    # the inverse BasisCvt steps beyond LDS update lo from hi in place: read
+    # both halves of the 2^(log2_len + 1)-bit buffer and write lo, 1.5x its
+    # bytes per launch (HBM-bound, the largest such kernel of this path)
+    roof = None
+    if "ibasiscvt_wide" in prof:
+        cnt, tot = prof["ibasiscvt_wide"]
+        per_launch = 3 * (1 << (log2_len + 1)) // 8 // 2
+        achieved = per_launch / (tot / cnt / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": "ibasiscvt_wide", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": per_launch,
+                "avg_launch_us": round(1e3 * tot / cnt, 1)}
     rec = {"workload": f"single product 2^{log2_len} x 2^{log2_len} bits, uniform random, seeds 0x5eed0037/8, "
                        f"2^{log2_len + 1}-bit transform over GF(2^128)",
-           "ms_per_product": round(ms, 2), "steps": steps,
+           "ms_per_product": round(ms, 2), "steps": steps, "roofline": roof,
            "product_roofline": {"nominal_bytes": nominal, "achieved": round(nominal / (ms / 1e3) / 1e9, 1),
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(nominal / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},

@@ -229,3 +229,52 @@ def test_tower_basis_is_a_basis_and_multiplicative():
                 if (prod >> b) & 1:
                     prod ^= span[b]
             assert prod == 0
+
+
+# --------------------------------------------------------------------------
+# m = 128 (GF(2^128), l_m = 7): the same readings one field up
+# --------------------------------------------------------------------------
+
+from oracle import method_model128 as M128   # noqa: E402
+
+
+def test_m128_modulus_irreducible_and_basis():
+    assert M128.is_irreducible_modulus()
+    v = M128.cantor_basis()
+    assert v[0] == 1
+    for i in range(1, 128):
+        assert M128.mul(v[i], v[i]) ^ v[i] == v[i - 1]
+    assert M128.rank(v) == 128
+    # V_64 = span(v_0 .. v_63) is the subfield GF(2^64): closed under products
+    rng = random.Random(64)
+    for _ in range(20):
+        x = M128.iota(rng.getrandbits(64))
+        y = M128.iota(rng.getrandbits(64))
+        assert M128.rank(list(v[:64]) + [M128.mul(x, y)]) == 64
+
+
+def test_m128_encode_reading_full_rank_and_literal_index_singular():
+    assert M128.rank(M128.encode_rows()) == 128
+    M128.inverse_rows(M128.encode_rows())
+    literal = M128.encode_rows(index=lambda k: 64 - 1 - k)
+    assert M128.rank(literal) < 128
+    with pytest.raises(ValueError):
+        M128.inverse_rows(literal)
+
+
+@pytest.mark.parametrize("l", [0, 1, 2, 3])
+def test_m128_transform_is_evaluation_at_sigma(l):
+    rng = random.Random(128 + l)
+    n = 128 << l
+    a = rng.getrandbits(n // 2)
+    vals = M128.forward(a, n)
+    for j in range(1 << l):
+        assert vals[j] == M128.eval_gf2poly(a, M128.iota((1 << (l + 64)) ^ j))
+    assert M128.inverse(vals, n) == a
+
+
+@pytest.mark.parametrize("la,lb", [(1, 1), (64, 65), (100, 29), (129, 1), (200, 300), (513, 511)])
+def test_m128_model_product_equals_oracle(la, lb):
+    rng = random.Random(la * 77 + lb)
+    a, b = rng.getrandbits(la), rng.getrandbits(lb)
+    assert M128.fp_polymul(a, la, b, lb) == O.py_clmul(a, b)
