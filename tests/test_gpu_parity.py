@@ -102,6 +102,37 @@ def test_addfft_full_length_operand_round_trip(ctx):
     assert np.array_equal(host(ctx.iaddfft(dev(vals), log2n, n)), a)
 
 
+def test_addfft_round_trip_above_fused_sizes():
+    """polymul_addfft / polymul_iaddfft at a 2^33-bit transform (the per-step
+    path): the inverse gives a full-length ragged A back, and for a 2^20-bit A
+    (the same full-size butterflies, cheap to evaluate on the host) sampled
+    values are A at the points of Sigma."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1803_11301_amd import fpmul
+    log2n, la, seed = 33, (1 << 32) + 12345, 0x5EED0A33
+    say("addfft round trip", log2n, la, hex(seed))
+    A = synth.dense_poly_device(seed, la, "cuda")
+    c = fpmul.Context(0)
+    try:
+        back = c.iaddfft(c.addfft(A, la, log2n), log2n, la)
+        torch.cuda.synchronize()
+        assert torch.equal(back, A)
+        del back
+        ls = 1 << 20
+        a = synth.dense_poly(seed + 1, ls)
+        vals = c.addfft(dev(a), ls, log2n)
+        torch.cuda.synchronize()
+        for j in (0, 12345, (1 << 27) - 1):
+            assert F.tower_to_poly(int(vals[j].item()) & ((1 << 64) - 1)) == \
+                O.eval_at(a, ls, F.point(log2n - 6, j))
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+        del A
+        torch.cuda.empty_cache()
+
+
 def test_frobenius_identity_on_transform(ctx):
     # the transform of A^2 is the elementwise square of the transform of A (Eq. 1)
     say("frobenius")
