@@ -482,7 +482,18 @@ def main():
 
     m128 = None
     if not args.no_m128 and args.workload == "large":
-        m128 = bench_m128(args.m128_steps)
+        # 2^37-bit operands, a 2^38-bit output and four 2^38-bit workspace
+        # buffers: about 192 GiB; the headline line must not depend on it
+        free = torch.cuda.mem_get_info()[0]
+        if free < (230 << 30):
+            m128 = {"skipped": f"needs 230 GiB of free device memory, {free >> 30} GiB free"}
+        else:
+            try:
+                m128 = bench_m128(args.m128_steps)
+            except Exception as e:   # reported in the record, not fatal to the headline
+                m128 = {"error": f"{type(e).__name__}: {e}"}
+                torch.cuda.empty_cache()
+        log(f"[bench] m128 record: {'ok' if m128 and 'ms_per_product' in m128 else m128}")
 
     cpu = None
     if not args.no_cpu:

@@ -182,10 +182,10 @@ __global__ void k_encode(const uint64_t *__restrict__ bits, int l, const DevTabl
     }
 }
 
-// Encode with the bit transpose done by wave ballots (l >= 9): one wave per
+// Encode with 64 x 64 bit transposes across the wave (l >= 9): one wave per
 // 8 blocks of 64 consecutive values; lane t loads the words of row t over
-// their columns (one 64-byte run), and value k's column is the ballot of bit
-// k of those words.  Rows at or above nzrows are zero and are not read.
+// their columns (one 64-byte run), and the transpose gives lane k the column
+// of value k.  Rows at or above nzrows are zero and are not read.
 #define ENC_NB 8
 __global__ __launch_bounds__(256) void k_encode_w8(const uint64_t *__restrict__ bits, int l, int nzrows,
                                                    const DevTables *__restrict__ T, uint64_t *__restrict__ vals)
@@ -206,12 +206,7 @@ __global__ __launch_bounds__(256) void k_encode_w8(const uint64_t *__restrict__ 
 #pragma unroll
         for (int bb = 0; bb < ENC_NB; ++bb) {
             const uint64_t x = (bb & 1) ? w[bb / 2].y : w[bb / 2].x;
-            uint64_t col = 0;
-#pragma unroll 8
-            for (int k = 0; k < 64; ++k) {
-                const uint64_t m = __ballot((int)((x >> k) & 1u));
-                col = lane == k ? m : col;
-            }
+            const uint64_t col = bc_wave_transpose64(x, lane);
             uint64_t f = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) f ^= s_win[k][(col >> (8 * k)) & 255u];
@@ -247,9 +242,9 @@ __global__ void k_decode_scatter(const uint64_t *__restrict__ vecs, int l, uint6
     }
 }
 
-// Decode, both parts, with ballots (l >= 9): R^-1 on every value, then the
-// word of row t over a block's 64 columns is the ballot of bit t, kept by
-// lane t; 8 blocks per wave, so every row is written as one 64-byte run
+// Decode, both parts, with wave transposes (l >= 9): R^-1 on every value,
+// then the transpose gives lane t the word of row t over a block's 64
+// columns; 8 blocks per wave, so every row is written as one 64-byte run
 __global__ __launch_bounds__(256) void k_decode_w8(const uint64_t *__restrict__ vecs, int l,
                                                    const DevTables *__restrict__ T, uint64_t *__restrict__ bits)
 {
@@ -268,13 +263,7 @@ __global__ __launch_bounds__(256) void k_decode_w8(const uint64_t *__restrict__ 
             uint64_t h = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) h ^= s_win[k][(v >> (8 * k)) & 255u];
-            uint64_t a = 0;
-#pragma unroll 8
-            for (int t = 0; t < 64; ++t) {
-                const uint64_t m = __ballot((int)((h >> t) & 1u));
-                a = lane == t ? m : a;
-            }
-            r[bb] = a;
+            r[bb] = bc_wave_transpose64(h, lane);
         }
         ulonglong2 *w = reinterpret_cast<ulonglong2 *>(bits + (uint64_t)lane * rw + b0);
 #pragma unroll

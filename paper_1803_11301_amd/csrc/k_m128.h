@@ -74,11 +74,11 @@ __global__ void k_encode128(const uint64_t *__restrict__ bits, int l, const DevT
     }
 }
 
-// The same with the bit transpose done by wave ballots (l >= 9): one wave
+// The same with 64 x 64 bit transposes across the wave (l >= 9): one wave
 // per 8 blocks of 64 consecutive values.  Lane t loads the words of rows 2t
 // and 2t + 1 over those columns, each row as one 64-byte run; bit t of value
-// k's halves is bit k of lane t's words, which the ballot over the lanes of
-// bit k collects.  Rows at or above nzrows are zero (the operand's bits end
+// k's halves is bit k of lane t's words, so the transposes of the even and
+// the odd words give lane k its two columns.  Rows at or above nzrows are zero (the operand's bits end
 // below nzrows n_p) and are not read.
 #define M128_NB 8
 __global__ __launch_bounds__(256) void k_encode128_w8(const uint64_t *__restrict__ bits, int l, int nzrows,
@@ -104,13 +104,7 @@ __global__ __launch_bounds__(256) void k_encode128_w8(const uint64_t *__restrict
 #pragma unroll
         for (int bb = 0; bb < M128_NB; ++bb) {
             const uint64_t e = (bb & 1) ? we[bb / 2].y : we[bb / 2].x, o = (bb & 1) ? wo[bb / 2].y : wo[bb / 2].x;
-            uint64_t c0 = 0, c1 = 0;
-#pragma unroll 8
-            for (int k = 0; k < 64; ++k) {
-                const uint64_t m0 = __ballot((int)((e >> k) & 1u)), m1 = __ballot((int)((o >> k) & 1u));
-                c0 = lane == k ? m0 : c0;
-                c1 = lane == k ? m1 : c1;
-            }
+            const uint64_t c0 = bc_wave_transpose64(e, lane), c1 = bc_wave_transpose64(o, lane);
             reinterpret_cast<ulonglong2 *>(vals)[(b0 + bb) * 64 + lane] =
                 make_ulonglong2(m128_win(s_win, c0), m128_win(s_win, c1));
         }
@@ -139,10 +133,10 @@ __global__ void k_decode128_scatter(const uint64_t *__restrict__ vecs, int l, ui
     }
 }
 
-// Decode, both parts, with ballots (l >= 9): lane k holds value i0 + k of a
-// block of 64; P^-1 on both halves, then the word of row 2t + e over the
-// block's columns is the ballot of bit t of half e, kept by lane t.  8 blocks
-// per wave, so every row is written as one 64-byte run.
+// Decode, both parts, with wave transposes (l >= 9): lane k holds value
+// i0 + k of a block of 64; P^-1 on both halves, then the transpose of half e
+// gives lane t the word of row 2t + e over the block's columns.  8 blocks per
+// wave, so every row is written as one 64-byte run.
 __global__ __launch_bounds__(256) void k_decode128_w8(const uint64_t *__restrict__ vecs, int l,
                                                       const DevTables128 *__restrict__ U, uint64_t *__restrict__ bits)
 {
@@ -159,15 +153,8 @@ __global__ __launch_bounds__(256) void k_decode128_w8(const uint64_t *__restrict
         for (int bb = 0; bb < M128_NB; ++bb) {
             const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(vecs)[(b0 + bb) * 64 + lane];
             const ulonglong2 h = make_ulonglong2(m128_win(s_win, v.x), m128_win(s_win, v.y));
-            uint64_t a0 = 0, a1 = 0;
-#pragma unroll 8
-            for (int t = 0; t < 64; ++t) {
-                const uint64_t m0 = __ballot((int)((h.x >> t) & 1u)), m1 = __ballot((int)((h.y >> t) & 1u));
-                a0 = lane == t ? m0 : a0;
-                a1 = lane == t ? m1 : a1;
-            }
-            r0[bb] = a0;
-            r1[bb] = a1;
+            r0[bb] = bc_wave_transpose64(h.x, lane);
+            r1[bb] = bc_wave_transpose64(h.y, lane);
         }
         ulonglong2 *we = reinterpret_cast<ulonglong2 *>(bits + (uint64_t)(2 * lane) * rw + b0);
         ulonglong2 *wo = reinterpret_cast<ulonglong2 *>(bits + (uint64_t)(2 * lane + 1) * rw + b0);
