@@ -938,7 +938,6 @@ static int ensure_tables128(polymul_ctx *ctx)
     for (int d = 0; d < M128_MAXD; ++d) D->lo[d] = H2->v[64 + d].lo;
     for (int d = 0; d <= 32; ++d)
         for (int t = 0; t < 64; ++t) D->gbase[d][t] = H->tw.m64(H2->v[64 + d].lo, 1ull << t);
-    D->v63 = H->cantor[63];
     static_assert(sizeof(D->ktab) == sizeof(H2->ktab), "window table layout");
     std::memcpy(D->ktab, H2->ktab, sizeof(D->ktab));
     DevTables128 *dev = nullptr;

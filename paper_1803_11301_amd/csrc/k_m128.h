@@ -31,8 +31,7 @@ struct DevTables128 {
     uint64_t enc_win[8][256];            // Encode: byte window k of a 64-row column -> sum of P_t
     uint64_t dec_win[8][256];            // Decode: byte window k of a half -> its 64 row bits
     uint64_t lo[M128_MAXD];              // L_d
-    uint64_t v63;                        // v_63, tower representation
-    uint64_t ktab[M128_MAXD][2][2048];   // window tables of H_d and H_d v_63
+    uint64_t ktab[M128_MAXD][2][2048];   // window tables of H_d and H_d v_63 (d = 0: 1 and v_63)
     uint64_t gbase[33][64];              // L_d unit_t (basis images of L_d), d <= 32
 };
 
@@ -427,15 +426,17 @@ __global__ __launch_bounds__(1024) void k_pointwise128(uint64_t *__restrict__ A,
                                                        const DevTables128 *__restrict__ U)
 {
     __shared__ __align__(16) uint8_t s_m8[M8V_BYTES];
+    __shared__ __align__(16) uint64_t s_v63[2048];   // window table of v_63 (H_0 v_63, H_0 = 1)
     const int tid = threadIdx.x, nth = blockDim.x;
     m128_load_mul8(s_m8, T, tid, nth);
+    for (int q = tid; q < 2048; q += nth) s_v63[q] = U->ktab[0][1][q];
     __syncthreads();
     const Mul8View mv{s_m8};
-    const uint64_t v63 = U->v63, stride = (uint64_t)gridDim.x * nth;
+    const uint64_t stride = (uint64_t)gridDim.x * nth;
     for (uint64_t j = (uint64_t)blockIdx.x * nth + tid; j < n_p; j += stride) {
         const ulonglong2 a = reinterpret_cast<const ulonglong2 *>(A)[j];
         const ulonglong2 b = reinterpret_cast<const ulonglong2 *>(B)[j];
         const uint64_t p0 = mv.m64(a.x, b.x), p2 = mv.m64(a.y, b.y), p1 = mv.m64(a.x ^ a.y, b.x ^ b.y);
-        reinterpret_cast<ulonglong2 *>(A)[j] = make_ulonglong2(p0 ^ mv.m64(p2, v63), p1 ^ p0);
+        reinterpret_cast<ulonglong2 *>(A)[j] = make_ulonglong2(p0 ^ tmul(s_v63, p2), p1 ^ p0);
     }
 }
