@@ -364,7 +364,7 @@ def main():
                     help="only run a plain device copy of MIB MiB three times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+        print("bench.py: measures one GPU; --gpus must be 1 "
               "(products shard without exchange across GPUs, see the design notes)", file=sys.stderr)
         sys.exit(2)
 
