@@ -365,7 +365,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: measures one GPU; --gpus must be 1 "
-              "(products shard without exchange across GPUs, see the design notes)", file=sys.stderr)
+              "(independent products shard across GPUs without exchange; one GPU is measured)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
