@@ -207,6 +207,17 @@ def test_m64_per_step_path_above_fused_sizes():
     _full_size_case((1 << 32) + 1, 4096, 0x5EED0033)
 
 
+def test_m64_at_its_largest_product():
+    """A product of exactly 2^37 bits, the largest GF(2^64) takes (a 2^37-bit
+    transform, l = 31 in the resident-table butterfly passes)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    free, total = torch.cuda.mem_get_info()
+    if free < (120 << 30):
+        pytest.skip("needs 120 GiB of free device memory")
+    _full_size_case((1 << 37) - 4095, 4096, 0x5EED0037 + 64)
+
+
 def test_m128_at_2e33_bits():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
