@@ -420,6 +420,135 @@ __global__ __launch_bounds__(M128_TILE2) void k_bfly128_2layer(uint64_t *__restr
     }
 }
 
+// Layers 2, 1 and 0 in one pass (forward: 2 first), eight consecutive values
+// j0 + e (e < 8, j0 = 8 g) per thread, 512 threads: layer 2 pairs (e, e + 4)
+// in block g, layer 1 pairs (e, e + 2) in blocks 2g and 2g + 1, layer 0 pairs
+// (e, e + 1) in blocks 4g .. 4g + 3.  Each layer splits its block index b at
+// bit 11 as k_bfly128_layer does below layer 3: K = L_d + iota((b >> 11) << 12)
+// from a window table rebuilt when a 4096-value tile starts a new range of
+// b >> 11, and beta = iota(2 (b mod 2^11)) in V_16 by byte permutes.  Needs
+// l >= 12 (whole tiles) and d = l <= 32.
+#define M128_LOW_THREADS 512
+
+// x (K + beta16) with T_K = tk, beta16 = beta0 + beta1 v_8 given by the v_perm
+// tables (p0, p02) of beta0 and (p1, p12) of beta1, (q01, q2) those of v_7
+__device__ __forceinline__ uint64_t m128_kb16(const uint64_t *__restrict__ tk, const uint4 &p0, uint32_t p02,
+                                              const uint4 &p1, uint32_t p12, const uint4 &q01, uint32_t q2,
+                                              uint64_t x)
+{
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const uint32_t rl = b2_pmul32(p0, p02, lo) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, lo));
+    const uint32_t rh = b2_pmul32(p0, p02, hi) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, hi));
+    return tmul(tk, x) ^ ((uint64_t)rl | ((uint64_t)rh << 32));
+}
+
+template <bool INV>
+__device__ __forceinline__ void m128_bfly16(const uint64_t *__restrict__ tk, const uint32_t (*__restrict__ pt8)[8],
+                                            uint32_t b16, const uint4 &q01, uint32_t q2,
+                                            const uint64_t *__restrict__ th, const uint64_t *__restrict__ thv,
+                                            ulonglong2 &u, ulonglong2 &v)
+{
+    const uint4 p0 = *reinterpret_cast<const uint4 *>(pt8[b16 & 255u]);
+    const uint4 p1 = *reinterpret_cast<const uint4 *>(pt8[b16 >> 8]);
+    const uint32_t p02 = pt8[b16 & 255u][4], p12 = pt8[b16 >> 8][4];
+    if (INV) {
+        v.x ^= u.x;
+        v.y ^= u.y;
+    }
+    const uint64_t a0 = m128_kb16(tk, p0, p02, p1, p12, q01, q2, v.x);
+    const uint64_t a1 = m128_kb16(tk, p0, p02, p1, p12, q01, q2, v.y);
+    u.x ^= a0 ^ tmul(thv, v.y);
+    u.y ^= tmul(th, v.x ^ v.y) ^ a1;
+    if (!INV) {
+        v.x ^= u.x;
+        v.y ^= u.y;
+    }
+}
+
+template <bool INV>
+__global__ __launch_bounds__(M128_LOW_THREADS) void k_bfly128_low3(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
+                                                                   int l, const DevTables *__restrict__ T,
+                                                                   const DevTables128 *__restrict__ U)
+{
+    __shared__ __align__(16) uint64_t s_h[3][2][2048];   // [i] window tables of H_{l-i}, H_{l-i} v_63
+    __shared__ __align__(16) uint64_t s_k[3][2048];      // [i] T_K of layer i
+    __shared__ __align__(16) uint32_t s_pt8[256][8];
+    __shared__ uint64_t s_img[3][64];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int q = tid; q < 3 * 2 * 2048; q += nth) {
+        const int i = q / 4096, r = q - i * 4096;
+        (&s_h[i][0][0])[r] = (&U->ktab[l - i][0][0])[r];
+    }
+    for (int q = tid; q < 256 * 8; q += nth) (&s_pt8[0][0])[q] = (&T->pt8[0][0])[q];
+    __syncthreads();
+    const uint4 q01 = *reinterpret_cast<const uint4 *>(s_pt8[0x80]);   // v_7 (Cantor byte 0x80)
+    const uint32_t q2 = s_pt8[0x80][4];
+    const uint64_t quarter8 = 1ull << (l - 3);   // groups of 8 per operand
+    const uint64_t total = B ? 2 * quarter8 : quarter8;
+    const uint64_t ntiles = total / M128_LOW_THREADS, per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t_end = min(ntiles, (uint64_t)(blockIdx.x + 1) * per);
+    uint64_t key[3] = {~0ull, ~0ull, ~0ull};
+    for (uint64_t tile = (uint64_t)blockIdx.x * per; tile < t_end; ++tile) {
+        const uint64_t j00 = ((tile * M128_LOW_THREADS) & (quarter8 - 1)) << 3;   // tile's first value
+        bool changed = false;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) changed |= (j00 >> (i + 12)) != key[i];
+        if (changed) {   // uniform over the tile
+            __syncthreads();   // the previous tile is done with the K tables
+            if (tid < 192) {
+                const int i = tid >> 6, t = tid & 63;
+                const uint64_t bh = j00 >> (i + 12);   // (b >> 11) for b = j >> (i + 1)
+                uint64_t v = U->gbase[l - i][t];
+                for (int k = 0; k < 20; ++k) v ^= ((bh >> k) & 1u) ? T->pbasis[k + 4][t] : 0ull;
+                s_img[i][t] = v;
+            }
+            __syncthreads();
+            for (int it = tid; it < 3 * 256; it += nth) ktable_fill_item(s_k[it >> 8], s_img[it >> 8], it & 255);
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < 3; ++i) key[i] = j00 >> (i + 12);
+        }
+        const uint64_t q = tile * M128_LOW_THREADS + tid;
+        ulonglong2 *P = reinterpret_cast<ulonglong2 *>(q < quarter8 ? A : B);
+        const uint64_t g = q & (quarter8 - 1), j0 = g << 3;
+        ulonglong2 x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = P[j0 + e];
+        // beta of block b at layer i: iota(2 (b mod 2^11)), a V_16 element
+        auto beta = [&](uint64_t b) {
+            const uint32_t cb = (uint32_t)(2 * (b & 2047u));
+            return (uint32_t)(T->iota[0][cb & 255u] ^ T->iota[1][cb >> 8]);
+        };
+        const uint32_t b2 = beta(g), b1a = beta(2 * g), b1b = beta(2 * g + 1);
+        const uint32_t b0a = beta(4 * g), b0b = beta(4 * g + 1), b0c = beta(4 * g + 2), b0d = beta(4 * g + 3);
+        if (!INV) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m128_bfly16<false>(s_k[2], s_pt8, b2, q01, q2, s_h[2][0], s_h[2][1], x[e], x[e + 4]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[0], x[2]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[1], x[3]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[4], x[6]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[5], x[7]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0a, q01, q2, s_h[0][0], s_h[0][1], x[0], x[1]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0b, q01, q2, s_h[0][0], s_h[0][1], x[2], x[3]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0c, q01, q2, s_h[0][0], s_h[0][1], x[4], x[5]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0d, q01, q2, s_h[0][0], s_h[0][1], x[6], x[7]);
+        } else {
+            m128_bfly16<true>(s_k[0], s_pt8, b0a, q01, q2, s_h[0][0], s_h[0][1], x[0], x[1]);
+            m128_bfly16<true>(s_k[0], s_pt8, b0b, q01, q2, s_h[0][0], s_h[0][1], x[2], x[3]);
+            m128_bfly16<true>(s_k[0], s_pt8, b0c, q01, q2, s_h[0][0], s_h[0][1], x[4], x[5]);
+            m128_bfly16<true>(s_k[0], s_pt8, b0d, q01, q2, s_h[0][0], s_h[0][1], x[6], x[7]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[0], x[2]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[1], x[3]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[4], x[6]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[5], x[7]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) m128_bfly16<true>(s_k[2], s_pt8, b2, q01, q2, s_h[2][0], s_h[2][1], x[e], x[e + 4]);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) P[j0 + e] = x[e];
+    }
+}
+
 // A[j] = A[j] B[j] over GF(2^128) (Alg. 5, the pointwise step)
 __global__ __launch_bounds__(1024) void k_pointwise128(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
                                                        uint64_t n_p, const DevTables *__restrict__ T,
