@@ -976,16 +976,20 @@ static int run_product128(polymul_ctx *ctx, uint64_t *A, uint64_t *B, int l, hip
 {
     const uint64_t n_p = 1ull << l;
     const uint64_t wgs = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->num_cu, (n_p + 1023) / 1024));
-    // layer groups from the top: pairs (i + 1, i) in one pass where the
-    // two-layer kernel applies (i >= 3, l >= 11, l - i <= 32), layers 2, 1, 0
-    // in one pass when 12 <= l <= 32, else single layers
+    // layer groups from the top: triples (i + 2, i + 1, i) in one pass where
+    // the three-layer kernel applies (i >= 4, l >= 12, l - i <= 32), pairs
+    // where the two-layer kernel does (i >= 3, l >= 11), layers 2, 1, 0 in one
+    // pass when 12 <= l <= 32, else single layers
     std::vector<std::pair<int, int>> plan;   // (lowest layer, layers)
     for (int i = l - 1; i >= 0;) {
-        if (i - 1 >= 3 && l >= 11 && l - (i - 1) <= 32) {
+        if (i - 2 >= 4 && l >= 12 && l - (i - 2) <= 32) {
+            plan.push_back({i - 2, 3});
+            i -= 3;
+        } else if (i - 1 >= 3 && l >= 11 && l - (i - 1) <= 32) {
             plan.push_back({i - 1, 2});
             i -= 2;
         } else if (i == 2 && l >= 12 && l <= 32) {
-            plan.push_back({0, 3});   // layers 2, 1, 0 in one pass
+            plan.push_back({0, 3});   // layers 2, 1, 0 in one pass (V_16 beta)
             i = -1;
         } else {
             plan.push_back({i, 1});
@@ -994,9 +998,12 @@ static int run_product128(polymul_ctx *ctx, uint64_t *A, uint64_t *B, int l, hip
     }
     const unsigned low_grid = (unsigned)ctx->num_cu;
     for (const auto &p : plan) {
-        if (p.second == 3)
+        if (p.second == 3 && p.first == 0)
             KLAUNCH(ctx, s, "butterfly128", k_bfly128_low3<false>, low_grid, M128_LOW_THREADS, A, B, l,
                     ctx->tables, ctx->tables128);
+        else if (p.second == 3)
+            KLAUNCH(ctx, s, "butterfly128", k_bfly128_3layer<false>, (unsigned)ctx->num_cu, M128_TILE2, A, B, l,
+                    p.first, ctx->tables, ctx->tables128);
         else if (p.second == 2)
             KLAUNCH(ctx, s, "butterfly128", k_bfly128_2layer<false>, (unsigned)ctx->num_cu, M128_TILE2, A, B, l,
                     p.first, ctx->tables, ctx->tables128);
@@ -1006,9 +1013,12 @@ static int run_product128(polymul_ctx *ctx, uint64_t *A, uint64_t *B, int l, hip
     }
     KLAUNCH(ctx, s, "pointwise128", k_pointwise128, (unsigned)wgs, 1024, A, B, n_p, ctx->tables, ctx->tables128);
     for (auto it = plan.rbegin(); it != plan.rend(); ++it) {
-        if (it->second == 3)
+        if (it->second == 3 && it->first == 0)
             KLAUNCH(ctx, s, "ibutterfly128", k_bfly128_low3<true>, low_grid, M128_LOW_THREADS, A, nullptr, l,
                     ctx->tables, ctx->tables128);
+        else if (it->second == 3)
+            KLAUNCH(ctx, s, "ibutterfly128", k_bfly128_3layer<true>, (unsigned)ctx->num_cu, M128_TILE2, A, nullptr,
+                    l, it->first, ctx->tables, ctx->tables128);
         else if (it->second == 2)
             KLAUNCH(ctx, s, "ibutterfly128", k_bfly128_2layer<true>, (unsigned)ctx->num_cu, M128_TILE2, A, nullptr,
                     l, it->first, ctx->tables, ctx->tables128);

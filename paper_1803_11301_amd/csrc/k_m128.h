@@ -420,6 +420,104 @@ __global__ __launch_bounds__(M128_TILE2) void k_bfly128_2layer(uint64_t *__restr
     }
 }
 
+// Layers i + 2, i + 1 and i in one pass (forward: i + 2 first), eight values
+// j0 + k 2^i (k < 8) per thread, 512 threads.  Layer i + 2 pairs (k, k + 4) in
+// block b = j0 >> (i + 3); layer i + 1 pairs (k, k + 2) in blocks 2b and
+// 2b + 1; layer i pairs (k, k + 1) in blocks 4b .. 4b + 3.  K and beta as in
+// the two-layer pass (beta in V_8 by byte permutes); the three K keys are
+// uniform over a tile of 512 groups when i >= 4.  Needs l >= 12 and
+// d = l - i <= 32.
+template <bool INV>
+__global__ __launch_bounds__(M128_TILE2) void k_bfly128_3layer(uint64_t *__restrict__ A, uint64_t *__restrict__ B, int l,
+                                                               int i, const DevTables *__restrict__ T,
+                                                               const DevTables128 *__restrict__ U)
+{
+    __shared__ __align__(16) uint32_t s_ptb[128][8];
+    __shared__ __align__(16) uint64_t s_h[3][2][2048];   // [m] tables of H, H v_63 of layer i + m
+    __shared__ __align__(16) uint64_t s_k[3][2048];      // [m] T_K of layer i + m
+    __shared__ uint64_t s_img[3][64];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int q = tid; q < 128 * 8; q += nth) (&s_ptb[0][0])[q] = (&T->pt_beta8[0][0])[q];
+    for (int q = tid; q < 3 * 2 * 2048; q += nth) {
+        const int m = q / 4096, r = q - m * 4096;
+        (&s_h[m][0][0])[r] = (&U->ktab[l - i - m][0][0])[r];
+    }
+    __syncthreads();
+    const uint64_t eighth = 1ull << (l - 3), total = B ? 2 * eighth : eighth, imask = (1ull << i) - 1;
+    const uint64_t ntiles = total / M128_TILE2, per = (ntiles + gridDim.x - 1) / gridDim.x;
+    const uint64_t t_end = min(ntiles, (uint64_t)(blockIdx.x + 1) * per);
+    uint64_t key[3] = {~0ull, ~0ull, ~0ull};
+    for (uint64_t tile = (uint64_t)blockIdx.x * per; tile < t_end; ++tile) {
+        const uint64_t g0 = (tile * M128_TILE2) & (eighth - 1);
+        // bh of layer i + m: (block >> 7) with block = (g >> i) << (2 - m) (+ lower bits)
+        bool changed = false;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) changed |= (g0 >> (i + 5 + m)) != key[m];
+        if (changed) {   // uniform over the tile
+            __syncthreads();   // the previous tile is done with the K tables
+            if (tid < 192) {
+                const int m = tid >> 6, t = tid & 63;
+                const uint64_t bh = g0 >> (i + 5 + m);
+                uint64_t v = U->gbase[l - i - m][t];
+#pragma unroll
+                for (int k = 0; k < 24; ++k) v ^= ((bh >> k) & 1u) ? T->pbasis[k][t] : 0ull;
+                s_img[m][t] = v;
+            }
+            __syncthreads();
+            for (int it = tid; it < 3 * 256; it += nth) ktable_fill_item(s_k[it >> 8], s_img[it >> 8], it & 255);
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 3; ++m) key[m] = g0 >> (i + 5 + m);
+        }
+        const uint64_t q = tile * M128_TILE2 + tid;
+        ulonglong2 *P = reinterpret_cast<ulonglong2 *>(q < eighth ? A : B);
+        const uint64_t g = q & (eighth - 1), b = g >> i;
+        const uint64_t j0 = (b << (i + 3)) | (g & imask), s = 1ull << i;
+        ulonglong2 x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = P[j0 + k * s];
+        const int r2 = (int)(b & 127u), r1 = (int)((2 * b) & 127u), r0 = (int)((4 * b) & 127u);
+        auto pt = [&](int r, uint4 &t01, uint32_t &t2) {
+            t01 = *reinterpret_cast<const uint4 *>(s_ptb[r]);
+            t2 = s_ptb[r][4];
+        };
+        uint4 p2, p1a, p1b, p0a, p0b, p0c, p0d;
+        uint32_t e2, e1a, e1b, e0a, e0b, e0c, e0d;
+        pt(r2, p2, e2);
+        pt(r1, p1a, e1a);
+        pt(r1 + 1, p1b, e1b);
+        pt(r0, p0a, e0a);
+        pt(r0 + 1, p0b, e0b);
+        pt(r0 + 2, p0c, e0c);
+        pt(r0 + 3, p0d, e0d);
+        if (!INV) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m128_bfly<false>(s_k[2], p2, e2, s_h[2][0], s_h[2][1], x[k], x[k + 4]);
+            m128_bfly<false>(s_k[1], p1a, e1a, s_h[1][0], s_h[1][1], x[0], x[2]);
+            m128_bfly<false>(s_k[1], p1a, e1a, s_h[1][0], s_h[1][1], x[1], x[3]);
+            m128_bfly<false>(s_k[1], p1b, e1b, s_h[1][0], s_h[1][1], x[4], x[6]);
+            m128_bfly<false>(s_k[1], p1b, e1b, s_h[1][0], s_h[1][1], x[5], x[7]);
+            m128_bfly<false>(s_k[0], p0a, e0a, s_h[0][0], s_h[0][1], x[0], x[1]);
+            m128_bfly<false>(s_k[0], p0b, e0b, s_h[0][0], s_h[0][1], x[2], x[3]);
+            m128_bfly<false>(s_k[0], p0c, e0c, s_h[0][0], s_h[0][1], x[4], x[5]);
+            m128_bfly<false>(s_k[0], p0d, e0d, s_h[0][0], s_h[0][1], x[6], x[7]);
+        } else {
+            m128_bfly<true>(s_k[0], p0a, e0a, s_h[0][0], s_h[0][1], x[0], x[1]);
+            m128_bfly<true>(s_k[0], p0b, e0b, s_h[0][0], s_h[0][1], x[2], x[3]);
+            m128_bfly<true>(s_k[0], p0c, e0c, s_h[0][0], s_h[0][1], x[4], x[5]);
+            m128_bfly<true>(s_k[0], p0d, e0d, s_h[0][0], s_h[0][1], x[6], x[7]);
+            m128_bfly<true>(s_k[1], p1a, e1a, s_h[1][0], s_h[1][1], x[0], x[2]);
+            m128_bfly<true>(s_k[1], p1a, e1a, s_h[1][0], s_h[1][1], x[1], x[3]);
+            m128_bfly<true>(s_k[1], p1b, e1b, s_h[1][0], s_h[1][1], x[4], x[6]);
+            m128_bfly<true>(s_k[1], p1b, e1b, s_h[1][0], s_h[1][1], x[5], x[7]);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) m128_bfly<true>(s_k[2], p2, e2, s_h[2][0], s_h[2][1], x[k], x[k + 4]);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) P[j0 + k * s] = x[k];
+    }
+}
+
 // Layers 2, 1 and 0 in one pass (forward: 2 first), eight consecutive values
 // j0 + e (e < 8, j0 = 8 g) per thread, 512 threads: layer 2 pairs (e, e + 4)
 // in block g, layer 1 pairs (e, e + 2) in blocks 2g and 2g + 1, layer 0 pairs
