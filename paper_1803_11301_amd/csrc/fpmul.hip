@@ -976,21 +976,29 @@ static int run_product128(polymul_ctx *ctx, uint64_t *A, uint64_t *B, int l, hip
 {
     const uint64_t n_p = 1ull << l;
     const uint64_t wgs = std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->num_cu, (n_p + 1023) / 1024));
-    // layer groups from the top: triples (i + 2, i + 1, i) in one pass where
-    // the three-layer kernel applies (i >= 4, l >= 12, l - i <= 32), pairs
-    // where the two-layer kernel does (i >= 3, l >= 11), layers 2, 1, 0 in one
-    // pass when 12 <= l <= 32, else single layers
+    // layer groups: for 12 <= l <= 32 triples (i + 2, i + 1, i) from the top
+    // (the three-layer kernel needs i >= 4), pairs down to layer 3, then layers
+    // 2, 1, 0 in one pass; otherwise from the top greedily pairs (i >= 3,
+    // l >= 11, l - i <= 32) and single layers
     std::vector<std::pair<int, int>> plan;   // (lowest layer, layers)
-    for (int i = l - 1; i >= 0;) {
+    if (l >= 12 && l <= 32) {
+        // layers 3 .. l - 1: triples from the top, then 1 to 3 pairs (a
+        // triple's lowest layer must be >= 4), no single layer; then 2, 1, 0
+        const int U = l - 3;
+        const int np = (2 * U) % 3 == 0 ? 3 : (2 * U) % 3;
+        int i = l - 1;
+        for (int t = 0; t < (U - 2 * np) / 3; ++t, i -= 3) plan.push_back({i - 2, 3});
+        for (int t = 0; t < np; ++t, i -= 2) plan.push_back({i - 1, 2});
+        if (i != 2) return fail(POLYMUL_EIO, "m = 128 layer grouping");
+        plan.push_back({0, 3});
+    }
+    for (int i = plan.empty() ? l - 1 : -1; i >= 0;) {
         if (i - 2 >= 4 && l >= 12 && l - (i - 2) <= 32) {
             plan.push_back({i - 2, 3});
             i -= 3;
         } else if (i - 1 >= 3 && l >= 11 && l - (i - 1) <= 32) {
             plan.push_back({i - 1, 2});
             i -= 2;
-        } else if (i == 2 && l >= 12 && l <= 32) {
-            plan.push_back({0, 3});   // layers 2, 1, 0 in one pass (V_16 beta)
-            i = -1;
         } else {
             plan.push_back({i, 1});
             i -= 1;
