@@ -484,17 +484,31 @@ static int build_psteps(PStepTable &P)
 }
 
 // Runs of consecutive steps whose segments fit BT_LDS_WORDS words, applied
-// chunk by chunk in LDS in place (each chunk holds whole segments)
+// chunk by chunk in LDS in place (each chunk holds whole segments).  When
+// the run holds BasisCvt(2^16) of every 2^16-bit block (bc16 = 1: its last
+// BC16_NSTEPS steps, forward; bc16 = 2: its first BC16_NSTEPS, inverse),
+// that part runs as the compile-time row conversion, whose steps within
+// 1024-bit segments stay in registers.
 __global__ __launch_bounds__(1024) void k_bcvt_lds_run(uint64_t *__restrict__ X, uint64_t nw, int chw,
                                                        const BatchStep *__restrict__ st0, int cnt, int inverse, int k0,
-                                                       int k1)
+                                                       int k1, int bc16)
 {
     __shared__ __align__(16) uint64_t lds[BT_LDS_WORDS];
     const int tid = threadIdx.x, nth = blockDim.x;
     for (uint64_t c0 = (uint64_t)blockIdx.x * chw; c0 < nw; c0 += (uint64_t)gridDim.x * chw) {
         for (int w = tid; w < chw; w += nth) lds[w] = X[c0 + w];
         __syncthreads();
-        bt_lds_steps(lds, chw, st0, cnt, inverse != 0, k0, k1, tid, nth);
+        if (bc16 == 1) {
+            bt_lds_steps(lds, chw, st0, cnt, false, k0, k1 - BC16_NSTEPS, tid, nth);
+            bc16_rows<false>(lds, chw / BC_TAU_WORDS, tid, nth);
+            __syncthreads();
+        } else if (bc16 == 2) {
+            bc16_rows<true>(lds, chw / BC_TAU_WORDS, tid, nth);
+            __syncthreads();
+            bt_lds_steps(lds, chw, st0, cnt, true, k0 + BC16_NSTEPS, k1, tid, nth);
+        } else {
+            bt_lds_steps(lds, chw, st0, cnt, inverse != 0, k0, k1, tid, nth);
+        }
         for (int w = tid; w < chw; w += nth) X[c0 + w] = lds[w];
         __syncthreads();
     }
@@ -514,13 +528,24 @@ static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *cur, u
     const BatchStep *st0 = ctx->psteps->st + pstep_index().first[lg];
     const uint64_t lds_bits = 64ull * BT_LDS_WORDS, chw = std::min<uint64_t>(nw, BT_LDS_WORDS);
     auto S_of = [&](int k) { return steps[inverse ? cnt - 1 - k : k].S; };
+    // for N >= 2^17 the list ends with BasisCvt(2^16) of every 2^16-bit block
+    bool tail16 = N >= (1ull << 17) && chw >= BC_TAU_WORDS && cnt >= BC16_NSTEPS;
+    if (tail16) {
+        std::vector<BStep> b16;
+        bcvt_steps(1ull << 16, 1, b16);
+        for (int j = 0; j < BC16_NSTEPS && tail16; ++j)
+            tail16 = steps[cnt - BC16_NSTEPS + j].S == b16[j].S && steps[cnt - BC16_NSTEPS + j].d == b16[j].d;
+    }
     for (int k = 0; k < cnt;) {
         if (S_of(k) <= lds_bits) {
             int e = k + 1;
             while (e < cnt && S_of(e) <= lds_bits) ++e;
+            // forward: the run ends the list; inverse: it starts it
+            int bc16 = 0;
+            if (tail16 && e - k >= BC16_NSTEPS) bc16 = !inverse && e == cnt ? 1 : (inverse && k == 0 ? 2 : 0);
             const unsigned grid = (unsigned)std::min<uint64_t>(nw / chw, GRID_CAP);
             KLAUNCH(ctx, s, inverse ? "ibasiscvt_lds" : "basiscvt_lds", k_bcvt_lds_run, grid, 1024, cur, nw,
-                    (int)chw, st0, cnt, inverse ? 1 : 0, k, e);
+                    (int)chw, st0, cnt, inverse ? 1 : 0, k, e, bc16);
             k = e;
         } else {
             const BStep &st = steps[inverse ? cnt - 1 - k : k];
