@@ -160,6 +160,19 @@ __global__ void k_bcvt_wide_lo(uint64_t *__restrict__ X, uint64_t nw, uint64_t S
     }
 }
 
+// Two consecutive steps with S >= 128 bits out of place: Y = step b of
+// (step a of X), word by word.  The array between the steps is read lazily
+// from X (a new word depends on at most seven old ones, nearly all of them
+// read by a neighbouring thread as well), so the pair costs one read and one
+// write of the array where the in-place updates cost two passes of 1.5.
+// nw is a multiple of both segment lengths, so every read stays in [0, nw).
+__global__ void k_bcvt_wide2(const uint64_t *__restrict__ X, uint64_t *__restrict__ Y, uint64_t nw, uint64_t Sa,
+                             uint64_t da, uint64_t Sb, uint64_t db, int inverse)
+{
+    const StepView<WordArray> va{WordArray{X}, Sa, da, inverse};
+    for (uint64_t w = gid(); w < nw; w += gstride()) Y[w] = step_word(va, w, Sb, db, inverse);
+}
+
 // ---------------------------------------------------------------------------
 // Encode (Alg. 4): f_i = sum_j a_{j n_p + i} r_j, the 64-bit column of bits
 // (a_{j n_p + i})_j multiplied into the rows r_j by 8-bit windows
@@ -514,10 +527,16 @@ __global__ __launch_bounds__(1024) void k_bcvt_lds_run(uint64_t *__restrict__ X,
     }
 }
 
-// run the BasisCvt steps for N bits (or their inverse) in place on the nw
-// words of cur (nw >= N / 64): every run of steps with segments of at most
-// 2^20 bits in one LDS pass, each larger step as its two updates
-static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *cur, uint64_t nw, hipStream_t s)
+// run the BasisCvt steps for N bits (or their inverse) on the nw words of cur
+// (nw >= N / 64), the result in cur: every run of steps with segments of at
+// most 2^20 bits in one LDS pass; larger steps two at a time out of place
+// between cur and spare (nw words, contents not kept) when spare is given,
+// an even number of such passes so that the result ends in cur, the others
+// in place as their two updates.  The callers give a spare to the inverse
+// only: there a pair takes 0.9 of the time of two in-place steps, while the
+// forward pair, whose lo words read the fixed hi, takes 1.02.
+static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *cur, uint64_t *spare, uint64_t nw,
+                    hipStream_t s)
 {
     std::vector<BStep> steps;
     bcvt_steps(N, 1, steps);
@@ -536,29 +555,47 @@ static int run_bcvt(polymul_ctx *ctx, uint64_t N, bool inverse, uint64_t *cur, u
         for (int j = 0; j < BC16_NSTEPS && tail16; ++j)
             tail16 = steps[cnt - BC16_NSTEPS + j].S == b16[j].S && steps[cnt - BC16_NSTEPS + j].d == b16[j].d;
     }
+    for (int k = 0; k < cnt; ++k)
+        if (S_of(k) > lds_bits && ((S_of(k) & (S_of(k) - 1)) || nw % (S_of(k) / 64)))
+            return fail(POLYMUL_EIO, "BasisCvt segment beyond the array");
+    // paired[k]: steps k and k + 1 run as one out-of-place pass
+    std::vector<char> paired(cnt, 0);
+    int npairs = 0, last = -1;
+    if (spare)
+        for (int k = 0; k + 1 < cnt; ++k)
+            if (S_of(k) > lds_bits && S_of(k + 1) > lds_bits) { paired[k] = 1; last = k; ++npairs; ++k; }
+    if (npairs & 1) paired[last] = 0;
+    uint64_t *X = cur, *Y = spare;
     for (int k = 0; k < cnt;) {
-        if (S_of(k) <= lds_bits) {
+        if (paired[k]) {
+            const BStep &a = steps[inverse ? cnt - 1 - k : k], &b = steps[inverse ? cnt - 2 - k : k + 1];
+            KLAUNCH(ctx, s, inverse ? "ibasiscvt_wide2" : "basiscvt_wide2", k_bcvt_wide2, grid_for(nw, 256), 256, X,
+                    Y, nw, a.S, a.d, b.S, b.d, inverse ? 1 : 0);
+            std::swap(X, Y);
+            k += 2;
+        } else if (S_of(k) <= lds_bits) {
             int e = k + 1;
             while (e < cnt && S_of(e) <= lds_bits) ++e;
             // forward: the run ends the list; inverse: it starts it
             int bc16 = 0;
             if (tail16 && e - k >= BC16_NSTEPS) bc16 = !inverse && e == cnt ? 1 : (inverse && k == 0 ? 2 : 0);
             const unsigned grid = (unsigned)std::min<uint64_t>(nw / chw, GRID_CAP);
-            KLAUNCH(ctx, s, inverse ? "ibasiscvt_lds" : "basiscvt_lds", k_bcvt_lds_run, grid, 1024, cur, nw,
+            KLAUNCH(ctx, s, inverse ? "ibasiscvt_lds" : "basiscvt_lds", k_bcvt_lds_run, grid, 1024, X, nw,
                     (int)chw, st0, cnt, inverse ? 1 : 0, k, e, bc16);
             k = e;
         } else {
             const BStep &st = steps[inverse ? cnt - 1 - k : k];
             const uint64_t nhi = (nw / (st.S / 64)) * ((st.d + 63) / 64), nlo = nw / 2;
             if (!inverse)
-                KLAUNCH(ctx, s, "basiscvt_wide_hi", k_bcvt_wide_hi, grid_for(nhi, 256), 256, cur, nw, st.S, st.d);
+                KLAUNCH(ctx, s, "basiscvt_wide_hi", k_bcvt_wide_hi, grid_for(nhi, 256), 256, X, nw, st.S, st.d);
             KLAUNCH(ctx, s, inverse ? "ibasiscvt_wide" : "basiscvt_wide", k_bcvt_wide_lo, grid_for(nlo, 256), 256,
-                    cur, nw, st.S, st.d);
+                    X, nw, st.S, st.d);
             if (inverse)
-                KLAUNCH(ctx, s, "ibasiscvt_wide_hi", k_bcvt_wide_hi, grid_for(nhi, 256), 256, cur, nw, st.S, st.d);
+                KLAUNCH(ctx, s, "ibasiscvt_wide_hi", k_bcvt_wide_hi, grid_for(nhi, 256), 256, X, nw, st.S, st.d);
             ++k;
         }
     }
+    if (X != cur) return fail(POLYMUL_EIO, "BasisCvt ended in the spare buffer");
     return 0;
 }
 
@@ -576,7 +613,7 @@ static int run_encode_in(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int 
     const uint64_t nwa = bcvt_active_words(N, nw);
     const unsigned bs = 256;
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, bs), bs, a, len, cur, nw);
-    int rc = run_bcvt(ctx, N, false, cur, nwa, s);
+    int rc = run_bcvt(ctx, N, false, cur, nullptr, nwa, s);
     if (rc) return rc;
     if (l >= 9) {
         // rows at or above ceil(N / n_p) hold no bit of the operand
@@ -601,7 +638,7 @@ static int run_decode_out(polymul_ctx *ctx, int log2n, uint64_t *&cur, uint64_t 
         KLAUNCH(ctx, s, "decode_scatter", k_decode_scatter, grid_for(nw, bs), bs, cur, l, spare);
     }
     std::swap(cur, spare);
-    return run_bcvt(ctx, 1ull << log2n, true, cur, nw, s);
+    return run_bcvt(ctx, 1ull << log2n, true, cur, spare, nw, s);
 }
 
 // the layers above the bottom tile, as (i_lo, k) groups of at most BF_UPPER_MAXK, lowest first
@@ -984,7 +1021,7 @@ static int run_encode128(polymul_ctx *ctx, const uint64_t *src, uint64_t len, in
     const uint64_t nw = 1ull << (log2n - 6), n_p = 1ull << l, N = next_pow2(std::max<uint64_t>(len, 1));
     uint64_t *cur = spare;
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, src, len, cur, nw);
-    int rc = run_bcvt(ctx, N, false, cur, bcvt_active_words(N, nw), s);
+    int rc = run_bcvt(ctx, N, false, cur, nullptr, bcvt_active_words(N, nw), s);
     if (rc) return rc;
     if (l >= 9) {
         // rows at or above ceil(N / n_p) hold no bit of the operand
@@ -1081,7 +1118,7 @@ static int product128_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, 
         KLAUNCH(ctx, s, "decode128_vec", k_decode128_vec, grid_for(nw, 256), 256, W0, nw, ctx->tables128);
         KLAUNCH(ctx, s, "decode128_scatter", k_decode128_scatter, grid_for(nw, 256), 256, W0, l, W1);
     }
-    if ((rc = run_bcvt(ctx, 1ull << log2n, true, W1, nw, s))) return rc;
+    if ((rc = run_bcvt(ctx, 1ull << log2n, true, W1, W0, nw, s))) return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, W1, lc, out);
     return 0;
 }
@@ -1176,8 +1213,8 @@ static int basiscvt_body(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int
     if (rc) return rc;
     uint64_t *cur = ctx->ws[0];
     KLAUNCH(ctx, s, "load", k_load_mask, grid_for(nw, 256), 256, in, inverse ? nbits : len, cur, nw);
-    if ((rc = run_bcvt(ctx, inverse ? nbits : next_pow2(std::max<uint64_t>(len, 1)), inverse != 0, cur, nw,
-                       s)))
+    if ((rc = run_bcvt(ctx, inverse ? nbits : next_pow2(std::max<uint64_t>(len, 1)), inverse != 0, cur,
+                       inverse ? ctx->ws[1] : nullptr, nw, s)))
         return rc;
     KLAUNCH(ctx, s, "store", k_store_mask, grid_for(nw, 256), 256, cur, nbits, out);
     return 0;
