@@ -10,20 +10,29 @@ resident in HBM.  Prints ONE JSON line on stdout; details go to stderr.
 The K timed steps run as a user runs them; then the same K steps run again
 with a HIP event pair that the library records around every kernel on its
 launch stream (polymul_profile_enable), which gives the per-kernel durations
-and the roofline (those events add about 0.1 ms per product, reported as
-ms_per_step_profiled).  The roofline entry
-is for the kernel with the largest total time, priced against HBM at 8 TB/s
-with the nominal algorithmic bytes of its stage (each stage streams its input
-and output once): BasisCvt 2A+2B, Encode A+B+2N, Butterfly 2N per transform,
-pointwise 3N, iButterfly 2N, Decode 2N, iBasisCvt 2N (A, B operand bytes,
-N transform bytes).  Fused kernels are priced by the data they transform,
-read once and written once (KERNEL_BYTES).
+(those events add about 0.1 ms per product, reported as ms_per_step_profiled).
+
+Byte model (every stage of Alg. 5 streams its input and output once at
+natural size; A, B operand bytes, N transform bytes): BasisCvt 2A + 2B,
+Encode (A + N) + (B + N), Butterfly 2N per transform (4N for both), pointwise
+3N, iButterfly 2N, Decode 2N, iBasisCvt 2N; 3A + 3B + 15N per product.  A
+kernel that runs part of a stage is priced at that part's share of the
+stage's bytes: a butterfly pass of k of the l layers at k / l of its stage,
+and a BasisCvt kernel at the share of the Taylor steps of Alg. 1 it applies
+(the superset-sum passes and the final unskew/carry store count the
+top-level expansion, the row kernels the inner BasisCvt(2^16), the column
+kernels the outer BasisCvt over rows); fused Encode/Decode add their stage.
+The `roofline` entry is the kernel with the largest total time, priced so;
+`stages` gives the same at stage level and `product_roofline` for the whole
+product.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -31,6 +40,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+NUM_CU, CLOCK_HZ = 256, 2.4e9            # MI355X: 256 compute units at 2.4 GHz
+VALU_LANE_OPS_PEAK = NUM_CU * 64 * CLOCK_HZ   # one wave64 VALU instruction per CU per clock
 
 WORKLOADS = {
     # name: (operand bits, seed, top bit forced, description)
@@ -39,41 +50,80 @@ WORKLOADS = {
     "large": (1 << 30, 0x5EED0030, False, "single product 2^30 x 2^30 bits, uniform random"),
 }
 
-# Algorithmic bytes per launch of each kernel of the large-size schedule: the
-# data it transforms read once and written once at natural size (A, B operand
-# bytes, N transform bytes).  Fused kernels count each input and output once.
-KERNEL_BYTES = {
-    "basiscvt_zeta": lambda A, B, N: 2 * A,             # two launches per operand
-    "basiscvt_rows": lambda A, B, N: 2 * A,             # one per operand
-    "basiscvt_outer_encode": lambda A, B, N: A + N,     # one per operand
-    "butterfly_upper": lambda A, B, N: 4 * N,           # A and B together
-    "butterfly_bottom": lambda A, B, N: 4 * N,          # A and B together
-    "pointwise": lambda A, B, N: 3 * N,                 # read A, B; write C
-    "ibutterfly_bottom": lambda A, B, N: 2 * N,
-    "ibutterfly_upper": lambda A, B, N: 2 * N,
-    "decode_outer": lambda A, B, N: 2 * N,
-    "ibasiscvt_rows": lambda A, B, N: 2 * N,
-    "ibasiscvt_zeta": lambda A, B, N: 2 * N,
-    "ibasiscvt_store": lambda A, B, N: 2 * N,
-}
+
+def bcvt_step_count(lg: int) -> int:
+    """Number of Taylor steps of BasisCvt(2^lg) in the recursion of Alg. 1
+    (tau = 2^(2^k), the largest with tau <= 2^(lg-1); steps for the segment
+    lengths 2^lg .. 2 tau; then the outer conversion of 2^lg / tau blocks and
+    the inner conversion of tau bits)."""
+    if lg <= 1:
+        return 0
+    lt = 1
+    while 2 * lt <= lg - 1:
+        lt *= 2
+    return (lg - lt) + bcvt_step_count(lg - lt) + bcvt_step_count(lt)
 
 
-# HBM bytes per launch measured with rocprofv3 (FETCH_SIZE and WRITE_SIZE
-# passes, each scaled by what the counter reads for a plain 1 GiB device copy:
-# fetch x2.000, write x1.000), valid only for the kernel sources they were
-# taken on: the sha256 of the listed files must match, else traffic is null.
-MEASURED_TRAFFIC = {
-    "butterfly_upper": {
-        "bytes": (262517 * 2 + 524288) * 1024,
-        "sources": ("paper_1803_11301_amd/csrc/k_bf3.h", "paper_1803_11301_amd/csrc/k_bf2.h",
-                    "paper_1803_11301_amd/csrc/gf_device.h"),
-        "sha256": "a3cd3fe8f5229566408c90f042529d188f42a3fab2d583c1d76c8abac2360db9",
-    },
+BUTTERFLY_BOTTOM_LAYERS = 7   # layers 0..6 in the bottom pass (transforms of 2^20 values and more)
+
+
+def kernel_bytes_per_product(A: int, B: int, N: int, log2n: int, la_log2: int) -> dict:
+    """Algorithmic bytes per product of each kernel of the fused 2^22..2^31-bit
+    schedule, from the stage model in the module docstring."""
+    l = log2n - 6
+    lb = BUTTERFLY_BOTTOM_LAYERS if l >= 20 else min(l, 11)
+    # forward BasisCvt of one 2^la_log2-bit operand: top-level Taylor steps
+    # (superset sums over the 2^(la_log2 - 16) rows), outer over rows, inner of 2^16
+    lgR_f, lgR_i = max(la_log2 - 16, 0), log2n - 16
+    tf, ti = bcvt_step_count(la_log2), bcvt_step_count(log2n)
+    top_f, out_f, in_f = la_log2 - 16, bcvt_step_count(lgR_f), bcvt_step_count(16)
+    top_i, out_i, in_i = log2n - 16, bcvt_step_count(lgR_i), bcvt_step_count(16)
+    assert top_f + out_f + in_f == tf and top_i + out_i + in_i == ti
+    bc_f, bc_i = 2 * A + 2 * B, 2 * N
+    return {
+        "basiscvt_zeta": bc_f * top_f / tf,
+        "basiscvt_rows": bc_f * in_f / tf,
+        "basiscvt_outer_encode": bc_f * out_f / tf + (A + N) + (B + N),
+        "butterfly_upper": 4 * N * (l - lb) / l,
+        "butterfly_bottom": 4 * N * lb / l,
+        "pointwise": 3 * N,
+        "ibutterfly_bottom": 2 * N * lb / l,
+        "ibutterfly_upper": 2 * N * (l - lb) / l,
+        "decode_outer": 2 * N + bc_i * out_i / ti,
+        "ibasiscvt_rows": bc_i * in_i / ti,
+        # the top-level inverse expansion: superset-sum passes plus the store (unskew, carry)
+        "ibasiscvt_zeta+ibasiscvt_store": bc_i * top_i / ti,
+    }
+
+
+STAGES = [
+    # (stage, kernels, nominal bytes from (A, B, N))
+    ("BasisCvt + Encode (A and B)", ("basiscvt_zeta", "basiscvt_rows", "basiscvt_outer_encode"),
+     lambda A, B, N: 3 * A + 3 * B + 2 * N),
+    ("Butterfly (A and B)", ("butterfly_upper", "butterfly_bottom"), lambda A, B, N: 4 * N),
+    ("Pointwise", ("pointwise",), lambda A, B, N: 3 * N),
+    ("iButterfly", ("ibutterfly_bottom", "ibutterfly_upper"), lambda A, B, N: 2 * N),
+    ("Decode + iBasisCvt", ("decode_outer", "ibasiscvt_rows", "ibasiscvt_zeta", "ibasiscvt_store"),
+     lambda A, B, N: 4 * N),
+]
+
+# Counters per dispatch measured with rocprofv3 on the 2^30 x 2^30-bit product
+# (profiles/): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
+# counter reads for a plain 1 GiB device copy (fetch x2.000, write x1.000), and
+# SQ_INSTS_VALU (wave instructions summed over the chip).  They hold only for
+# the kernel sources they were taken on: the sha256 of the listed files must
+# match, else the bench reports them as null.
+COUNTER_SOURCES = ("paper_1803_11301_amd/csrc/fpmul.hip", "paper_1803_11301_amd/csrc/k_basiscvt.h",
+                   "paper_1803_11301_amd/csrc/k_bf3.h", "paper_1803_11301_amd/csrc/k_bf2.h",
+                   "paper_1803_11301_amd/csrc/gf_device.h")
+COUNTERS_SHA256 = None
+COUNTERS = {
+    # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB, SQ_INSTS_VALU) per dispatch
 }
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 
 def sources_sha256(paths) -> str:
-    import hashlib
     h = hashlib.sha256()
     for p in paths:
         with open(os.path.join(ROOT, p), "rb") as f:
@@ -81,11 +131,24 @@ def sources_sha256(paths) -> str:
     return h.hexdigest()
 
 
+def counters_current() -> bool:
+    return COUNTERS_SHA256 is not None and sources_sha256(COUNTER_SOURCES) == COUNTERS_SHA256
+
+
 def measured_traffic(kernel: str):
-    rec = MEASURED_TRAFFIC.get(kernel)
-    if rec is None or sources_sha256(rec["sources"]) != rec["sha256"]:
+    """HBM bytes per dispatch from the committed counters, or None."""
+    if not counters_current() or kernel not in COUNTERS:
         return None
-    return rec["bytes"]
+    f, w, _ = COUNTERS[kernel]
+    return int((f * FETCH_SCALE + w * WRITE_SCALE) * 1024)
+
+
+def valu_utilisation(kernel: str, avg_launch_s: float):
+    """VALU busy fraction of the chip over a launch: wave64 VALU instructions
+    (SQ_INSTS_VALU) x 64 lanes / (launch time x 256 CUs x 64 lanes x 2.4 GHz)."""
+    if not counters_current() or kernel not in COUNTERS or avg_launch_s <= 0:
+        return None
+    return COUNTERS[kernel][2] * 64 / (avg_launch_s * VALU_LANE_OPS_PEAK)
 
 
 def nominal_bytes(A: int, B: int, N: int) -> int:
@@ -99,11 +162,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu() -> dict:
+    """CPU model and core counts of the host the oracle runs on."""
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+# One full-size oracle run on the GPU box's host: `python bench.py --cpu-full`
+# (profiles/cpu_oracle_2e30x2e30.md holds its output); the default bench run
+# times the bounded sample below and reports this measurement beside it.
+CPU_FULL_MEASURED = None
+
+
 def cpu_baseline(log2_len: int, target_log2: int):
     """The oracle (as it stands) on a bounded sample of the same workload: one
     product of 2^log2_len-bit operands from the same generator, on all host
-    threads, projected to 2^target_log2-bit operands by the 3x-per-doubling
-    cost of its Karatsuba recursion."""
+    threads, scaled to 2^target_log2-bit operands by the 3x-per-doubling cost
+    of its Karatsuba recursion; beside it the one measured full-size run."""
     import oracle as O
     from paper_1803_11301_amd import synth
     O.build(force=False)
@@ -114,9 +201,39 @@ def cpu_baseline(log2_len: int, target_log2: int):
     O.polymul(a, L, b, L, threads=threads)
     sec = time.perf_counter() - t0
     scale = 3 ** (target_log2 - log2_len)
+    cpu = host_cpu()
     return {"value": round(sec * 1e3 * scale, 3), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": f"one 2^{log2_len} x 2^{log2_len}-bit product ({sec:.2f} s on {threads} threads, "
-                      f"Karatsuba oracle), x3^{target_log2 - log2_len} for 2^{target_log2}-bit operands"}
+            "sample": f"one 2^{log2_len} x 2^{log2_len}-bit product of the same generator (seed 0x5eed0030) "
+                      f"took {sec:.2f} s on {threads} threads; value = that x 3^{target_log2 - log2_len} "
+                      f"(Karatsuba: 3x per doubling) for 2^{target_log2}-bit operands",
+            "sample_s": round(sec, 3), "cpu_model": cpu["model"], "nproc": cpu["nproc"],
+            "usable_cpus": cpu["usable_cpus"], "full_size_measured": CPU_FULL_MEASURED}
+
+
+def cpu_full(log2_len: int = 30):
+    """Time the oracle once on the whole 2^30 x 2^30-bit workload on all host
+    threads, and check its output against the stored oracle digest."""
+    import numpy as np
+    import oracle as O
+    from paper_1803_11301_amd import synth
+    O.build(force=False)
+    L = 1 << log2_len
+    a, b = synth.single_pair(synth.SEED_LARGE, L)
+    threads = O.max_threads()
+    log(f"[bench] oracle 2^{log2_len} x 2^{log2_len} on {threads} threads")
+    t0 = time.perf_counter()
+    c = O.polymul(a, L, b, L, threads=threads)
+    sec = time.perf_counter() - t0
+    digest = hashlib.sha256(np.ascontiguousarray(c, dtype="<u8").tobytes()).hexdigest()
+    want = None
+    gpath = os.path.join(ROOT, "tests", "golden", "digests.json")
+    if log2_len == 30 and os.path.exists(gpath):
+        with open(gpath) as f:
+            want = json.load(f)["large"]["sha256"]
+    rec = {"kind": "oracle", "workload": f"single product 2^{log2_len} x 2^{log2_len} bits, seed 0x5eed0030",
+           "seconds": round(sec, 2), "ms": round(sec * 1e3, 1), "threads": threads, **host_cpu(),
+           "sha256": digest, "matches_stored_digest": None if want is None else digest == want}
+    return rec
 
 
 def bench_batch(ctx, steps: int):
@@ -280,16 +397,19 @@ def _m128_at_2e30():
     return ms30
 
 
-def bench_serve(ctx, count: int, warmup: int, rho: float, slots: int = 8, batch_limit_bits: int = 1 << 20,
-                max_batch: int = 512):
+def bench_serve(ctx, count: int, warmup: int, rhos, sat_count: int, slots: int = 8,
+                batch_limit_bits: int = 1 << 20, max_batch: int = 512):
     """Poisson stream of products, operands log-uniform in [2^12, 2^24] bits
-    (seed 0x5EED05E5), through the continuous-batching server: first the
-    saturated throughput X (every request submitted at once), then arrivals
-    at rate rho * X; latency = submit to completion seen by the server."""
+    (seed 0x5EED05E5), through the continuous-batching server.  First the
+    saturated throughput X: sat_count requests submitted at once.  Then for
+    each offered load rho: `warmup` requests, then `count` timed requests,
+    arriving open loop at rate rho * X; latency = submit to completion as the
+    server sees it."""
     import numpy as np
     import torch
     from paper_1803_11301_amd import fpmul, synth
-    total = warmup + count
+    per = warmup + count
+    total = sat_count + len(rhos) * per
     _, la, lb, sa, sb = synth.serve_plan(total, 1.0)
     pool_bits = 1 << 25
     pa = torch.from_numpy(synth.dense_poly(synth.SEED_SERVE + 1, pool_bits).view(np.int64)).cuda()
@@ -300,50 +420,153 @@ def bench_serve(ctx, count: int, warmup: int, rho: float, slots: int = 8, batch_
     offa = (sa % np.uint64(1 << 40)).astype(np.int64) % (pw - aw + 1)
     offb = (sb % np.uint64(1 << 40)).astype(np.int64) % (pw - bw + 1)
     ow = (la + lb - 1 + 63) // 64
-    oofs = np.concatenate([[0], np.cumsum(ow)[:-1]])
-    out = torch.empty(int(ow.sum()), dtype=torch.int64, device="cuda")
+    # outputs of one phase at a time (the phases run one after the other)
+    phase_words = max(int(ow[:sat_count].sum()),
+                      max(int(ow[sat_count + k * per: sat_count + (k + 1) * per].sum()) for k in range(len(rhos))))
+    out = torch.empty(phase_words, dtype=torch.int64, device="cuda")
     ab, bb, ob = pa.data_ptr(), pb.data_ptr(), out.data_ptr()
-    args = [(ab + 8 * int(offa[k]), int(la[k]), bb + 8 * int(offb[k]), int(lb[k]), ob + 8 * int(oofs[k]))
-            for k in range(total)]
+
+    def args_for(lo, hi):
+        o = 0
+        res = []
+        for k in range(lo, hi):
+            res.append((ab + 8 * int(offa[k]), int(la[k]), bb + 8 * int(offb[k]), int(lb[k]), ob + 8 * o))
+            o += int(ow[k])
+        return res
+
     torch.cuda.synchronize()
     srv = fpmul.Server(ctx, hbm_budget=8 << 30, slots=slots, batch_limit_bits=batch_limit_bits, max_batch=max_batch)
-    # saturation: the warm-up requests plus the first measured ones all at once
-    nsat = max(warmup, 1)
+    sat = args_for(0, sat_count)
     t0 = time.perf_counter()
-    tks = [srv.submit(*args[k]) for k in range(nsat)]
+    tks = [srv.submit(*x) for x in sat]
     for tk in tks:
         srv.wait(tk)
-    X = nsat / (time.perf_counter() - t0)
-    # open-loop Poisson arrivals at rho * X
-    rate = rho * X
-    arr, _, _, _, _ = synth.serve_plan(count, rate)
-    tks = []
-    t0 = time.perf_counter()
-    for k in range(count):
-        due = t0 + float(arr[k])
-        while True:
-            now = time.perf_counter()
-            if now >= due:
-                break
-            if due - now > 2e-4:
-                time.sleep((due - now) - 1e-4)
-        tks.append(srv.submit(*args[warmup + k]))
-    for tk in tks:
-        srv.wait(tk)
-    wall = time.perf_counter() - t0
-    lat = np.array([(lambda s, st, d: (d - s) / 1e6)(*srv.times(tk)) for tk in tks])
-    queue = np.array([(lambda s, st, d: (st - s) / 1e6)(*srv.times(tk)) for tk in tks])
+    X = sat_count / (time.perf_counter() - t0)
+    log(f"[bench] serve: saturated {X:.0f}/s over {sat_count} requests submitted at once")
+    rows = []
+    for k, rho in enumerate(rhos):
+        lo = sat_count + k * per
+        reqs = args_for(lo, lo + per)
+        rate = rho * X
+        arr = synth.serve_plan(per, rate)[0]
+        tks = []
+        t0 = time.perf_counter()
+        t_meas = None
+        for j in range(per):
+            due = t0 + float(arr[j])
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 2e-4:
+                    time.sleep((due - now) - 1e-4)
+            if j == warmup:
+                t_meas = time.perf_counter()
+            tks.append(srv.submit(*reqs[j]))
+        for tk in tks:
+            srv.wait(tk)
+        wall = time.perf_counter() - (t_meas if t_meas is not None else t0)
+        timed = tks[warmup:]
+        tm = [srv.times(tk) for tk in timed]
+        lat = np.array([(d - s0) / 1e6 for s0, st, d in tm])
+        queue = np.array([(st - s0) / 1e6 for s0, st, d in tm])
+        row = {"rho": rho, "offered_per_s": round(rate, 1), "achieved_products_per_s": round(count / wall, 1),
+               "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+               "mean_ms": round(float(lat.mean()), 3), "p99_queue_ms": round(float(np.percentile(queue, 99)), 3)}
+        rows.append(row)
+        log(f"[bench] serve: rho {rho:.2f}: offered {rate:.0f}/s, achieved {row['achieved_products_per_s']:.0f}/s, "
+            f"p50 {row['p50_ms']} ms, p99 {row['p99_ms']} ms")
     srv.close()
-    rec = {"workload": "Poisson stream, operands log-uniform 2^12..2^24 bits, seed 0x5eed05e5",
-           "requests": count, "warmup": warmup, "saturated_products_per_s": round(X, 1), "rho": rho,
-           "offered_per_s": round(rate, 1), "achieved_products_per_s": round(count / wall, 1),
-           "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-           "mean_ms": round(float(lat.mean()), 3), "p99_queue_ms": round(float(np.percentile(queue, 99)), 3),
-           "slots": slots, "batch_limit_bits": batch_limit_bits, "max_batch": max_batch,
-           "hbm_budget_bytes": 8 << 30}
-    log(f"[bench] serve: saturated {X:.0f}/s; at {rho:.2f}: {count / wall:.0f}/s, p50 {rec['p50_ms']} ms, "
-        f"p99 {rec['p99_ms']} ms")
-    return rec
+    return {"workload": "Poisson stream, operands log-uniform 2^12..2^24 bits, seed 0x5eed05e5",
+            "requests_per_load": count, "warmup_per_load": warmup, "saturation_requests": sat_count,
+            "saturated_products_per_s": round(X, 1), "loads": rows, "slots": slots,
+            "batch_limit_bits": batch_limit_bits, "max_batch": max_batch, "hbm_budget_bytes": 8 << 30}
+
+
+def bench_latency(ctx, names=("small", "mid"), runs=(100, 20)):
+    """Latency of single products: the median over `runs` products of the
+    time between HIP events recorded before and after each polymul_ex call
+    on the stream (operands resident)."""
+    import numpy as np
+    import torch
+    from paper_1803_11301_amd import synth
+    res = {}
+    stream = torch.cuda.current_stream()
+    for name, nrun in zip(names, runs):
+        L, seed, top, desc = WORKLOADS[name]
+        a_np, b_np = synth.single_pair(seed, L, top_bit=top)
+        a = torch.from_numpy(a_np.view(np.int64)).cuda()
+        b = torch.from_numpy(b_np.view(np.int64)).cuda()
+        out = torch.empty(((2 * L - 1) + 63) // 64, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            ctx.polymul(a, L, b, L, out=out, stream=stream)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrun)]
+        for e0, e1 in ev:
+            e0.record(stream)
+            ctx.polymul(a, L, b, L, out=out, stream=stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+        res[name] = {"workload": desc, "runs": nrun, "median_ms": round(float(np.median(ms)), 4),
+                     "p10_ms": round(float(np.percentile(ms, 10)), 4),
+                     "p90_ms": round(float(np.percentile(ms, 90)), 4)}
+        log(f"[bench] latency {name}: median {res[name]['median_ms']} ms over {nrun} products")
+    return res
+
+
+def kernel_table(prof: dict, steps: int, A: int, B: int, N: int, log2n: int, la_log2: int, fused: bool):
+    """Per-kernel times with their algorithmic bytes, achieved rate, measured
+    traffic and VALU utilisation; and the dominant kernel's roofline entry."""
+    kb = kernel_bytes_per_product(A, B, N, log2n, la_log2) if fused else {}
+    per_kernel = {}
+    for name, (cnt, tot) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        avg_s = tot / cnt / 1e3
+        rec = {"launches_per_step": cnt / steps, "ms_per_step": round(tot / steps, 4),
+               "avg_launch_us": round(avg_s * 1e6, 2)}
+        key = name if name in kb else next((k for k in kb if name in k.split("+")), None)
+        if key is not None:
+            # launches of every kernel that shares this part of the stage
+            share = sum(prof[k][0] for k in key.split("+") if k in prof) / steps
+            per_launch = kb[key] / share
+            rec["algorithmic_bytes_per_launch"] = int(per_launch)
+            rec["achieved_GBs"] = round(per_launch / avg_s / 1e9, 1)
+            rec["hbm_frac"] = round(per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+            t = measured_traffic(name)
+            rec["traffic_bytes_per_launch"] = t
+            rec["traffic_over_algorithmic"] = None if t is None else round(t / per_launch, 3)
+        v = valu_utilisation(name, avg_s)
+        rec["valu_utilisation"] = None if v is None else round(v, 3)
+        per_kernel[name] = rec
+        log(f"[bench] {name:26s} {cnt / steps:6.1f} launches/step {tot / steps:9.4f} ms/step "
+            f"{avg_s * 1e6:9.2f} us/launch" + (f"  {rec['achieved_GBs']:8.1f} GB/s algorithmic"
+                                               if "achieved_GBs" in rec else ""))
+    known = [n for n in per_kernel if "algorithmic_bytes_per_launch" in per_kernel[n]]
+    roof = None
+    if known:
+        dom = max(known, key=lambda n: prof[n][1])
+        r = per_kernel[dom]
+        roof = {"bound": "hbm", "kernel": dom, "achieved": r["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": r["hbm_frac"], "traffic": r["traffic_bytes_per_launch"],
+                "bytes_per_launch": r["algorithmic_bytes_per_launch"], "avg_launch_us": r["avg_launch_us"],
+                "traffic_over_algorithmic": r["traffic_over_algorithmic"], "valu_utilisation": r["valu_utilisation"],
+                "bytes_model": "share of its stage's nominal bytes (3A+3B+15N per product): a pass of k of the l "
+                               "butterfly layers is k/l of the stage's 2N per transform"}
+    stages = []
+    if fused:
+        for stage, kernels, fn in STAGES:
+            ks = [k for k in kernels if k in prof]
+            if not ks:
+                continue
+            ms = sum(prof[k][1] for k in ks) / steps
+            nb = fn(A, B, N)
+            tr = [measured_traffic(k) for k in ks]
+            traffic = None if any(t is None for t in tr) else sum(t * prof[k][0] / steps for t, k in zip(tr, ks))
+            stages.append({"stage": stage, "kernels": ks, "ms_per_product": round(ms, 4), "nominal_bytes": nb,
+                           "achieved_GBs": round(nb / (ms / 1e3) / 1e9, 1),
+                           "hbm_frac": round(nb / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic_bytes": None if traffic is None else int(traffic)})
+    return per_kernel, roof, stages
 
 
 def main():
@@ -353,13 +576,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
-    ap.add_argument("--cpu-log2", type=int, default=27, help="operand size of the oracle sample")
+    ap.add_argument("--cpu-log2", type=int, default=28, help="operand size of the oracle sample")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time the oracle once on the whole 2^30 x 2^30-bit workload (no GPU)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-products measurement")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-warmup", type=int, default=200)
-    ap.add_argument("--serve-rho", type=float, default=0.8, help="offered load as a fraction of saturation")
+    ap.add_argument("--serve-requests", type=int, default=10000, help="timed requests per offered load")
+    ap.add_argument("--serve-warmup", type=int, default=500, help="untimed requests before them")
+    ap.add_argument("--serve-rhos", default="0.5,0.8,0.95", help="offered loads as fractions of saturation")
+    ap.add_argument("--serve-saturation", type=int, default=4000, help="requests submitted at once for X")
+    ap.add_argument("--no-latency", action="store_true", help="skip the 2^16 and 2^24 latency lines")
     ap.add_argument("--no-m128", action="store_true", help="skip the GF(2^128) measurement")
     ap.add_argument("--m128-steps", type=int, default=2)
     ap.add_argument("--m128-only", action="store_true",
@@ -371,6 +598,10 @@ def main():
         print("bench.py: measures one GPU; --gpus must be 1 "
               "(independent products shard across GPUs without exchange; one GPU is measured)", file=sys.stderr)
         sys.exit(2)
+
+    if args.cpu_full:
+        print(json.dumps(cpu_full()), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -434,34 +665,14 @@ def main():
     prof = ctx.profile_report()
     ctx.profile(False)
 
-    # nominal bytes of the workload
     A = B = L // 8
     log2n = max(6, (lc - 1).bit_length())
     N = (1 << log2n) // 8
     nominal = nominal_bytes(A, B, N)
-    per_kernel = {}
-    for name, (cnt, tot) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
-        per_kernel[name] = {"launches_per_step": cnt / args.steps, "ms_per_step": tot / args.steps,
-                            "avg_launch_us": 1e3 * tot / cnt}
-        if name in KERNEL_BYTES:
-            gbs = KERNEL_BYTES[name](A, B, N) / (tot / cnt / 1e3) / 1e9
-            per_kernel[name]["achieved_GBs"] = round(gbs, 1)
-        log(f"[bench] {name:26s} {cnt / args.steps:6.1f} launches/step {tot / args.steps:9.4f} ms/step "
-            f"{1e3 * tot / cnt:9.2f} us/launch")
-    known = [n for n in prof if n in KERNEL_BYTES]
-    dom = max(known, key=lambda n: prof[n][1]) if known else None
-    roof = None
-    if dom:
-        cnt, tot = prof[dom]
-        bytes_per_launch = KERNEL_BYTES[dom](A, B, N)
-        avg_s = tot / cnt / 1e3
-        achieved = bytes_per_launch / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(dom), "bytes_per_launch": int(bytes_per_launch),
-                "avg_launch_us": round(avg_s * 1e6, 3)}
-    # the butterfly kernels are bound by LDS table lookups rather than HBM:
-    # report their rate of multiplications by constants (l/2 * n_p per transform,
-    # three transforms) per CU per clock at 2.4 GHz
+    fused = 22 <= log2n <= 31
+    per_kernel, roof, stages = kernel_table(prof, args.steps, A, B, N, log2n, L.bit_length() - 1, fused)
+    # multiplications by constants in the butterfly kernels: (l/2) n_p per
+    # transform, three transforms; their rate per CU per clock
     bfly = [n for n in prof if "butterfly" in n]
     bfly_ms = sum(prof[n][1] for n in bfly) / args.steps
     l = log2n - 6
@@ -469,12 +680,15 @@ def main():
     bfly_rate = None
     if bfly_ms > 0:
         bfly_rate = {"multiplications_per_product": mults, "ms_per_product": round(bfly_ms, 4),
-                     "per_cu_per_clock": round(mults / (bfly_ms / 1e3) / (256 * 2.4e9), 3),
+                     "per_cu_per_clock": round(mults / (bfly_ms / 1e3) / (NUM_CU * CLOCK_HZ), 3),
                      "lookups_per_multiplication": 8}
     product_gbs = nominal / (ms / 1e3) / 1e9
     log(f"[bench] {ms:.3f} ms/product ({ms_profiled:.3f} with per-kernel events); nominal {nominal / 1e9:.3f} GB -> "
-        f"{product_gbs:.1f} GB/s "
-        f"({100 * product_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+        f"{product_gbs:.1f} GB/s ({100 * product_gbs / HBM_PEAK_GBS:.1f}% of HBM peak)")
+
+    latency = None
+    if not args.no_latency and args.workload == "large":
+        latency = bench_latency(ctx)
 
     batch = None
     if not args.no_batch and args.workload == "large":
@@ -482,7 +696,8 @@ def main():
 
     serve = None
     if not args.no_serve and args.workload == "large":
-        serve = bench_serve(ctx, args.serve_requests, args.serve_warmup, args.serve_rho)
+        rhos = [float(x) for x in args.serve_rhos.split(",") if x]
+        serve = bench_serve(ctx, args.serve_requests, args.serve_warmup, rhos, args.serve_saturation)
 
     m128 = None
     if not args.no_m128 and args.workload == "large":
@@ -501,8 +716,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        log(f"[bench] oracle sample 2^{args.cpu_log2} on the host")
         target = L.bit_length() - 1
+        log(f"[bench] oracle sample 2^{min(args.cpu_log2, target)} on the host")
         cpu = cpu_baseline(min(args.cpu_log2, target), target)
         log(f"[bench] cpu baseline {cpu}")
 
@@ -516,10 +731,14 @@ def main():
         "config": {"workload": desc, "len_a": L, "len_b": L, "transform_bits": 1 << log2n,
                    "seed": hex(seed), "field": "GF(2^64)"},
         "roofline": roof,
-        "butterfly_rate": bfly_rate,
         "product_roofline": {"nominal_bytes": nominal, "achieved": round(product_gbs, 2), "peak": HBM_PEAK_GBS,
-                             "unit": "GB/s", "frac": round(product_gbs / HBM_PEAK_GBS, 5)},
+                             "unit": "GB/s", "frac": round(product_gbs / HBM_PEAK_GBS, 5),
+                             "target_frac": 0.5, "ms_at_target": round(nominal / (0.5 * HBM_PEAK_GBS * 1e9) * 1e3, 4)},
+        "stages": stages,
+        "butterfly_rate": bfly_rate,
+        "counters_current": counters_current(),
         "kernels": per_kernel,
+        "latency": latency,
         "batch": batch,
         "serve": serve,
         "m128": m128,

@@ -179,10 +179,19 @@ int polymul_set_large_field(polymul_ctx *ctx, int min_log2n);
  *   done; the server copies nothing) and returns its ticket.  A product whose
  *   workspace exceeds the whole arena is refused with POLYMUL_ENOMEM.
  * polymul_poll -- *done = 1 once the ticket's product is in out; then returns
- *   the product's result code (0, or the error of its launch).
- * polymul_wait -- blocks until the ticket is done; returns its result code.
+ *   the product's result code (0, or the error of its launch).  Polling does
+ *   not release the ticket.
+ * polymul_wait -- blocks until the ticket is done, returns its result code
+ *   and releases the ticket: afterwards the server no longer knows it (poll,
+ *   wait and ticket_times then return POLYMUL_EINVAL).  Every ticket is
+ *   released by exactly one wait (or wait_times), which returns at once for
+ *   a ticket already done; the server keeps nothing of released tickets.
+ * polymul_wait_times -- polymul_wait that also stores the ticket's times
+ *   (as polymul_ticket_times; any pointer may be NULL) before releasing it.
  * polymul_ticket_times -- host steady-clock times (ns since server creation)
- *   at which the ticket was submitted, launched and seen complete.
+ *   at which a ticket not yet released was submitted, launched and seen
+ *   complete (0 for a step not reached yet).
+ * polymul_server_tickets -- *count = tickets submitted and not yet released.
  * polymul_server_destroy -- finishes every submitted request, then frees the
  *   arena, streams and thread.
  * submit, poll, wait and ticket_times may be called from any host thread.
@@ -202,8 +211,11 @@ int polymul_submit(polymul_server *srv, const uint64_t *a_bits, uint64_t len_a, 
                    uint64_t len_b, uint64_t *out, uint64_t *ticket);
 int polymul_poll(polymul_server *srv, uint64_t ticket, int *done);
 int polymul_wait(polymul_server *srv, uint64_t ticket);
+int polymul_wait_times(polymul_server *srv, uint64_t ticket, uint64_t *submit_ns, uint64_t *start_ns,
+                       uint64_t *done_ns);
 int polymul_ticket_times(polymul_server *srv, uint64_t ticket, uint64_t *submit_ns, uint64_t *start_ns,
                          uint64_t *done_ns);
+int polymul_server_tickets(polymul_server *srv, uint64_t *count);
 
 /*
  * polymul_addfft -- the modified additive FFT of Sec. 3.4: BasisCvt (Alg. 1),

@@ -28,6 +28,7 @@
 
 #include "../../include/fpmul.h"
 #include "consts_host.h"
+#include "plan.h"
 
 #define FPMUL_VERSION "fpmul 0.1 (gfx950)"
 
@@ -294,7 +295,7 @@ struct ProfRec {
 };
 
 #define SMALL_FIELD_DEFAULT_LOG2N 20   // m = 32 batch items: transforms up to 2^20 bits
-#define M64_MAX_LOG2N 37               // m = 64 field bound: n <= (m/2) 2^(m/2) = 2^37
+using fpmul_plan::M64_MAX_LOG2N;               // m = 64 field bound: n <= (m/2) 2^(m/2) = 2^37
 #define LARGE_FIELD_DEFAULT_LOG2N 38   // m = 128 from the first transform m = 64 cannot take
 
 struct PStepTable;
@@ -428,19 +429,8 @@ static int check_dev_ptr(const void *p, const char *name)
     return 0;
 }
 
-static uint64_t next_pow2(uint64_t x)
-{
-    uint64_t p = 1;
-    while (p < x) p <<= 1;
-    return p;
-}
-
-static int ilog2(uint64_t x)
-{
-    int r = 0;
-    while ((1ull << r) < x) ++r;
-    return r;
-}
+using fpmul_plan::ilog2;
+using fpmul_plan::next_pow2;
 
 // Step lists of BasisCvt(2^k) for every k <= PSTEP_MAX_LOG2N, in one device
 // table built once per context: entries first[k] .. first[k] + count[k] - 1,
@@ -813,15 +803,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
     return 0;
 }
 
-// log2 of the transform length of a product of lc bits: n = max(64,
-// 2^ceil(log2 lc)), except that a 2^21-bit transform is taken as 2^22 bits,
-// which the fused path (from 2^22) computes faster than the per-step path
-// (0.28 against 0.50 ms); any n >= lc gives the same product
-static int product_log2n(uint64_t lc)
-{
-    const int k = std::max(6, ilog2(lc));
-    return k == 21 ? 22 : k;
-}
+using fpmul_plan::product_log2n;
 
 static int transform_log2(uint64_t len_a, uint64_t len_b) { return product_log2n(len_a + len_b - 1); }
 
@@ -851,7 +833,7 @@ struct DeviceGuard {
 // fast BasisCvt + Encode / Decode + iBasisCvt (k_basiscvt.h), 2^22 <= n <= 2^31
 // ---------------------------------------------------------------------------
 
-static bool fast_path(int log2n) { return log2n >= 22 && log2n <= 31; }
+using fpmul_plan::fast_path;
 
 static BcSteps make_steps(uint64_t N)
 {
@@ -877,22 +859,9 @@ static BcSteps make_steps(uint64_t N)
     return st;
 }
 
-// words per skewed row: tau + R bits, the extension rounded up to 64 words
-static int bc_ew(int lgR)
-{
-    uint64_t R = 1ull << lgR, ext = (R + 63) / 64;
-    ext = (ext + 63) / 64 * 64;
-    return (int)(BC_TAU_WORDS + ext);
-}
-
-// workspace words one buffer needs for transform length 2^log2n
-static uint64_t ws_words_for(int log2n)
-{
-    uint64_t nw = 1ull << (log2n - 6);
-    if (!fast_path(log2n)) return nw;
-    const int lgR = log2n - 16;
-    return std::max<uint64_t>(nw, (1ull << lgR) * (uint64_t)bc_ew(lgR));
-}
+using fpmul_plan::bc_ew;
+using fpmul_plan::ws_words_for;
+static_assert(fpmul_plan::TAU_WORDS == BC_TAU_WORDS, "row length of the fused BasisCvt");
 
 static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t *in, uint64_t len, int lgR, int EW,
                     bool skew_first)
@@ -1103,10 +1072,10 @@ static int product128_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, 
                            uint64_t *out, hipStream_t s)
 {
     const uint64_t lc = len_a + len_b - 1;
-    const int log2n = std::max(7, ilog2(lc)), l = log2n - 7;
+    const int log2n = fpmul_plan::product128_log2n(lc), l = log2n - 7;
     const uint64_t nw = 1ull << (log2n - 6);
-    int rc = ensure_ws(ctx, nw);
-    if (rc) return rc;
+    if (ctx->ws_words < nw) return fail(POLYMUL_EIO, "m = 128 product: workspace smaller than its transform");
+    int rc;
     if ((rc = ensure_tables128(ctx))) return rc;
     uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2];
     if ((rc = run_encode128(ctx, a, len_a, log2n, W0, W2, s))) return rc;
@@ -1128,10 +1097,10 @@ static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, con
 {
     const uint64_t lc = len_a + len_b - 1;
     const int log2n = transform_log2(len_a, len_b);
-    if (log2n >= ctx->large_field_log2n || log2n > M64_MAX_LOG2N)
-        return product128_body(ctx, a, len_a, b, len_b, out, s);
-    int rc = ensure_ws(ctx, ws_words_for(log2n));
+    // the workspace of either route, sized by the rule the server's admission uses too
+    int rc = ensure_ws(ctx, fpmul_plan::product_ws_words(len_a, len_b, ctx->large_field_log2n));
     if (rc) return rc;
+    if (fpmul_plan::routes_m128(lc, ctx->large_field_log2n)) return product128_body(ctx, a, len_a, b, len_b, out, s);
     if ((rc = set_lds_limits())) return rc;
     uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2], *W3 = ctx->ws[3];
     uint64_t *pa, *pb;

@@ -48,10 +48,7 @@ uint64_t srv_now_ns(std::chrono::steady_clock::time_point t0)
 }
 
 // device bytes of one single-product launch (the four workspace buffers)
-uint64_t srv_single_bytes(uint64_t lc)
-{
-    return 4 * ws_words_for(product_log2n(lc)) * 8;
-}
+uint64_t srv_single_bytes(uint64_t lc) { return fpmul_plan::single_launch_bytes(lc); }
 
 }  // namespace
 
@@ -77,7 +74,9 @@ static void srv_finish(polymul_server *S, SrvSlot &slot, int rc)
 {
     const uint64_t t = srv_now_ns(S->t0);
     for (const auto &r : slot.plan.reqs) {
-        SrvTicket &tk = S->tickets[r.ticket];
+        auto it = S->tickets.find(r.ticket);   // a ticket is only released once it is done
+        if (it == S->tickets.end()) continue;
+        SrvTicket &tk = it->second;
         tk.state = 2;
         tk.rc = rc;
         if (rc) tk.err = g_err;
@@ -99,8 +98,13 @@ static int srv_launch(polymul_server *S, SrvSlot &slot)
     int rc;
     if (!p.batch) {
         const fpmul_srv::Req &r = p.reqs[0];
-        // the transform product_body will use, so that the borrowed buffers fit
-        const uint64_t words = ws_words_for(product_log2n(fpmul_srv::product_bits(r)));
+        // four buffers of the words product_body asks for; never launch on a
+        // reservation smaller than that (plan.h sizes both, and the CPU check
+        // of tests/native/plan_check.cpp holds them together)
+        const uint64_t words = fpmul_plan::product_ws_words(r.la, r.lb, v->large_field_log2n);
+        if (4 * words * 8 > p.bytes)
+            return fail(POLYMUL_EIO, "server reservation of " + std::to_string(p.bytes) + " bytes is smaller than the " +
+                                         std::to_string(4 * words * 8) + " bytes of the product's workspace");
         for (int k = 0; k < 4; ++k) v->ws[k] = reinterpret_cast<uint64_t *>(base + (size_t)k * words * 8);
         v->ws_words = words;
         rc = product_body(v, r.a, r.la, r.b, r.lb, r.out, s);
@@ -145,9 +149,10 @@ static void srv_loop(polymul_server *S)
             S->busy++;
             const uint64_t t = srv_now_ns(S->t0);
             for (const auto &r : slot.plan.reqs) {
-                SrvTicket &tk = S->tickets[r.ticket];
-                tk.state = 1;
-                tk.t_start = t;
+                auto it = S->tickets.find(r.ticket);
+                if (it == S->tickets.end()) continue;
+                it->second.state = 1;
+                it->second.t_start = t;
             }
             const int rc = srv_launch(S, slot);
             if (rc) {
@@ -316,16 +321,36 @@ int polymul_poll(polymul_server *S, uint64_t ticket, int *done)
     return 0;
 }
 
-int polymul_wait(polymul_server *S, uint64_t ticket)
+// wait for a ticket, read its times, and forget it
+static int srv_wait_release(polymul_server *S, uint64_t ticket, uint64_t *submit_ns, uint64_t *start_ns,
+                            uint64_t *done_ns)
 {
-    if (!S) return fail(POLYMUL_EINVAL, "server is null");
     std::unique_lock<std::mutex> lk(S->m);
     auto it = S->tickets.find(ticket);
     if (it == S->tickets.end()) return fail(POLYMUL_EINVAL, "unknown ticket");
-    S->cv_done.wait(lk, [&] { return S->tickets[ticket].state == 2; });
-    const SrvTicket &tk = S->tickets[ticket];
+    // a rehash by another submit invalidates iterators but not the element's address
+    const SrvTicket *tp = &it->second;
+    S->cv_done.wait(lk, [tp] { return tp->state == 2; });
+    const SrvTicket tk = *tp;
+    S->tickets.erase(ticket);
+    if (submit_ns) *submit_ns = tk.t_submit;
+    if (start_ns) *start_ns = tk.t_start;
+    if (done_ns) *done_ns = tk.t_done;
     if (tk.rc) return fail(tk.rc, tk.err);
     return 0;
+}
+
+int polymul_wait(polymul_server *S, uint64_t ticket)
+{
+    if (!S) return fail(POLYMUL_EINVAL, "server is null");
+    return srv_wait_release(S, ticket, nullptr, nullptr, nullptr);
+}
+
+int polymul_wait_times(polymul_server *S, uint64_t ticket, uint64_t *submit_ns, uint64_t *start_ns,
+                       uint64_t *done_ns)
+{
+    if (!S) return fail(POLYMUL_EINVAL, "server is null");
+    return srv_wait_release(S, ticket, submit_ns, start_ns, done_ns);
 }
 
 int polymul_ticket_times(polymul_server *S, uint64_t ticket, uint64_t *submit_ns, uint64_t *start_ns,
@@ -338,6 +363,14 @@ int polymul_ticket_times(polymul_server *S, uint64_t ticket, uint64_t *submit_ns
     if (submit_ns) *submit_ns = it->second.t_submit;
     if (start_ns) *start_ns = it->second.t_start;
     if (done_ns) *done_ns = it->second.t_done;
+    return 0;
+}
+
+int polymul_server_tickets(polymul_server *S, uint64_t *count)
+{
+    if (!S || !count) return fail(POLYMUL_EINVAL, "server or count pointer is null");
+    std::lock_guard<std::mutex> lk(S->m);
+    *count = S->tickets.size();
     return 0;
 }
 

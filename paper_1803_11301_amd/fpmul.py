@@ -35,7 +35,9 @@ SIGNATURES = {
     "polymul_submit": (_I, [_V, _P, _U64, _P, _U64, _P, ctypes.POINTER(_U64)]),
     "polymul_poll": (_I, [_V, _U64, ctypes.POINTER(_I)]),
     "polymul_wait": (_I, [_V, _U64]),
+    "polymul_wait_times": (_I, [_V, _U64, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
     "polymul_ticket_times": (_I, [_V, _U64, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
+    "polymul_server_tickets": (_I, [_V, ctypes.POINTER(_U64)]),
     "polymul_addfft": (_I, [_V, _P, _U64, _I, _P, _V]),
     "polymul_iaddfft": (_I, [_V, _P, _I, _P, _U64, _V]),
     "polymul_pointwise": (_I, [_V, _P, _P, _I, _P, _V]),
@@ -259,10 +261,21 @@ class Server:
         return bool(d.value)
 
     def wait(self, ticket: int):
-        _check(lib().polymul_wait(self.handle, ticket))
+        """Block until the ticket is done and release it; returns its
+        (submit, launch, done) times in ns since the server was created."""
+        s, st, d = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().polymul_wait_times(self.handle, ticket, ctypes.byref(s), ctypes.byref(st), ctypes.byref(d)))
+        return s.value, st.value, d.value
+
+    def outstanding(self) -> int:
+        """Tickets submitted and not yet released by wait."""
+        n = ctypes.c_uint64()
+        _check(lib().polymul_server_tickets(self.handle, ctypes.byref(n)))
+        return n.value
 
     def times(self, ticket: int):
-        """(submit, launch, done) in ns since the server was created."""
+        """(submit, launch, done) in ns since the server was created, for a
+        ticket not yet released by wait."""
         s, st, d = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
         _check(lib().polymul_ticket_times(self.handle, ticket, ctypes.byref(s), ctypes.byref(st), ctypes.byref(d)))
         return s.value, st.value, d.value

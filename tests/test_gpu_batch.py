@@ -1,10 +1,9 @@
 """GPU parity of polymul_batch: every product of a batch against the CPU oracle.
 
-Small batches are compared word for word.  The full 4096-product mix
-(operand lengths log-uniform in [2^10, 2^20] bits, 10% sparse) is compared
-word for word for every product up to 2^15-bit operands and, for the rest, on
-sampled output words computed one by one from the definition plus the
-evaluation identity A(z) B(z) = C(z) at a random point of GF(2^64).
+Every product of every batch is compared word for word with the oracle,
+including all 4096 products of the full mix (operand lengths log-uniform in
+[2^10, 2^20] bits, 10% sparse), whose oracle products run on a pool of host
+threads.
 """
 import random
 import sys
@@ -41,6 +40,14 @@ def dev64(arr):
 
 
 SENTINEL = np.uint64(0xA5A5A5A5A5A5A5A5)
+
+
+def oracle_products(As, las, Bs, lbs):
+    """The oracle's product of every pair, on up to 16 host threads (the oracle
+    call leaves Python, so the threads run in parallel)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        return list(ex.map(lambda k: O.polymul(As[k], las[k], Bs[k], lbs[k]), range(len(As))))
 
 
 def run_batch(ctx, As, Bs, las, lbs, max_bits=None, with_status=True):
@@ -156,23 +163,9 @@ def test_full_mixed_batch_4096(ctx):
     lbs = [it.len_b for it in plan]
     outs, st = run_batch(ctx, list(As), list(Bs), las, lbs, max_bits=1 << 21)
     assert np.all(st == 0)
-    rng = random.Random(4096)
-    exact = 0
+    refs = oracle_products(As, las, Bs, lbs)
     for k, it in enumerate(plan):
-        la, lb = it.len_a, it.len_b
-        n = O.nwords(la + lb - 1)
-        if la <= (1 << 15) and lb <= (1 << 15):
-            ref = O.polymul(As[k], la, Bs[k], lb)
-            assert np.array_equal(outs[k], ref), (k, la, lb)
-            exact += 1
-            continue
-        idx = np.array(sorted({0, n - 1, n // 2} | {rng.randrange(n) for _ in range(4)}), dtype=np.uint64)
-        ref = O.product_words(As[k], la, Bs[k], lb, idx)
-        assert np.array_equal(outs[k][idx.astype(np.int64)], ref), (k, la, lb)
-        z = rng.getrandbits(64) | 1
-        lhs = O.gf64_mul(O.eval_at(As[k], la, z), O.eval_at(Bs[k], lb, z))
-        assert lhs == O.eval_at(outs[k], la + lb - 1, z), (k, la, lb)
-    assert exact > 600
+        assert np.array_equal(outs[k], refs[k]), (k, it.len_a, it.len_b, it.sparse)
 
 
 @pytest.mark.parametrize("limit", [0, 12, 20])
@@ -194,15 +187,9 @@ def test_small_field_limit_changes_field_not_products(ctx, limit):
     finally:
         ctx.set_small_field(20)
     assert (st == 0).all()
-    for (la, lb), a, b, got in zip(lens, As, Bs, outs):
-        n = O.nwords(la + lb - 1)
-        if la + lb <= (1 << 17):
-            assert np.array_equal(got[:n], O.polymul(a, la, b, lb)), (la, lb)
-        else:
-            idx = np.array(sorted({0, n - 1, n // 2} | {rng.randrange(n) for _ in range(5)}), dtype=np.uint64)
-            assert np.array_equal(got[idx.astype(np.int64)], O.product_words(a, la, b, lb, idx)), (la, lb)
-            z = rng.getrandbits(64) | 1
-            assert O.gf64_mul(O.eval_at(a, la, z), O.eval_at(b, lb, z)) == O.eval_at(got[:n], la + lb - 1, z)
+    refs = oracle_products(As, [x for x, _ in lens], Bs, [y for _, y in lens])
+    for (la, lb), got, ref in zip(lens, outs, refs):
+        assert np.array_equal(got[: O.nwords(la + lb - 1)], ref), (la, lb)
 
 
 def test_small_field_limit_rejects_out_of_range(ctx):

@@ -236,18 +236,22 @@ def test_m128_beyond_the_m64_bound():
     _full_size_case((1 << 37) + 1, 4096, 0x5EED0038)
 
 
-def test_m128_balanced_2e37_end_words():
-    """The bench shape, 2^37 x 2^37 bits over GF(2^128): the lowest and highest
-    output words, which the definition computes from the lowest (highest)
-    words of A and B alone."""
+def test_m128_balanced_2e37_words():
+    """The bench shape, 2^37 x 2^37 bits over GF(2^128): the 16 lowest and 16
+    highest output words (the definition computes them from the lowest or
+    highest words of A and B alone) and 8 words from the middle of the
+    product, each of which collects about 2^31 word products of the whole of
+    A and B (the operands are copied to the host; the oracle computes those
+    words on parallel host threads)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     free, total = torch.cuda.mem_get_info()
     if free < (230 << 30):
         pytest.skip("needs 230 GiB of free device memory")
+    from concurrent.futures import ThreadPoolExecutor
     from paper_1803_11301_amd import fpmul
     L, seed = 1 << 37, 0x5EED0037
-    say("balanced 2^37 x 2^37 end words, seeds", hex(seed), hex(seed + 1))
+    say("balanced 2^37 x 2^37 end and middle words, seeds", hex(seed), hex(seed + 1))
     A = synth.dense_poly_device(seed, L, "cuda")
     B = synth.dense_poly_device(seed + 1, L, "cuda")
     torch.cuda.empty_cache()
@@ -267,6 +271,17 @@ def test_m128_balanced_2e37_end_words():
                 b_w = B[s0:].cpu().numpy().view(np.uint64)
                 ref = O.product_words(a_w, L - 64 * s0, b_w, L - 64 * s0, np.array([w - 2 * s0], np.uint64))[0]
             assert int(out[w].item()) & ((1 << 64) - 1) == int(ref), ("word", w)
+        rng = random.Random(37)
+        mid = sorted({nc // 2 - 2, nc // 2 - 1, nc // 2, nc // 2 + 1, nc // 4, 3 * nc // 4,
+                      rng.randrange(nc // 8, 7 * nc // 8), rng.randrange(nc // 8, 7 * nc // 8)})
+        got = [int(out[w].item()) & ((1 << 64) - 1) for w in mid]
+        del out
+        say("middle words", mid, "on the host")
+        a_h = A.cpu().numpy().view(np.uint64)
+        b_h = B.cpu().numpy().view(np.uint64)
+        with ThreadPoolExecutor(max_workers=len(mid)) as ex:
+            refs = list(ex.map(lambda w: int(O.product_words(a_h, L, b_h, L, np.array([w], np.uint64))[0]), mid))
+        assert got == refs, [w for w, g, r in zip(mid, got, refs) if g != r]
     finally:
         torch.cuda.synchronize()
         c.close()

@@ -237,18 +237,71 @@ def test_mid_config_exact(ctx):
     assert int(got[-1]) >> 62 == 1   # degree 2^25 - 2 is present
 
 
-@pytest.mark.parametrize("L", [1 << 25, (1 << 26) - 5, 1 << 30])
-def test_large_config_sampled(ctx, L):
-    say(L, "x", L, "sampled", hex(synth.SEED_LARGE))
+@pytest.mark.parametrize("L", [1 << 25, (1 << 26) - 5])
+def test_large_products_exact(ctx, L):
+    say(L, "x", L, "whole output against the oracle", hex(synth.SEED_LARGE))
     a, b = synth.single_pair(synth.SEED_LARGE, L)
     got = gpu_product(ctx, a, L, b, L)
+    assert np.array_equal(got, O.polymul(a, L, b, L, threads=16))
+
+
+def _golden_digest(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")) as f:
+        return json.load(f)[name]
+
+
+@pytest.mark.parametrize("name", ["small", "mid", "large"])
+def test_single_product_workloads_match_oracle_digest(ctx, name):
+    """The whole output of each single-product workload (2^16, 2^24 with the top
+    bit forced, and the 2^30 x 2^30-bit headline product) against the SHA-256
+    of the oracle's product, stored by tests/golden/make_digests.py.  The
+    product is unique (Prop. 2), so equal digests mean equal outputs; a few
+    words are also checked one by one from the definition, which names the
+    word that differs if the digest does not match."""
+    import hashlib
+    g = _golden_digest(name)
+    L = g["len_a"]
+    say(name, L, "x", L, "digest", g["seed_a"])
+    a, b = synth.single_pair(int(g["seed_a"], 16), L, top_bit=g["top_bit"])
+    got = gpu_product(ctx, a, L, b, L)
+    assert got.size == g["words"]
     rng = random.Random(30)
     nw = got.size
     idx = np.array(sorted({0, 1, nw // 2 - 1, nw // 2, nw - 1} | {rng.randrange(nw) for _ in range(11)}), np.uint64)
-    ref = O.product_words(a, L, b, L, idx)
-    assert np.array_equal(got[idx.astype(np.int64)], ref)
-    z = rng.getrandbits(64)
-    assert O.eval_at(got, 2 * L - 1, z) == O.gf64_mul(O.eval_at(a, L, z), O.eval_at(b, L, z))
+    assert np.array_equal(got[idx.astype(np.int64)], O.product_words(a, L, b, L, idx))
+    assert hashlib.sha256(np.ascontiguousarray(got, dtype="<u8").tobytes()).hexdigest() == g["sha256"]
+
+
+def test_synchronous_polymul_entry_point(ctx):
+    """polymul(): the synchronous product with the library-owned context of the
+    current device, on the 2^16 x 2^16 workload, and its argument errors."""
+    import ctypes
+    from paper_1803_11301_amd import fpmul
+    L = 1 << 16
+    say("polymul() 2^16 x 2^16", hex(synth.SEED_SMALL))
+    a, b = synth.single_pair(synth.SEED_SMALL, L)
+    ta, tb = dev(a), dev(b)
+    out = torch.full((O.nwords(2 * L - 1),), -1, dtype=torch.int64, device="cuda")
+    lib = fpmul.lib()
+    assert lib.polymul(ta.data_ptr(), L, tb.data_ptr(), L, out.data_ptr()) == 0
+    # synchronous: the result is there without a further synchronisation
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), O.polymul(a, L, b, L, threads=8))
+    assert lib.polymul(None, L, tb.data_ptr(), L, out.data_ptr()) == fpmul.EINVAL
+    assert "null" in lib.polymul_last_error().decode()
+    assert lib.polymul(ta.data_ptr(), L, tb.data_ptr(), L, None) == fpmul.EINVAL
+    # the output overlapping an input
+    assert lib.polymul(ta.data_ptr(), L, tb.data_ptr(), L, ta.data_ptr()) == fpmul.EINVAL
+    assert lib.polymul(ta.data_ptr(), L, tb.data_ptr(), L, tb.data_ptr() + 8) == fpmul.EINVAL
+    assert "overlap" in lib.polymul_last_error().decode()
+    # host memory is refused
+    hbuf = np.zeros(O.nwords(2 * L - 1), np.uint64)
+    assert lib.polymul(ta.data_ptr(), L, tb.data_ptr(), L, hbuf.ctypes.data_as(ctypes.c_void_p)) == fpmul.EINVAL
+    # an empty operand: nothing written, success
+    keep = out.clone()
+    assert lib.polymul(ta.data_ptr(), 0, tb.data_ptr(), L, out.data_ptr()) == 0
+    assert torch.equal(out, keep)
 
 
 # --------------------------------------------------------------------------

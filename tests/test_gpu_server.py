@@ -79,9 +79,9 @@ def test_mix_equals_alone_and_oracle(ctx):
     for (a, x, b, y), (ta, tb, out) in zip(ops, tensors):
         tickets.append(srv.submit(ta, x, tb, y, out))
     for tk in tickets:
-        srv.wait(tk)
-        s, st, d = srv.times(tk)
+        s, st, d = srv.wait(tk)
         assert s <= st <= d
+    assert srv.outstanding() == 0
     srv.close()
     for (a, x, b, y), (ta, tb, out) in zip(ops, tensors):
         n = O.nwords(x + y - 1)
@@ -116,7 +116,8 @@ def test_tight_budget_serialises_and_refuses_too_large(ctx):
     assert ei.value.code == fpmul.ENOMEM
     for tk in tickets:
         srv.wait(tk)
-        assert srv.poll(tk)
+        with pytest.raises(fpmul.FpmulError):   # released by wait
+            srv.poll(tk)
     srv.close()
     for a, x, b, y, ta, tb, out in ops:
         check_against_oracle(a, x, b, y, host(out, O.nwords(x + y - 1)), rng)
@@ -170,3 +171,27 @@ def test_policy_rejects_out_of_range(ctx):
     for limit, mb in [((1 << 22) + 1, 16), (1 << 20, 0), (1 << 20, 4097)]:
         with pytest.raises(fpmul.FpmulError):
             fpmul.Server(ctx, hbm_budget=16 << 20, slots=1, batch_limit_bits=limit, max_batch=mb)
+
+
+def test_tickets_are_released_by_wait(ctx):
+    """A long run of tickets (empty products, done at submit, and small real
+    ones) leaves nothing behind: every wait releases its ticket, after which
+    the ticket is unknown; polling keeps a ticket until its wait."""
+    from paper_1803_11301_amd import fpmul
+    srv = fpmul.Server(ctx, hbm_budget=64 << 20, slots=2)
+    say("ticket release, 5000 tickets")
+    t = torch.zeros(64, dtype=torch.int64, device="cuda")
+    outs = [torch.zeros(4, dtype=torch.int64, device="cuda") for _ in range(16)]
+    for rnd in range(250):
+        tks = [srv.submit(t, 0, t, 100, outs[0]) for _ in range(12)]
+        tks += [srv.submit(t[:2], 100, t[2:4], 90, outs[1 + k]) for k in range(8)]
+        assert srv.outstanding() == 20
+        srv.poll(tks[0])
+        for tk in tks:
+            srv.wait(tk)
+        assert srv.outstanding() == 0
+    with pytest.raises(fpmul.FpmulError):
+        srv.wait(tks[-1])
+    with pytest.raises(fpmul.FpmulError):
+        srv.times(tks[-1])
+    srv.close()
