@@ -183,7 +183,8 @@ def host_cpu() -> dict:
 # One full-size oracle run on the GPU machine's host: `python bench.py --cpu-full`
 # (profiles/cpu_oracle_2e30x2e30.md holds its output); the default bench run
 # times the bounded sample below and reports this measurement beside it.
-CPU_FULL_MEASURED = None
+CPU_FULL_MEASURED = {"ms": 104283.2, "threads": 16, "cpu_model": "AMD EPYC", "nproc": 16,
+                     "matches_stored_digest": True, "record": "profiles/cpu_oracle_2e30x2e30.md"}
 
 
 def cpu_baseline(log2_len: int, target_log2: int):
@@ -463,11 +464,10 @@ def bench_serve(ctx, count: int, warmup: int, rhos, sat_count: int, slots: int =
             if j == warmup:
                 t_meas = time.perf_counter()
             tks.append(srv.submit(*reqs[j]))
-        for tk in tks:
-            srv.wait(tk)
+        # wait releases each ticket and returns its (submit, launch, done) times
+        done = [srv.wait(tk) for tk in tks]
         wall = time.perf_counter() - (t_meas if t_meas is not None else t0)
-        timed = tks[warmup:]
-        tm = [srv.times(tk) for tk in timed]
+        tm = done[warmup:]
         lat = np.array([(d - s0) / 1e6 for s0, st, d in tm])
         queue = np.array([(st - s0) / 1e6 for s0, st, d in tm])
         row = {"rho": rho, "offered_per_s": round(rate, 1), "achieved_products_per_s": round(count / wall, 1),
