@@ -1,8 +1,8 @@
 """The paper's multiplication, step by step in plain Python (test infrastructure only).
 
-Follows Alg. 5 (FP_Polymul) with the steps in the paper's order and notation,
-for small n, so that the readings taken where the paper is ambiguous are
-checked against the plain product before any kernel relies on them:
+Computes the transform of Alg. 5 (FP_Polymul) from the definitions of its
+steps, for small n, so that the readings taken where the paper is ambiguous
+are checked against the plain product before any kernel relies on them:
 
 * BasisCvt (Alg. 1): the novelpoly coefficients, here by their definition
   (repeated division by s_i, ``cantor.to_novelpoly``);
@@ -11,11 +11,12 @@ checked against the plain product before any kernel relies on them:
   is the offset 2^(l+k) that the butterfly layer i = l+k of the virtual
   length-n transform pairs, and that layer multiplies by s_{l+k}(v_{l+m/2}) =
   v_{m/2-k} by Eq. 4.  The printed index m/2-1-k gives a singular matrix;
-* Butterfly (Alg. 2) at alpha = v_{l+m/2}, written recursively as printed:
-  h0 = p0 + s_i(alpha) p1, h1 = h0 + p1 (s_i(v_i) = 1), recurse on
-  (h0, alpha) and (h1, v_i + alpha);
-* pointwise products, iButterfly (the butterfly undone layer by layer),
-  Decode (R^{-1} per element, then the bits back to rows), iBasisCvt.
+* Butterfly (Alg. 2) at alpha = v_{l+m/2}: what it computes, the values of
+  sum_k f_k X_k at the points alpha + j, here evaluated directly from the
+  product form of the novel polynomial basis (``evaluate``);
+* pointwise products, then the inverse steps: the interpolation that undoes
+  that evaluation (Gauss-Jordan on its matrix, ``interpolate``), Decode
+  (R^{-1} per element, then the bits back to rows), iBasisCvt.
 """
 from __future__ import annotations
 
@@ -69,34 +70,55 @@ def gf2_inverse_rows(rows: list) -> list:
     return q
 
 
-def butterfly(g: list, alpha_c: int) -> list:
-    """Alg. 2: evaluations of sum_k g_k X_k at alpha + V_{log2 len}, alpha given in
-    Cantor coordinates; output j is the value at alpha XOR j."""
-    n = len(g)
-    if n == 1:
-        return [g[0]]
-    i = n.bit_length() - 2
-    h = n // 2
-    p0, p1 = g[:h], g[h:]
-    c = s_eval(i, alpha_c)
-    h0 = [p0[t] ^ F.mul(c, p1[t]) for t in range(h)]
-    h1 = [h0[t] ^ p1[t] for t in range(h)]
-    return butterfly(h0, alpha_c) + butterfly(h1, alpha_c ^ (1 << i))
+def x_basis_at(cvec: int, l: int) -> list:
+    """[X_k(x) for k < 2^l] at the point x with Cantor vector cvec.  The novel
+    polynomial basis is the product of the subspace polynomials over the set
+    bits of k (Sec. 2.3), each normalised by s_i(v_i), which is 1 for the
+    Cantor basis; so X_{k + 2^i} = X_k s_i for k < 2^i."""
+    vals = [1]
+    for i in range(l):
+        si = s_eval(i, cvec)
+        vals = vals + [F.mul(v, si) for v in vals]
+    return vals
 
 
-def ibutterfly(vals: list, alpha_c: int) -> list:
-    """Inverse of Alg. 2: undo the recursion from the bottom."""
+def evaluate(g: list, alpha_c: int) -> list:
+    """The values of sum_k g_k X_k at the points alpha + j, j < len(g) (alpha
+    given by its Cantor vector), each computed from the definition: what the
+    butterfly network of Alg. 2 produces, without its recursion."""
+    l = len(g).bit_length() - 1
+    out = []
+    for j in range(len(g)):
+        xs = x_basis_at(alpha_c ^ j, l)
+        v = 0
+        for gk, xk in zip(g, xs):
+            if gk:
+                v ^= F.mul(gk, xk)
+        out.append(v)
+    return out
+
+
+def _inv(a: int) -> int:
+    return F.power(a, (1 << M) - 2)
+
+
+def interpolate(vals: list, alpha_c: int) -> list:
+    """The coefficients g with evaluate(g, alpha_c) == vals: Gauss-Jordan
+    elimination on the matrix [X_k(alpha + j)] over GF(2^64), which is
+    invertible because the points are distinct and deg X_k = k."""
     n = len(vals)
-    if n == 1:
-        return [vals[0]]
-    i = n.bit_length() - 2
-    h = n // 2
-    h0 = ibutterfly(vals[:h], alpha_c)
-    h1 = ibutterfly(vals[h:], alpha_c ^ (1 << i))
-    c = s_eval(i, alpha_c)
-    p1 = [h0[t] ^ h1[t] for t in range(h)]
-    p0 = [h0[t] ^ F.mul(c, p1[t]) for t in range(h)]
-    return p0 + p1
+    l = n.bit_length() - 1
+    rows = [x_basis_at(alpha_c ^ j, l) + [vals[j]] for j in range(n)]
+    for col in range(n):
+        piv = next(r for r in range(col, n) if rows[r][col])
+        rows[col], rows[piv] = rows[piv], rows[col]
+        inv = _inv(rows[col][col])
+        rows[col] = [F.mul(inv, x) for x in rows[col]]
+        for r in range(n):
+            if r != col and rows[r][col]:
+                f = rows[r][col]
+                rows[r] = [x ^ F.mul(f, y) for x, y in zip(rows[r], rows[col])]
+    return [rows[k][n] for k in range(n)]
 
 
 def params(n: int):
@@ -138,13 +160,13 @@ def forward(a: int, n: int) -> list:
     l, n_p = params(n)
     g = F.to_novelpoly(a, n)
     f = encode(g, n)
-    return butterfly(f, 1 << (l + M // 2))
+    return evaluate(f, 1 << (l + M // 2))
 
 
 def inverse(vals: list, n: int) -> int:
     """iButterfly, Decode, iBasisCvt (Alg. 5, the inverse steps)."""
     l, n_p = params(n)
-    h = ibutterfly(vals, 1 << (l + M // 2))
+    h = interpolate(vals, 1 << (l + M // 2))
     return F.from_novelpoly(decode(h, n))
 
 

@@ -176,32 +176,56 @@ def inverse_rows(rows: list) -> list:
     return [basis[t][1] for t in range(n)]
 
 
-def butterfly(g: list, alpha_c: int) -> list:
-    """Alg. 2: values of sum_k g_k X_k at alpha + V_{log2 len} (alpha as a
-    Cantor vector); output j is the value at alpha XOR j."""
-    n = len(g)
-    if n == 1:
-        return [g[0]]
-    i = n.bit_length() - 2
-    h = n // 2
-    c = s_eval(i, alpha_c)
-    h0 = [g[t] ^ mul(c, g[h + t]) for t in range(h)]
-    h1 = [h0[t] ^ g[h + t] for t in range(h)]
-    return butterfly(h0, alpha_c) + butterfly(h1, alpha_c ^ (1 << i))
+def x_basis_at(cvec: int, l: int) -> list:
+    """[X_k(x) for k < 2^l] at the point with Cantor vector cvec: X_k is the
+    product of s_i over the set bits of k (s_i(v_i) = 1 for this basis)."""
+    vals = [1]
+    for i in range(l):
+        si = s_eval(i, cvec)
+        vals = vals + [mul(v, si) for v in vals]
+    return vals
 
 
-def ibutterfly(vals: list, alpha_c: int) -> list:
+def evaluate(g: list, alpha_c: int) -> list:
+    """Values of sum_k g_k X_k at alpha + j (alpha as a Cantor vector), from
+    the definition of the basis: what Alg. 2 computes."""
+    l = len(g).bit_length() - 1
+    out = []
+    for j in range(len(g)):
+        v = 0
+        for gk, xk in zip(g, x_basis_at(alpha_c ^ j, l)):
+            if gk:
+                v ^= mul(gk, xk)
+        out.append(v)
+    return out
+
+
+def _inv(a: int) -> int:
+    r, e = 1, (1 << M) - 2
+    while e:
+        if e & 1:
+            r = mul(r, a)
+        a = mul(a, a)
+        e >>= 1
+    return r
+
+
+def interpolate(vals: list, alpha_c: int) -> list:
+    """g with evaluate(g, alpha_c) == vals, by Gauss-Jordan elimination on
+    [X_k(alpha + j)] over GF(2^128) (distinct points, deg X_k = k)."""
     n = len(vals)
-    if n == 1:
-        return [vals[0]]
-    i = n.bit_length() - 2
-    h = n // 2
-    h0 = ibutterfly(vals[:h], alpha_c)
-    h1 = ibutterfly(vals[h:], alpha_c ^ (1 << i))
-    c = s_eval(i, alpha_c)
-    p1 = [h0[t] ^ h1[t] for t in range(h)]
-    p0 = [h0[t] ^ mul(c, p1[t]) for t in range(h)]
-    return p0 + p1
+    l = n.bit_length() - 1
+    rows = [x_basis_at(alpha_c ^ j, l) + [vals[j]] for j in range(n)]
+    for col in range(n):
+        piv = next(r for r in range(col, n) if rows[r][col])
+        rows[col], rows[piv] = rows[piv], rows[col]
+        inv = _inv(rows[col][col])
+        rows[col] = [mul(inv, x) for x in rows[col]]
+        for r in range(n):
+            if r != col and rows[r][col]:
+                f = rows[r][col]
+                rows[r] = [x ^ mul(f, y) for x, y in zip(rows[r], rows[col])]
+    return [rows[k][n] for k in range(n)]
 
 
 def params(n: int):
@@ -241,12 +265,12 @@ def decode(h: list, n: int) -> int:
 def forward(a: int, n: int) -> list:
     """BasisCvt, Encode, Butterfly at alpha = v_{l+64}."""
     l, _ = params(n)
-    return butterfly(encode(cantor.to_novelpoly(a, n), n), 1 << (l + M // 2))
+    return evaluate(encode(cantor.to_novelpoly(a, n), n), 1 << (l + M // 2))
 
 
 def inverse(vals: list, n: int) -> int:
     l, _ = params(n)
-    return cantor.from_novelpoly(decode(ibutterfly(vals, 1 << (l + M // 2)), n))
+    return cantor.from_novelpoly(decode(interpolate(vals, 1 << (l + M // 2)), n))
 
 
 def fp_polymul(a: int, len_a: int, b: int, len_b: int) -> int:

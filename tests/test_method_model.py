@@ -278,3 +278,33 @@ def test_m128_model_product_equals_oracle(la, lb):
     rng = random.Random(la * 77 + lb)
     a, b = rng.getrandbits(la), rng.getrandbits(lb)
     assert M128.fp_polymul(a, la, b, lb) == O.py_clmul(a, b)
+
+
+@pytest.mark.parametrize("i", [0, 1, 2, 3, 4])
+def test_butterfly_step_identity(i):
+    # One butterfly layer from the definitions alone: on a coset beta + V_{i+1}
+    # the values of g = g_lo + X_{2^i} g_hi (X_{k + 2^i} = X_k s_i for k < 2^i)
+    # are those of h0 = g_lo + s_i(beta) g_hi on beta + V_i and of
+    # h1 = h0 + g_hi on beta + v_i + V_i, because s_i is GF(2)-linear, vanishes
+    # on V_i and s_i(v_i) = 1 (Eq. 4).  Checked with the direct evaluation, at
+    # the base points the kernels use: alpha + b 2^(i+1), alpha = v_{l+32},
+    # whose multiplier is the element with Cantor vector 2^(32+l-i) + 2b.
+    rng = random.Random(100 + i)
+    l = i + 3
+    h = 1 << i
+    for b in range(1 << (l - i - 1)):
+        beta = (1 << (l + 32)) ^ (b << (i + 1))
+        g = [rng.getrandbits(64) for _ in range(2 * h)]
+        c = MM.s_eval(i, beta)
+        assert c == F.iota((1 << (32 + l - i)) ^ (2 * b))
+        h0 = [g[t] ^ F.mul(c, g[h + t]) for t in range(h)]
+        h1 = [h0[t] ^ g[h + t] for t in range(h)]
+        assert MM.evaluate(g, beta) == MM.evaluate(h0, beta) + MM.evaluate(h1, beta ^ (1 << i))
+
+
+def test_interpolate_inverts_evaluate():
+    rng = random.Random(7)
+    for l in range(0, 5):
+        g = [rng.getrandbits(64) for _ in range(1 << l)]
+        alpha = (1 << (l + 32)) ^ rng.getrandbits(l + 1) << l
+        assert MM.interpolate(MM.evaluate(g, alpha), alpha) == g
