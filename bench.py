@@ -483,13 +483,89 @@ def bench_serve(ctx, count: int, warmup: int, rhos, sat_count: int, slots: int =
             "batch_limit_bits": batch_limit_bits, "max_batch": max_batch, "hbm_budget_bytes": 8 << 30}
 
 
+def bench_serve_resident(ctx, count: int, warmup: int, rho: float, sat_count: int, n_res: int = 4,
+                         la: int = 1 << 20, max_bits: int = 1 << 22, slots: int = 8):
+    """Transform reuse in serving: every request multiplies one of n_res
+    operands of la bits (seed 0x5EED05E6 + k) by a B of log-uniform 2^12 ..
+    2^21 bits, submitted once as ordinary products (polymul_submit) and once
+    on the operands kept as forward transforms of max_bits bits
+    (polymul_submit_resident).  For each: the saturated rate over sat_count
+    requests submitted at once, then count timed requests (after warmup)
+    arriving open loop at rho times that rate; p50/p99 latency."""
+    import numpy as np
+    import torch
+    from paper_1803_11301_amd import fpmul, synth
+    rng = np.random.default_rng(0x5EED05E6)
+    total = sat_count + warmup + count
+    lbs = np.floor(np.exp2(12 + 9 * rng.random(total))).astype(np.int64)
+    which = rng.integers(0, n_res, total)
+    A = [torch.from_numpy(synth.dense_poly(0x5EED05E6 + k, la).view(np.int64)).cuda() for k in range(n_res)]
+    pool_bits = 1 << 22
+    pb = torch.from_numpy(synth.dense_poly(0x5EED05F0, pool_bits).view(np.int64)).cuda()
+    pw = pool_bits // 64
+    offb = rng.integers(0, pw - (1 << 21) // 64, total)
+    ow = (la + lbs - 1 + 63) // 64
+    outs = torch.empty(int(ow.sum()), dtype=torch.int64, device="cuda")
+    ooff = np.concatenate([[0], np.cumsum(ow)[:-1]])
+    res = [fpmul.Resident(ctx, A[k], la, max_bits) for k in range(n_res)]
+    torch.cuda.synchronize()
+    rows = {}
+    for mode in ("plain", "resident"):
+        srv = fpmul.Server(ctx, hbm_budget=8 << 30, slots=slots)
+
+        def submit(j):
+            b = pb.data_ptr() + 8 * int(offb[j])
+            o = outs.data_ptr() + 8 * int(ooff[j])
+            k = int(which[j])
+            if mode == "resident":
+                return srv.submit_resident(res[k], b, int(lbs[j]), o)
+            return srv.submit(A[k].data_ptr(), la, b, int(lbs[j]), o)
+        t0 = time.perf_counter()
+        tks = [submit(j) for j in range(sat_count)]
+        for tk in tks:
+            srv.wait(tk)
+        X = sat_count / (time.perf_counter() - t0)
+        rate = rho * X
+        arr = synth.serve_plan(warmup + count, rate)[0]
+        tks = []
+        t0 = time.perf_counter()
+        t_meas = None
+        for j in range(warmup + count):
+            due = t0 + float(arr[j])
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 2e-4:
+                    time.sleep((due - now) - 1e-4)
+            if j == warmup:
+                t_meas = time.perf_counter()
+            tks.append(submit(sat_count + j))
+        done = [srv.wait(tk) for tk in tks]
+        wall = time.perf_counter() - t_meas
+        lat = np.array([(d - s0) / 1e6 for s0, st, d in done[warmup:]])
+        rows[mode] = {"saturated_products_per_s": round(X, 1), "rho": rho, "offered_per_s": round(rate, 1),
+                      "achieved_products_per_s": round(count / wall, 1),
+                      "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 3)}
+        log(f"[bench] serve {mode}: saturated {X:.0f}/s; rho {rho}: p50 {rows[mode]['p50_ms']} ms, "
+            f"p99 {rows[mode]['p99_ms']} ms")
+        srv.close()
+    for r in res:
+        r.close()
+    return {"workload": f"{n_res} operands of {la} bits x B log-uniform 2^12..2^21 bits, seed 0x5eed05e6",
+            "resident_transform_bits": max_bits, "requests": count, "warmup": warmup,
+            "saturation_requests": sat_count, **rows}
+
+
 def bench_latency(ctx, names=("small", "mid"), runs=(100, 20)):
     """Latency of single products: the median over `runs` products of the
     time between HIP events recorded before and after each polymul_ex call
-    on the stream (operands resident)."""
+    on the stream (operands resident), and the same for a replay of the
+    product's captured launch chain (polymul_graph_launch)."""
     import numpy as np
     import torch
-    from paper_1803_11301_amd import synth
+    from paper_1803_11301_amd import fpmul, synth
     res = {}
     stream = torch.cuda.current_stream()
     for name, nrun in zip(names, runs):
@@ -511,7 +587,22 @@ def bench_latency(ctx, names=("small", "mid"), runs=(100, 20)):
         res[name] = {"workload": desc, "runs": nrun, "median_ms": round(float(np.median(ms)), 4),
                      "p10_ms": round(float(np.percentile(ms, 10)), 4),
                      "p90_ms": round(float(np.percentile(ms, 90)), 4)}
-        log(f"[bench] latency {name}: median {res[name]['median_ms']} ms over {nrun} products")
+        # the same product replayed from its captured launch chain
+        g = fpmul.Graph.product(ctx, a, L, b, L, out)
+        for _ in range(3):
+            g.launch(stream)
+        torch.cuda.synchronize()
+        for e0, e1 in ev:
+            e0.record(stream)
+            g.launch(stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        gms = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+        g.close()
+        res[name].update({"graph_median_ms": round(float(np.median(gms)), 4),
+                          "graph_p90_ms": round(float(np.percentile(gms, 90)), 4)})
+        log(f"[bench] latency {name}: median {res[name]['median_ms']} ms over {nrun} products, "
+            f"{res[name]['graph_median_ms']} ms replayed from the captured graph")
     return res
 
 
@@ -586,6 +677,9 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=500, help="untimed requests before them")
     ap.add_argument("--serve-rhos", default="0.5,0.8,0.95", help="offered loads as fractions of saturation")
     ap.add_argument("--serve-saturation", type=int, default=4000, help="requests submitted at once for X")
+    ap.add_argument("--no-resident", action="store_true", help="skip the transform-reuse serving measurement")
+    ap.add_argument("--no-tune", action="store_true", help="time the default schedule (no polymul_tune first)")
+    ap.add_argument("--tune-reps", type=int, default=3, help="timed products per schedule choice of the tuner")
     ap.add_argument("--no-latency", action="store_true", help="skip the 2^16 and 2^24 latency lines")
     ap.add_argument("--no-m128", action="store_true", help="skip the GF(2^128) measurement")
     ap.add_argument("--m128-steps", type=int, default=2)
@@ -634,6 +728,21 @@ def main():
     out = torch.empty((lc + 63) // 64, dtype=torch.int64, device=dev)
     ctx = fpmul.Context(0)
     stream = torch.cuda.current_stream()
+
+    lc0 = 2 * L - 1
+    log2n0 = max(6, (lc0 - 1).bit_length())
+    tune = None
+    if not args.no_tune and 22 <= log2n0 <= 31:
+        # the schedule the tuner picks for this transform length (layer split
+        # of the upper butterfly passes, row and zeta grids), as a user would
+        # run after tuning once
+        t0 = time.perf_counter()
+        rep = ctx.tune(log2n0, reps=args.tune_reps)
+        fields = dict(kv.split("=", 1) for kv in rep.replace("|", " ").split() if "=" in kv)
+        tune = {"log2n": log2n0, "seconds": round(time.perf_counter() - t0, 2),
+                "default_ms": float(fields.get("default_ms", "nan")), "tuned_ms": float(fields.get("tuned_ms", "nan")),
+                "tried": int(fields.get("tried", "0")), "schedule": ctx.schedule(log2n0)}
+        log(f"[bench] tuned: {rep}")
 
     log(f"[bench] {desc}; warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -699,6 +808,10 @@ def main():
         rhos = [float(x) for x in args.serve_rhos.split(",") if x]
         serve = bench_serve(ctx, args.serve_requests, args.serve_warmup, rhos, args.serve_saturation)
 
+    serve_resident = None
+    if not args.no_serve and not args.no_resident and args.workload == "large":
+        serve_resident = bench_serve_resident(ctx, 5000, 500, 0.8, 2000)
+
     m128 = None
     if not args.no_m128 and args.workload == "large":
         # 2^37-bit operands, a 2^38-bit output and four 2^38-bit workspace
@@ -741,6 +854,8 @@ def main():
         "latency": latency,
         "batch": batch,
         "serve": serve,
+        "serve_resident": serve_resident,
+        "tune": tune,
         "m128": m128,
         "cpu_baseline": cpu,
     }

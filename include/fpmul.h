@@ -161,6 +161,96 @@ int polymul_set_small_field(polymul_ctx *ctx, int max_log2n);
 int polymul_set_large_field(polymul_ctx *ctx, int min_log2n);
 
 /*
+ * Schedule tuner for the fused path (transforms of 2^22 .. 2^31 bits).  The
+ * product of one transform length can be computed under several schedules
+ * of the same kernels: the upper butterfly layers (those above the bottom
+ * pass of layers 0..6, Alg. 2) split into passes of up to 7 layers in any
+ * way whose lowest pass has at least 5 layers, and the row and zeta
+ * kernels of BasisCvt (Alg. 1) with 1, 2 or 4 and 4, 8 or 16 workgroups
+ * per CU.  polymul_tune times them on ctx's device for 2^log2n-bit
+ * transforms (operands of 2^(log2n-1) bits from a fixed generator; the path
+ * is data-oblivious), by coordinate descent from the default with `reps`
+ * timed products per choice (1..100), keeps the fastest in ctx, checks
+ * that it gives the default schedule's product word for word
+ * (POLYMUL_EIO otherwise, the previous choice kept), appends the line
+ * "<arch> cu=<CUs> log2n=<k> upper=<a,b,..> rows=<r> zeta=<z> ms=<t>" to
+ * cache_path when it is not NULL, and writes a one-line report (default
+ * and tuned ms) into report (may be NULL).  It allocates device memory for
+ * its operands and may grow ctx's workspace; it runs on a private stream
+ * and returns when done.  Tune before creating servers or graphs on ctx:
+ * they read ctx's schedules when they launch (graphs: when captured).
+ * polymul_tune_load applies every line of cache_path written for this
+ * device's architecture and CU count (a later line for the same length
+ * wins; malformed or invalid lines are skipped) and reports how many it
+ * applied.  polymul_tune_get writes the schedule ctx uses for 2^log2n-bit
+ * transforms as such a line (ms=0).
+ */
+int polymul_tune(polymul_ctx *ctx, int log2n, int reps, const char *cache_path, char *report,
+                 size_t report_len);
+int polymul_tune_load(polymul_ctx *ctx, const char *cache_path, int *applied);
+int polymul_tune_get(polymul_ctx *ctx, int log2n, char *buf, size_t buflen);
+
+/*
+ * Captured launch chains.  polymul_graph_create records the kernels of the
+ * product polymul_ex would run for these operands and this output (Alg. 5,
+ * FP_Polymul, over GF(2^64)) into a HIP graph, once, on a private stream;
+ * polymul_graph_launch replays it on `stream` (a hipStream_t; NULL = null
+ * stream) with one call instead of one launch per kernel.  The pointers are
+ * DEVICE memory owned by the caller and are baked into the graph: every
+ * replay reads a_bits and b_bits as they are when it runs and writes out.
+ * The graph owns its workspace (allocated by create, freed by destroy), so
+ * later calls on ctx do not disturb it; replays of one graph that overlap
+ * in time (two streams) race on that workspace.  Products of at most
+ * POLYMUL_M64_MAX_PRODUCT_BITS bits with two non-empty operands; errors as
+ * polymul_ex.  The kernels follow the same schedule as polymul_ex, so the
+ * result is the same product.
+ *
+ * polymul_batch_graph_create records the two launches of polymul_batch
+ * (the size-ordering plan and the persistent batch kernel) for these device
+ * arrays.  Lengths and offsets are read from the arrays on the device at
+ * every replay, so the caller may rewrite them between replays (count and
+ * max_product_bits stay fixed, every product at most max_product_bits).
+ *
+ * polymul_graph_destroy waits for the device to finish, then frees the
+ * graph and its workspace.
+ */
+typedef struct polymul_graph polymul_graph;
+int polymul_graph_create(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a,
+                         const uint64_t *b_bits, uint64_t len_b, uint64_t *out, polymul_graph **graph);
+int polymul_batch_graph_create(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool,
+                               const uint64_t *a_word_off, const uint64_t *len_a, const uint64_t *b_pool,
+                               const uint64_t *b_word_off, const uint64_t *len_b, uint64_t *out_pool,
+                               const uint64_t *out_word_off, uint64_t max_product_bits, int32_t *status,
+                               polymul_graph **graph);
+int polymul_graph_launch(polymul_graph *graph, void *stream);
+int polymul_graph_destroy(polymul_graph *graph);
+
+/*
+ * Resident operands (transform reuse).  A product's forward transform of A
+ * (BasisCvt, Encode, Butterfly of Alg. 5) depends on A and the transform
+ * length only, so an operand that is multiplied many times can keep it on the
+ * device: polymul_resident_create computes A's transform once at the length
+ * of the longest product it will serve, max_product_bits (len_a <=
+ * max_product_bits <= POLYMUL_M64_MAX_PRODUCT_BITS), into device memory
+ * owned by the resident object (2^ceil(log2 max_product_bits) bits; the
+ * call returns when it is done; a_bits may be reused afterwards).
+ * polymul_resident_mul computes C = A * B for any B with len_a + len_b - 1 <=
+ * max_product_bits, stream-ordered like polymul_ex, running only B's
+ * forward transform, the pointwise products and the inverse steps (same
+ * output rules as polymul).  polymul_submit_resident queues the same
+ * product on a server (always as a launch of its own; see below).
+ * polymul_resident_destroy waits for the device and frees the transform.
+ * Errors: POLYMUL_EINVAL for null pointers, lengths out of range or an
+ * operand on another device, POLYMUL_ENOMEM when the transform does not fit.
+ */
+typedef struct polymul_resident polymul_resident;
+int polymul_resident_create(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a,
+                            uint64_t max_product_bits, polymul_resident **res);
+int polymul_resident_destroy(polymul_resident *res);
+int polymul_resident_mul(polymul_ctx *ctx, const polymul_resident *res, const uint64_t *b_bits,
+                         uint64_t len_b, uint64_t *out, void *stream);
+
+/*
  * Product server: continuous batching of product requests on one GPU.
  *
  * polymul_server_create -- a server on `ctx`'s device (ctx must outlive it).
@@ -178,6 +268,11 @@ int polymul_set_large_field(polymul_ctx *ctx, int min_log2n);
  *   device pointers the caller keeps alive and unmodified until the ticket is
  *   done; the server copies nothing) and returns its ticket.  A product whose
  *   workspace exceeds the whole arena is refused with POLYMUL_ENOMEM.
+ * polymul_submit_resident -- queues C = A * B for a resident operand A
+ *   (polymul_resident_create on the server's device; it must outlive the
+ *   ticket): only B's transform is computed.  It runs as a launch of its own
+ *   on the workspace of the resident transform length; same rules as
+ *   polymul_submit otherwise.
  * polymul_poll -- *done = 1 once the ticket's product is in out; then returns
  *   the product's result code (0, or the error of its launch).  Polling does
  *   not release the ticket.
@@ -209,6 +304,8 @@ int polymul_server_destroy(polymul_server *srv);
 int polymul_server_set_policy(polymul_server *srv, uint64_t batch_limit_bits, uint32_t max_batch);
 int polymul_submit(polymul_server *srv, const uint64_t *a_bits, uint64_t len_a, const uint64_t *b_bits,
                    uint64_t len_b, uint64_t *out, uint64_t *ticket);
+int polymul_submit_resident(polymul_server *srv, const polymul_resident *res, const uint64_t *b_bits,
+                            uint64_t len_b, uint64_t *out, uint64_t *ticket);
 int polymul_poll(polymul_server *srv, uint64_t ticket, int *done);
 int polymul_wait(polymul_server *srv, uint64_t ticket);
 int polymul_wait_times(polymul_server *srv, uint64_t ticket, uint64_t *submit_ns, uint64_t *start_ns,

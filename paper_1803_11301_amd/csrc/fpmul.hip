@@ -322,6 +322,10 @@ struct polymul_ctx {
     int large_field_log2n = LARGE_FIELD_DEFAULT_LOG2N;
     DevTables128 *tables128 = nullptr;   // built on the first m = 128 product
     PStepTable *psteps = nullptr;        // BasisCvt step lists of the per-step path
+    // schedules of the fused path chosen by polymul_tune (or loaded from its
+    // cache), by log2 of the transform length; views point at their parent's
+    std::map<int, fpmul_plan::Schedule> tuned_own;
+    const std::map<int, fpmul_plan::Schedule> *tuned = &tuned_own;
     // per-kernel timing with HIP events on the launch stream (off by default)
     bool prof = false;
     std::vector<ProfRec> prof_live;       // recorded, not yet read
@@ -646,6 +650,30 @@ static std::vector<std::pair<int, int>> upper_groups(int l, int R)
     return g;
 }
 
+// the schedule of transforms of 2^log2n bits: the tuned one, else the default
+static fpmul_plan::Schedule sched_of(const polymul_ctx *ctx, int log2n)
+{
+    if (ctx->tuned) {
+        auto it = ctx->tuned->find(log2n);
+        if (it != ctx->tuned->end()) return it->second;
+    }
+    return fpmul_plan::Schedule();
+}
+
+// the resident-table upper passes of a 2^l-value transform as (i_lo, k), lowest first
+static std::vector<std::pair<int, int>> upper_groups_of(const polymul_ctx *ctx, int l)
+{
+    const fpmul_plan::Schedule sc = sched_of(ctx, l + 6);
+    if (sc.upper.empty() || !fpmul_plan::upper_valid(l, sc.upper)) return upper_groups(l, B3_BOT_LAYERS);
+    std::vector<std::pair<int, int>> g;
+    int lo = B3_BOT_LAYERS;
+    for (int k : sc.upper) {
+        g.push_back({lo, k});
+        lo += k;
+    }
+    return g;
+}
+
 static int set_lds_limits()
 {
     static std::mutex mu;
@@ -734,7 +762,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         // the layers above the bottom pass split evenly into passes of at most
         // 7; the lowest starts at layer 7 and needs K >= 5 (i_lo >= 12 - K),
         // which every split for l >= 20 gives
-        const auto groups = upper_groups(l, B3_BOT_LAYERS);
+        const auto groups = upper_groups_of(ctx, l);
         int rc;
         if (mode != BF_INV) {
             for (auto it = groups.rbegin(); it != groups.rend(); ++it)
@@ -864,7 +892,7 @@ using fpmul_plan::ws_words_for;
 static_assert(fpmul_plan::TAU_WORDS == BC_TAU_WORDS, "row length of the fused BasisCvt");
 
 static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t *in, uint64_t len, int lgR, int EW,
-                    bool skew_first)
+                    bool skew_first, int zeta_mult)
 {
     const int nb1 = std::min(lgR, 8), nb2 = lgR - nb1;
     for (int pass = 0; pass < 2; ++pass) {
@@ -875,13 +903,13 @@ static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t
         const int lgWc = std::min(6, 12 - nb);
         if ((1 << (nb + lgWc)) > BC_ZETA_LDS) return fail(POLYMUL_EINVAL, "zeta tile exceeds LDS");
         const uint64_t tiles = (1ull << (lgR - nb)) * (uint64_t)(EW >> lgWc);
-        const unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->num_cu * 8);
+        const unsigned grid = (unsigned)std::min<uint64_t>(tiles, (uint64_t)ctx->num_cu * zeta_mult);
         const char *name = skew_first ? "basiscvt_zeta" : "ibasiscvt_zeta";
         const int skew = (pass == 0 && skew_first && in) ? 1 : 0;
         if (nb >= 6 && nb <= 8 && (EW % (1 << (12 - nb))) == 0) {
             // register-resident tiles of 2^12 words
             const uint64_t rt = (1ull << (lgR - nb)) * (uint64_t)(EW >> (12 - nb));
-            const unsigned g = (unsigned)std::min<uint64_t>(rt, (uint64_t)ctx->num_cu * 8);
+            const unsigned g = (unsigned)std::min<uint64_t>(rt, (uint64_t)ctx->num_cu * zeta_mult);
             if (nb == 8)
                 KLAUNCH(ctx, s, name, k_bc_zeta_r<8>, g, 256, X, in, len, lgR, EW, b0, skew);
             else if (nb == 7)
@@ -903,13 +931,14 @@ static int run_encode_fast(polymul_ctx *ctx, const uint64_t *a, uint64_t len, in
     const uint64_t N = next_pow2(std::max<uint64_t>(len, 1));
     const int lgR = N <= (1ull << 16) ? 0 : ilog2(N) - 16;
     const int EW = bc_ew(lgR);
+    const fpmul_plan::Schedule sc = sched_of(ctx, log2n);
     if (lgR >= 1) {
-        int rc = run_zeta(ctx, s, X, a, len, lgR, EW, true);
+        int rc = run_zeta(ctx, s, X, a, len, lgR, EW, true, sc.zeta_mult);
         if (rc) return rc;
     }
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
     const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / BC_ROWS,
-                                                                              (uint64_t)ctx->num_cu * 2));
+                                                                              (uint64_t)ctx->num_cu * sc.rows_mult));
     KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_ROW_THREADS, X, a, len, lgR, EW, Y, inner);
     KLAUNCH(ctx, s, "basiscvt_outer_encode", k_bc_outer_encode, (unsigned)std::min(BC_TAU_WORDS, ctx->num_cu),
             BC_COL_THREADS, Y, lgR, l, vals, outer, ctx->tables);
@@ -921,13 +950,14 @@ static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, ui
                            uint64_t *X, uint64_t *Y, hipStream_t s)
 {
     const int l = log2n - 6, lgR = log2n - 16, EW = bc_ew(lgR);
+    const fpmul_plan::Schedule sc = sched_of(ctx, log2n);
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
     KLAUNCH(ctx, s, "decode_outer", k_bc_decode_outer, (unsigned)std::min(2 * BC_TAU_WORDS, ctx->num_cu), BC_COL_THREADS,
             vals, lgR, l, reinterpret_cast<uint32_t *>(Y), outer, ctx->tables);
-    const unsigned grows = (unsigned)std::min<uint64_t>((1ull << lgR) / BC_ROWS, (uint64_t)ctx->num_cu * 2);
+    const unsigned grows = (unsigned)std::min<uint64_t>((1ull << lgR) / BC_ROWS, (uint64_t)ctx->num_cu * sc.rows_mult);
     KLAUNCH(ctx, s, "ibasiscvt_rows", k_bc_inv_rows, grows, BC_ROW_THREADS, reinterpret_cast<const uint32_t *>(Y), lgR,
             EW, X, inner);
-    int rc = run_zeta(ctx, s, X, nullptr, 0, lgR, EW, false);
+    int rc = run_zeta(ctx, s, X, nullptr, 0, lgR, EW, false, sc.zeta_mult);
     if (rc) return rc;
     KLAUNCH(ctx, s, "ibasiscvt_store", k_bc_inv_store, (unsigned)std::min<uint64_t>(1ull << lgR,
                                                                                     (uint64_t)ctx->num_cu * 4),
@@ -1174,6 +1204,42 @@ static int iaddfft_body(polymul_ctx *ctx, const uint64_t *values, int log2n, uin
     return 0;
 }
 
+// C = A B (lc bits) from A's forward transform fa of 2^log2n bits (f2:
+// transform reuse): B's BasisCvt, Encode and Butterfly, the pointwise
+// products with fa, then the inverse steps (Alg. 5 with A's forward steps
+// already done; any n >= lc gives the same product)
+static int resident_body(polymul_ctx *ctx, const uint64_t *fa, int log2n, const uint64_t *b, uint64_t len_b,
+                         uint64_t *out, uint64_t lc, hipStream_t s)
+{
+    const uint64_t nw = 1ull << (log2n - 6);
+    int rc = ensure_ws(ctx, ws_words_for(log2n));
+    if (rc) return rc;
+    if ((rc = set_lds_limits())) return rc;
+    uint64_t *cur = ctx->ws[0], *spare = ctx->ws[1];
+    const uint64_t N = next_pow2(std::max<uint64_t>(len_b, 1));
+    if (fast_path(log2n) && N <= (1ull << 30)) {
+        if ((rc = run_encode_fast(ctx, b, len_b, log2n, cur, ctx->ws[2], ctx->ws[3], s))) return rc;
+    } else {
+        if ((rc = run_encode_in(ctx, b, len_b, log2n, cur, spare, s))) return rc;
+    }
+    if ((rc = run_butterflies(ctx, BF_FWD, cur, nullptr, log2n - 6, s))) return rc;
+    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu * 2),
+            1024, cur, fa, nw, ctx->tables);
+    if ((rc = run_butterflies(ctx, BF_INV, cur, nullptr, log2n - 6, s))) return rc;
+    if (fast_path(log2n)) return run_decode_fast(ctx, cur, log2n, out, lc, ctx->ws[2], ctx->ws[3], s);
+    if ((rc = run_decode_out(ctx, log2n, cur, spare, s))) return rc;
+    KLAUNCH(ctx, s, "store", k_store_mask, grid_for((lc + 63) / 64, 256), 256, cur, lc, out);
+    return 0;
+}
+
+// an operand kept on the device as its forward transform (polymul_resident_*)
+struct polymul_resident {
+    int device = 0;
+    int log2n = 0;
+    uint64_t len_a = 0;
+    uint64_t *vals = nullptr;   // 2^(log2n - 6) transform values
+};
+
 static int basiscvt_body(polymul_ctx *ctx, const uint64_t *in, uint64_t len, int log2n, int inverse, uint64_t *out,
                          hipStream_t s)
 {
@@ -1383,6 +1449,129 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
 }
 
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// captured launch chains (polymul_graph_*): the kernels of one product (or of
+// one batch) recorded once into a HIP graph on a private stream and replayed
+// on the caller's stream.  A graph owns the workspaces its kernels were
+// recorded with, so nothing the context later grows or frees can move them.
+// ---------------------------------------------------------------------------
+
+struct polymul_graph {
+    polymul_ctx view;        // the parent's tables, this graph's workspaces (borrowed)
+    void *mem = nullptr;     // 4 product workspaces, then the batch workspace
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+static void graph_free(polymul_graph *g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->mem) (void)hipFree(g->mem);
+    delete g;
+}
+
+// a graph whose view shares ctx's tables and owns ws_words x 4 + bws_bytes of workspace
+static int graph_new(polymul_ctx *ctx, uint64_t ws_words, size_t bws_bytes, polymul_graph **out)
+{
+    std::unique_ptr<polymul_graph> g(new polymul_graph());
+    g->device = ctx->device;
+    polymul_ctx &v = g->view;
+    v.device = ctx->device;
+    v.tables = ctx->tables;
+    v.psteps = ctx->psteps;
+    v.bsteps = ctx->bsteps;
+    v.num_cu = ctx->num_cu;
+    v.tuned = ctx->tuned;
+    v.small_field_log2n = ctx->small_field_log2n;
+    v.large_field_log2n = M64_MAX_LOG2N + 1;   // graphs run over GF(2^64)
+    v.borrowed = true;
+    const size_t ws_bytes = (size_t)ws_words * 8, bws_al = (bws_bytes + 255) / 256 * 256;
+    hipError_t e = hipMalloc(&g->mem, 4 * ws_bytes + bws_al);
+    if (e != hipSuccess) {
+        g->mem = nullptr;
+        return fail(POLYMUL_ENOMEM, std::string("hipMalloc graph workspace: ") + hipGetErrorString(e));
+    }
+    for (int k = 0; k < 4; ++k) v.ws[k] = reinterpret_cast<uint64_t *>(static_cast<char *>(g->mem) + k * ws_bytes);
+    v.ws_words = ws_words;
+    v.bws = bws_al ? static_cast<char *>(g->mem) + 4 * ws_bytes : nullptr;
+    v.bws_bytes = bws_al;
+    *out = g.release();
+    return 0;
+}
+
+// record body(view, stream) into g->graph on a private stream and instantiate it
+template <typename Body>
+static int graph_capture(polymul_graph *g, Body body)
+{
+    int rc;
+    if ((rc = set_lds_limits())) return rc;   // function attributes are set outside the capture
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return fail(POLYMUL_EIO, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    rc = body(&g->view, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess || !graph) return fail(POLYMUL_EIO, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    g->graph = graph;
+    e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        g->exec = nullptr;
+        return fail(POLYMUL_EIO, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// schedule tuner (polymul_tune): times the fused path's schedule choices on
+// the device -- the split of the upper butterfly layers into passes, the
+// row-kernel and zeta-kernel grids -- by coordinate descent from the default,
+// keeps the fastest, checks that it gives the default's product word for
+// word, and can append it to a text cache keyed by device architecture, CU
+// count and transform length.  Every choice is a valid schedule of the same
+// computation (any split of the layers, any grid of the grid-stride loops).
+// ---------------------------------------------------------------------------
+
+// operand words from SplitMix64 (the product path is data-oblivious: any
+// operands time the same)
+__global__ void k_tune_fill(uint64_t *__restrict__ p, uint64_t n, uint64_t seed)
+{
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        p[i] = z ^ (z >> 31);
+    }
+}
+
+static std::string device_arch(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static int write_report(char *buf, size_t len, const std::string &text)
+{
+    if (!buf || len == 0) return 0;
+    std::snprintf(buf, len, "%s", text.c_str());
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
 
@@ -1485,6 +1674,342 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
                           1ull << log2n, nullptr, (hipStream_t)stream, &one);
     }
     return product_body(ctx, a, len_a, b, len_b, out, (hipStream_t)stream);
+}
+
+int polymul_graph_create(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
+                         uint64_t *out, polymul_graph **graph)
+{
+    if (!graph) return fail(POLYMUL_EINVAL, "graph out pointer is null");
+    *graph = nullptr;
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (len_a == 0 || len_b == 0) return fail(POLYMUL_EINVAL, "a graph needs two non-empty operands");
+    if (len_a > POLYMUL_M64_MAX_PRODUCT_BITS || len_b > POLYMUL_M64_MAX_PRODUCT_BITS ||
+        len_a + len_b - 1 > POLYMUL_M64_MAX_PRODUCT_BITS)
+        return fail(POLYMUL_EINVAL, "graphs take products of at most 2^37 bits (GF(2^64))");
+    const uint64_t lc = len_a + len_b - 1;
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(dg.err);
+    int rc;
+    if ((rc = check_dev_ptr(a, "a_bits")) || (rc = check_dev_ptr(b, "b_bits")) || (rc = check_dev_ptr(out, "out")))
+        return rc;
+    size_t ob = (size_t)((lc + 63) / 64) * 8;
+    if (ranges_overlap(out, ob, a, (size_t)((len_a + 63) / 64) * 8) ||
+        ranges_overlap(out, ob, b, (size_t)((len_b + 63) / 64) * 8))
+        return fail(POLYMUL_EINVAL, "out overlaps an input");
+    if ((rc = batch_steps_upload(ctx))) return rc;
+    const int log2n = transform_log2(len_a, len_b);
+    const bool one_item = log2n <= SINGLE_VIA_BATCH_LOG2N;
+    const uint64_t ws_words = one_item ? 1 : fpmul_plan::ws_words_for(log2n);
+    const size_t bws = one_item ? batch_ws_bytes(ctx, 1, 1ull << log2n) : 0;
+    polymul_graph *g = nullptr;
+    if ((rc = graph_new(ctx, ws_words, bws, &g))) return rc;
+    rc = graph_capture(g, [&](polymul_ctx *v, hipStream_t cs) {
+        if (one_item) {
+            const BtDesc one{a, b, out, len_a, len_b};
+            return batch_body(v, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              1ull << log2n, nullptr, cs, &one);
+        }
+        return product_body(v, a, len_a, b, len_b, out, cs);
+    });
+    if (rc) {
+        graph_free(g);
+        return rc;
+    }
+    *graph = g;
+    return 0;
+}
+
+int polymul_batch_graph_create(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, const uint64_t *a_word_off,
+                               const uint64_t *len_a, const uint64_t *b_pool, const uint64_t *b_word_off,
+                               const uint64_t *len_b, uint64_t *out_pool, const uint64_t *out_word_off,
+                               uint64_t max_product_bits, int32_t *status, polymul_graph **graph)
+{
+    if (!graph) return fail(POLYMUL_EINVAL, "graph out pointer is null");
+    *graph = nullptr;
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (count == 0) return fail(POLYMUL_EINVAL, "a batch graph needs at least one item");
+    if (max_product_bits == 0 || max_product_bits > POLYMUL_BATCH_MAX_PRODUCT_BITS)
+        return fail(POLYMUL_EINVAL, "max_product_bits must be in [1, 2^22]");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(dg.err);
+    int rc;
+    if ((rc = check_dev_ptr(a_pool, "a_pool")) || (rc = check_dev_ptr(a_word_off, "a_word_off")) ||
+        (rc = check_dev_ptr(len_a, "len_a")) || (rc = check_dev_ptr(b_pool, "b_pool")) ||
+        (rc = check_dev_ptr(b_word_off, "b_word_off")) || (rc = check_dev_ptr(len_b, "len_b")) ||
+        (rc = check_dev_ptr(out_pool, "out_pool")) || (rc = check_dev_ptr(out_word_off, "out_word_off")))
+        return rc;
+    if (status && (rc = check_dev_ptr(status, "status"))) return rc;
+    if ((rc = batch_steps_upload(ctx))) return rc;
+    polymul_graph *g = nullptr;
+    if ((rc = graph_new(ctx, 1, batch_ws_bytes(ctx, count, max_product_bits), &g))) return rc;
+    rc = graph_capture(g, [&](polymul_ctx *v, hipStream_t cs) {
+        return batch_body(v, count, a_pool, a_word_off, len_a, b_pool, b_word_off, len_b, out_pool, out_word_off,
+                          nullptr, max_product_bits, status, cs);
+    });
+    if (rc) {
+        graph_free(g);
+        return rc;
+    }
+    *graph = g;
+    return 0;
+}
+
+int polymul_graph_launch(polymul_graph *graph, void *stream)
+{
+    if (!graph || !graph->exec) return fail(POLYMUL_EINVAL, "graph is null");
+    DeviceGuard dg(graph->device);
+    HIP_TRY(dg.err);
+    HIP_TRY(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return 0;
+}
+
+int polymul_graph_destroy(polymul_graph *graph)
+{
+    if (!graph) return 0;
+    DeviceGuard dg(graph->device);
+    (void)hipDeviceSynchronize();   // no replay may still use the workspace
+    graph_free(graph);
+    return 0;
+}
+
+int polymul_tune(polymul_ctx *ctx, int log2n, int reps, const char *cache_path, char *report, size_t report_len)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (!fpmul_plan::fast_path(log2n))
+        return fail(POLYMUL_EINVAL, "polymul_tune takes transforms of 2^22 .. 2^31 bits (the fused path)");
+    if (reps < 1 || reps > 100) return fail(POLYMUL_EINVAL, "reps must be in [1, 100]");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(dg.err);
+    const uint64_t L = 1ull << (log2n - 1), aw = L / 64, ow = (2 * L + 63) / 64;
+    uint64_t *a = nullptr, *b = nullptr, *out = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<uint64_t> ref(ow), got(ow);
+    const bool prof = ctx->prof;
+    const bool had = ctx->tuned_own.count(log2n) != 0;
+    const fpmul_plan::Schedule before = had ? ctx->tuned_own[log2n] : fpmul_plan::Schedule();
+    auto cleanup = [&]() {
+        if (a) (void)hipFree(a);
+        if (b) (void)hipFree(b);
+        if (out) (void)hipFree(out);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+        ctx->prof = prof;
+    };
+    auto restore = [&]() {
+        if (had)
+            ctx->tuned_own[log2n] = before;
+        else
+            ctx->tuned_own.erase(log2n);
+    };
+    hipError_t e = hipMalloc(&a, aw * 8);
+    if (e == hipSuccess) e = hipMalloc(&b, aw * 8);
+    if (e == hipSuccess) e = hipMalloc(&out, ow * 8);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(POLYMUL_ENOMEM, std::string("tuner buffers: ") + hipGetErrorString(e));
+    }
+    ctx->prof = false;
+    k_tune_fill<<<grid_for(aw, 256), 256, 0, st>>>(a, aw, 0x5EED7E57ull);
+    k_tune_fill<<<grid_for(aw, 256), 256, 0, st>>>(b, aw, 0x5EED7E58ull);
+    int rc = 0;
+    // mean time of reps products under schedule sc (one untimed product first)
+    auto time_of = [&](const fpmul_plan::Schedule &sc, double &ms) -> int {
+        ctx->tuned_own[log2n] = sc;
+        int r = product_body(ctx, a, L, b, L, out, st);
+        if (r) return r;
+        HIP_TRY(hipEventRecord(e0, st));
+        for (int k = 0; k < reps && !r; ++k) r = product_body(ctx, a, L, b, L, out, st);
+        if (r) return r;
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        float t = 0;
+        HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        ms = t / reps;
+        return 0;
+    };
+    const int l = log2n - 6;
+    fpmul_plan::Schedule best;
+    best.upper = fpmul_plan::default_upper(l);
+    double t_def = 0, t_best = 0;
+    if ((rc = time_of(best, t_def))) {
+        restore();
+        cleanup();
+        return rc;
+    }
+    if ((e = hipMemcpy(ref.data(), out, ow * 8, hipMemcpyDeviceToHost)) != hipSuccess) {
+        restore();
+        cleanup();
+        return fail(POLYMUL_EIO, std::string("tuner copy: ") + hipGetErrorString(e));
+    }
+    t_best = t_def;
+    int tried = 1;
+    auto consider = [&](const fpmul_plan::Schedule &sc) -> int {
+        double t = 0;
+        int r = time_of(sc, t);
+        ++tried;
+        if (!r && t < t_best * 0.995) {
+            t_best = t;
+            best = sc;
+        }
+        return r;
+    };
+    for (const auto &u : fpmul_plan::upper_candidates(l)) {
+        if (u == best.upper) continue;
+        fpmul_plan::Schedule sc = best;
+        sc.upper = u;
+        if ((rc = consider(sc))) break;
+    }
+    for (int m : {1, 2, 4}) {
+        if (rc || m == best.rows_mult) continue;
+        fpmul_plan::Schedule sc = best;
+        sc.rows_mult = m;
+        rc = consider(sc);
+    }
+    for (int m : {4, 8, 16}) {
+        if (rc || m == best.zeta_mult) continue;
+        fpmul_plan::Schedule sc = best;
+        sc.zeta_mult = m;
+        rc = consider(sc);
+    }
+    if (rc) {
+        restore();
+        cleanup();
+        return rc;
+    }
+    // the chosen schedule gives the default's product, word for word
+    ctx->tuned_own[log2n] = best;
+    rc = product_body(ctx, a, L, b, L, out, st);
+    if (!rc && (e = hipStreamSynchronize(st)) != hipSuccess) rc = fail(POLYMUL_EIO, hipGetErrorString(e));
+    if (!rc && (e = hipMemcpy(got.data(), out, ow * 8, hipMemcpyDeviceToHost)) != hipSuccess)
+        rc = fail(POLYMUL_EIO, hipGetErrorString(e));
+    if (!rc && std::memcmp(got.data(), ref.data(), ow * 8) != 0)
+        rc = fail(POLYMUL_EIO, "tuned schedule changed the product (kept the previous one)");
+    if (rc) {
+        restore();
+        cleanup();
+        return rc;
+    }
+    const std::string arch = device_arch(ctx->device);
+    const std::string line = fpmul_plan::schedule_line(arch.c_str(), ctx->num_cu, log2n, best, t_best);
+    if (cache_path && *cache_path) {
+        FILE *f = std::fopen(cache_path, "a");
+        if (!f) {
+            cleanup();
+            return fail(POLYMUL_EIO, std::string("cannot append to ") + cache_path);
+        }
+        std::fprintf(f, "%s\n", line.c_str());
+        std::fclose(f);
+    }
+    char head[160];
+    std::snprintf(head, sizeof head, "default_ms=%.4f tuned_ms=%.4f tried=%d | ", t_def, t_best, tried);
+    write_report(report, report_len, head + line);
+    cleanup();
+    return 0;
+}
+
+int polymul_tune_load(polymul_ctx *ctx, const char *cache_path, int *applied)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (!cache_path) return fail(POLYMUL_EINVAL, "cache path is null");
+    if (applied) *applied = 0;
+    FILE *f = std::fopen(cache_path, "r");
+    if (!f) return fail(POLYMUL_EINVAL, std::string("cannot read ") + cache_path);
+    const std::string arch = device_arch(ctx->device);
+    char line[512];
+    int n = 0;
+    while (std::fgets(line, sizeof line, f)) {
+        int lg = 0;
+        fpmul_plan::Schedule sc;
+        if (fpmul_plan::schedule_parse(line, arch.c_str(), ctx->num_cu, lg, sc)) {
+            ctx->tuned_own[lg] = sc;   // a later line for the same length wins
+            ++n;
+        }
+    }
+    std::fclose(f);
+    if (applied) *applied = n;
+    return 0;
+}
+
+int polymul_tune_get(polymul_ctx *ctx, int log2n, char *buf, size_t buflen)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (!fpmul_plan::fast_path(log2n)) return fail(POLYMUL_EINVAL, "log2n must be in [22, 31]");
+    fpmul_plan::Schedule sc = sched_of(ctx, log2n);
+    if (sc.upper.empty()) sc.upper = fpmul_plan::default_upper(log2n - 6);
+    const std::string arch = device_arch(ctx->device);
+    return write_report(buf, buflen, fpmul_plan::schedule_line(arch.c_str(), ctx->num_cu, log2n, sc, 0.0));
+}
+
+int polymul_resident_create(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, uint64_t max_product_bits,
+                            polymul_resident **res)
+{
+    if (!res) return fail(POLYMUL_EINVAL, "resident out pointer is null");
+    *res = nullptr;
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (len_a == 0) return fail(POLYMUL_EINVAL, "a resident operand needs at least one bit");
+    if (max_product_bits < len_a || max_product_bits > POLYMUL_M64_MAX_PRODUCT_BITS)
+        return fail(POLYMUL_EINVAL, "max_product_bits must be in [len_a, 2^37]");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(dg.err);
+    int rc;
+    if ((rc = check_dev_ptr(a, "a_bits"))) return rc;
+    std::unique_ptr<polymul_resident> r(new polymul_resident());
+    r->device = ctx->device;
+    r->log2n = fpmul_plan::product_log2n(max_product_bits);
+    r->len_a = len_a;
+    hipError_t e = hipMalloc(&r->vals, (1ull << (r->log2n - 6)) * 8);
+    if (e != hipSuccess) {
+        r->vals = nullptr;
+        return fail(POLYMUL_ENOMEM, std::string("hipMalloc resident transform: ") + hipGetErrorString(e));
+    }
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)hipFree(r->vals);
+        return fail(POLYMUL_EIO, std::string("resident stream: ") + hipGetErrorString(e));
+    }
+    rc = addfft_body(ctx, a, len_a, r->log2n, r->vals, st);
+    e = hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (!rc && e != hipSuccess) rc = fail(POLYMUL_EIO, std::string("resident transform: ") + hipGetErrorString(e));
+    if (rc) {
+        (void)hipFree(r->vals);
+        return rc;
+    }
+    *res = r.release();
+    return 0;
+}
+
+int polymul_resident_destroy(polymul_resident *res)
+{
+    if (!res) return 0;
+    DeviceGuard dg(res->device);
+    (void)hipDeviceSynchronize();   // no launch may still read the transform
+    if (res->vals) (void)hipFree(res->vals);
+    delete res;
+    return 0;
+}
+
+int polymul_resident_mul(polymul_ctx *ctx, const polymul_resident *res, const uint64_t *b, uint64_t len_b,
+                         uint64_t *out, void *stream)
+{
+    if (!ctx || !res) return fail(POLYMUL_EINVAL, "ctx or resident operand is null");
+    if (res->device != ctx->device) return fail(POLYMUL_EINVAL, "resident operand is on another device");
+    if (len_b == 0) return 0;
+    const uint64_t lc = res->len_a + len_b - 1;
+    if (lc > (1ull << res->log2n)) return fail(POLYMUL_EINVAL, "product longer than the resident operand's transform");
+    DeviceGuard dg(ctx->device);
+    HIP_TRY(dg.err);
+    int rc;
+    if ((rc = check_dev_ptr(b, "b_bits")) || (rc = check_dev_ptr(out, "out"))) return rc;
+    if (ranges_overlap(out, (size_t)((lc + 63) / 64) * 8, b, (size_t)((len_b + 63) / 64) * 8))
+        return fail(POLYMUL_EINVAL, "out overlaps an input");
+    return resident_body(ctx, res->vals, res->log2n, b, len_b, out, lc, (hipStream_t)stream);
 }
 
 int polymul_set_large_field(polymul_ctx *ctx, int min_log2n)

@@ -645,45 +645,84 @@ __device__ __forceinline__ void bc_xorv(uint2 &a, uint2 b) { a.x ^= b.x; a.y ^= 
 __device__ __forceinline__ void bc_xorv(uint4 &a, uint4 b) { a.x ^= b.x; a.y ^= b.y; a.z ^= b.z; a.w ^= b.w; }
 __device__ __forceinline__ void bc_xorv(ulonglong2 &a, ulonglong2 b) { a.x ^= b.x; a.y ^= b.y; }
 
-// one phase of step (2^LGS, 2^LGD) on the column, V consecutive elements per
-// access (V divides d, so both operands of every access are V-aligned)
-template <int LGS, int LGD, int PHASE, typename T>
-__device__ __forceinline__ void bc_elem_phase(T *v, int lgR, int tid, int nth)
+// A column of 2^lgR elements sits in LDS with element r at bc_swz(r): bits
+// [G, G + 5) of r (G = log2 of the elements in one 16-byte access) take the
+// XOR of bits [sws, sws + 5).  With sws >= G + 5 the map is an involution
+// that keeps every aligned 16-byte group in place, so vector accesses and the
+// per-wave shares of the steps stay valid; it spreads the 64 rows j rpj + r0
+// (rpj = 2^sws) that Encode and Decode gather over distinct banks.  sws >=
+// lgR leaves the column unpermuted.
+template <typename T>
+__device__ __forceinline__ int bc_swz(int r, int sws)
+{
+    constexpr int G = sizeof(T) == 8 ? 1 : 2;
+    return r ^ (((r >> sws) & 31) << G);
+}
+
+// one phase of step (2^LGS, 2^LGD) on the 2^LGN elements of a column that
+// start at element off, by 2^LGT threads (tid < 2^LGT), V consecutive
+// elements per access (V divides d, so both operands of every access are
+// V-aligned).  A phase writes elements it does not read, so every thread
+// issues all its reads before its writes.
+#ifndef BC_PHASE_BATCH
+#define BC_PHASE_BATCH 4   // items of a phase whose reads a thread issues together
+#endif
+template <int LGS, int LGD, int PHASE, int LGN, int LGT, typename T>
+__device__ __forceinline__ void bc_elem_phase(T *col, int off, int tid, int sws)
 {
     constexpr int LGH = LGS - 1, H = 1 << LGH, d = 1 << LGD;
     constexpr int VMAX = 16 / (int)sizeof(T), V = d < VMAX ? d : VMAX, LGV = V == 4 ? 2 : V == 2 ? 1 : 0;
+    constexpr int G = sizeof(T) == 8 ? 1 : 2;
     using VT = typename BcVec<T, V>::type;
-    VT *vv = reinterpret_cast<VT *>(v);
-    if (PHASE == 0) {
-        // hi[0, d) ^= hi[H - d, H) in every segment
-        const int nt = 1 << (lgR - LGS + LGD - LGV);
-        for (int t = tid; t < nt; t += nth) {
+    VT *vv = reinterpret_cast<VT *>(col);
+    // phase 0 (hi[0, d) ^= hi[H - d, H)) and phase 1 with H - d = d have
+    // d / V items per segment; phase 1 otherwise runs over all of lo and
+    // leaves its first d elements alone
+    constexpr bool ALL_LO = PHASE != 0 && 2 * d != H;
+    constexpr int LGI = ALL_LO ? LGN - 1 - LGV : LGN - LGS + LGD - LGV;
+    constexpr int PER = LGI > LGT ? 1 << (LGI - LGT) : 1;
+    const int offv = off >> LGV;
+    auto phys = [&](int a) -> int {   // vector index a of the region -> LDS vector index
+        const int e = (offv + a) << LGV;
+        return (offv + a) ^ ((((e >> sws) & 31) << G) >> LGV);
+    };
+    // item t -> vector index of its destination (region-relative) and whether it is written
+    auto item = [&](int t, bool &w) -> int {
+        int a;
+        if constexpr (!ALL_LO) {
             const int sg = t >> (LGD - LGV), q = t & ((d >> LGV) - 1);
-            const int a = (sg << (LGS - LGV)) + ((H >> LGV) + q);
-            VT x = vv[a];
-            bc_xorv(x, vv[a + ((H - d) >> LGV)]);
-            vv[a] = x;
-        }
-    } else if (2 * d == H) {
-        // lo[d, H) ^= hi[0, H - d): H - d = d chunks of a power-of-two count
-        const int nt = 1 << (lgR - LGS + LGD - LGV);
-        for (int t = tid; t < nt; t += nth) {
-            const int sg = t >> (LGD - LGV), q = t & ((d >> LGV) - 1);
-            const int a = (sg << (LGS - LGV)) + ((d >> LGV) + q);
-            VT x = vv[a];
-            bc_xorv(x, vv[a + ((H - d) >> LGV)]);
-            vv[a] = x;
-        }
-    } else {
-        // lo[d, H) ^= hi[0, H - d): all of lo, the first d elements left alone
-        const int nt = 1 << (lgR - 1 - LGV);
-        for (int t = tid; t < nt; t += nth) {
+            a = (sg << (LGS - LGV)) + (PHASE == 0 ? (H >> LGV) : (d >> LGV)) + q;
+            w = true;
+        } else {
             const int sg = t >> (LGH - LGV), q = t & ((H >> LGV) - 1);
-            if (q < (d >> LGV)) continue;
-            const int a = (sg << (LGS - LGV)) + q;
-            VT x = vv[a];
-            bc_xorv(x, vv[a + ((H - d) >> LGV)]);
-            vv[a] = x;
+            a = (sg << (LGS - LGV)) + q;
+            w = q >= (d >> LGV);
+        }
+        if (LGI < LGT && !(t < (1 << LGI))) {
+            w = false;
+            a = 0;   // keeps the read in range
+        }
+        return a;
+    };
+    constexpr int CH = PER < BC_PHASE_BATCH ? PER : BC_PHASE_BATCH;
+#pragma unroll
+    for (int p0 = 0; p0 < PER; p0 += CH) {
+        VT x[CH], y[CH];
+#pragma unroll
+        for (int p = 0; p < CH; ++p) {
+            bool w;
+            const int a = item(tid + ((p0 + p) << LGT), w);
+            x[p] = vv[phys(a)];
+            y[p] = vv[phys(a + ((H - d) >> LGV))];
+        }
+#pragma unroll
+        for (int p = 0; p < CH; ++p) {
+            bool w;
+            const int a = item(tid + ((p0 + p) << LGT), w);
+            if (w) {
+                bc_xorv(x[p], y[p]);
+                vv[phys(a)] = x[p];
+            }
         }
     }
 }
@@ -703,7 +742,7 @@ __device__ __forceinline__ void bc_wave_sync()
 // of 2^(LGR - 4) consecutive elements runs on that share alone, ordered by
 // wave-level syncs instead of workgroup barriers.
 template <int LGR, int K, bool INV, typename T>
-__device__ __forceinline__ void bc_elem_steps_from(T *v, int tid, int nth)
+__device__ __forceinline__ void bc_elem_steps_from(T *v, int tid, int sws)
 {
     constexpr BcStepList L = BcElemSteps<LGR>::L;
     constexpr int LGL = LGR - 4;   // log2 elements per wave (16 waves)
@@ -715,35 +754,37 @@ __device__ __forceinline__ void bc_elem_steps_from(T *v, int tid, int nth)
         if constexpr (LOCAL) {
             constexpr int kn = INV ? L.n - 2 - K : K + 1;   // the next step, if any
             constexpr bool NEXT_LOCAL = K + 1 < L.n && L.lgs[kn < 0 ? 0 : kn] <= LGL;
-            T *w = v + ((tid >> 6) << LGL);
-            bc_elem_phase<LGS, LGD, INV ? 1 : 0>(w, LGL, tid & 63, 64);
+            const int off = (tid >> 6) << LGL;
+            bc_elem_phase<LGS, LGD, INV ? 1 : 0, LGL, 6>(v, off, tid & 63, sws);
             bc_wave_sync();
-            bc_elem_phase<LGS, LGD, INV ? 0 : 1>(w, LGL, tid & 63, 64);
+            bc_elem_phase<LGS, LGD, INV ? 0 : 1, LGL, 6>(v, off, tid & 63, sws);
             if constexpr (NEXT_LOCAL)
                 bc_wave_sync();
             else
                 __syncthreads();
         } else {
-            bc_elem_phase<LGS, LGD, INV ? 1 : 0>(v, LGR, tid, nth);
+            bc_elem_phase<LGS, LGD, INV ? 1 : 0, LGR, 10>(v, 0, tid, sws);
             __syncthreads();
-            bc_elem_phase<LGS, LGD, INV ? 0 : 1>(v, LGR, tid, nth);
+            bc_elem_phase<LGS, LGD, INV ? 0 : 1, LGR, 10>(v, 0, tid, sws);
             __syncthreads();
         }
-        bc_elem_steps_from<LGR, K + 1, INV>(v, tid, nth);
+        bc_elem_steps_from<LGR, K + 1, INV>(v, tid, sws);
     }
 }
 
-// BasisCvt(2^lgR) on the elements of a column in LDS; compile-time steps for
-// lgR in 6 .. 15, the run-time list otherwise
+// BasisCvt(2^lgR) on the elements of a column in LDS (swizzled by sws);
+// compile-time steps for lgR in 6 .. 15, the run-time list otherwise (the
+// column is then unpermuted: bc_col_sws gives sws >= lgR)
 template <typename T>
-__device__ __forceinline__ void bc_elem_steps_any(T *v, int lgR, const BcSteps &st, bool inverse, int tid, int nth)
+__device__ __forceinline__ void bc_elem_steps_any(T *v, int lgR, const BcSteps &st, bool inverse, int tid, int nth,
+                                                  int sws)
 {
 #define BC_ELEM_CASE(R)                                                         \
     case R:                                                                     \
         if (inverse)                                                            \
-            bc_elem_steps_from<R, 0, true>(v, tid, nth);                        \
+            bc_elem_steps_from<R, 0, true>(v, tid, sws);                        \
         else                                                                    \
-            bc_elem_steps_from<R, 0, false>(v, tid, nth);                       \
+            bc_elem_steps_from<R, 0, false>(v, tid, sws);                       \
         return;
     switch (lgR) {
         BC_ELEM_CASE(6)
@@ -762,6 +803,16 @@ __device__ __forceinline__ void bc_elem_steps_any(T *v, int lgR, const BcSteps &
 #undef BC_ELEM_CASE
 }
 
+// swizzle shift of a column of 2^lgR elements whose gathered rows are
+// 2^lgrpj apart (only the compile-time step lists handle a swizzled column)
+template <typename T>
+__device__ __forceinline__ int bc_col_sws(int lgR, int lgrpj)
+{
+    constexpr int G = sizeof(T) == 8 ? 1 : 2;
+    if (lgR < 6 || lgR > 15) return 31;
+    return lgrpj > G + 5 ? lgrpj : G + 5;
+}
+
 // ------------------------------------ forward: unskew, carry, inner --------
 //
 // Rows q of X (skewed, superset-summed) -> digits h_q -> inner BasisCvt(2^16)
@@ -769,6 +820,25 @@ __device__ __forceinline__ void bc_elem_steps_any(T *v, int lgR, const BcSteps &
 // the transposed store writes 64-byte runs.  With R == 1 (a single row, no
 // Taylor step) the row is read from `in` directly.
 #define BC_ROWS 8
+#define BC_ROW_PER (BC_ROWS * BC_TAU_WORDS / BC_ROW_THREADS)   // row words per thread
+
+// word i of w[0, nw), 0 outside; the load itself is unconditional (clamped
+// index), so that a thread's loads go out together
+__device__ __forceinline__ uint64_t bc_ld0(const uint64_t *w, long i, int nw)
+{
+    const uint64_t v = w[i < 0 ? 0 : (i >= nw ? nw - 1 : i)];
+    return (i >= 0 && i < nw) ? v : 0ull;
+}
+
+// bc_bits with unconditional loads
+__device__ __forceinline__ uint64_t bc_bits_u(const uint64_t *w, int nw, long off)
+{
+    const long i0 = off >> 6;
+    const int s = (int)(off & 63);
+    const uint64_t a = bc_ld0(w, i0, nw), b = bc_ld0(w, i0 + 1, nw);
+    return s ? ((a >> s) | (b << (64 - s))) : a;
+}
+
 __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *__restrict__ X,
                                                             const uint64_t *__restrict__ in, uint64_t len, int lgR,
                                                             int EW, uint64_t *__restrict__ Y, BcSteps inner)
@@ -778,36 +848,79 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *
     const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
     const uint64_t inwords = (len + 63) / 64;
     for (int q0 = blockIdx.x * T; q0 < R; q0 += gridDim.x * T) {
-        for (int e = tid; e < T * BC_TAU_WORDS; e += nth) {
-            const int k = e / BC_TAU_WORDS, w = e % BC_TAU_WORDS, q = q0 + k;
-            uint64_t v;
-            if (R == 1) {
-                v = (uint64_t)w < inwords ? in[w] : 0ull;
-                if ((uint64_t)w == inwords - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
-            } else {
-                const uint64_t *pq = X + (uint64_t)q * EW;
-                v = bc_bits(pq, EW, 64L * w + q);                                   // L_q
-                if (64 * w <= R) {                                                 // x U_q: U bit b -> bit b + 1
-                    uint64_t u = bc_bits(pq, EW, 64L * (BC_TAU_WORDS + w) + q - 1);
-                    uint64_t m = ~0ull;
-                    if (w == 0) m &= ~1ull;
-                    if ((long)R + 1 - 64L * w < 64) m &= bc_lowmask(R + 1 - 64 * w);
-                    v ^= u & m;
-                }
-                if (q > 0 && 64 * w < R) {                                         // U_{q-1}
-                    const uint64_t *pp = X + (uint64_t)(q - 1) * EW;
-                    uint64_t u = bc_bits(pp, EW, 64L * (BC_TAU_WORDS + w) + (q - 1));
-                    if (64 * (w + 1) > R) u &= bc_lowmask(R - 64 * w);
-                    v ^= u;
-                }
+        if (T == BC_ROWS && nth == BC_ROW_THREADS) {
+            // L_q: bits [64 w + q, 64 w + q + 64) of row q, words w + q/64 and
+            // the next (both below EW); all loads of the thread in flight together
+            uint64_t a[BC_ROW_PER], b[BC_ROW_PER];
+#pragma unroll
+            for (int i = 0; i < BC_ROW_PER; ++i) {
+                const int e = tid + i * BC_ROW_THREADS, k = e / BC_TAU_WORDS, w = e % BC_TAU_WORDS, q = q0 + k;
+                const uint64_t *p = X + (uint64_t)q * EW + w + (q >> 6);
+                a[i] = p[0];
+                b[i] = p[1];
             }
-            rows[e] = v;
+#pragma unroll
+            for (int i = 0; i < BC_ROW_PER; ++i) {
+                const int e = tid + i * BC_ROW_THREADS, k = e / BC_TAU_WORDS, s = (q0 + k) & 63;
+                rows[e] = s ? ((a[i] >> s) | (b[i] << (64 - s))) : a[i];
+            }
+            __syncthreads();
+            // x U_q + U_{q-1} on the first R/64 + 1 words of every row
+            const int nu = R / 64 + 1;
+            for (int e = tid; e < BC_ROWS * nu; e += BC_ROW_THREADS) {
+                const int k = e / nu, w = e % nu, q = q0 + k;
+                const uint64_t *pq = X + (uint64_t)q * EW;
+                uint64_t u = bc_bits_u(pq, EW, 64L * (BC_TAU_WORDS + w) + q - 1);   // U bit b -> bit b + 1
+                uint64_t m = ~0ull;
+                if (w == 0) m &= ~1ull;
+                if ((long)R + 1 - 64L * w < 64) m &= bc_lowmask(R + 1 - 64 * w);
+                uint64_t v = u & m;
+                const uint64_t *pp = X + (uint64_t)(q > 0 ? q - 1 : 0) * EW;
+                uint64_t up = bc_bits_u(pp, EW, 64L * (BC_TAU_WORDS + w) + (q - 1));
+                if (64 * (w + 1) > R) up &= bc_lowmask(R - 64 * w);
+                if (q > 0 && 64 * w < R) v ^= up;
+                rows[k * BC_TAU_WORDS + w] ^= v;
+            }
+        } else {
+            for (int e = tid; e < T * BC_TAU_WORDS; e += nth) {
+                const int k = e / BC_TAU_WORDS, w = e % BC_TAU_WORDS, q = q0 + k;
+                uint64_t v;
+                if (R == 1) {
+                    v = (uint64_t)w < inwords ? in[w] : 0ull;
+                    if ((uint64_t)w == inwords - 1 && (len & 63)) v &= (~0ull) >> (64 - (len & 63));
+                } else {
+                    const uint64_t *pq = X + (uint64_t)q * EW;
+                    v = bc_bits(pq, EW, 64L * w + q);                                   // L_q
+                    if (64 * w <= R) {                                                 // x U_q: U bit b -> bit b + 1
+                        uint64_t u = bc_bits(pq, EW, 64L * (BC_TAU_WORDS + w) + q - 1);
+                        uint64_t m = ~0ull;
+                        if (w == 0) m &= ~1ull;
+                        if ((long)R + 1 - 64L * w < 64) m &= bc_lowmask(R + 1 - 64 * w);
+                        v ^= u & m;
+                    }
+                    if (q > 0 && 64 * w < R) {                                         // U_{q-1}
+                        const uint64_t *pp = X + (uint64_t)(q - 1) * EW;
+                        uint64_t u = bc_bits(pp, EW, 64L * (BC_TAU_WORDS + w) + (q - 1));
+                        if (64 * (w + 1) > R) u &= bc_lowmask(R - 64 * w);
+                        v ^= u;
+                    }
+                }
+                rows[e] = v;
+            }
         }
         __syncthreads();
         bc16_rows<false>(rows, T, tid, nth);
-        for (int e = tid; e < T * BC_TAU_WORDS; e += nth) {
-            const int k = e % T, w = e / T;
-            Y[(uint64_t)w * R + q0 + k] = rows[k * BC_TAU_WORDS + w];
+        if (T == BC_ROWS) {
+            // eight consecutive threads write one 64-byte run of a column
+            for (int e = tid; e < BC_ROWS * BC_TAU_WORDS; e += nth) {
+                const int k = e & (BC_ROWS - 1), w = e >> 3;
+                Y[(uint64_t)w * R + q0 + k] = rows[k * BC_TAU_WORDS + w];
+            }
+        } else {
+            for (int e = tid; e < T * BC_TAU_WORDS; e += nth) {
+                const int k = e % T, w = e / T;
+                Y[(uint64_t)w * R + q0 + k] = rows[k * BC_TAU_WORDS + w];
+            }
         }
         __syncthreads();
     }
@@ -874,31 +987,66 @@ __device__ __forceinline__ uint64_t bc_wave_transpose64(uint64_t x, int lane)
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 
+// the 8-bit window product sum_k tab[k][byte k of x] (Encode's R, Decode's
+// R^-1), the eight lookups issued together
+__device__ __forceinline__ uint64_t bc_win8(const uint64_t (*tab)[256], uint64_t x)
+{
+    const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    const uint64_t t0 = tab[0][lo & 255u], t1 = tab[1][(lo >> 8) & 255u], t2 = tab[2][(lo >> 16) & 255u],
+                   t3 = tab[3][lo >> 24], t4 = tab[4][hi & 255u], t5 = tab[5][(hi >> 8) & 255u],
+                   t6 = tab[6][(hi >> 16) & 255u], t7 = tab[7][hi >> 24];
+    return ((t0 ^ t1) ^ (t2 ^ t3)) ^ ((t4 ^ t5) ^ (t6 ^ t7));
+}
+
 // Outer BasisCvt(R) on one 64-bit column of Y, then Encode: element
 // i = r0 tau + 64 col + t takes bits j n_p + i, found in rows j (n_p/tau) + r0.
-// One column per workgroup iteration; R <= 2^14 (the column fits LDS).
+// One column per workgroup iteration; R <= 2^14 (the column fits LDS).  The
+// next column is loaded into registers while this one is converted and
+// encoded.
+#define BC_ENC_PRE 16   // column words per thread: R <= 2^14 = BC_ENC_PRE x BC_COL_THREADS
 __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64_t *__restrict__ Y, int lgR, int l,
                                                                 uint64_t *__restrict__ vals, BcSteps outer,
                                                                 const DevTables *__restrict__ T)
 {
-    __shared__ uint64_t col[1 << 14];
+    __shared__ __align__(16) uint64_t col[1 << 14];
     __shared__ uint64_t enc[8][256];
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+    constexpr int NW = BC_COL_THREADS / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int R = 1 << lgR;
-    const int rows_per_j = 1 << (l - 16);          // n_p / tau
-    for (int i = tid; i < 8 * 256; i += nth) (&enc[0][0])[i] = (&T->enc_win[0][0])[i];
-    for (int c = blockIdx.x; c < BC_TAU_WORDS; c += gridDim.x) {
-        for (int r = tid; r < R; r += nth) col[r] = Y[(uint64_t)c * R + r];
-        __syncthreads();
-        bc_elem_steps_any<uint64_t>(col, lgR, outer, false, tid, nth);
-        for (int r0 = wave; r0 < rows_per_j; r0 += nwave) {
-            const int rr = lane * rows_per_j + r0;         // row of Encode input row j = lane
-            uint64_t x = rr < R ? col[rr] : 0ull;
-            x = bc_wave_transpose64(x, lane);
-            uint64_t f = 0;
+    const int lgrpj = l - 16, rpj = 1 << lgrpj;           // n_p / tau
+    const int sws = bc_col_sws<uint64_t>(lgR, lgrpj);
+    const int per = R >= BC_COL_THREADS ? R / BC_COL_THREADS : 1;
+    for (int i = tid; i < 8 * 256; i += BC_COL_THREADS) (&enc[0][0])[i] = (&T->enc_win[0][0])[i];
+    uint64_t pre[BC_ENC_PRE];
+    auto load = [&](int c, int tid_c) {
+        const uint64_t *src = Y + (uint64_t)c * R;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) f ^= enc[k][(x >> (8 * k)) & 255u];
-            vals[((uint64_t)r0 << 16) + 64u * c + lane] = f;
+        for (int k = 0; k < BC_ENC_PRE; ++k) {
+            const int r = tid_c + k * BC_COL_THREADS;
+            if (k < per) pre[k] = src[r < R ? r : R - 1];
+        }
+    };
+    int c = blockIdx.x;
+    if (c < BC_TAU_WORDS) load(c, tid);
+    for (; c < BC_TAU_WORDS; c += gridDim.x) {
+        // every address below depends on tid only; recomputing them per
+        // column keeps the compiler from holding hundreds of them live (and
+        // spilled) across the loop
+        int tid_c = tid;
+        asm volatile("" : "+v"(tid_c));
+#pragma unroll
+        for (int k = 0; k < BC_ENC_PRE; ++k) {
+            const int r = tid_c + k * BC_COL_THREADS;
+            if (k < per && r < R) col[bc_swz<uint64_t>(r, sws)] = pre[k];
+        }
+        __syncthreads();
+        if (c + (int)gridDim.x < BC_TAU_WORDS) load(c + gridDim.x, tid_c);   // in flight during this column
+        bc_elem_steps_any<uint64_t>(col, lgR, outer, false, tid_c, BC_COL_THREADS, sws);
+        for (int r0 = wave; r0 < rpj; r0 += NW) {
+            const int rr = lane * rpj + r0;              // row of Encode input row j = lane
+            uint64_t x = rr < R ? col[bc_swz<uint64_t>(rr, sws)] : 0ull;
+            x = bc_wave_transpose64(x, lane);
+            vals[((uint64_t)r0 << 16) + 64u * c + lane] = bc_win8(enc, x);
         }
         __syncthreads();
     }
@@ -908,28 +1056,48 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64
 
 // Decode and the inverse outer conversion: for a 32-bit column c (bits
 // [32 c, 32 c + 32) of every row), element i = r0 tau + 32 c + t decodes to 64
-// bits; bit j goes to row j (n_p/tau) + r0.  Then iOuter on the column.
+// bits; bit j goes to row j (n_p/tau) + r0.  Then iOuter on the column.  A
+// half-wave decodes the 32 elements of one r0; the values of the next column
+// are loaded into registers while this one is converted and stored.
+#define BC_DEC_PRE 16   // r0 pairs per wave and column: n_p / tau <= 2 x 16 waves x BC_DEC_PRE
 __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64_t *__restrict__ vals, int lgR, int l,
                                                                 uint32_t *__restrict__ Y32, BcSteps outer,
                                                                 const DevTables *__restrict__ T)
 {
-    __shared__ uint32_t col[1 << 15];
+    __shared__ __align__(16) uint32_t col[1 << 15];
     __shared__ uint64_t dec[8][256];
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid & 63, wave = tid >> 6, nwave = nth >> 6;
+    constexpr int NW = BC_COL_THREADS / 64;
     const int R = 1 << lgR;
-    const int rows_per_j = 1 << (l - 16);
-    for (int i = tid; i < 8 * 256; i += nth) (&dec[0][0])[i] = (&T->dec_win[0][0])[i];
-    __syncthreads();
-    for (int c = blockIdx.x; c < 2 * BC_TAU_WORDS; c += gridDim.x) {
-        // two r0 per wave pass: lanes 0..31 and 32..63 each decode 32 elements
-        for (int r0b = 2 * wave; r0b < rows_per_j; r0b += 2 * nwave) {
-            const int half = lane >> 5, t = lane & 31, r0 = r0b + half;
-            uint64_t a = 0;
-            if (r0 < rows_per_j) {
-                const uint64_t h = vals[((uint64_t)r0 << 16) + 32u * c + t];
+    const int lgrpj = l - 16, rpj = 1 << lgrpj;
+    const int sws = bc_col_sws<uint32_t>(lgR, lgrpj);
+    const int kmax = (rpj + 2 * NW - 1) / (2 * NW);       // r0 passes per wave
+    constexpr int NCOL = 2 * BC_TAU_WORDS;
+    for (int i = threadIdx.x; i < 8 * 256; i += BC_COL_THREADS) (&dec[0][0])[i] = (&T->dec_win[0][0])[i];
+    uint64_t pre[BC_DEC_PRE];
+    // lane (half, t) of wave w decodes element 32 c + t of r0 = 2 w + 2 NW k + half
+    auto load = [&](int c, int tid_c) {
+        const int wave = tid_c >> 6, half = (tid_c >> 5) & 1, t = tid_c & 31;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) a ^= dec[k][(h >> (8 * k)) & 255u];
-            }
+        for (int k = 0; k < BC_DEC_PRE; ++k) {
+            const int r0 = 2 * wave + 2 * NW * k + half;
+            if (k < kmax) pre[k] = vals[((uint64_t)(r0 < rpj ? r0 : rpj - 1) << 16) + 32u * c + t];
+        }
+    };
+    int c = blockIdx.x;
+    if (c < NCOL) load(c, threadIdx.x);
+    __syncthreads();   // dec
+    for (; c < NCOL; c += gridDim.x) {
+        // every address below depends on the thread index only; recomputing
+        // them per column keeps the compiler from holding them live (and
+        // spilled) across the loop
+        int tid_c = threadIdx.x;
+        asm volatile("" : "+v"(tid_c));
+        const int lane = tid_c & 63, wave = tid_c >> 6, half = lane >> 5, t = lane & 31;
+#pragma unroll
+        for (int k = 0; k < BC_DEC_PRE; ++k) {
+            if (k >= kmax) continue;   // uniform
+            const int r0 = 2 * wave + 2 * NW * k + half;
+            const uint64_t a = bc_win8(dec, pre[k]);
             // transpose the two 32 x 64 blocks (one per half-wave): afterwards lane
             // (half, j) holds bits j and j + 32 of the 32 decoded vectors
             uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
@@ -943,16 +1111,25 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
             hi = bc_tstage<2>(hi, 0x33333333u, lane);
             lo = bc_tstage<1>(lo, 0x55555555u, lane);
             hi = bc_tstage<1>(hi, 0x55555555u, lane);
-            if (r0 < rows_per_j) {
+            if (r0 < rpj) {
                 // lane t now holds bit t of vector s at bit s: that is row j = t (lo) and j = t + 32 (hi)
-                const int rlo = t * rows_per_j + r0, rhi = (t + 32) * rows_per_j + r0;
-                if (rlo < R) col[rlo] = lo;
-                if (rhi < R) col[rhi] = hi;
+                const int rlo = t * rpj + r0, rhi = (t + 32) * rpj + r0;
+                if (rlo < R) col[bc_swz<uint32_t>(rlo, sws)] = lo;
+                if (rhi < R) col[bc_swz<uint32_t>(rhi, sws)] = hi;
             }
         }
         __syncthreads();
-        bc_elem_steps_any<uint32_t>(col, lgR, outer, true, tid, nth);
-        for (int r = tid; r < R; r += nth) Y32[(uint64_t)c * R + r] = col[r];
+        if (c + (int)gridDim.x < NCOL) load(c + gridDim.x, tid_c);   // in flight during this column
+        bc_elem_steps_any<uint32_t>(col, lgR, outer, true, tid_c, BC_COL_THREADS, sws);
+        uint32_t *dst = Y32 + (uint64_t)c * R;
+        if (R >= 4 * BC_COL_THREADS) {
+            // 16-byte groups stay whole under the swizzle
+            const uint4 *c4 = reinterpret_cast<const uint4 *>(col);
+            uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+            for (int g = tid_c; g < R / 4; g += BC_COL_THREADS) d4[g] = c4[bc_swz<uint32_t>(4 * g, sws) >> 2];
+        } else {
+            for (int r = tid_c; r < R; r += BC_COL_THREADS) dst[r] = col[bc_swz<uint32_t>(r, sws)];
+        }
         __syncthreads();
     }
 }
@@ -972,20 +1149,29 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *
     const unsigned w = G % BC_XCDS == 0 ? (b % BC_XCDS) * (G / BC_XCDS) + b / BC_XCDS : b;
     for (int q0 = (int)w * T; q0 < R; q0 += (int)G * T) {
         uint32_t *rows32 = reinterpret_cast<uint32_t *>(rows);
-        if (T == BC_ROWS) {
-            // one 32-bit column c per thread: a 32-byte run of Y32 in, LDS writes
-            // of consecutive words per wave (no bank conflicts)
-            for (int c = tid; c < 2 * BC_TAU_WORDS; c += nth) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(Y32 + (uint64_t)c * R + q0);
-                const uint4 v0 = src[0], v1 = src[1];
-                rows32[0 * 2 * BC_TAU_WORDS + c] = v0.x;
-                rows32[1 * 2 * BC_TAU_WORDS + c] = v0.y;
-                rows32[2 * 2 * BC_TAU_WORDS + c] = v0.z;
-                rows32[3 * 2 * BC_TAU_WORDS + c] = v0.w;
-                rows32[4 * 2 * BC_TAU_WORDS + c] = v1.x;
-                rows32[5 * 2 * BC_TAU_WORDS + c] = v1.y;
-                rows32[6 * 2 * BC_TAU_WORDS + c] = v1.z;
-                rows32[7 * 2 * BC_TAU_WORDS + c] = v1.w;
+        if (T == BC_ROWS && nth == BC_ROW_THREADS) {
+            // 32-bit columns c = tid + j BC_ROW_THREADS: a 32-byte run of Y32
+            // each, all loads in flight together; LDS writes of consecutive
+            // words per wave (no bank conflicts)
+            constexpr int NC = 2 * BC_TAU_WORDS / BC_ROW_THREADS;
+            uint4 v0[NC], v1[NC];
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(Y32 + (uint64_t)(tid + j * BC_ROW_THREADS) * R + q0);
+                v0[j] = src[0];
+                v1[j] = src[1];
+            }
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+                const int c = tid + j * BC_ROW_THREADS;
+                rows32[0 * 2 * BC_TAU_WORDS + c] = v0[j].x;
+                rows32[1 * 2 * BC_TAU_WORDS + c] = v0[j].y;
+                rows32[2 * 2 * BC_TAU_WORDS + c] = v0[j].z;
+                rows32[3 * 2 * BC_TAU_WORDS + c] = v0[j].w;
+                rows32[4 * 2 * BC_TAU_WORDS + c] = v1[j].x;
+                rows32[5 * 2 * BC_TAU_WORDS + c] = v1[j].y;
+                rows32[6 * 2 * BC_TAU_WORDS + c] = v1[j].z;
+                rows32[7 * 2 * BC_TAU_WORDS + c] = v1[j].w;
             }
         } else {
             for (int e = tid; e < T * 2 * BC_TAU_WORDS; e += nth) {
@@ -995,9 +1181,12 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *
         }
         __syncthreads();
         bc16_rows<true>(rows, T, tid, nth);
-        for (int e = tid; e < T * EW; e += nth) {
-            const int k = e / EW, w = e % EW, q = q0 + k;
-            X[(uint64_t)q * EW + w] = bc_bits(rows + k * BC_TAU_WORDS, BC_TAU_WORDS, 64L * w - q);
+        // row by row: no division by the run-time row length
+        for (int k = 0; k < T; ++k) {
+            const int q = q0 + k;
+            const uint64_t *rk = rows + k * BC_TAU_WORDS;
+            uint64_t *xq = X + (uint64_t)q * EW;
+            for (int w = tid; w < EW; w += nth) xq[w] = bc_bits(rk, BC_TAU_WORDS, 64L * w - q);
         }
         __syncthreads();
     }

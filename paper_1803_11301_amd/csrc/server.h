@@ -101,13 +101,17 @@ static int srv_launch(polymul_server *S, SrvSlot &slot)
         // four buffers of the words product_body asks for; never launch on a
         // reservation smaller than that (plan.h sizes both, and the CPU check
         // of tests/native/plan_check.cpp holds them together)
-        const uint64_t words = fpmul_plan::product_ws_words(r.la, r.lb, v->large_field_log2n);
+        const uint64_t words = r.fa ? fpmul_plan::ws_words_for(r.res_log2n)
+                                    : fpmul_plan::product_ws_words(r.la, r.lb, v->large_field_log2n);
         if (4 * words * 8 > p.bytes)
             return fail(POLYMUL_EIO, "server reservation of " + std::to_string(p.bytes) + " bytes is smaller than the " +
                                          std::to_string(4 * words * 8) + " bytes of the product's workspace");
         for (int k = 0; k < 4; ++k) v->ws[k] = reinterpret_cast<uint64_t *>(base + (size_t)k * words * 8);
         v->ws_words = words;
-        rc = product_body(v, r.a, r.la, r.b, r.lb, r.out, s);
+        if (r.fa)
+            rc = resident_body(v, r.fa, r.res_log2n, r.b, r.lb, r.out, r.la + r.lb - 1, s);
+        else
+            rc = product_body(v, r.a, r.la, r.b, r.lb, r.out, s);
     } else {
         const uint32_t count = (uint32_t)p.reqs.size();
         const size_t wsb = batch_ws_bytes(v, count, p.max_lc);
@@ -207,6 +211,7 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
         slot.view->psteps = ctx->psteps;
         slot.view->bsteps = ctx->bsteps;
         slot.view->num_cu = ctx->num_cu;
+        slot.view->tuned = ctx->tuned;
         slot.view->small_field_log2n = ctx->small_field_log2n;
         slot.view->large_field_log2n = M64_MAX_LOG2N + 1;   // the server admits m = 64 products only
         slot.view->borrowed = true;
@@ -302,6 +307,52 @@ int polymul_submit(polymul_server *S, const uint64_t *a, uint64_t len_a, const u
             r.a = a;
             r.b = b;
             r.out = out;
+            S->pending.push_back(r);
+        }
+        *ticket = id;
+    }
+    S->cv_work.notify_all();
+    return 0;
+}
+
+int polymul_submit_resident(polymul_server *S, const polymul_resident *res, const uint64_t *b, uint64_t len_b,
+                            uint64_t *out, uint64_t *ticket)
+{
+    if (!S || !ticket || !res) return fail(POLYMUL_EINVAL, "server, resident operand or ticket pointer is null");
+    *ticket = 0;
+    if (res->device != S->ctx->device) return fail(POLYMUL_EINVAL, "resident operand is on another device");
+    const bool empty = len_b == 0;
+    if (!empty) {
+        if (res->len_a + len_b - 1 > (1ull << res->log2n))
+            return fail(POLYMUL_EINVAL, "product longer than the resident operand's transform");
+        DeviceGuard g(S->ctx->device);
+        HIP_TRY(g.err);
+        int rc;
+        if ((rc = check_dev_ptr(b, "b_bits")) || (rc = check_dev_ptr(out, "out"))) return rc;
+        const uint64_t lc = res->len_a + len_b - 1;
+        if (ranges_overlap(out, (size_t)((lc + 63) / 64) * 8, b, (size_t)((len_b + 63) / 64) * 8))
+            return fail(POLYMUL_EINVAL, "out overlaps an input");
+        const uint64_t need = S->fp.single(1ull << res->log2n);
+        if (fpmul_srv::Arena::round(need) > S->arena.size())
+            return fail(POLYMUL_ENOMEM, "request needs " + std::to_string(need) + " bytes, more than the server budget");
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->m);
+        const uint64_t id = S->next_ticket++;
+        SrvTicket &tk = S->tickets[id];
+        tk.t_submit = srv_now_ns(S->t0);
+        if (empty) {
+            tk.state = 2;
+            tk.t_start = tk.t_done = tk.t_submit;
+        } else {
+            fpmul_srv::Req r;
+            r.ticket = id;
+            r.la = res->len_a;
+            r.lb = len_b;
+            r.b = b;
+            r.out = out;
+            r.fa = res->vals;
+            r.res_log2n = res->log2n;
             S->pending.push_back(r);
         }
         *ticket = id;

@@ -3,7 +3,8 @@
 // Requests wait in arrival order.  A request is admitted when a launch slot
 // is free and its workspace fits in the server's device-memory arena; small
 // products (at most `batch_limit_bits`) are grouped, in arrival order, into
-// one batched launch, large ones run on a slot of their own.  A later request
+// one batched launch, large ones (and every product on a resident operand's
+// kept transform) run on a slot of their own.  A later request
 // may pass an earlier one that does not fit yet, but a request that has been
 // passed `starve_after` times blocks all later ones until it is admitted.
 #pragma once
@@ -83,6 +84,11 @@ struct Req {
     const uint64_t *a = nullptr, *b = nullptr;
     uint64_t *out = nullptr;
     uint32_t skipped = 0;
+    // a request on a resident operand: A's forward transform of 2^res_log2n
+    // bits is kept on the device (fa); it always runs alone, on the
+    // workspace of that transform length
+    const uint64_t *fa = nullptr;
+    int res_log2n = 0;
 };
 
 struct Policy {
@@ -107,6 +113,9 @@ struct Plan {
 
 inline uint64_t product_bits(const Req &r) { return r.la + r.lb - 1; }
 
+// the length whose single-launch footprint holds the request
+inline uint64_t launch_bits(const Req &r) { return r.fa ? (1ull << r.res_log2n) : product_bits(r); }
+
 // Takes the next launch out of `pending` if one can be admitted now.
 inline bool next_plan(std::deque<Req> &pending, Arena &arena, const Policy &P, const Footprint &F, Plan &out)
 {
@@ -116,12 +125,12 @@ inline bool next_plan(std::deque<Req> &pending, Arena &arena, const Policy &P, c
         const Req &r = pending[idx];
         std::vector<size_t> group;
         uint64_t bytes = 0, max_lc = 0;
-        bool batch = product_bits(r) <= P.batch_limit_bits;
+        bool batch = !r.fa && product_bits(r) <= P.batch_limit_bits;
         uint64_t off = 0;
         if (batch) {
             for (size_t j = idx; j < n && group.size() < P.max_batch; ++j) {
                 const Req &q = pending[j];
-                if (product_bits(q) > P.batch_limit_bits) continue;
+                if (q.fa || product_bits(q) > P.batch_limit_bits) continue;
                 group.push_back(j);
                 max_lc = product_bits(q) > max_lc ? product_bits(q) : max_lc;
             }
@@ -134,7 +143,7 @@ inline bool next_plan(std::deque<Req> &pending, Arena &arena, const Policy &P, c
             }
         } else {
             group.assign(1, idx);
-            max_lc = product_bits(r);
+            max_lc = launch_bits(r);
             bytes = F.single(max_lc);
             if (!arena.alloc(bytes, off)) continue;
         }

@@ -29,10 +29,22 @@ SIGNATURES = {
     "polymul_batch": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _V]),
     "polymul_set_small_field": (_I, [_V, _I]),
     "polymul_set_large_field": (_I, [_V, _I]),
+    "polymul_tune": (_I, [_V, _I, _I, ctypes.c_char_p, ctypes.c_char_p, _SZ]),
+    "polymul_tune_load": (_I, [_V, ctypes.c_char_p, ctypes.POINTER(_I)]),
+    "polymul_tune_get": (_I, [_V, _I, ctypes.c_char_p, _SZ]),
+    "polymul_graph_create": (_I, [_V, _P, _U64, _P, _U64, _P, ctypes.POINTER(_V)]),
+    "polymul_batch_graph_create": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P,
+                                        ctypes.POINTER(_V)]),
+    "polymul_graph_launch": (_I, [_V, _V]),
+    "polymul_graph_destroy": (_I, [_V]),
     "polymul_server_create": (_I, [ctypes.POINTER(_V), _V, _SZ, ctypes.c_uint32]),
     "polymul_server_destroy": (_I, [_V]),
     "polymul_server_set_policy": (_I, [_V, _U64, ctypes.c_uint32]),
     "polymul_submit": (_I, [_V, _P, _U64, _P, _U64, _P, ctypes.POINTER(_U64)]),
+    "polymul_submit_resident": (_I, [_V, _V, _P, _U64, _P, ctypes.POINTER(_U64)]),
+    "polymul_resident_create": (_I, [_V, _P, _U64, _U64, ctypes.POINTER(_V)]),
+    "polymul_resident_destroy": (_I, [_V]),
+    "polymul_resident_mul": (_I, [_V, _V, _P, _U64, _P, _V]),
     "polymul_poll": (_I, [_V, _U64, ctypes.POINTER(_I)]),
     "polymul_wait": (_I, [_V, _U64]),
     "polymul_wait_times": (_I, [_V, _U64, ctypes.POINTER(_U64), ctypes.POINTER(_U64), ctypes.POINTER(_U64)]),
@@ -175,6 +187,26 @@ class Context:
         over GF(2^128); transforms above 2^37 bits always do."""
         _check(lib().polymul_set_large_field(self.handle, min_log2n))
 
+    def tune(self, log2n: int, reps: int = 3, cache_path=None) -> str:
+        """polymul_tune: time the fused path's schedules for 2^log2n-bit
+        transforms, keep the fastest; returns the one-line report."""
+        buf = ctypes.create_string_buffer(512)
+        _check(lib().polymul_tune(self.handle, log2n, reps,
+                                  None if cache_path is None else os.fsencode(cache_path), buf, len(buf)))
+        return buf.value.decode()
+
+    def tune_load(self, cache_path) -> int:
+        """polymul_tune_load: apply the cache lines for this device; returns their number."""
+        n = ctypes.c_int()
+        _check(lib().polymul_tune_load(self.handle, os.fsencode(cache_path), ctypes.byref(n)))
+        return n.value
+
+    def schedule(self, log2n: int) -> str:
+        """polymul_tune_get: the schedule used for 2^log2n-bit transforms."""
+        buf = ctypes.create_string_buffer(256)
+        _check(lib().polymul_tune_get(self.handle, log2n, buf, len(buf)))
+        return buf.value.decode()
+
     def addfft(self, a, len_a: int, log2n: int, values=None, stream=None):
         import torch
         if values is None:
@@ -216,6 +248,77 @@ def polymul(a, len_a: int, b, len_b: int, out=None):
     return out
 
 
+class Graph:
+    """A captured launch chain (polymul_graph_create or
+    polymul_batch_graph_create), replayed with launch()."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    @classmethod
+    def product(cls, ctx: "Context", a, len_a: int, b, len_b: int, out) -> "Graph":
+        h = ctypes.c_void_p()
+        _check(lib().polymul_graph_create(ctx.handle, _dptr(a), len_a, _dptr(b), len_b, _dptr(out),
+                                          ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def batch(cls, ctx: "Context", a_pool, a_off, len_a, b_pool, b_off, len_b, out_pool, out_off,
+              max_product_bits: int, status=None) -> "Graph":
+        h = ctypes.c_void_p()
+        _check(lib().polymul_batch_graph_create(ctx.handle, int(len_a.numel()), _dptr(a_pool), _dptr(a_off),
+                                                _dptr(len_a), _dptr(b_pool), _dptr(b_off), _dptr(len_b),
+                                                _dptr(out_pool), _dptr(out_off), max_product_bits,
+                                                status.data_ptr() if status is not None else None,
+                                                ctypes.byref(h)))
+        return cls(h)
+
+    def launch(self, stream=None):
+        _check(lib().polymul_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().polymul_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Resident:
+    """An operand kept on the device as its forward transform
+    (polymul_resident_create), for products with many B."""
+
+    def __init__(self, ctx: "Context", a, len_a: int, max_product_bits: int):
+        h = ctypes.c_void_p()
+        _check(lib().polymul_resident_create(ctx.handle, _dptr(a), len_a, max_product_bits, ctypes.byref(h)))
+        self.handle = h
+        self.len_a = len_a
+
+    def mul(self, ctx: "Context", b, len_b: int, out=None, stream=None):
+        """C = A * B reusing A's transform, stream-ordered; returns out."""
+        import torch
+        lc = self.len_a + len_b - 1 if len_b else 0
+        if out is None:
+            out = torch.empty(max(1, nwords(lc)), dtype=torch.int64, device=b.device)
+        _check(lib().polymul_resident_mul(ctx.handle, self.handle, _dptr(b), len_b, _dptr(out), _stream(stream)))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().polymul_resident_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Continuous-batching product server on a Context (polymul_server_* in fpmul.h).
 
@@ -253,6 +356,12 @@ class Server:
         t = ctypes.c_uint64()
         _check(lib().polymul_submit(self.handle, self._addr(a), len_a, self._addr(b), len_b, self._addr(out),
                                     ctypes.byref(t)))
+        return t.value
+
+    def submit_resident(self, res: "Resident", b, len_b: int, out) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().polymul_submit_resident(self.handle, res.handle, self._addr(b), len_b, self._addr(out),
+                                             ctypes.byref(t)))
         return t.value
 
     def poll(self, ticket: int) -> bool:

@@ -121,8 +121,53 @@ static void fused_buffers_fit()
     std::printf("ok fused_buffers_fit\n");
 }
 
+// the tuner's schedule space: every candidate split of the upper butterfly
+// layers is valid (parts 1..7 summing to l - 7, the lowest at least 5), the
+// default split is among them, no candidate repeats, and a cache line
+// written for a schedule parses back to it (and only for its own device)
+static void schedule_space()
+{
+    for (int l = 16; l <= 25; ++l) {
+        const auto cands = upper_candidates(l);
+        const auto def = default_upper(l);
+        CHECK(upper_valid(l, def), "l=%d default split invalid", l);
+        bool has_def = false;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            CHECK(upper_valid(l, cands[i]), "l=%d candidate %zu invalid", l, i);
+            has_def = has_def || cands[i] == def;
+            for (size_t j = i + 1; j < cands.size(); ++j) CHECK(cands[i] != cands[j], "l=%d repeated candidate", l);
+        }
+        CHECK(has_def, "l=%d default split not among the candidates", l);
+        for (const auto &u : cands) {
+            Schedule s;
+            s.upper = u;
+            s.rows_mult = 1 + (int)(u.size() % 4);
+            s.zeta_mult = 4 << (u[0] % 3);
+            const std::string line = schedule_line("gfx950", 256, l + 6, s, 1.25);
+            int lg = 0;
+            Schedule r;
+            CHECK(schedule_parse(line.c_str(), "gfx950", 256, lg, r), "%s does not parse", line.c_str());
+            CHECK(lg == l + 6 && r.upper == s.upper && r.rows_mult == s.rows_mult && r.zeta_mult == s.zeta_mult,
+                  "%s parses to another schedule", line.c_str());
+            CHECK(!schedule_parse(line.c_str(), "gfx942", 256, lg, r), "%s applied to another arch", line.c_str());
+            CHECK(!schedule_parse(line.c_str(), "gfx950", 304, lg, r), "%s applied to another CU count", line.c_str());
+        }
+    }
+    int lg = 0;
+    Schedule r;
+    // malformed or invalid lines are refused
+    for (const char *bad : {"gfx950 cu=256 log2n=31 upper=4,7,7 rows=2 zeta=8 ms=1",   // lowest pass below 5
+                            "gfx950 cu=256 log2n=31 upper=6,6,5 rows=2 zeta=8 ms=1",   // 17 layers, not 18
+                            "gfx950 cu=256 log2n=31 upper=6,6,6 rows=0 zeta=8 ms=1",   // no row workgroups
+                            "gfx950 cu=256 log2n=21 upper=- rows=2 zeta=8 ms=1",       // outside the fused path
+                            "gfx950 cu=256 log2n=31 upper=6,x,6 rows=2 zeta=8 ms=1", "garbage"})
+        CHECK(!schedule_parse(bad, "gfx950", 256, lg, r), "accepted: %s", bad);
+    if (!failures) std::printf("ok schedule_space\n");
+}
+
 int main()
 {
+    schedule_space();
     ilog2_is_ceiling();
     transform_holds_the_product();
     server_reservation_holds_the_workspace();

@@ -223,8 +223,37 @@ static void simulated_stream()
     std::printf("ok simulated_stream peak=%llu\n", (unsigned long long)peak);
 }
 
+// a product on a resident operand's kept transform is never batched, even
+// when it is short, and reserves the single-launch footprint of the resident
+// transform length, not of its own product length
+static void resident_runs_alone_at_its_length()
+{
+    Policy P;
+    P.batch_limit_bits = 1000;
+    Arena A(1 << 20);
+    std::deque<Req> q;
+    static const uint64_t fa = 0;
+    q.push_back(req(1, 10, 10));
+    Req r = req(2, 20, 20);
+    r.fa = &fa;
+    r.res_log2n = 12;
+    q.push_back(r);
+    q.push_back(req(3, 30, 30));
+    Plan p;
+    CHECK(next_plan(q, A, P, toy_fp(), p));
+    CHECK(p.batch && p.reqs.size() == 2 && p.reqs[0].ticket == 1 && p.reqs[1].ticket == 3);
+    CHECK(q.size() == 1 && q[0].ticket == 2);
+    Plan p2;
+    CHECK(next_plan(q, A, P, toy_fp(), p2));
+    CHECK(!p2.batch && p2.reqs.size() == 1 && p2.reqs[0].ticket == 2 && p2.reqs[0].fa == &fa);
+    CHECK(p2.bytes == 4096 && p2.max_lc == 4096);
+    CHECK(q.empty());
+    std::printf("ok resident_runs_alone_at_its_length\n");
+}
+
 int main()
 {
+    resident_runs_alone_at_its_length();
     arena_basics();
     arena_random();
     batches_small_in_order();

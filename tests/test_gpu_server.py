@@ -195,3 +195,66 @@ def test_tickets_are_released_by_wait(ctx):
     with pytest.raises(fpmul.FpmulError):
         srv.times(tks[-1])
     srv.close()
+
+
+def test_resident_operand_in_the_mix(ctx):
+    # transform reuse (f2): one operand kept on the device as its forward
+    # transform, multiplied by many B inside a mix of ordinary requests; every
+    # product equals the same product computed alone (polymul_ex) and the oracle
+    from paper_1803_11301_amd import fpmul
+    la = (1 << 20) + 333
+    say("resident operand", la, "bits in a server mix")
+    rng = random.Random(5150)
+    a = synth.dense_poly(0x5EED2000, la)
+    ta = dev64(a)
+    res = fpmul.Resident(ctx, ta, la, 1 << 22)          # transforms of 2^22 bits
+    srv = fpmul.Server(ctx, hbm_budget=1 << 30, slots=4)
+    try:
+        jobs = []
+        for k in range(24):
+            lb = [1, 63, 64, 4097, (1 << 16) + 5, (1 << 20) - 1, (1 << 21) + 7][k % 7]
+            lb = min(lb, (1 << 22) + 1 - la)
+            b = synth.dense_poly(0x5EED2100 + k, lb)
+            tb = dev64(b)
+            out = torch.full((O.nwords(la + lb - 1),), -1, dtype=torch.int64, device="cuda")
+            jobs.append((b, lb, tb, out))
+            if k % 3 == 2:   # an ordinary request between the resident ones
+                x = 1000 + 37 * k
+                c = synth.dense_poly(0x5EED2200 + k, x)
+                tc = dev64(c)
+                o2 = torch.full((O.nwords(x + x - 1),), -1, dtype=torch.int64, device="cuda")
+                jobs.append((("plain", c, x), x, tc, o2))
+        torch.cuda.synchronize()
+        tickets = []
+        for b, lb, tb, out in jobs:
+            if isinstance(b, tuple):
+                tickets.append(srv.submit(tb, lb, tb, lb, out))
+            else:
+                tickets.append(srv.submit_resident(res, tb, lb, out))
+        for tk in tickets:
+            srv.wait(tk)
+        torch.cuda.synchronize()
+        for (b, lb, tb, out) in jobs:
+            if isinstance(b, tuple):
+                _, c, x = b
+                assert np.array_equal(host(out, O.nwords(2 * x - 1)), O.polymul(c, x, c, x))
+                continue
+            n = O.nwords(la + lb - 1)
+            got = host(out, n)
+            alone = ctx.polymul(ta, la, tb, lb)
+            torch.cuda.synchronize()
+            assert np.array_equal(got, host(alone, n)), f"resident x {lb} bits differs from polymul_ex"
+            check_against_oracle(a, la, b, lb, got, rng)
+        say("resident operand, direct (no server)")
+        b = synth.dense_poly(0x5EED2300, 3000000)
+        tb = dev64(b)
+        got = res.mul(ctx, tb, 3000000)
+        torch.cuda.synchronize()
+        check_against_oracle(a, la, b, 3000000, host(got, O.nwords(la + 3000000 - 1)), rng)
+        say("resident operand errors")
+        with pytest.raises(fpmul.FpmulError) as ei:
+            res.mul(ctx, tb, (1 << 22) - la + 2)       # longer than the kept transform
+        assert ei.value.code == fpmul.EINVAL
+    finally:
+        srv.close()
+        res.close()

@@ -22,7 +22,8 @@ def test_policy_and_arena(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     for name in ("arena_basics", "arena_random", "batches_small_in_order", "large_runs_alone_and_batch_skips_it",
-                 "budget_and_starvation", "max_batch_respected", "batch_shrinks_to_fit", "simulated_stream"):
+                 "budget_and_starvation", "max_batch_respected", "batch_shrinks_to_fit", "simulated_stream",
+                 "resident_runs_alone_at_its_length"):
         assert f"ok {name}" in r.stdout
 
 
@@ -42,5 +43,5 @@ def test_launch_sizing_rules(tmp_path):
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
     for name in ("ilog2_is_ceiling", "transform_holds_the_product", "server_reservation_holds_the_workspace",
-                 "workspace_holds_every_route", "fused_buffers_fit"):
+                 "workspace_holds_every_route", "fused_buffers_fit", "schedule_space"):
         assert f"ok {name}" in r.stdout
