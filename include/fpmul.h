@@ -91,6 +91,27 @@ int polymul_ctx_destroy(polymul_ctx *ctx);
 int polymul_ex(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a,
                const uint64_t *b_bits, uint64_t len_b, uint64_t *out, void *stream);
 
+/* Largest product length, in bits, of polymul_ex_noalloc. */
+#define POLYMUL_NOALLOC_MAX_PRODUCT_BITS (1ull << 25)
+
+/*
+ * polymul_ex_noalloc -- polymul_ex for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and stream semantics as
+ * polymul_ex; the call itself allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  Its workspace is a file-scope device array of
+ * the library (about 17 MiB, one copy per GPU, held until the process ends),
+ * whose address polymul_ctx_create looks up; ctx supplies the constant tables
+ * uploaded then.  Products longer than POLYMUL_NOALLOC_MAX_PRODUCT_BITS
+ * (len_a + len_b - 1 bits, or an operand longer than that) return
+ * POLYMUL_EINVAL.  Every call on one GPU shares that GPU's array and leaves
+ * its contents behind (no call depends on what an earlier one left): calls
+ * that overlap on one GPU (two streams, or two host threads) race and must be
+ * serialised by the caller.
+ */
+int polymul_ex_noalloc(polymul_ctx *ctx, const uint64_t *a_bits, uint64_t len_a,
+                       const uint64_t *b_bits, uint64_t len_b, uint64_t *out, void *stream);
+
 /* Largest product length, in bits, of one item of polymul_batch. */
 #define POLYMUL_BATCH_MAX_PRODUCT_BITS (1ull << 22)
 

@@ -322,6 +322,7 @@ struct polymul_ctx {
     int large_field_log2n = LARGE_FIELD_DEFAULT_LOG2N;
     DevTables128 *tables128 = nullptr;   // built on the first m = 128 product
     PStepTable *psteps = nullptr;        // BasisCvt step lists of the per-step path
+    uint64_t *scratch = nullptr;         // device address of this GPU's `scratch` (polymul_ex_noalloc)
     // schedules of the fused path chosen by polymul_tune (or loaded from its
     // cache), by log2 of the transform length; views point at their parent's
     std::map<int, fpmul_plan::Schedule> tuned_own;
@@ -1449,6 +1450,31 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
 }
 
 // ---------------------------------------------------------------------------
+// The workspace of polymul_ex_noalloc: a file-scope device array, one copy
+// per GPU that the library runs on, held until the process ends.  Host code
+// never names it except to look up its device address, once per device with
+// that device current; kernels get that address.
+// ---------------------------------------------------------------------------
+
+static __device__ __align__(256) uint64_t scratch[fpmul_plan::NOALLOC_SCRATCH_WORDS];
+
+static int scratch_address(int device, uint64_t **out)
+{
+    static std::mutex mu;
+    static std::map<int, uint64_t *> addr;   // device -> address of its copy
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it == addr.end()) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the caller made `device` current
+        if (e != hipSuccess || !p)
+            return fail(POLYMUL_EIO, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = addr.emplace(device, static_cast<uint64_t *>(p)).first;
+    }
+    *out = it->second;
+    return 0;
+}
+
 // ---------------------------------------------------------------------------
 // captured launch chains (polymul_graph_*): the kernels of one product (or of
 // one batch) recorded once into a HIP graph on a private stream and replayed
@@ -1622,6 +1648,14 @@ int polymul_ctx_create(polymul_ctx **out, int device, size_t workspace_cap)
         delete ctx;
         return fail(POLYMUL_EIO, std::string("upload tables: ") + hipGetErrorString(e));
     }
+    // everything polymul_ex_noalloc needs is in place before its first call:
+    // the batch step lists and the address of this device's scratch
+    int rc = batch_steps_upload(ctx);
+    if (!rc) rc = scratch_address(device, &ctx->scratch);
+    if (rc) {
+        (void)polymul_ctx_destroy(ctx);
+        return rc;
+    }
     *out = ctx;
     return 0;
 }
@@ -1674,6 +1708,54 @@ int polymul_ex(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64
                           1ull << log2n, nullptr, (hipStream_t)stream, &one);
     }
     return product_body(ctx, a, len_a, b, len_b, out, (hipStream_t)stream);
+}
+
+int polymul_ex_noalloc(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,
+                       uint64_t *out, void *stream)
+{
+    if (!ctx) return fail(POLYMUL_EINVAL, "ctx is null");
+    if (len_a == 0 || len_b == 0) return 0;
+    if (len_a > (1ull << fpmul_plan::NOALLOC_MAX_LOG2N) || len_b > (1ull << fpmul_plan::NOALLOC_MAX_LOG2N) ||
+        len_a + len_b - 1 > (1ull << fpmul_plan::NOALLOC_MAX_LOG2N))
+        return fail(POLYMUL_EINVAL, "polymul_ex_noalloc takes products of at most 2^" +
+                                        std::to_string(fpmul_plan::NOALLOC_MAX_LOG2N) +
+                                        " bits (its device scratch holds one such product's workspace); "
+                                        "polymul_ex takes longer ones");
+    if (!ctx->scratch) return fail(POLYMUL_EIO, "ctx has no device scratch address");
+    const uint64_t lc = len_a + len_b - 1;
+    DeviceGuard g(ctx->device);
+    HIP_TRY(g.err);
+    int rc;
+    if ((rc = check_dev_ptr(a, "a_bits")) || (rc = check_dev_ptr(b, "b_bits")) || (rc = check_dev_ptr(out, "out")))
+        return rc;
+    size_t ob = (size_t)((lc + 63) / 64) * 8;
+    if (ranges_overlap(out, ob, a, (size_t)((len_a + 63) / 64) * 8) ||
+        ranges_overlap(out, ob, b, (size_t)((len_b + 63) / 64) * 8))
+        return fail(POLYMUL_EINVAL, "out overlaps an input");
+    // a view of ctx whose workspaces are slices of the scratch: borrowed, so
+    // nothing on the path below grows or frees them
+    polymul_ctx view;
+    view.device = ctx->device;
+    view.tables = ctx->tables;
+    view.psteps = ctx->psteps;
+    view.bsteps = ctx->bsteps;
+    view.num_cu = ctx->num_cu;
+    view.tuned = ctx->tuned;
+    view.small_field_log2n = ctx->small_field_log2n;
+    view.large_field_log2n = M64_MAX_LOG2N + 1;   // every product it takes is m = 64
+    view.borrowed = true;
+    for (int k = 0; k < 4; ++k) view.ws[k] = ctx->scratch + (uint64_t)k * fpmul_plan::NOALLOC_WS_WORDS;
+    view.ws_words = fpmul_plan::NOALLOC_WS_WORDS;
+    view.bws = ctx->scratch + 4 * fpmul_plan::NOALLOC_WS_WORDS;
+    view.bws_bytes = fpmul_plan::NOALLOC_BWS_BYTES;
+    if (!view.bsteps) return fail(POLYMUL_EIO, "ctx has no batch step lists");
+    const int log2n = transform_log2(len_a, len_b);
+    if (log2n <= SINGLE_VIA_BATCH_LOG2N) {
+        const BtDesc one{a, b, out, len_a, len_b};
+        return batch_body(&view, 1, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                          1ull << log2n, nullptr, (hipStream_t)stream, &one);
+    }
+    return product_body(&view, a, len_a, b, len_b, out, (hipStream_t)stream);
 }
 
 int polymul_graph_create(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, const uint64_t *b, uint64_t len_b,

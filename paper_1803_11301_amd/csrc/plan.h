@@ -15,6 +15,7 @@ constexpr int M64_MAX_LOG2N = 37;        // m = 64 field bound: n <= (m/2) 2^(m/
 constexpr int FUSED_MIN_LOG2N = 22;      // the fused BasisCvt/Encode/Decode path: 2^22 <= n ...
 constexpr int FUSED_MAX_LOG2N = 31;      // ... <= 2^31 bits
 constexpr int SINGLE_VIA_BATCH_LOG2N = 17;   // polymul_ex of products up to 2^17 bits: a one-item batch
+constexpr int NOALLOC_MAX_LOG2N = 25;        // polymul_ex_noalloc: products up to 2^25 bits
 
 constexpr int ilog2(uint64_t x)   // ceil(log2 x), 0 for x <= 1
 {
@@ -84,6 +85,18 @@ constexpr uint64_t product_ws_words(uint64_t la, uint64_t lb, int large_field_lo
 // device bytes the server reserves for one single-product launch of lc bits
 // (it admits m = 64 products only)
 constexpr uint64_t single_launch_bytes(uint64_t lc) { return 4 * ws_words_for(product_log2n(lc)) * 8; }
+
+}  // namespace fpmul_plan
+
+namespace fpmul_plan {
+
+// the device scratch of polymul_ex_noalloc: four workspace buffers for the
+// largest product it takes, then the batch workspace of a one-item batch
+// (grid 1, one slab of four 2^SINGLE_VIA_BATCH_LOG2N-bit buffers, the queue
+// order and the counter, as the library's batch layout sizes them)
+constexpr uint64_t NOALLOC_WS_WORDS = ws_words_for(NOALLOC_MAX_LOG2N);
+constexpr uint64_t NOALLOC_BWS_BYTES = 4 * (1ull << (SINGLE_VIA_BATCH_LOG2N - 6)) * 8 + 256 + 256;
+constexpr uint64_t NOALLOC_SCRATCH_WORDS = 4 * NOALLOC_WS_WORDS + NOALLOC_BWS_BYTES / 8;
 
 }  // namespace fpmul_plan
 

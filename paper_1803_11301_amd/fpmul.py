@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libfpmul.so")
 
 EIO, ENOMEM, EINVAL = -5, -12, -22
 M64_MAX_PRODUCT_BITS = 1 << 37
+NOALLOC_MAX_PRODUCT_BITS = 1 << 25
 MAX_PRODUCT_BITS = 1 << 62
 SERVER_MAX_PRODUCT_BITS = M64_MAX_PRODUCT_BITS
 BATCH_MAX_PRODUCT_BITS = 1 << 22
@@ -26,6 +27,7 @@ SIGNATURES = {
     "polymul_ctx_create": (_I, [ctypes.POINTER(_V), _I, _SZ]),
     "polymul_ctx_destroy": (_I, [_V]),
     "polymul_ex": (_I, [_V, _P, _U64, _P, _U64, _P, _V]),
+    "polymul_ex_noalloc": (_I, [_V, _P, _U64, _P, _U64, _P, _V]),
     "polymul_batch": (_I, [_V, ctypes.c_uint32, _P, _P, _P, _P, _P, _P, _P, _P, _U64, _P, _V]),
     "polymul_set_small_field": (_I, [_V, _I]),
     "polymul_set_large_field": (_I, [_V, _I]),
@@ -158,6 +160,13 @@ class Context:
         if out is None:
             out = torch.empty(max(1, nwords(lc)), dtype=torch.int64, device=a.device)
         _check(lib().polymul_ex(self.handle, _dptr(a), len_a, _dptr(b), len_b, _dptr(out), _stream(stream)))
+        return out
+
+    def polymul_noalloc(self, a, len_a: int, b, len_b: int, out, stream=None):
+        """polymul_ex_noalloc: the same product with the library's device
+        scratch as workspace (products up to 2^25 bits; out is required)."""
+        _check(lib().polymul_ex_noalloc(self.handle, _dptr(a), len_a, _dptr(b), len_b, _dptr(out),
+                                        _stream(stream)))
         return out
 
     def polymul_batch(self, a_pool, a_off, len_a, b_pool, b_off, len_b, out_pool, out_off,
