@@ -664,9 +664,11 @@ __device__ __forceinline__ int bc_swz(int r, int sws)
 // elements per access (V divides d, so both operands of every access are
 // V-aligned).  A phase writes elements it does not read, so every thread
 // issues all its reads before its writes.
-#ifndef BC_PHASE_BATCH
-#define BC_PHASE_BATCH 4   // items of a phase whose reads a thread issues together
-#endif
+// items of a phase whose reads a thread issues together: four 16-byte
+// accesses for 32-bit columns; two for 64-bit ones, whose kernel also holds
+// the next column's 16 words in registers and would spill with four
+template <typename T>
+constexpr int bc_phase_batch() { return sizeof(T) == 8 ? 2 : 4; }
 template <int LGS, int LGD, int PHASE, int LGN, int LGT, typename T>
 __device__ __forceinline__ void bc_elem_phase(T *col, int off, int tid, int sws)
 {
@@ -704,7 +706,7 @@ __device__ __forceinline__ void bc_elem_phase(T *col, int off, int tid, int sws)
         }
         return a;
     };
-    constexpr int CH = PER < BC_PHASE_BATCH ? PER : BC_PHASE_BATCH;
+    constexpr int CH = PER < bc_phase_batch<T>() ? PER : bc_phase_batch<T>();
 #pragma unroll
     for (int p0 = 0; p0 < PER; p0 += CH) {
         VT x[CH], y[CH];
@@ -1042,6 +1044,7 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64
         __syncthreads();
         if (c + (int)gridDim.x < BC_TAU_WORDS) load(c + gridDim.x, tid_c);   // in flight during this column
         bc_elem_steps_any<uint64_t>(col, lgR, outer, false, tid_c, BC_COL_THREADS, sws);
+#pragma unroll 1
         for (int r0 = wave; r0 < rpj; r0 += NW) {
             const int rr = lane * rpj + r0;              // row of Encode input row j = lane
             uint64_t x = rr < R ? col[bc_swz<uint64_t>(rr, sws)] : 0ull;
