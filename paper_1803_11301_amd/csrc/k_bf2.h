@@ -281,9 +281,28 @@ __device__ __forceinline__ uint32_t b2_mulv8(const uint4 &q01, uint32_t q2, uint
     return (m & (w ^ sw)) | (~m & t);
 }
 
-// acc XOR x * (K16 + beta16): P0, P1 = tables of beta0, beta1; Q = tables of v7
+// x * beta16 on the two tower pairs a0 + a1 y of a 32-bit word, with y^2 =
+// y + c (c = v_7, Cantor byte 0x80) and beta16 = b0 + b1 y: the low byte of a
+// pair becomes a0 b0 + a1 (b1 c), the high byte a0 b1 + a1 (b0 + b1).  The
+// three byte products (by b0, b1 and b1 c; tables P0, P1, PC) share one set of
+// selectors, and one byte permutation places the cross terms.
+__device__ __forceinline__ uint32_t b2_mulv16(const uint4 &p0, uint32_t p02, const uint4 &p1, uint32_t p12,
+                                              const uint4 &pc, uint32_t pc2, uint32_t w)
+{
+    const uint32_t s0 = w & 0x07070707u, s1 = (w >> 3) & 0x07070707u, s2 = (w >> 6) & 0x03030303u;
+    auto pm = [&](const uint4 &t01, uint32_t t2) {
+        return xor3(__builtin_amdgcn_perm(t01.y, t01.x, s0), __builtin_amdgcn_perm(t01.w, t01.z, s1),
+                    __builtin_amdgcn_perm(t2, t2, s2));
+    };
+    const uint32_t a = pm(p0, p02), b = pm(p1, p12), bc = pm(pc, pc2);
+    // bytes (bc[1], b[0], bc[3], b[2]): a1 b1 c to the low byte, a0 b1 to the high byte
+    return xor3(a, __builtin_amdgcn_perm(bc, b, 0x02070005u), b & 0xFF00FF00u);
+}
+
+// acc XOR x * (K16 + beta16): tab = window table of K16, (P0, P1, PC) = byte
+// tables of b0, b1 and b1 c
 __device__ __forceinline__ uint64_t b2_mul_acc16(const uint64_t *__restrict__ tab, const uint4 &p0, uint32_t p02,
-                                                 const uint4 &p1, uint32_t p12, const uint4 &q01, uint32_t q2,
+                                                 const uint4 &p1, uint32_t p12, const uint4 &pc, uint32_t pc2,
                                                  uint64_t x, uint64_t acc)
 {
     const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
@@ -291,13 +310,12 @@ __device__ __forceinline__ uint64_t b2_mul_acc16(const uint64_t *__restrict__ ta
     const uint64_t v2 = tab[512 + ((lo >> 16) & 255u)], v3 = tab[768 + (lo >> 24)];
     const uint64_t v4 = tab[1024 + (hi & 255u)], v5 = tab[1280 + ((hi >> 8) & 255u)];
     const uint64_t v6 = tab[1536 + ((hi >> 16) & 255u)], v7 = tab[1792 + (hi >> 24)];
-    const uint32_t al = b2_pmul32(p0, p02, lo), ah = b2_pmul32(p0, p02, hi);
-    const uint32_t bl = b2_pmul32(p1, p12, b2_mulv8(q01, q2, lo)), bh = b2_pmul32(p1, p12, b2_mulv8(q01, q2, hi));
+    const uint32_t al = b2_mulv16(p0, p02, p1, p12, pc, pc2, lo), ah = b2_mulv16(p0, p02, p1, p12, pc, pc2, hi);
     const uint32_t rl = xor3(xor3((uint32_t)v0, (uint32_t)v1, (uint32_t)v2), xor3((uint32_t)v3, (uint32_t)v4,
-                             (uint32_t)v5), xor3((uint32_t)v6, (uint32_t)v7, al)) ^ bl ^ (uint32_t)acc;
+                             (uint32_t)v5), xor3((uint32_t)v6, (uint32_t)v7, al)) ^ (uint32_t)acc;
     const uint32_t rh = xor3(xor3((uint32_t)(v0 >> 32), (uint32_t)(v1 >> 32), (uint32_t)(v2 >> 32)),
                              xor3((uint32_t)(v3 >> 32), (uint32_t)(v4 >> 32), (uint32_t)(v5 >> 32)),
-                             xor3((uint32_t)(v6 >> 32), (uint32_t)(v7 >> 32), ah)) ^ bh ^ (uint32_t)(acc >> 32);
+                             xor3((uint32_t)(v6 >> 32), (uint32_t)(v7 >> 32), ah)) ^ (uint32_t)(acc >> 32);
     return (uint64_t)rl | ((uint64_t)rh << 32);
 }
 
@@ -307,7 +325,7 @@ __device__ __forceinline__ uint64_t b2_mul_acc16(const uint64_t *__restrict__ ta
 template <int M, bool INV, bool TWO>
 __device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], uint64_t (&xb)[8], const uint64_t *__restrict__ tab,
                                            const PermTab *__restrict__ s_pt8, const uint16_t (*s_io16)[256],
-                                           const uint4 &q01, uint32_t q2, uint32_t b_t, uint32_t bw1, uint32_t bw2)
+                                           uint32_t b_t, uint32_t bw1, uint32_t bw2)
 {
 #pragma unroll
     for (int u = 0; u < (1 << (2 - M)); ++u) {
@@ -323,21 +341,24 @@ __device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], uint64_t (&xb)[8],
         const PermTab *P0 = s_pt8 + (beta & 255u), *P1 = s_pt8 + (beta >> 8);
         const uint4 p0 = *reinterpret_cast<const uint4 *>(P0), p1 = *reinterpret_cast<const uint4 *>(P1);
         const uint32_t p02 = P0->t2, p12 = P1->t2;
+        const PermTab *PC = s_pt8 + ((p12 >> 16) & 255u);   // b1 c: entry 2 of P1's bit-6/7 table
+        const uint4 pc = *reinterpret_cast<const uint4 *>(PC);
+        const uint32_t pc2 = PC->t2;
 #pragma unroll
         for (int low = 0; low < (1 << M); ++low) {
             const int r0 = low | (u << (M + 1)), r1 = r0 | (1 << M);
             if (!INV) {
-                const uint64_t h0 = b2_mul_acc16(tab, p0, p02, p1, p12, q01, q2, xa[r1], xa[r0]);
+                const uint64_t h0 = b2_mul_acc16(tab, p0, p02, p1, p12, pc, pc2, xa[r1], xa[r0]);
                 xa[r1] ^= h0;
                 xa[r0] = h0;
                 if (TWO) {
-                    const uint64_t g0 = b2_mul_acc16(tab, p0, p02, p1, p12, q01, q2, xb[r1], xb[r0]);
+                    const uint64_t g0 = b2_mul_acc16(tab, p0, p02, p1, p12, pc, pc2, xb[r1], xb[r0]);
                     xb[r1] ^= g0;
                     xb[r0] = g0;
                 }
             } else {
                 const uint64_t p = xa[r0] ^ xa[r1];
-                xa[r0] = b2_mul_acc16(tab, p0, p02, p1, p12, q01, q2, p, xa[r0]);
+                xa[r0] = b2_mul_acc16(tab, p0, p02, p1, p12, pc, pc2, p, xa[r0]);
                 xa[r1] = p;
             }
         }
@@ -366,8 +387,7 @@ template <bool INV, bool TWO>
 __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&xa)[8], uint64_t (&xb)[8],
                                                   uint64_t (*s_tab)[2048], const PermTab *s_ptb,
                                                   const PermTab *s_pt8, const uint16_t (*s_io16)[256],
-                                                  const uint4 &q01, uint32_t q2, uint64_t gb_t,
-                                                  const DevTables *__restrict__ T)
+                                                  uint64_t gb_t, const DevTables *__restrict__ T)
 {
     auto run = [&](auto Mc) {
         constexpr int M = decltype(Mc)::value;
@@ -376,7 +396,7 @@ __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&x
         if (b2_wide(i)) {
             const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
             const uint32_t bw1 = (1u << g.s[1]) >> (i + 1), bw2 = (1u << g.s[2]) >> (i + 1);
-            b2_layer16<M, INV, TWO>(xa, xb, s_tab[M], s_pt8, s_io16, q01, q2, b_t, bw1 & 0x7FFFu, bw2 & 0x7FFFu);
+            b2_layer16<M, INV, TWO>(xa, xb, s_tab[M], s_pt8, s_io16, b_t, bw1 & 0x7FFFu, bw2 & 0x7FFFu);
         } else {
             const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
             const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 127u, bw2 = ((1u << g.s[2]) >> (i + 1)) & 127u;
@@ -418,9 +438,6 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
     for (int q = tid; q < 2 * 256; q += nth) (&s_io16[0][0])[q] = (uint16_t)(&T->iota[0][0])[q];
     b2_load_pbasis(s_pb, T, tid, nth);
     __syncthreads();
-    const PermTab *Q = s_pt8 + 0x80;   // v_7 = Cantor byte 0x80
-    const uint4 q01 = *reinterpret_cast<const uint4 *>(Q);
-    const uint32_t q2 = Q->t2;
 
     const uint64_t ntiles = 1ull << (l - B2_TILE_LG);
     // contiguous runs of tiles keep most layers' K (and the cached images) unchanged
@@ -473,7 +490,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
             for (int m = 0; m < 3; ++m) slot[m] = g.layer[m] ? g.s[m] : 0;
             b2_fill(g, s_tab, s_img, slot, tid, nth);
             __syncthreads();
-            b2_bottom_compute<INV, TWO>(g, xa, xb, s_tab, s_ptb, s_pt8, s_io16, q01, q2, gb_t, T);
+            b2_bottom_compute<INV, TWO>(g, xa, xb, s_tab, s_ptb, s_pt8, s_io16, gb_t, T);
             if (cc == NC - 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
