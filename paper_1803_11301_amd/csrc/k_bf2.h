@@ -319,46 +319,88 @@ __device__ __forceinline__ uint64_t b2_mul_acc16(const uint64_t *__restrict__ ta
     return (uint64_t)rl | ((uint64_t)rh << 32);
 }
 
+// byte tables of beta16 = b0 + b1 y: those of b0, b1 and b1 c.  They are
+// linear in beta16, so the tables of beta16 + d are those of beta16 XOR those of d.
+struct B16Tabs {
+    uint4 p0, p1, pc;
+    uint32_t p02, p12, pc2;
+};
+
+__device__ __forceinline__ B16Tabs b16_tabs(const PermTab *__restrict__ pt, uint32_t beta)
+{
+    B16Tabs t;
+    const PermTab *P0 = pt + (beta & 255u), *P1 = pt + (beta >> 8);
+    t.p0 = *reinterpret_cast<const uint4 *>(P0);
+    t.p1 = *reinterpret_cast<const uint4 *>(P1);
+    t.p02 = P0->t2;
+    t.p12 = P1->t2;
+    const PermTab *PC = pt + ((t.p12 >> 16) & 255u);   // b1 c: entry 2 of P1's bit-6/7 table
+    t.pc = *reinterpret_cast<const uint4 *>(PC);
+    t.pc2 = PC->t2;
+    return t;
+}
+
+__device__ __forceinline__ uint4 b16_xor4(const uint4 &a, const uint4 &b)
+{
+    return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
+}
+
+__device__ __forceinline__ B16Tabs b16_xor(const B16Tabs &a, const B16Tabs &b)
+{
+    B16Tabs t;
+    t.p0 = b16_xor4(a.p0, b.p0);
+    t.p1 = b16_xor4(a.p1, b.p1);
+    t.pc = b16_xor4(a.pc, b.pc);
+    t.p02 = a.p02 ^ b.p02;
+    t.p12 = a.p12 ^ b.p12;
+    t.pc2 = a.pc2 ^ b.pc2;
+    return t;
+}
+
 // one V_16 layer on register bit M: block of a pair = b_t | register bits
-// above M times bw; beta16 = iota(2 (b mod 2^15)) through the iota tables of
-// the low two bytes (s_io16), then the byte tables of its two tower bytes
+// above M times bw; beta16 = iota(2 (b mod 2^15)).  The thread's own beta16
+// comes through the iota tables of the low two Cantor bytes (s_io16) and its
+// byte tables from LDS; the blocks that differ in register bits above M add
+// iota(2 bw), the same for the whole workgroup, whose tables are read from T.
 template <int M, bool INV, bool TWO>
 __device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], uint64_t (&xb)[8], const uint64_t *__restrict__ tab,
                                            const PermTab *__restrict__ s_pt8, const uint16_t (*s_io16)[256],
-                                           uint32_t b_t, uint32_t bw1, uint32_t bw2)
+                                           const DevTables *__restrict__ T, uint32_t b_t, uint32_t bw1,
+                                           uint32_t bw2)
 {
+    const uint32_t v = (2u * b_t) & 0xFFFFu;
+    const B16Tabs base = b16_tabs(s_pt8, (uint32_t)s_io16[0][v & 255u] ^ (uint32_t)s_io16[1][v >> 8]);
+    auto delta = [&](uint32_t bw) {   // bw < 2^15
+        const uint32_t w = 2u * bw;
+        const uint32_t d = (uint32_t)(T->iota[0][w & 255u] ^ T->iota[1][w >> 8]) & 0xFFFFu;
+        return b16_tabs(reinterpret_cast<const PermTab *>(T->pt8), d);
+    };
+    B16Tabs d1 = base, d2 = base, d3 = base;
+    if (M == 0) {
+        d1 = delta(bw1);
+        d2 = delta(bw2);
+        d3 = b16_xor(d1, d2);
+    } else if (M == 1) {
+        d1 = delta(bw2);
+    }
 #pragma unroll
     for (int u = 0; u < (1 << (2 - M)); ++u) {
-        uint32_t b = b_t;
-        if (M == 0) {
-            if (u & 1) b ^= bw1;
-            if (u & 2) b ^= bw2;
-        } else if (M == 1) {
-            if (u & 1) b ^= bw2;
-        }
-        const uint32_t v = (2u * b) & 0xFFFFu;
-        const uint32_t beta = (uint32_t)s_io16[0][v & 255u] ^ (uint32_t)s_io16[1][v >> 8];
-        const PermTab *P0 = s_pt8 + (beta & 255u), *P1 = s_pt8 + (beta >> 8);
-        const uint4 p0 = *reinterpret_cast<const uint4 *>(P0), p1 = *reinterpret_cast<const uint4 *>(P1);
-        const uint32_t p02 = P0->t2, p12 = P1->t2;
-        const PermTab *PC = s_pt8 + ((p12 >> 16) & 255u);   // b1 c: entry 2 of P1's bit-6/7 table
-        const uint4 pc = *reinterpret_cast<const uint4 *>(PC);
-        const uint32_t pc2 = PC->t2;
+        const B16Tabs t = u == 0 ? base : b16_xor(base, u == 1 ? d1 : u == 2 ? d2 : d3);
 #pragma unroll
         for (int low = 0; low < (1 << M); ++low) {
             const int r0 = low | (u << (M + 1)), r1 = r0 | (1 << M);
             if (!INV) {
-                const uint64_t h0 = b2_mul_acc16(tab, p0, p02, p1, p12, pc, pc2, xa[r1], xa[r0]);
+                const uint64_t h0 = b2_mul_acc16(tab, t.p0, t.p02, t.p1, t.p12, t.pc, t.pc2, xa[r1], xa[r0]);
                 xa[r1] ^= h0;
                 xa[r0] = h0;
                 if (TWO) {
-                    const uint64_t g0 = b2_mul_acc16(tab, p0, p02, p1, p12, pc, pc2, xb[r1], xb[r0]);
+                    const uint64_t g0 = b2_mul_acc16(tab, t.p0, t.p02, t.p1, t.p12, t.pc, t.pc2, xb[r1], xb[r0]);
                     xb[r1] ^= g0;
                     xb[r0] = g0;
                 }
             } else {
                 const uint64_t p = xa[r0] ^ xa[r1];
-                xa[r0] = b2_mul_acc16(tab, p0, p02, p1, p12, pc, pc2, p, xa[r0]);
+                xa[r0] = b2_mul_acc16(tab, t.p0, t.p02, t.p1, t.p12, t.pc, t.pc2, p, xa[r0]);
                 xa[r1] = p;
             }
         }
@@ -396,7 +438,7 @@ __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&x
         if (b2_wide(i)) {
             const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
             const uint32_t bw1 = (1u << g.s[1]) >> (i + 1), bw2 = (1u << g.s[2]) >> (i + 1);
-            b2_layer16<M, INV, TWO>(xa, xb, s_tab[M], s_pt8, s_io16, b_t, bw1 & 0x7FFFu, bw2 & 0x7FFFu);
+            b2_layer16<M, INV, TWO>(xa, xb, s_tab[M], s_pt8, s_io16, T, b_t, bw1 & 0x7FFFu, bw2 & 0x7FFFu);
         } else {
             const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
             const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 127u, bw2 = ((1u << g.s[2]) >> (i + 1)) & 127u;

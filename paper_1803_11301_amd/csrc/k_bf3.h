@@ -212,7 +212,8 @@ __device__ __forceinline__ B2Group bf3_bottom_group(int c)
 
 template <bool INV>
 __device__ __forceinline__ void bf3_bottom_compute(const B2Group &g, uint64_t (&x)[8], uint64_t (*s_tab)[2048],
-                                                   const PermTab *s_pt8, const uint16_t (*s_io16)[256], uint64_t gb_t)
+                                                   const PermTab *s_pt8, const uint16_t (*s_io16)[256], uint64_t gb_t,
+                                                   const DevTables *__restrict__ T)
 {
     auto run = [&](auto Mc) {
         constexpr int M = decltype(Mc)::value;
@@ -220,7 +221,7 @@ __device__ __forceinline__ void bf3_bottom_compute(const B2Group &g, uint64_t (&
         const int i = g.s[M];
         const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
         const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 0x7FFFu, bw2 = ((1u << g.s[2]) >> (i + 1)) & 0x7FFFu;
-        b2_layer16<M, INV, false>(x, x, s_tab[i], s_pt8, s_io16, b_t, bw1, bw2);
+        b2_layer16<M, INV, false>(x, x, s_tab[i], s_pt8, s_io16, T, b_t, bw1, bw2);
     };
     if (!INV) {
         run(std::integral_constant<int, 2>());
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
                     x[r] = s_x[b2_pad(e)];
                 }
             }
-            bf3_bottom_compute<INV>(g, x, s_tab, s_pt8, s_io16, gbase | (uint64_t)e_t);
+            bf3_bottom_compute<INV>(g, x, s_tab, s_pt8, s_io16, gbase | (uint64_t)e_t, T);
             if (cc == B3_BOT_GROUPS - 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
