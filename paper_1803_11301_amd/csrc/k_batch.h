@@ -474,8 +474,6 @@ __device__ void bt_bfly32_layer(uint32_t *__restrict__ X, uint32_t *__restrict__
     const int d = l - i;
     for (int q = tid; q < 1024; q += nth) s_k[q] = T->kt32[d][q];
     __syncthreads();
-    const uint4 q01 = *reinterpret_cast<const uint4 *>(s_pt8 + 0x80);   // v_7 = Cantor byte 0x80
-    const uint32_t q2 = s_pt8[0x80].t2;
     const uint32_t half = 1u << (l - 1);
     for (uint32_t q = tid; q < half; q += nth) {
         const uint32_t tb = q >> i, off = q & ((1u << i) - 1u);
@@ -485,10 +483,13 @@ __device__ void bt_bfly32_layer(uint32_t *__restrict__ X, uint32_t *__restrict__
         const PermTab *P0 = s_pt8 + (beta & 255u), *P1 = s_pt8 + (beta >> 8);
         const uint4 t0 = *reinterpret_cast<const uint4 *>(P0), t1 = *reinterpret_cast<const uint4 *>(P1);
         const uint32_t t02 = P0->t2, t12 = P1->t2;
+        const PermTab *PC = s_pt8 + ((t12 >> 16) & 255u);   // beta1 v_7: entry 2 of beta1's bit-6/7 table
+        const uint4 tc = *reinterpret_cast<const uint4 *>(PC);
+        const uint32_t tc2 = PC->t2;
         auto mul = [&](uint32_t x) {
             const uint32_t k = s_k[x & 255u] ^ s_k[256 + ((x >> 8) & 255u)] ^ s_k[512 + ((x >> 16) & 255u)] ^
                                s_k[768 + (x >> 24)];
-            return k ^ b2_pmul32(t0, t02, x) ^ b2_pmul32(t1, t12, b2_mulv8(q01, q2, x));
+            return k ^ b2_mulv16(t0, t02, t1, t12, tc, tc2, x);
         };
         if (!inverse) {
             const uint32_t b = X[p1], h0 = X[p0] ^ mul(b);

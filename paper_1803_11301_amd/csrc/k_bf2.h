@@ -272,15 +272,6 @@ __device__ __forceinline__ uint32_t b2_pmul32(const uint4 &t01, uint32_t t2, uin
                 __builtin_amdgcn_perm(t2, t2, s2));
 }
 
-// x * v8 on the two tower pairs of a 32-bit word (tables of v7 in q01, q2)
-__device__ __forceinline__ uint32_t b2_mulv8(const uint4 &q01, uint32_t q2, uint32_t w)
-{
-    const uint32_t sw = __builtin_amdgcn_perm(w, w, 0x02030001u);   // swap the bytes of each pair
-    const uint32_t t = b2_pmul32(q01, q2, sw);                      // v7 * y1 in the low byte of each pair
-    const uint32_t m = 0xFF00FF00u;
-    return (m & (w ^ sw)) | (~m & t);
-}
-
 // x * beta16 on the two tower pairs a0 + a1 y of a 32-bit word, with y^2 =
 // y + c (c = v_7, Cantor byte 0x80) and beta16 = b0 + b1 y: the low byte of a
 // pair becomes a0 b0 + a1 (b1 c), the high byte a0 b1 + a1 (b0 + b1).  The

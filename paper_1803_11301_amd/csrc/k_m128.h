@@ -234,8 +234,6 @@ __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A
     // 12-bit rest, an element of V_16 applied as beta0 x + beta1 (x v_8)
     const bool tabled = l >= 11 && d <= 32;
     const int kshift = i >= 3 ? 7 : 11;
-    const uint4 q01 = *reinterpret_cast<const uint4 *>(s_pt8[0x80]);   // v_7 (Cantor byte 0x80)
-    const uint32_t q2 = s_pt8[0x80][4];
     const uint64_t ntiles = (total + M128_TILE - 1) / M128_TILE;
     const uint64_t per = (ntiles + gridDim.x - 1) / gridDim.x;
     const uint64_t t_end = min(ntiles, (uint64_t)(blockIdx.x + 1) * per);
@@ -284,10 +282,13 @@ __global__ __launch_bounds__(1024) void k_bfly128_layer(uint64_t *__restrict__ A
             const uint4 p0 = *reinterpret_cast<const uint4 *>(s_pt8[b16 & 255u]);
             const uint4 p1 = *reinterpret_cast<const uint4 *>(s_pt8[b16 >> 8]);
             const uint32_t p02 = s_pt8[b16 & 255u][4], p12 = s_pt8[b16 >> 8][4];
+            const uint32_t bc = (p12 >> 16) & 255u;   // beta1 v_7
+            const uint4 pc = *reinterpret_cast<const uint4 *>(s_pt8[bc]);
+            const uint32_t pc2 = s_pt8[bc][4];
             auto mul16 = [&](uint64_t x) {
                 const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-                const uint32_t rl = b2_pmul32(p0, p02, lo) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, lo));
-                const uint32_t rh = b2_pmul32(p0, p02, hi) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, hi));
+                const uint32_t rl = b2_mulv16(p0, p02, p1, p12, pc, pc2, lo);
+                const uint32_t rh = b2_mulv16(p0, p02, p1, p12, pc, pc2, hi);
                 return (uint64_t)rl | ((uint64_t)rh << 32);
             };
             a0 = tmul(s_k, x0) ^ mul16(x0);
@@ -529,32 +530,34 @@ __global__ __launch_bounds__(M128_TILE2) void k_bfly128_3layer(uint64_t *__restr
 #define M128_LOW_THREADS 512
 
 // x (K + beta16) with T_K = tk, beta16 = beta0 + beta1 v_8 given by the v_perm
-// tables (p0, p02) of beta0 and (p1, p12) of beta1, (q01, q2) those of v_7
+// tables (p0, p02) of beta0, (p1, p12) of beta1 and (pc, pc2) of beta1 v_7
 __device__ __forceinline__ uint64_t m128_kb16(const uint64_t *__restrict__ tk, const uint4 &p0, uint32_t p02,
-                                              const uint4 &p1, uint32_t p12, const uint4 &q01, uint32_t q2,
+                                              const uint4 &p1, uint32_t p12, const uint4 &pc, uint32_t pc2,
                                               uint64_t x)
 {
     const uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
-    const uint32_t rl = b2_pmul32(p0, p02, lo) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, lo));
-    const uint32_t rh = b2_pmul32(p0, p02, hi) ^ b2_pmul32(p1, p12, b2_mulv8(q01, q2, hi));
+    const uint32_t rl = b2_mulv16(p0, p02, p1, p12, pc, pc2, lo);
+    const uint32_t rh = b2_mulv16(p0, p02, p1, p12, pc, pc2, hi);
     return tmul(tk, x) ^ ((uint64_t)rl | ((uint64_t)rh << 32));
 }
 
 template <bool INV>
 __device__ __forceinline__ void m128_bfly16(const uint64_t *__restrict__ tk, const uint32_t (*__restrict__ pt8)[8],
-                                            uint32_t b16, const uint4 &q01, uint32_t q2,
-                                            const uint64_t *__restrict__ th, const uint64_t *__restrict__ thv,
-                                            ulonglong2 &u, ulonglong2 &v)
+                                            uint32_t b16, const uint64_t *__restrict__ th,
+                                            const uint64_t *__restrict__ thv, ulonglong2 &u, ulonglong2 &v)
 {
     const uint4 p0 = *reinterpret_cast<const uint4 *>(pt8[b16 & 255u]);
     const uint4 p1 = *reinterpret_cast<const uint4 *>(pt8[b16 >> 8]);
     const uint32_t p02 = pt8[b16 & 255u][4], p12 = pt8[b16 >> 8][4];
+    const uint32_t bc = (p12 >> 16) & 255u;   // beta1 v_7: entry 2 of beta1's bit-6/7 table
+    const uint4 pc = *reinterpret_cast<const uint4 *>(pt8[bc]);
+    const uint32_t pc2 = pt8[bc][4];
     if (INV) {
         v.x ^= u.x;
         v.y ^= u.y;
     }
-    const uint64_t a0 = m128_kb16(tk, p0, p02, p1, p12, q01, q2, v.x);
-    const uint64_t a1 = m128_kb16(tk, p0, p02, p1, p12, q01, q2, v.y);
+    const uint64_t a0 = m128_kb16(tk, p0, p02, p1, p12, pc, pc2, v.x);
+    const uint64_t a1 = m128_kb16(tk, p0, p02, p1, p12, pc, pc2, v.y);
     u.x ^= a0 ^ tmul(thv, v.y);
     u.y ^= tmul(th, v.x ^ v.y) ^ a1;
     if (!INV) {
@@ -579,8 +582,6 @@ __global__ __launch_bounds__(M128_LOW_THREADS) void k_bfly128_low3(uint64_t *__r
     }
     for (int q = tid; q < 256 * 8; q += nth) (&s_pt8[0][0])[q] = (&T->pt8[0][0])[q];
     __syncthreads();
-    const uint4 q01 = *reinterpret_cast<const uint4 *>(s_pt8[0x80]);   // v_7 (Cantor byte 0x80)
-    const uint32_t q2 = s_pt8[0x80][4];
     const uint64_t quarter8 = 1ull << (l - 3);   // groups of 8 per operand
     const uint64_t total = B ? 2 * quarter8 : quarter8;
     const uint64_t ntiles = total / M128_LOW_THREADS, per = (ntiles + gridDim.x - 1) / gridDim.x;
@@ -621,26 +622,26 @@ __global__ __launch_bounds__(M128_LOW_THREADS) void k_bfly128_low3(uint64_t *__r
         const uint32_t b0a = beta(4 * g), b0b = beta(4 * g + 1), b0c = beta(4 * g + 2), b0d = beta(4 * g + 3);
         if (!INV) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) m128_bfly16<false>(s_k[2], s_pt8, b2, q01, q2, s_h[2][0], s_h[2][1], x[e], x[e + 4]);
-            m128_bfly16<false>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[0], x[2]);
-            m128_bfly16<false>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[1], x[3]);
-            m128_bfly16<false>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[4], x[6]);
-            m128_bfly16<false>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[5], x[7]);
-            m128_bfly16<false>(s_k[0], s_pt8, b0a, q01, q2, s_h[0][0], s_h[0][1], x[0], x[1]);
-            m128_bfly16<false>(s_k[0], s_pt8, b0b, q01, q2, s_h[0][0], s_h[0][1], x[2], x[3]);
-            m128_bfly16<false>(s_k[0], s_pt8, b0c, q01, q2, s_h[0][0], s_h[0][1], x[4], x[5]);
-            m128_bfly16<false>(s_k[0], s_pt8, b0d, q01, q2, s_h[0][0], s_h[0][1], x[6], x[7]);
+            for (int e = 0; e < 4; ++e) m128_bfly16<false>(s_k[2], s_pt8, b2, s_h[2][0], s_h[2][1], x[e], x[e + 4]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1a, s_h[1][0], s_h[1][1], x[0], x[2]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1a, s_h[1][0], s_h[1][1], x[1], x[3]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1b, s_h[1][0], s_h[1][1], x[4], x[6]);
+            m128_bfly16<false>(s_k[1], s_pt8, b1b, s_h[1][0], s_h[1][1], x[5], x[7]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0a, s_h[0][0], s_h[0][1], x[0], x[1]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0b, s_h[0][0], s_h[0][1], x[2], x[3]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0c, s_h[0][0], s_h[0][1], x[4], x[5]);
+            m128_bfly16<false>(s_k[0], s_pt8, b0d, s_h[0][0], s_h[0][1], x[6], x[7]);
         } else {
-            m128_bfly16<true>(s_k[0], s_pt8, b0a, q01, q2, s_h[0][0], s_h[0][1], x[0], x[1]);
-            m128_bfly16<true>(s_k[0], s_pt8, b0b, q01, q2, s_h[0][0], s_h[0][1], x[2], x[3]);
-            m128_bfly16<true>(s_k[0], s_pt8, b0c, q01, q2, s_h[0][0], s_h[0][1], x[4], x[5]);
-            m128_bfly16<true>(s_k[0], s_pt8, b0d, q01, q2, s_h[0][0], s_h[0][1], x[6], x[7]);
-            m128_bfly16<true>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[0], x[2]);
-            m128_bfly16<true>(s_k[1], s_pt8, b1a, q01, q2, s_h[1][0], s_h[1][1], x[1], x[3]);
-            m128_bfly16<true>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[4], x[6]);
-            m128_bfly16<true>(s_k[1], s_pt8, b1b, q01, q2, s_h[1][0], s_h[1][1], x[5], x[7]);
+            m128_bfly16<true>(s_k[0], s_pt8, b0a, s_h[0][0], s_h[0][1], x[0], x[1]);
+            m128_bfly16<true>(s_k[0], s_pt8, b0b, s_h[0][0], s_h[0][1], x[2], x[3]);
+            m128_bfly16<true>(s_k[0], s_pt8, b0c, s_h[0][0], s_h[0][1], x[4], x[5]);
+            m128_bfly16<true>(s_k[0], s_pt8, b0d, s_h[0][0], s_h[0][1], x[6], x[7]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1a, s_h[1][0], s_h[1][1], x[0], x[2]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1a, s_h[1][0], s_h[1][1], x[1], x[3]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1b, s_h[1][0], s_h[1][1], x[4], x[6]);
+            m128_bfly16<true>(s_k[1], s_pt8, b1b, s_h[1][0], s_h[1][1], x[5], x[7]);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) m128_bfly16<true>(s_k[2], s_pt8, b2, q01, q2, s_h[2][0], s_h[2][1], x[e], x[e + 4]);
+            for (int e = 0; e < 4; ++e) m128_bfly16<true>(s_k[2], s_pt8, b2, s_h[2][0], s_h[2][1], x[e], x[e + 4]);
         }
 #pragma unroll
         for (int e = 0; e < 8; ++e) P[j0 + e] = x[e];
