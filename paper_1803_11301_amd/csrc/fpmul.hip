@@ -775,7 +775,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         }
         if (mode == BF_PRODUCT)
             KLAUNCH(ctx, s, "pointwise", k_pointwise,
-                    (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu * 2), 1024, A, B, n,
+                    (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, A, B, n,
                     ctx->tables);
         if (mode != BF_FWD) {
             if ((rc = launch_bf3_bottom<true>(ctx, s, "ibutterfly_bottom", A, nullptr, l))) return rc;
@@ -803,7 +803,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         if (mode == BF_PRODUCT) {
             KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD2>, bt, B2_THREADS, A, B, l, ctx->tables);
             KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
-                                                                                   (uint64_t)ctx->num_cu * 2),
+                                                                                   (uint64_t)ctx->num_cu),
                     1024, A, B, n, ctx->tables);
             KLAUNCH(ctx, s, "ibutterfly_bottom", k_bf2_bottom<BF_INV>, bt, B2_THREADS, A, B, l, ctx->tables);
         } else if (mode == BF_FWD) {
@@ -1224,7 +1224,7 @@ static int resident_body(polymul_ctx *ctx, const uint64_t *fa, int log2n, const 
         if ((rc = run_encode_in(ctx, b, len_b, log2n, cur, spare, s))) return rc;
     }
     if ((rc = run_butterflies(ctx, BF_FWD, cur, nullptr, log2n - 6, s))) return rc;
-    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu * 2),
+    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu),
             1024, cur, fa, nw, ctx->tables);
     if ((rc = run_butterflies(ctx, BF_INV, cur, nullptr, log2n - 6, s))) return rc;
     if (fast_path(log2n)) return run_decode_fast(ctx, cur, log2n, out, lc, ctx->ws[2], ctx->ws[3], s);
@@ -1432,6 +1432,11 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
     };
     for (int bl = 0; bl < 128; ++bl) permtab((uint8_t)H.iota[0][2 * bl], D.pt_beta8[bl]);   // iota(2 bl) is in V_8
     for (int e = 0; e < 256; ++e) permtab((uint8_t)e, D.pt8[e]);
+    for (int a = 0; a < 256; ++a)
+        for (int b = 0; b < 256; ++b) {
+            const uint8_t p = tw.mul8[a][b];
+            D.mulp[a][b] = (uint16_t)(p | (tw.mul8[0x80][p] << 8));   // v_7 = Cantor byte 0x80
+        }
     for (int k = 0; k < 4; ++k)
         for (int e = 0; e < 256; ++e) {
             uint32_t f = 0, a = 0;
@@ -2185,7 +2190,7 @@ int polymul_pointwise(polymul_ctx *ctx, const uint64_t *fa, const uint64_t *fb, 
     } else if (fc != fa) {
         HIP_TRY(hipMemcpyAsync(fc, fa, bytes, hipMemcpyDeviceToDevice, s));
     }
-    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu * 2),
+    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu),
             1024, fc, other, n, ctx->tables);
     return 0;
 }

@@ -32,6 +32,7 @@ struct DevTables {
     uint32_t enc32_win[4][256];  // Encode: byte window k of the 32-bit column -> sum of r_j
     uint32_t dec32_win[4][256];  // Decode: byte window k of the value -> bits
     uint32_t kt32[16][1024];     // window tables of v_{16+d}: [d][256 k + e] = v_{16+d} * (e at byte k)
+    uint16_t mulp[256][256];     // GF(2^8) products with their v_7 multiples: p | (v_7 p) << 8, p = a b
 };
 
 // ----------------------------------------------------------------- tmul ----
@@ -96,6 +97,52 @@ struct Mul8View {
     __device__ __forceinline__ uint32_t mv31(uint32_t x) const
     {
         const uint32_t *c31 = reinterpret_cast<const uint32_t *>(base + M8V_OFF_C31);
+        return c31[x & 255u] ^ c31[256 + ((x >> 8) & 255u)] ^ c31[512 + ((x >> 16) & 255u)] ^ c31[768 + (x >> 24)];
+    }
+    __device__ __forceinline__ uint64_t m64(uint64_t a, uint64_t b) const
+    {
+        uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+        uint32_t p0 = m32(a0, b0), p2 = m32(a1, b1), p1 = m32(a0 ^ a1, b0 ^ b1);
+        uint32_t hi = p1 ^ p0, lo = p0 ^ mv31(p2);
+        return (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+};
+
+// The same tower products from the pair table (DevTables::mulp) in LDS: a
+// GF(2^16) product takes three lookups instead of four, the v_7 multiple of
+// a1 b1 coming with it.  Layout: the pair table (128 KiB), then the v_15 and
+// v_31 tables as in Mul8View.
+#define MPV_OFF_C15 131072
+#define MPV_OFF_C31 (131072 + 1024)
+#define MPV_BYTES (131072 + 1024 + 4096)
+struct MulPairView {
+    const uint8_t *base;
+    __device__ __forceinline__ uint32_t mp(uint32_t a, uint32_t b) const
+    {
+        return reinterpret_cast<const uint16_t *>(base)[(a << 8) | b];
+    }
+    __device__ __forceinline__ uint32_t m16(uint32_t a, uint32_t b) const
+    {
+        const uint32_t a0 = a & 255u, a1 = a >> 8, b0 = b & 255u, b1 = b >> 8;
+        const uint32_t p0 = mp(a0, b0) & 255u, q2 = mp(a1, b1), p1 = mp(a0 ^ a1, b0 ^ b1) & 255u;
+        const uint32_t hi = p1 ^ p0, lo = p0 ^ (q2 >> 8);   // q2 >> 8 = v_7 a1 b1
+        return lo | (hi << 8);
+    }
+    __device__ __forceinline__ uint32_t mv15(uint32_t x) const
+    {
+        const uint16_t *c15 = reinterpret_cast<const uint16_t *>(base + MPV_OFF_C15);
+        return c15[x & 255u] ^ c15[256 + (x >> 8)];
+    }
+    __device__ __forceinline__ uint32_t m32(uint32_t a, uint32_t b) const
+    {
+        uint32_t a0 = a & 0xFFFFu, a1 = a >> 16, b0 = b & 0xFFFFu, b1 = b >> 16;
+        uint32_t p0 = m16(a0, b0), p2 = m16(a1, b1), p1 = m16(a0 ^ a1, b0 ^ b1);
+        uint32_t hi = p1 ^ p0, lo = p0 ^ mv15(p2);
+        return lo | (hi << 16);
+    }
+    __device__ __forceinline__ uint32_t mv31(uint32_t x) const
+    {
+        const uint32_t *c31 = reinterpret_cast<const uint32_t *>(base + MPV_OFF_C31);
         return c31[x & 255u] ^ c31[256 + ((x >> 8) & 255u)] ^ c31[512 + ((x >> 16) & 255u)] ^ c31[768 + (x >> 24)];
     }
     __device__ __forceinline__ uint64_t m64(uint64_t a, uint64_t b) const

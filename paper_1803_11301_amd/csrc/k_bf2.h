@@ -538,21 +538,33 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
 
 // ------------------------------------------------------------ pointwise ---
 // A[j] = A[j] * B[j] (Alg. 5, the pointwise step), tower Karatsuba with the
-// GF(2^8) table in LDS (Mul8View layout)
+// GF(2^8) pair table in LDS (MulPairView layout); one workgroup per CU
 __global__ __launch_bounds__(1024) void k_pointwise(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
                                                     uint64_t n, const DevTables *__restrict__ T)
 {
-    __shared__ __align__(16) uint8_t s_m8[M8V_BYTES];
+    __shared__ __align__(16) uint8_t s_mp[MPV_BYTES];
     const int tid = threadIdx.x, nth = blockDim.x;
-    const uint4 *src = reinterpret_cast<const uint4 *>(&T->mul8[0][0]);
-    uint4 *dst = reinterpret_cast<uint4 *>(s_m8);
-    for (int idx = tid; idx < 256 * 16; idx += nth) {
-        const int a = idx >> 4, c = idx & 15;   // row a, 16-byte column c
-        dst[((a & 1) << 11) | ((a >> 1) << 4) | c] = src[idx];
-    }
-    for (int q = tid; q < 512; q += nth) reinterpret_cast<uint16_t *>(s_m8 + M8V_OFF_C15)[q] = (&T->c15[0][0])[q];
-    for (int q = tid; q < 1024; q += nth) reinterpret_cast<uint32_t *>(s_m8 + M8V_OFF_C31)[q] = (&T->c31[0][0])[q];
+    const uint4 *src = reinterpret_cast<const uint4 *>(&T->mulp[0][0]);
+    uint4 *dst = reinterpret_cast<uint4 *>(s_mp);
+    for (int idx = tid; idx < 131072 / 16; idx += nth) dst[idx] = src[idx];
+    for (int q = tid; q < 512; q += nth) reinterpret_cast<uint16_t *>(s_mp + MPV_OFF_C15)[q] = (&T->c15[0][0])[q];
+    for (int q = tid; q < 1024; q += nth) reinterpret_cast<uint32_t *>(s_mp + MPV_OFF_C31)[q] = (&T->c31[0][0])[q];
     __syncthreads();
-    const Mul8View mv{s_m8};
-    for (uint64_t j = (uint64_t)blockIdx.x * nth + tid; j < n; j += (uint64_t)gridDim.x * nth) A[j] = mv.m64(A[j], B[j]);
+    const MulPairView mv{s_mp};
+    // PW_ILP independent products per thread and iteration, so that their
+    // lookups overlap (one workgroup per CU leaves few waves to hide them)
+    constexpr int PW_ILP = 4;
+    const uint64_t G = (uint64_t)gridDim.x * nth;
+    uint64_t j = (uint64_t)blockIdx.x * nth + tid;
+    for (; j + (PW_ILP - 1) * G < n; j += PW_ILP * G) {
+        uint64_t a[PW_ILP], b[PW_ILP];
+#pragma unroll
+        for (int k = 0; k < PW_ILP; ++k) {
+            a[k] = A[j + k * G];
+            b[k] = B[j + k * G];
+        }
+#pragma unroll
+        for (int k = 0; k < PW_ILP; ++k) A[j + k * G] = mv.m64(a[k], b[k]);
+    }
+    for (; j < n; j += G) A[j] = mv.m64(A[j], B[j]);
 }
