@@ -931,19 +931,21 @@ __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *
 // Lane exchanges without the LDS: the value of lane (lane ^ J) for J < 64,
 // through DPP row operations (J <= 8; row_ror:N delivers lane (i - N) mod 16
 // of each 16-lane row) and the gfx950 half-row / half-wave swaps (J = 16, 32).
+// Every lane has a source lane in these DPP patterns, so bound_ctrl (zero for
+// a lane without one) never applies; it lets the move drop its old operand.
 template <int J>
 __device__ __forceinline__ uint32_t bc_xor_lane(uint32_t v, int lane)
 {
     if constexpr (J == 1) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xf, 0xf, true);   // quad_perm [1,0,3,2]
     } else if constexpr (J == 2) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xf, 0xf, true);   // quad_perm [2,3,0,1]
     } else if constexpr (J == 4) {
-        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12C, 0xf, 0xf, false);   // i + 4
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false);   // i - 4
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12C, 0xf, 0xf, true);   // i + 4
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, true);   // i - 4
         return (lane & 4) ? dn : up;
     } else if constexpr (J == 8) {
-        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false);   // row_ror:8
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, true);   // row_ror:8
     } else if constexpr (J == 16) {
         const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
         return (lane & 16) ? r[0] : r[1];
@@ -956,11 +958,19 @@ __device__ __forceinline__ uint32_t bc_xor_lane(uint32_t v, int lane)
 // one stage of the transpose on a 32-bit word: lanes with bit J clear keep
 // the bits of mask m and take the partner's bits of m shifted up by J; the
 // others keep ~m and take the partner's bits of ~m shifted down by J
+//
+// Both cases are one rotation and one bit-field insert: the partner's word
+// rotated right by J (upper lanes) or by 32 - J (lower lanes) has the wanted
+// bits in place, and the bits that wrap around fall outside the taken mask.
+// The rotation amount and the kept mask depend on the lane only.
 template <int J>
 __device__ __forceinline__ uint32_t bc_tstage(uint32_t x, uint32_t m, int lane)
 {
     const uint32_t y = bc_xor_lane<J>(x, lane);
-    return (lane & J) ? (((y & ~m) >> J) | (x & ~m)) : ((x & m) | ((y & m) << J));
+    const bool up = (lane & J) != 0;
+    const uint32_t keep = up ? ~m : m, rot = up ? (uint32_t)J : (uint32_t)(32 - J);
+    const uint32_t t = __builtin_amdgcn_alignbit(y, y, rot);   // y rotated right by rot
+    return ((x ^ t) & keep) ^ t;   // x on keep, t elsewhere: one bit-field insert
 }
 
 // 64 x 64 bit transpose across a wavefront: lane i holds row i; afterwards
