@@ -973,6 +973,21 @@ __device__ __forceinline__ uint32_t bc_tstage(uint32_t x, uint32_t m, int lane)
     return ((x ^ t) & keep) ^ t;   // x on keep, t elsewhere: one bit-field insert
 }
 
+// The J = 16 stage on both words of a lane at once: the low 16-bit halves
+// of lo and hi packed in one register, the high halves in another.  One
+// half-row swap (odd rows of the first with even rows of the second) leaves
+// a lane of an even row its own low halves and its partner's, a lane of an
+// odd row its partner's high halves and its own, in the same two registers;
+// two byte permutes put them back as lo and hi.
+__device__ __forceinline__ void bc_tstage16_pair(uint32_t &lo, uint32_t &hi)
+{
+    const uint32_t a = __builtin_amdgcn_perm(hi, lo, 0x05040100u);   // lo[15:0], hi[15:0]
+    const uint32_t b = __builtin_amdgcn_perm(hi, lo, 0x07060302u);   // lo[31:16], hi[31:16]
+    const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+    lo = __builtin_amdgcn_perm(r[1], r[0], 0x05040100u);
+    hi = __builtin_amdgcn_perm(r[1], r[0], 0x07060302u);
+}
+
 // 64 x 64 bit transpose across a wavefront: lane i holds row i; afterwards
 // lane t holds column t (bit i = bit t of row i)
 __device__ __forceinline__ uint64_t bc_wave_transpose64(uint64_t x, int lane)
@@ -986,8 +1001,7 @@ __device__ __forceinline__ uint64_t bc_wave_transpose64(uint64_t x, int lane)
         lo = r[0];
         hi = r[1];
     }
-    lo = bc_tstage<16>(lo, 0x0000FFFFu, lane);
-    hi = bc_tstage<16>(hi, 0x0000FFFFu, lane);
+    bc_tstage16_pair(lo, hi);
     lo = bc_tstage<8>(lo, 0x00FF00FFu, lane);
     hi = bc_tstage<8>(hi, 0x00FF00FFu, lane);
     lo = bc_tstage<4>(lo, 0x0F0F0F0Fu, lane);
@@ -1007,7 +1021,15 @@ __device__ __forceinline__ uint64_t bc_win8(const uint64_t (*tab)[256], uint64_t
     const uint64_t t0 = tab[0][lo & 255u], t1 = tab[1][(lo >> 8) & 255u], t2 = tab[2][(lo >> 16) & 255u],
                    t3 = tab[3][lo >> 24], t4 = tab[4][hi & 255u], t5 = tab[5][(hi >> 8) & 255u],
                    t6 = tab[6][(hi >> 16) & 255u], t7 = tab[7][hi >> 24];
-    return ((t0 ^ t1) ^ (t2 ^ t3)) ^ ((t4 ^ t5) ^ (t6 ^ t7));
+    auto x3 = [](uint64_t a, uint64_t b, uint64_t c, int h) -> uint32_t {   // three-input XOR of half h
+        return (uint32_t)__builtin_amdgcn_bitop3_b32((uint32_t)(a >> (32 * h)), (uint32_t)(b >> (32 * h)),
+                                           (uint32_t)(c >> (32 * h)), 0x96);
+    };
+    auto half = [&](int h) -> uint32_t {   // unsigned: the halves are joined below without sign extension
+        return (uint32_t)__builtin_amdgcn_bitop3_b32(x3(t0, t1, t2, h), x3(t3, t4, t5, h),
+                                                     (uint32_t)(t6 >> (32 * h)) ^ (uint32_t)(t7 >> (32 * h)), 0x96);
+    };
+    return (uint64_t)half(0) | ((uint64_t)half(1) << 32);
 }
 
 // Outer BasisCvt(R) on one 64-bit column of Y, then Encode: element
@@ -1114,8 +1136,7 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
             // transpose the two 32 x 64 blocks (one per half-wave): afterwards lane
             // (half, j) holds bits j and j + 32 of the 32 decoded vectors
             uint32_t lo = (uint32_t)a, hi = (uint32_t)(a >> 32);
-            lo = bc_tstage<16>(lo, 0x0000FFFFu, lane);
-            hi = bc_tstage<16>(hi, 0x0000FFFFu, lane);
+            bc_tstage16_pair(lo, hi);
             lo = bc_tstage<8>(lo, 0x00FF00FFu, lane);
             hi = bc_tstage<8>(hi, 0x00FF00FFu, lane);
             lo = bc_tstage<4>(lo, 0x0F0F0F0Fu, lane);
