@@ -116,21 +116,21 @@ STAGES = [
 COUNTER_SOURCES = ("paper_1803_11301_amd/csrc/fpmul.hip", "paper_1803_11301_amd/csrc/k_basiscvt.h",
                    "paper_1803_11301_amd/csrc/k_bf3.h", "paper_1803_11301_amd/csrc/k_bf2.h",
                    "paper_1803_11301_amd/csrc/gf_device.h")
-COUNTERS_SHA256 = "4687ba5899100c3ec26b9d26fb42f888b4dddbd1a1d02d545212b92eaf08e4b2"
+COUNTERS_SHA256 = "ae08db7562fa8c91c19ffd3109857452f4933941d958b340eb9a2d6e2f55f44f"
 COUNTERS = {
     # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB, SQ_INSTS_VALU) per dispatch
-    "basiscvt_zeta": (106593, 163840, 1.358e+07),
-    "basiscvt_rows": (75734, 131072, 5.868e+07),
-    "basiscvt_outer_encode": (78085, 280539, 9.398e+07),
-    "butterfly_upper": (262516, 524288, 1.475e+08),
-    "butterfly_bottom": (262606, 524288, 2.961e+08),
-    "pointwise": (262454, 262144, 1.328e+08),
+    "basiscvt_zeta": (106590, 163840, 1.358e+07),
+    "basiscvt_rows": (75585, 131072, 5.887e+07),
+    "basiscvt_outer_encode": (90366, 305152, 7.67e+07),
+    "butterfly_upper": (262512, 524288, 1.475e+08),
+    "butterfly_bottom": (262604, 524288, 2.961e+08),
+    "pointwise": (262756, 262144, 1.05e+08),
     "ibutterfly_bottom": (131470, 262144, 1.529e+08),
     "ibutterfly_upper": (131376, 262144, 7.336e+07),
-    "decode_outer": (131809, 262144, 1.597e+08),
-    "ibasiscvt_rows": (132438, 393216, 1.121e+08),
-    "ibasiscvt_zeta": (196699, 393216, 2.046e+07),
-    "ibasiscvt_store": (174405, 262144, 1.844e+07),
+    "decode_outer": (131459, 262144, 1.41e+08),
+    "ibasiscvt_rows": (135158, 393216, 1.123e+08),
+    "ibasiscvt_zeta": (196696, 393216, 2.046e+07),
+    "ibasiscvt_store": (174423, 262144, 1.844e+07),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
