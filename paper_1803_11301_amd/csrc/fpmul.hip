@@ -1958,13 +1958,13 @@ int polymul_tune(polymul_ctx *ctx, int log2n, int reps, const char *cache_path, 
         sc.upper = u;
         if ((rc = consider(sc))) break;
     }
-    for (int m : {1, 2, 4}) {
+    for (int m : {1, 2, 4, 8}) {
         if (rc || m == best.rows_mult) continue;
         fpmul_plan::Schedule sc = best;
         sc.rows_mult = m;
         rc = consider(sc);
     }
-    for (int m : {4, 8, 16}) {
+    for (int m : {4, 8, 16, 32}) {
         if (rc || m == best.zeta_mult) continue;
         fpmul_plan::Schedule sc = best;
         sc.zeta_mult = m;

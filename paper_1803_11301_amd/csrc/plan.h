@@ -118,8 +118,8 @@ constexpr int TILE_LG = 12;            // 2^12 values per butterfly tile
 
 struct Schedule {
     std::vector<int> upper;   // layers per upper pass, lowest pass first; empty = the default split
-    int rows_mult = 2;        // row-kernel workgroups per CU
-    int zeta_mult = 8;        // zeta-kernel workgroups per CU
+    int rows_mult = 4;        // row-kernel workgroups per CU (the tuner's usual choice on MI355X)
+    int zeta_mult = 16;       // zeta-kernel workgroups per CU (likewise)
 };
 
 // the default split of the U = l - 7 upper layers: as even as possible over
