@@ -892,6 +892,15 @@ using fpmul_plan::bc_ew;
 using fpmul_plan::ws_words_for;
 static_assert(fpmul_plan::TAU_WORDS == BC_TAU_WORDS, "row length of the fused BasisCvt");
 
+// rows per workgroup iteration of the row kernels: BC_ROWS (the fast path)
+// while that still gives every CU a workgroup, fewer for shorter operands
+static int rows_per_wg(const polymul_ctx *ctx, int lgR)
+{
+    int rpw = BC_ROWS;
+    while (rpw > 1 && ((1ull << lgR) / rpw) < (uint64_t)ctx->num_cu) rpw /= 2;
+    return rpw;
+}
+
 static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t *in, uint64_t len, int lgR, int EW,
                     bool skew_first, int zeta_mult)
 {
@@ -938,9 +947,10 @@ static int run_encode_fast(polymul_ctx *ctx, const uint64_t *a, uint64_t len, in
         if (rc) return rc;
     }
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
-    const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / BC_ROWS,
+    const int rpw = rows_per_wg(ctx, lgR);
+    const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / rpw,
                                                                               (uint64_t)ctx->num_cu * sc.rows_mult));
-    KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_ROW_THREADS, X, a, len, lgR, EW, Y, inner);
+    KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_ROW_THREADS, X, a, len, lgR, EW, Y, inner, rpw);
     KLAUNCH(ctx, s, "basiscvt_outer_encode", k_bc_outer_encode, (unsigned)std::min(BC_TAU_WORDS, ctx->num_cu),
             BC_COL_THREADS, Y, lgR, l, vals, outer, ctx->tables);
     return 0;
@@ -955,9 +965,10 @@ static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, ui
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
     KLAUNCH(ctx, s, "decode_outer", k_bc_decode_outer, (unsigned)std::min(2 * BC_TAU_WORDS, ctx->num_cu), BC_COL_THREADS,
             vals, lgR, l, reinterpret_cast<uint32_t *>(Y), outer, ctx->tables);
-    const unsigned grows = (unsigned)std::min<uint64_t>((1ull << lgR) / BC_ROWS, (uint64_t)ctx->num_cu * sc.rows_mult);
+    const int rpw = rows_per_wg(ctx, lgR);
+    const unsigned grows = (unsigned)std::min<uint64_t>((1ull << lgR) / rpw, (uint64_t)ctx->num_cu * sc.rows_mult);
     KLAUNCH(ctx, s, "ibasiscvt_rows", k_bc_inv_rows, grows, BC_ROW_THREADS, reinterpret_cast<const uint32_t *>(Y), lgR,
-            EW, X, inner);
+            EW, X, inner, rpw);
     int rc = run_zeta(ctx, s, X, nullptr, 0, lgR, EW, false, sc.zeta_mult);
     if (rc) return rc;
     // a row per workgroup iteration; 16 workgroups per CU keep enough rows in

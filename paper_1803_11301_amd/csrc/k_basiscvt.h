@@ -841,13 +841,16 @@ __device__ __forceinline__ uint64_t bc_bits_u(const uint64_t *w, int nw, long of
     return s ? ((a >> s) | (b << (64 - s))) : a;
 }
 
+// rpw: rows per workgroup iteration, a power of two up to BC_ROWS (fewer
+// spread a short operand's few rows over more CUs)
 __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *__restrict__ X,
                                                             const uint64_t *__restrict__ in, uint64_t len, int lgR,
-                                                            int EW, uint64_t *__restrict__ Y, BcSteps inner)
+                                                            int EW, uint64_t *__restrict__ Y, BcSteps inner,
+                                                            int rpw)
 {
     __shared__ __align__(16) uint64_t rows[BC_ROWS * BC_TAU_WORDS];
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
+    const int R = 1 << lgR, T = R < rpw ? R : rpw;
     const uint64_t inwords = (len + 63) / 64;
     for (int q0 = blockIdx.x * T; q0 < R; q0 += gridDim.x * T) {
         if (T == BC_ROWS && nth == BC_ROW_THREADS) {
@@ -1171,11 +1174,11 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
 // Inverse inner conversion of rows (read from the 32-bit columns of Y32,
 // BC_ROWS per iteration), then skew: X row q = h_q << q (EW words).
 __global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_inv_rows(const uint32_t *__restrict__ Y32, int lgR, int EW,
-                                                            uint64_t *__restrict__ X, BcSteps inner)
+                                                            uint64_t *__restrict__ X, BcSteps inner, int rpw)
 {
     __shared__ __align__(16) uint64_t rows[BC_ROWS * BC_TAU_WORDS];
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int R = 1 << lgR, T = R < BC_ROWS ? R : BC_ROWS;
+    const int R = 1 << lgR, T = R < rpw ? R : rpw;
     // workgroups go to the 8 XCDs round robin; those of one XCD take
     // consecutive row groups, so that each 128-byte line of a column (32
     // rows) is fetched once into that XCD's L2 rather than into four
