@@ -667,7 +667,7 @@ static std::vector<std::pair<int, int>> upper_groups_of(const polymul_ctx *ctx, 
     const fpmul_plan::Schedule sc = sched_of(ctx, l + 6);
     if (sc.upper.empty() || !fpmul_plan::upper_valid(l, sc.upper)) return upper_groups(l, B3_BOT_LAYERS);
     std::vector<std::pair<int, int>> g;
-    int lo = B3_BOT_LAYERS;
+    int lo = fpmul_plan::bottom_layers(l, sc.upper);   // the lowest upper pass starts above the bottom pass
     for (int k : sc.upper) {
         g.push_back({lo, k});
         lo += k;
@@ -740,14 +740,20 @@ static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
 #define MID_MIN_LOG2N 18            // mid-size path (LDS BasisCvt in one workgroup per operand) ...
 #define MID_MAX_LOG2N 20            // ... up to 2^20-bit transforms
 
+// the bottom pass of layers 0 .. nl - 1 (nl = 6 or 7)
 template <bool INV>
-static int launch_bf3_bottom(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l)
+static int launch_bf3_bottom(polymul_ctx *ctx, hipStream_t s, const char *name, uint64_t *A, uint64_t *B, int l,
+                             int nl)
 {
     const uint64_t nops = B ? 2 : 1, ntiles = 1ull << (l - B3_TILE_LG);
     const uint64_t per_op = std::max<uint64_t>(1, std::min<uint64_t>(ntiles, (uint64_t)ctx->num_cu / nops));
     if (l < B3_TILE_LG) return fail(POLYMUL_EINVAL, "bottom pass needs at least one tile");
-    KLAUNCH(ctx, s, name, k_bf3_bottom<INV>, (unsigned)(per_op * nops), B3_THREADS, A, B, l,
-            ctx->tables);
+    if (nl == 7)
+        KLAUNCH(ctx, s, name, (k_bf3_bottom<INV, 7>), (unsigned)(per_op * nops), B3_THREADS, A, B, l, ctx->tables);
+    else if (nl == 6)
+        KLAUNCH(ctx, s, name, (k_bf3_bottom<INV, 6>), (unsigned)(per_op * nops), B3_THREADS, A, B, l, ctx->tables);
+    else
+        return fail(POLYMUL_EINVAL, "bottom pass of 6 or 7 layers");
     return 0;
 }
 
@@ -760,17 +766,20 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
 {
     const uint64_t n = 1ull << l;
     if (l >= BF3_MIN_L) {
-        // the layers above the bottom pass split evenly into passes of at most
-        // 7; the lowest starts at layer 7 and needs K >= 5 (i_lo >= 12 - K),
-        // which every split for l >= 20 gives
+        // the layers above the bottom pass split into passes of at most 7
+        // (evenly by default, or the tuned split); the bottom pass has 7
+        // layers, or 6 under a split that gives layer 6 to the lowest upper
+        // pass, which needs K >= 12 - i_lo (every split for l >= 20 allows one)
         const auto groups = upper_groups_of(ctx, l);
+        const int nl = groups.empty() ? B3_BOT_LAYERS : groups.front().first;   // layers of the bottom pass
         int rc;
         if (mode != BF_INV) {
             for (auto it = groups.rbegin(); it != groups.rend(); ++it)
                 if ((rc = launch_bf3_upper<false>(ctx, s, "butterfly_upper", A, mode == BF_PRODUCT ? B : nullptr, l,
                                                   it->first, it->second)))
                     return rc;
-            if ((rc = launch_bf3_bottom<false>(ctx, s, "butterfly_bottom", A, mode == BF_PRODUCT ? B : nullptr, l)))
+            if ((rc = launch_bf3_bottom<false>(ctx, s, "butterfly_bottom", A, mode == BF_PRODUCT ? B : nullptr, l,
+                                               nl)))
                 return rc;
         }
         if (mode == BF_PRODUCT)
@@ -778,7 +787,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
                     (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, A, B, n,
                     ctx->tables);
         if (mode != BF_FWD) {
-            if ((rc = launch_bf3_bottom<true>(ctx, s, "ibutterfly_bottom", A, nullptr, l))) return rc;
+            if ((rc = launch_bf3_bottom<true>(ctx, s, "ibutterfly_bottom", A, nullptr, l, nl))) return rc;
             for (auto it = groups.begin(); it != groups.end(); ++it)
                 if ((rc = launch_bf3_upper<true>(ctx, s, "ibutterfly_upper", A, nullptr, l, it->first, it->second)))
                     return rc;

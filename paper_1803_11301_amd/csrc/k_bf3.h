@@ -166,22 +166,24 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_upper(uint64_t *__restric
 
 // ----------------------------------------------------------- bottom pass ---
 //
-// Layers 0 .. 6 on contiguous tiles of 2^12 values, all seven K tables
-// resident.  Register groups (forward order) {4,5,6}, {1,2,3} and {0} (with
-// two tile bits on which no layer runs); an exchange between groups.  Every
-// layer uses the V_16 split of k_bf2.h: K16 = 2^(32+d) + (b >> 15) << 16
-// changes once per 2^(i+4) tiles, so the tables are rebuilt almost never
-// (with the V_8 split, K of the lowest layers would change every tile or two
-// and vary inside a 2^12 tile below layer 4).
+// Layers 0 .. 6 (or 0 .. 5) on contiguous tiles of 2^12 values, every
+// layer's K table resident.  Register groups (forward order) {4,5,6}, {1,2,3}
+// and {0} (with two tile bits on which no layer runs), or {3,4,5} and {0,1,2}
+// for six layers; an exchange between groups.  Every layer uses the V_16
+// split of k_bf2.h: K16 = 2^(32+d) + (b >> 15) << 16 changes once per 2^(i+4)
+// tiles, so the tables are rebuilt almost never (with the V_8 split, K of the
+// lowest layers would change every tile or two and vary inside a 2^12 tile
+// below layer 4).  With six bottom layers the lowest upper pass takes layer 6.
 
-#define B3_BOT_LAYERS 7
-#define B3_BOT_GROUPS 3
+#define B3_BOT_LAYERS 7   // the default; a schedule may give the bottom pass 6 layers (two register groups)
 
+// NL bottom layers in ceil(NL / 3) register groups
+template <int NL>
 __device__ __forceinline__ B2Group bf3_bottom_group(int c)
 {
     // layers hi .. lo of group c, counted from the top, then padding bits from
     // the highest tile bits outside the group
-    const int hi = B3_BOT_LAYERS - 1 - 3 * c, lo = hi - 2 < 0 ? 0 : hi - 2;
+    const int hi = NL - 1 - 3 * c, lo = hi - 2 < 0 ? 0 : hi - 2;
     int bits[3], lay[3], cnt = 0;
     for (int r = lo; r <= hi; ++r) {
         bits[cnt] = r;
@@ -234,13 +236,15 @@ __device__ __forceinline__ void bf3_bottom_compute(const B2Group &g, uint64_t (&
     }
 }
 
-// Layers 0 .. 6 of A (and of B when B is not null: the second half of the
-// grid takes B; the grid is then even).  l >= 12.
-template <bool INV>
+// Layers 0 .. NL - 1 (NL = 6 or 7) of A (and of B when B is not null: the
+// second half of the grid takes B; the grid is then even).  l >= 12.
+template <bool INV, int NL>
 __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restrict__ A, uint64_t *__restrict__ B,
                                                                 int l, const DevTables *__restrict__ T)
 {
-    __shared__ __align__(16) uint64_t s_tab[B3_BOT_LAYERS][2048];   // K16 table of layer i
+    static_assert(NL == 6 || NL == 7, "bottom pass of 6 or 7 layers");
+    constexpr int NG = (NL + 2) / 3;   // register groups
+    __shared__ __align__(16) uint64_t s_tab[NL][2048];   // K16 table of layer i
     __shared__ __align__(16) uint64_t s_x[B3_STAGE_WORDS];
     __shared__ __align__(16) PermTab s_pt8[256];        // tables of every byte of V_8
     __shared__ uint16_t s_io16[2][256];                 // iota of the low two Cantor bytes
@@ -262,10 +266,10 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
     const uint64_t t_beg = bid * per, t_end = t_beg + per < ntiles ? t_beg + per : ntiles;
     if (t_beg >= t_end) return;   // uniform per workgroup
 
-    const B2Group g0 = bf3_bottom_group(INV ? B3_BOT_GROUPS - 1 : 0);
-    const int e0 = b2_thread_base<B3_TILE_LG>(g0, tid);
-    auto load = [&](uint64_t tile, uint64_t(&v)[8]) {
+    const B2Group g0 = bf3_bottom_group<NL>(INV ? NG - 1 : 0);
+    auto load = [&](uint64_t tile, uint64_t(&v)[8], int tid_t) {
         const uint64_t gbase = tile << B3_TILE_LG;
+        const int e0 = b2_thread_base<B3_TILE_LG>(g0, tid_t);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int e = e0 | ((r & 1) << g0.s[0]) | (((r >> 1) & 1) << g0.s[1]) | ((r >> 2) << g0.s[2]);
@@ -273,41 +277,47 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
         }
     };
 
-    uint32_t key[B3_BOT_LAYERS];
+    uint32_t key[NL];
 #pragma unroll
-    for (int i = 0; i < B3_BOT_LAYERS; ++i) key[i] = 0xFFFFFFFFu;
+    for (int i = 0; i < NL; ++i) key[i] = 0xFFFFFFFFu;
     uint64_t x[8], nx[8];
-    load(t_beg, nx);
+    load(t_beg, nx, tid);
     for (uint64_t tile = t_beg; tile < t_end; ++tile) {
         const uint64_t gbase = tile << B3_TILE_LG;
+        // every address below depends on the thread index only; in the
+        // forward pass, taking it through an opaque copy per tile keeps the
+        // compiler from holding the offsets live (and spilled) across the loop
+        // (the inverse pass has the registers, and runs faster without)
+        int tid_t = tid;
+        if constexpr (!INV) asm volatile("" : "+v"(tid_t));
 #pragma unroll
         for (int r = 0; r < 8; ++r) x[r] = nx[r];
-        if (tile + 1 < t_end) load(tile + 1, nx);   // in flight during this tile
+        if (tile + 1 < t_end) load(tile + 1, nx, tid_t);   // in flight during this tile
 
         // rebuild the tables whose K16 changed; uniform over the workgroup
         bool changed = false;
 #pragma unroll
-        for (int i = 0; i < B3_BOT_LAYERS; ++i) {
+        for (int i = 0; i < NL; ++i) {
             const uint32_t bh = (uint32_t)(gbase >> (i + 16)) << 8;
             if (key[i] != bh) {
                 key[i] = bh;
                 changed = true;
                 __syncthreads();   // s_tab[i] and s_img no longer read
-                ktable_basis(s_img, l - i, bh, T, tid);
+                ktable_basis(s_img, l - i, bh, T, tid_t);
                 __syncthreads();
-                for (int item = tid; item < 256; item += nth) ktable_fill_item(s_tab[i], s_img, item);
+                for (int item = tid_t; item < 256; item += nth) ktable_fill_item(s_tab[i], s_img, item);
             }
         }
         if (changed) __syncthreads();
 
 #pragma unroll
-        for (int cc = 0; cc < B3_BOT_GROUPS; ++cc) {
-            const int c = INV ? B3_BOT_GROUPS - 1 - cc : cc;
-            const B2Group g = bf3_bottom_group(c);
-            const int e_t = b2_thread_base<B3_TILE_LG>(g, tid);
+        for (int cc = 0; cc < NG; ++cc) {
+            const int c = INV ? NG - 1 - cc : cc;
+            const B2Group g = bf3_bottom_group<NL>(c);
+            const int e_t = b2_thread_base<B3_TILE_LG>(g, tid_t);
             if (cc > 0) {
-                const B2Group gp = bf3_bottom_group(INV ? c + 1 : c - 1);
-                const int ep = b2_thread_base<B3_TILE_LG>(gp, tid);
+                const B2Group gp = bf3_bottom_group<NL>(INV ? c + 1 : c - 1);
+                const int ep = b2_thread_base<B3_TILE_LG>(gp, tid_t);
                 __syncthreads();   // the previous exchange has been read
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(B3_THREADS, 1) void k_bf3_bottom(uint64_t *__restri
                 }
             }
             bf3_bottom_compute<INV>(g, x, s_tab, s_pt8, s_io16, gbase | (uint64_t)e_t, T);
-            if (cc == B3_BOT_GROUPS - 1) {
+            if (cc == NG - 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);

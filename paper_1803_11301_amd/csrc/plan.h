@@ -111,10 +111,14 @@ constexpr uint64_t NOALLOC_SCRATCH_WORDS = 4 * NOALLOC_WS_WORDS + NOALLOC_BWS_BY
 
 namespace fpmul_plan {
 
-constexpr int BOTTOM_LAYERS = 7;       // layers 0..6 in the bottom butterfly pass
+constexpr int BOTTOM_LAYERS = 7;       // layers 0..6 in the bottom butterfly pass (the default)
+constexpr int BOTTOM_LAYERS_MIN = 6;   // or layers 0..5, the upper passes taking layer 6
 constexpr int UPPER_MAXK = 7;          // layers per upper pass at most
-constexpr int UPPER_LOW_MINK = 5;      // the lowest upper pass starts at layer 7 and needs K >= 5 (12 - K <= 7)
 constexpr int TILE_LG = 12;            // 2^12 values per butterfly tile
+
+// the lowest upper pass starts at the bottom pass's layer count b and needs
+// K >= 12 - b layers (its tile's column bits lie below layer b)
+constexpr int upper_low_mink(int bottom) { return TILE_LG - bottom; }
 
 struct Schedule {
     std::vector<int> upper;   // layers per upper pass, lowest pass first; empty = the default split
@@ -134,39 +138,46 @@ inline std::vector<int> default_upper(int l)
     return g;
 }
 
-// a split is valid when its parts are 1..7 layers, sum to U, and the lowest
-// pass (from layer 7) has at least 5 layers
-inline bool upper_valid(int l, const std::vector<int> &g)
+// the bottom pass's layer count under a split: the layers below the upper passes
+inline int bottom_layers(int l, const std::vector<int> &g)
 {
-    const int U = l - BOTTOM_LAYERS;
-    if (U <= 0) return g.empty();
-    if (g.empty() || g[0] < UPPER_LOW_MINK) return false;
     int s = 0;
-    for (int k : g) {
-        if (k < 1 || k > UPPER_MAXK) return false;
-        s += k;
-    }
-    return s == U;
+    for (int k : g) s += k;
+    return g.empty() ? BOTTOM_LAYERS : l - s;
 }
 
-// every valid split into the fewest passes or one more
+// a split is valid when its parts are 1..7 layers, they leave 6 or 7 layers
+// to the bottom pass, and the lowest pass (from layer b) has at least 12 - b
+inline bool upper_valid(int l, const std::vector<int> &g)
+{
+    if (l - BOTTOM_LAYERS <= 0) return g.empty();
+    if (g.empty()) return false;
+    for (int k : g)
+        if (k < 1 || k > UPPER_MAXK) return false;
+    const int b = bottom_layers(l, g);
+    return b >= BOTTOM_LAYERS_MIN && b <= BOTTOM_LAYERS && g[0] >= upper_low_mink(b);
+}
+
+// every valid split into the fewest passes or one more, for either bottom pass
 inline std::vector<std::vector<int>> upper_candidates(int l)
 {
     std::vector<std::vector<int>> out;
-    const int U = l - BOTTOM_LAYERS;
-    if (U <= 0) return out;
-    const int m0 = (U + UPPER_MAXK - 1) / UPPER_MAXK;
-    for (int m = m0; m <= m0 + 1; ++m) {
-        // enumerate compositions of U into m parts in [1, 7] (odometer)
-        std::vector<int> c(m, 1);
-        while (true) {
-            int s = 0;
-            for (int k : c) s += k;
-            if (s == U && c[0] >= UPPER_LOW_MINK) out.push_back(c);
-            int i = m - 1;
-            while (i >= 0 && c[i] == UPPER_MAXK) c[i--] = 1;
-            if (i < 0) break;
-            ++c[i];
+    if (l - BOTTOM_LAYERS <= 0) return out;
+    for (int b = BOTTOM_LAYERS; b >= BOTTOM_LAYERS_MIN; --b) {
+        const int U = l - b;
+        const int m0 = (U + UPPER_MAXK - 1) / UPPER_MAXK;
+        for (int m = m0; m <= m0 + 1; ++m) {
+            // enumerate compositions of U into m parts in [1, 7] (odometer)
+            std::vector<int> c(m, 1);
+            while (true) {
+                int s = 0;
+                for (int k : c) s += k;
+                if (s == U && c[0] >= upper_low_mink(b)) out.push_back(c);
+                int i = m - 1;
+                while (i >= 0 && c[i] == UPPER_MAXK) c[i--] = 1;
+                if (i < 0) break;
+                ++c[i];
+            }
         }
     }
     return out;

@@ -122,8 +122,9 @@ static void fused_buffers_fit()
 }
 
 // the tuner's schedule space: every candidate split of the upper butterfly
-// layers is valid (parts 1..7 summing to l - 7, the lowest at least 5), the
-// default split is among them, no candidate repeats, and a cache line
+// layers is valid (parts 1..7 leaving 7 or 6 layers to the bottom pass, the
+// lowest at least 12 minus the bottom's layers), the default split is among
+// them, both bottom passes occur, no candidate repeats, and a cache line
 // written for a schedule parses back to it (and only for its own device)
 static void schedule_space()
 {
@@ -131,13 +132,20 @@ static void schedule_space()
         const auto cands = upper_candidates(l);
         const auto def = default_upper(l);
         CHECK(upper_valid(l, def), "l=%d default split invalid", l);
-        bool has_def = false;
+        bool has_def = false, has6 = false, has7 = false;
         for (size_t i = 0; i < cands.size(); ++i) {
             CHECK(upper_valid(l, cands[i]), "l=%d candidate %zu invalid", l, i);
+            const int b = bottom_layers(l, cands[i]);
+            CHECK(b == 6 || b == 7, "l=%d candidate %zu leaves %d bottom layers", l, i, b);
+            CHECK(cands[i][0] >= 12 - b, "l=%d candidate %zu: lowest pass too short", l, i);
+            has6 = has6 || b == 6;
+            has7 = has7 || b == 7;
             has_def = has_def || cands[i] == def;
             for (size_t j = i + 1; j < cands.size(); ++j) CHECK(cands[i] != cands[j], "l=%d repeated candidate", l);
         }
         CHECK(has_def, "l=%d default split not among the candidates", l);
+        CHECK(has6 && has7, "l=%d candidates miss a bottom pass size", l);
+        CHECK(bottom_layers(l, def) == 7, "l=%d default bottom pass", l);
         for (const auto &u : cands) {
             Schedule s;
             s.upper = u;
@@ -156,7 +164,12 @@ static void schedule_space()
     int lg = 0;
     Schedule r;
     // malformed or invalid lines are refused
+    CHECK(schedule_parse("gfx950 cu=256 log2n=31 upper=7,6,6 rows=2 zeta=8 ms=1", "gfx950", 256, lg, r) &&
+              bottom_layers(25, r.upper) == 6,
+          "a six-layer bottom split refused");
     for (const char *bad : {"gfx950 cu=256 log2n=31 upper=4,7,7 rows=2 zeta=8 ms=1",   // lowest pass below 5
+                            "gfx950 cu=256 log2n=31 upper=5,7,7 rows=2 zeta=8 ms=1",   // bottom 6, lowest below 6
+                            "gfx950 cu=256 log2n=31 upper=6,6,7,1 rows=2 zeta=8 ms=1", // 20 layers, bottom 5
                             "gfx950 cu=256 log2n=31 upper=6,6,5 rows=2 zeta=8 ms=1",   // 17 layers, not 18
                             "gfx950 cu=256 log2n=31 upper=6,6,6 rows=0 zeta=8 ms=1",   // no row workgroups
                             "gfx950 cu=256 log2n=21 upper=- rows=2 zeta=8 ms=1",       // outside the fused path
