@@ -184,9 +184,10 @@ int polymul_set_large_field(polymul_ctx *ctx, int min_log2n);
 /*
  * Schedule tuner for the fused path (transforms of 2^22 .. 2^31 bits).  The
  * product of one transform length can be computed under several schedules
- * of the same kernels: the upper butterfly layers (those above the bottom
- * pass of layers 0..6, Alg. 2) split into passes of up to 7 layers in any
- * way whose lowest pass has at least 5 layers, and the row and zeta
+ * of the same kernels: the bottom butterfly pass of layers 0..6 or 0..5
+ * (Alg. 2), the layers above it split into passes of up to 7 layers in any
+ * way whose lowest pass has at least 12 minus the bottom's layers, and the
+ * row and zeta
  * kernels of BasisCvt (Alg. 1) with 1, 2, 4 or 8 and 4, 8, 16 or 32
  * workgroups per CU.  polymul_tune times them on ctx's device for 2^log2n-bit
  * transforms (operands of 2^(log2n-1) bits from a fixed generator; the path
