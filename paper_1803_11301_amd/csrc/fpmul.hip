@@ -960,8 +960,13 @@ static int run_encode_fast(polymul_ctx *ctx, const uint64_t *a, uint64_t len, in
     const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / rpw,
                                                                               (uint64_t)ctx->num_cu * sc.rows_mult));
     KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_ROW_THREADS, X, a, len, lgR, EW, Y, inner, rpw);
-    KLAUNCH(ctx, s, "basiscvt_outer_encode", k_bc_outer_encode, (unsigned)std::min(BC_TAU_WORDS, ctx->num_cu),
-            BC_COL_THREADS, Y, lgR, l, vals, outer, ctx->tables);
+    // short columns: the compact kernel, four workgroups per CU
+    if (lgR <= BC_ENC_SMALL_LG)
+        KLAUNCH(ctx, s, "basiscvt_outer_encode", (k_bc_outer_encode<2, BC_ENC_SMALL_LG, 4, 4>),
+                (unsigned)std::min(BC_TAU_WORDS, 4 * ctx->num_cu), 256, Y, lgR, l, vals, outer, ctx->tables);
+    else
+        KLAUNCH(ctx, s, "basiscvt_outer_encode", (k_bc_outer_encode<4, 14, BC_ENC_PRE, 1>),
+                (unsigned)std::min(BC_TAU_WORDS, ctx->num_cu), BC_COL_THREADS, Y, lgR, l, vals, outer, ctx->tables);
     return 0;
 }
 
@@ -972,8 +977,14 @@ static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, ui
     const int l = log2n - 6, lgR = log2n - 16, EW = bc_ew(lgR);
     const fpmul_plan::Schedule sc = sched_of(ctx, log2n);
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
-    KLAUNCH(ctx, s, "decode_outer", k_bc_decode_outer, (unsigned)std::min(2 * BC_TAU_WORDS, ctx->num_cu), BC_COL_THREADS,
-            vals, lgR, l, reinterpret_cast<uint32_t *>(Y), outer, ctx->tables);
+    if (lgR <= BC_DEC_SMALL_LG)
+        KLAUNCH(ctx, s, "decode_outer", (k_bc_decode_outer<2, BC_DEC_SMALL_LG, 4, 4>),
+                (unsigned)std::min(2 * BC_TAU_WORDS, 4 * ctx->num_cu), 256, vals, lgR, l,
+                reinterpret_cast<uint32_t *>(Y), outer, ctx->tables);
+    else
+        KLAUNCH(ctx, s, "decode_outer", (k_bc_decode_outer<4, 15, BC_DEC_PRE, 1>),
+                (unsigned)std::min(2 * BC_TAU_WORDS, ctx->num_cu), BC_COL_THREADS, vals, lgR, l,
+                reinterpret_cast<uint32_t *>(Y), outer, ctx->tables);
     const int rpw = rows_per_wg(ctx, lgR);
     const unsigned grows = (unsigned)std::min<uint64_t>((1ull << lgR) / rpw, (uint64_t)ctx->num_cu * sc.rows_mult);
     KLAUNCH(ctx, s, "ibasiscvt_rows", k_bc_inv_rows, grows, BC_ROW_THREADS, reinterpret_cast<const uint32_t *>(Y), lgR,

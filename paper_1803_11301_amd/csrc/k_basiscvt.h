@@ -739,16 +739,15 @@ __device__ __forceinline__ void bc_wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Steps [K, L.n) of BasisCvt(2^LGR) on a column of a BC_COL_THREADS
-// workgroup.  A step whose segments (2^LGS elements) fit in one wave's share
-// of 2^(LGR - 4) consecutive elements runs on that share alone, ordered by
+// Steps [K, L.n) of BasisCvt(2^LGR) on a column of a workgroup of 2^LGW
+// waves.  A step whose segments (2^LGS elements) fit in one wave's share of
+// 2^(LGR - LGW) consecutive elements runs on that share alone, ordered by
 // wave-level syncs instead of workgroup barriers.
-template <int LGR, int K, bool INV, typename T>
+template <int LGR, int K, bool INV, typename T, int LGW = 4>
 __device__ __forceinline__ void bc_elem_steps_from(T *v, int tid, int sws)
 {
     constexpr BcStepList L = BcElemSteps<LGR>::L;
-    constexpr int LGL = LGR - 4;   // log2 elements per wave (16 waves)
-    static_assert(BC_COL_THREADS == 1024, "16 waves per column workgroup");
+    constexpr int LGL = LGR - LGW;   // log2 elements per wave
     if constexpr (K < L.n) {
         constexpr int k = INV ? L.n - 1 - K : K;
         constexpr int LGS = L.lgs[k], LGD = L.lgd[k];
@@ -765,29 +764,33 @@ __device__ __forceinline__ void bc_elem_steps_from(T *v, int tid, int sws)
             else
                 __syncthreads();
         } else {
-            bc_elem_phase<LGS, LGD, INV ? 1 : 0, LGR, 10>(v, 0, tid, sws);
+            bc_elem_phase<LGS, LGD, INV ? 1 : 0, LGR, 6 + LGW>(v, 0, tid, sws);
             __syncthreads();
-            bc_elem_phase<LGS, LGD, INV ? 0 : 1, LGR, 10>(v, 0, tid, sws);
+            bc_elem_phase<LGS, LGD, INV ? 0 : 1, LGR, 6 + LGW>(v, 0, tid, sws);
             __syncthreads();
         }
-        bc_elem_steps_from<LGR, K + 1, INV>(v, tid, sws);
+        bc_elem_steps_from<LGR, K + 1, INV, T, LGW>(v, tid, sws);
     }
 }
 
 // BasisCvt(2^lgR) on the elements of a column in LDS (swizzled by sws);
 // compile-time steps for lgR in 6 .. 15, the run-time list otherwise (the
 // column is then unpermuted: bc_col_sws gives sws >= lgR)
-template <typename T>
+// (a workgroup of 2^LGW waves; compile-time lists up to 2^MAXLG elements)
+template <typename T, int LGW = 4, int MAXLG = 15>
 __device__ __forceinline__ void bc_elem_steps_any(T *v, int lgR, const BcSteps &st, bool inverse, int tid, int nth,
                                                   int sws)
 {
 #define BC_ELEM_CASE(R)                                                         \
     case R:                                                                     \
-        if (inverse)                                                            \
-            bc_elem_steps_from<R, 0, true>(v, tid, sws);                        \
-        else                                                                    \
-            bc_elem_steps_from<R, 0, false>(v, tid, sws);                       \
-        return;
+        if constexpr (R <= MAXLG) {                                             \
+            if (inverse)                                                        \
+                bc_elem_steps_from<R, 0, true, T, LGW>(v, tid, sws);            \
+            else                                                                \
+                bc_elem_steps_from<R, 0, false, T, LGW>(v, tid, sws);           \
+            return;                                                             \
+        }                                                                       \
+        break;
     switch (lgR) {
         BC_ELEM_CASE(6)
         BC_ELEM_CASE(7)
@@ -800,8 +803,9 @@ __device__ __forceinline__ void bc_elem_steps_any(T *v, int lgR, const BcSteps &
         BC_ELEM_CASE(14)
         BC_ELEM_CASE(15)
     default:
-        bc_elem_steps<T>(v, lgR, st, inverse, tid, nth);
+        break;
     }
+    bc_elem_steps<T>(v, lgR, st, inverse, tid, nth);
 #undef BC_ELEM_CASE
 }
 
@@ -1041,25 +1045,35 @@ __device__ __forceinline__ uint64_t bc_win8(const uint64_t (*tab)[256], uint64_t
 // next column is loaded into registers while this one is converted and
 // encoded.
 #define BC_ENC_PRE 16   // column words per thread: R <= 2^14 = BC_ENC_PRE x BC_COL_THREADS
-__global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64_t *__restrict__ Y, int lgR, int l,
-                                                                uint64_t *__restrict__ vals, BcSteps outer,
-                                                                const DevTables *__restrict__ T)
+// Column kernels come in two sizes: the full one (16 waves, columns of up to
+// 2^14 (Encode) or 2^15 (Decode) rows in LDS, one workgroup per CU) and a
+// compact one for short columns (4 waves, up to 2^10 or 2^11 rows, four
+// workgroups per CU), so that the columns of a short operand are converted
+// side by side on a CU rather than one after another.  2^LGW waves, columns
+// of up to 2^LGCAP elements (the host launches only lgR <= LGCAP), PRE column
+// words per thread in flight, at least MINW waves per SIMD.
+#define BC_ENC_SMALL_LG 10   // compact Encode kernel for lgR up to this
+template <int LGW, int LGCAP, int PRE, int MINW>
+__global__ __launch_bounds__(64 << LGW, MINW) void k_bc_outer_encode(const uint64_t *__restrict__ Y, int lgR, int l,
+                                                                   uint64_t *__restrict__ vals, BcSteps outer,
+                                                                   const DevTables *__restrict__ T)
 {
-    __shared__ __align__(16) uint64_t col[1 << 14];
+    constexpr int NT = 64 << LGW, NW = NT / 64;
+    static_assert((1 << LGCAP) <= PRE * NT, "a thread's share of the column is in flight at once");
+    __shared__ __align__(16) uint64_t col[1 << LGCAP];
     __shared__ uint64_t enc[8][256];
-    constexpr int NW = BC_COL_THREADS / 64;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int R = 1 << lgR;
     const int lgrpj = l - 16, rpj = 1 << lgrpj;           // n_p / tau
     const int sws = bc_col_sws<uint64_t>(lgR, lgrpj);
-    const int per = R >= BC_COL_THREADS ? R / BC_COL_THREADS : 1;
-    for (int i = tid; i < 8 * 256; i += BC_COL_THREADS) (&enc[0][0])[i] = (&T->enc_win[0][0])[i];
-    uint64_t pre[BC_ENC_PRE];
+    const int per = R >= NT ? R / NT : 1;
+    for (int i = tid; i < 8 * 256; i += NT) (&enc[0][0])[i] = (&T->enc_win[0][0])[i];
+    uint64_t pre[PRE];
     auto load = [&](int c, int tid_c) {
         const uint64_t *src = Y + (uint64_t)c * R;
 #pragma unroll
-        for (int k = 0; k < BC_ENC_PRE; ++k) {
-            const int r = tid_c + k * BC_COL_THREADS;
+        for (int k = 0; k < PRE; ++k) {
+            const int r = tid_c + k * NT;
             if (k < per) pre[k] = src[r < R ? r : R - 1];
         }
     };
@@ -1072,13 +1086,13 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64
         int tid_c = tid;
         asm volatile("" : "+v"(tid_c));
 #pragma unroll
-        for (int k = 0; k < BC_ENC_PRE; ++k) {
-            const int r = tid_c + k * BC_COL_THREADS;
+        for (int k = 0; k < PRE; ++k) {
+            const int r = tid_c + k * NT;
             if (k < per && r < R) col[bc_swz<uint64_t>(r, sws)] = pre[k];
         }
         __syncthreads();
         if (c + (int)gridDim.x < BC_TAU_WORDS) load(c + gridDim.x, tid_c);   // in flight during this column
-        bc_elem_steps_any<uint64_t>(col, lgR, outer, false, tid_c, BC_COL_THREADS, sws);
+        bc_elem_steps_any<uint64_t, LGW, LGCAP>(col, lgR, outer, false, tid_c, NT, sws);
 #pragma unroll 1
         for (int r0 = wave; r0 < rpj; r0 += NW) {
             const int rr = lane * rpj + r0;              // row of Encode input row j = lane
@@ -1098,25 +1112,29 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_outer_encode(const uint64
 // half-wave decodes the 32 elements of one r0; the values of the next column
 // are loaded into registers while this one is converted and stored.
 #define BC_DEC_PRE 16   // r0 pairs per wave and column: n_p / tau <= 2 x 16 waves x BC_DEC_PRE
-__global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64_t *__restrict__ vals, int lgR, int l,
-                                                                uint32_t *__restrict__ Y32, BcSteps outer,
-                                                                const DevTables *__restrict__ T)
+#define BC_DEC_SMALL_LG 11   // compact Decode kernel for lgR up to this
+// (sizes as for k_bc_outer_encode; PRE r0 passes per wave in flight)
+template <int LGW, int LGCAP, int PRE, int MINW>
+__global__ __launch_bounds__(64 << LGW, MINW) void k_bc_decode_outer(const uint64_t *__restrict__ vals, int lgR, int l,
+                                                                   uint32_t *__restrict__ Y32, BcSteps outer,
+                                                                   const DevTables *__restrict__ T)
 {
-    __shared__ __align__(16) uint32_t col[1 << 15];
+    constexpr int NT = 64 << LGW, NW = NT / 64;
+    static_assert((1 << (LGCAP - 6)) <= 2 * NW * PRE, "a wave's r0 passes are in flight at once");
+    __shared__ __align__(16) uint32_t col[1 << LGCAP];
     __shared__ uint64_t dec[8][256];
-    constexpr int NW = BC_COL_THREADS / 64;
     const int R = 1 << lgR;
     const int lgrpj = l - 16, rpj = 1 << lgrpj;
     const int sws = bc_col_sws<uint32_t>(lgR, lgrpj);
     const int kmax = (rpj + 2 * NW - 1) / (2 * NW);       // r0 passes per wave
     constexpr int NCOL = 2 * BC_TAU_WORDS;
-    for (int i = threadIdx.x; i < 8 * 256; i += BC_COL_THREADS) (&dec[0][0])[i] = (&T->dec_win[0][0])[i];
-    uint64_t pre[BC_DEC_PRE];
+    for (int i = threadIdx.x; i < 8 * 256; i += NT) (&dec[0][0])[i] = (&T->dec_win[0][0])[i];
+    uint64_t pre[PRE];
     // lane (half, t) of wave w decodes element 32 c + t of r0 = 2 w + 2 NW k + half
     auto load = [&](int c, int tid_c) {
         const int wave = tid_c >> 6, half = (tid_c >> 5) & 1, t = tid_c & 31;
 #pragma unroll
-        for (int k = 0; k < BC_DEC_PRE; ++k) {
+        for (int k = 0; k < PRE; ++k) {
             const int r0 = 2 * wave + 2 * NW * k + half;
             if (k < kmax) pre[k] = vals[((uint64_t)(r0 < rpj ? r0 : rpj - 1) << 16) + 32u * c + t];
         }
@@ -1132,7 +1150,7 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
         asm volatile("" : "+v"(tid_c));
         const int lane = tid_c & 63, wave = tid_c >> 6, half = lane >> 5, t = lane & 31;
 #pragma unroll
-        for (int k = 0; k < BC_DEC_PRE; ++k) {
+        for (int k = 0; k < PRE; ++k) {
             if (k >= kmax) continue;   // uniform
             const int r0 = 2 * wave + 2 * NW * k + half;
             const uint64_t a = bc_win8(dec, pre[k]);
@@ -1157,15 +1175,15 @@ __global__ __launch_bounds__(BC_COL_THREADS) void k_bc_decode_outer(const uint64
         }
         __syncthreads();
         if (c + (int)gridDim.x < NCOL) load(c + gridDim.x, tid_c);   // in flight during this column
-        bc_elem_steps_any<uint32_t>(col, lgR, outer, true, tid_c, BC_COL_THREADS, sws);
+        bc_elem_steps_any<uint32_t, LGW, LGCAP>(col, lgR, outer, true, tid_c, NT, sws);
         uint32_t *dst = Y32 + (uint64_t)c * R;
-        if (R >= 4 * BC_COL_THREADS) {
+        if (R >= 4 * NT) {
             // 16-byte groups stay whole under the swizzle
             const uint4 *c4 = reinterpret_cast<const uint4 *>(col);
             uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-            for (int g = tid_c; g < R / 4; g += BC_COL_THREADS) d4[g] = c4[bc_swz<uint32_t>(4 * g, sws) >> 2];
+            for (int g = tid_c; g < R / 4; g += NT) d4[g] = c4[bc_swz<uint32_t>(4 * g, sws) >> 2];
         } else {
-            for (int r = tid_c; r < R; r += BC_COL_THREADS) dst[r] = col[bc_swz<uint32_t>(r, sws)];
+            for (int r = tid_c; r < R; r += NT) dst[r] = col[bc_swz<uint32_t>(r, sws)];
         }
         __syncthreads();
     }
