@@ -689,10 +689,6 @@ static int set_lds_limits()
     // k_batch also has static LDS, so its dynamic limit is exactly what it uses
     HIP_TRY(hipFuncSetAttribute((const void *)k_batch, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)bf_bottom_lds(BF_BOTTOM_R, true)));
-    HIP_TRY(hipFuncSetAttribute((const void *)k_mid_encode, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                MID_LDS_BYTES));
-    HIP_TRY(hipFuncSetAttribute((const void *)k_mid_decode, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                MID_LDS_BYTES));
     done = 1;
     return 0;
 }
@@ -737,8 +733,6 @@ static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
 
 #define BF3_MIN_L 20    // resident-table bottom pass from 2^20 transform values
 #define SINGLE_VIA_BATCH_LOG2N 17   // polymul_ex of products up to 2^17 bits runs as a one-item batch
-#define MID_MIN_LOG2N 18            // mid-size path (LDS BasisCvt in one workgroup per operand) ...
-#define MID_MAX_LOG2N 20            // ... up to 2^20-bit transforms
 
 // the bottom pass of layers 0 .. nl - 1 (nl = 6 or 7)
 template <bool INV>
@@ -1168,17 +1162,6 @@ static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, con
     if ((rc = set_lds_limits())) return rc;
     uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2], *W3 = ctx->ws[3];
     uint64_t *pa, *pb;
-    if (log2n >= MID_MIN_LOG2N && log2n <= MID_MAX_LOG2N && ilog2(std::max<uint64_t>(len_a, 1)) <= 20 &&
-        ilog2(std::max<uint64_t>(len_b, 1)) <= 20) {
-        // each operand's BasisCvt whole in one workgroup's LDS (2^20 bits)
-        if ((rc = batch_steps_upload(ctx))) return rc;
-        KLAUNCH_LDS(ctx, s, "mid_encode", k_mid_encode, 2, BT_THREADS, MID_LDS_BYTES, a, len_a, b, len_b, log2n, W0,
-                    W1, ctx->tables, ctx->bsteps);
-        if ((rc = run_butterflies(ctx, BF_PRODUCT, W0, W1, log2n - 6, s))) return rc;
-        KLAUNCH_LDS(ctx, s, "mid_decode", k_mid_decode, 1, BT_THREADS, MID_LDS_BYTES, W0, log2n, out, lc, W2, W3,
-                    ctx->tables, ctx->bsteps);
-        return 0;
-    }
     // forward transforms of A into W0, of B into W1 (W2, W3 scratch)
     for (int side = 0; side < 2; ++side) {
         const uint64_t *src = side ? b : a;

@@ -618,60 +618,3 @@ __global__ __launch_bounds__(BT_THREADS) void k_batch(
     }
 }
 
-// ------------------------------------------------------ mid-size products --
-//
-// Products with transforms of 2^18 .. 2^21 bits and operands of at most
-// 2^20 bits (polymul_ex): each operand's BasisCvt runs whole in the LDS of
-// one workgroup and Encode reads it from there (k_mid_encode, one workgroup
-// per operand); the butterflies are the multi-workgroup passes; Decode and
-// the inverse BasisCvt run in one workgroup (k_mid_decode).  Three launches
-// plus the butterflies, instead of one launch per BasisCvt step.
-#define MID_LDS_BYTES (BT_LDS_WORDS * 8)
-
-__global__ __launch_bounds__(BT_THREADS) void k_mid_encode(const uint64_t *__restrict__ a, uint64_t la,
-                                                           const uint64_t *__restrict__ b, uint64_t lb, int log2n,
-                                                           uint64_t *__restrict__ ta, uint64_t *__restrict__ tb,
-                                                           const DevTables *__restrict__ T,
-                                                           const BatchSteps *__restrict__ BS)
-{
-    extern __shared__ __align__(16) uint8_t smem[];
-    uint64_t *v = reinterpret_cast<uint64_t *>(smem);
-    const int tid = threadIdx.x, nth = blockDim.x;
-    const bool side = blockIdx.x != 0;
-    const uint64_t *src = side ? b : a;
-    const uint64_t len = side ? lb : la;
-    int lgN = bt_ceil_log2(len);
-    if (lgN < BT_MIN_LOG2N) lgN = BT_MIN_LOG2N;
-    const int nw = (int)((1ull << lgN) / 64);   // at most BT_LDS_WORDS (checked on the host)
-    const uint64_t inw = (len + 63) / 64;
-    for (int w = tid; w < nw; w += nth) {
-        uint64_t x = 0;
-        if ((uint64_t)w < inw) {
-            x = src[w];
-            if ((uint64_t)w == inw - 1 && (len & 63)) x &= (~0ull) >> (64 - (len & 63));
-        }
-        v[w] = x;
-    }
-    __syncthreads();
-    bt_lds_steps(v, nw, BS->st + BS->first[lgN], BS->count[lgN], false, 0, BS->count[lgN], tid, nth);
-    bt_encode(v, log2n - 6, side ? tb : ta, T, tid, nth, (uint64_t)nw);
-}
-
-__global__ __launch_bounds__(BT_THREADS) void k_mid_decode(const uint64_t *__restrict__ vals, int log2n,
-                                                           uint64_t *__restrict__ out, uint64_t lc,
-                                                           uint64_t *__restrict__ X, uint64_t *__restrict__ Y,
-                                                           const DevTables *__restrict__ T,
-                                                           const BatchSteps *__restrict__ BS)
-{
-    extern __shared__ __align__(16) uint8_t smem[];
-    const int tid = threadIdx.x, nth = blockDim.x;
-    bt_decode(vals, log2n - 6, X, Y, T, tid, nth);
-    __syncthreads();
-    const uint64_t *res = bt_basiscvt_lds(X, Y, log2n, true, BS, reinterpret_cast<uint64_t *>(smem), tid, nth);
-    const uint64_t ow = (lc + 63) / 64;
-    for (uint64_t w = tid; w < ow; w += nth) {
-        uint64_t x = res[w];
-        if (w == ow - 1 && (lc & 63)) x &= (~0ull) >> (64 - (lc & 63));
-        out[w] = x;
-    }
-}

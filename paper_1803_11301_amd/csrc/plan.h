@@ -33,14 +33,16 @@ constexpr uint64_t next_pow2(uint64_t x)
 }
 
 // log2 of the transform length of a product of lc bits: n = max(64,
-// 2^ceil(log2 lc)), except that a 2^21-bit transform is taken as 2^22 bits,
-// which the fused path (from 2^22) computes faster than the per-step path;
-// any n >= lc gives the same product (the transform is a bijection on
-// polynomials of fewer than n bits)
+// 2^ceil(log2 lc)), except that transforms of 2^18 .. 2^21 bits are taken as
+// 2^22 bits, which the fused path (from 2^22) computes faster (its chain of
+// launches spreads over the chip, about 0.14 ms for any of these products,
+// where a one-workgroup BasisCvt per operand took 0.20 ms at 2^19 bits and
+// 0.29 ms at 2^20); any n >= lc gives the same product (the transform is a
+// bijection on polynomials of fewer than n bits)
 constexpr int product_log2n(uint64_t lc)
 {
     const int k = std::max(6, ilog2(lc));
-    return k == 21 ? 22 : k;
+    return (k >= 18 && k <= 21) ? 22 : k;
 }
 
 // log2 of the transform length of a GF(2^128) product (m = 128: n >= 128)

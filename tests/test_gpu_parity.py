@@ -394,9 +394,8 @@ def test_pointwise_rejects_bad_arguments(ctx):
                                    ((1 << 20) - 10, 5), ((1 << 19) - 1, (1 << 19) + 5), (1 << 20, 1 << 20),
                                    (1000, (1 << 20) - 1), ((1 << 20) + 1, 1 << 10)])
 def test_mid_size_products_exact(ctx, la, lb):
-    """Products with transforms of 2^18..2^20 bits (each operand's BasisCvt in
-    one workgroup's LDS) and of 2^21 bits (computed with 2^22-bit transforms
-    on the fused path)."""
+    """Products of 2^17 .. 2^21 bits, computed with 2^22-bit transforms on the
+    fused path (short operands: few rows, short columns)."""
     say("mid size", la, lb)
     rng = random.Random(la * 3 + lb)
     a, b = rand_words(rng, la), rand_words(rng, lb)
