@@ -116,21 +116,21 @@ STAGES = [
 COUNTER_SOURCES = ("paper_1803_11301_amd/csrc/fpmul.hip", "paper_1803_11301_amd/csrc/k_basiscvt.h",
                    "paper_1803_11301_amd/csrc/k_bf3.h", "paper_1803_11301_amd/csrc/k_bf2.h",
                    "paper_1803_11301_amd/csrc/gf_device.h")
-COUNTERS_SHA256 = "62e168c7af9fb9f69b2f009729d83ad7afdc85e39b6977637c389ae27f0d178c"
+COUNTERS_SHA256 = "400256a219cddd6ed411613ab41aa843994d898bd45407904eaf60d3d89f3b1c"
 COUNTERS = {
     # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB, SQ_INSTS_VALU) per dispatch
-    "basiscvt_zeta": (106590, 163840, 1.358e+07),
-    "basiscvt_rows": (75830, 131072, 5.927e+07),
-    "basiscvt_outer_encode": (90366, 305152, 7.67e+07),
-    "butterfly_upper": (262512, 524288, 1.475e+08),
-    "butterfly_bottom": (262604, 524288, 2.961e+08),
-    "pointwise": (262756, 262144, 1.05e+08),
+    "basiscvt_zeta": (106592, 163840, 1.358e+07),
+    "basiscvt_rows": (75595, 131072, 5.905e+07),
+    "basiscvt_outer_encode": (65784, 262144, 7.314e+07),
+    "butterfly_upper": (262517, 524288, 1.475e+08),
+    "butterfly_bottom": (262612, 524288, 3.087e+08),
+    "pointwise": (262762, 262144, 1.05e+08),
     "ibutterfly_bottom": (131470, 262144, 1.529e+08),
     "ibutterfly_upper": (131376, 262144, 7.336e+07),
-    "decode_outer": (131459, 262144, 1.41e+08),
-    "ibasiscvt_rows": (139932, 393216, 1.127e+08),
-    "ibasiscvt_zeta": (196696, 393216, 2.046e+07),
-    "ibasiscvt_store": (168386, 262144, 1.91e+07),
+    "decode_outer": (131460, 262144, 1.41e+08),
+    "ibasiscvt_rows": (135708, 393216, 1.125e+08),
+    "ibasiscvt_zeta": (196697, 393216, 2.046e+07),
+    "ibasiscvt_store": (168365, 262144, 1.91e+07),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
