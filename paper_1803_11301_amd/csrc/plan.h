@@ -124,7 +124,7 @@ constexpr int upper_low_mink(int bottom) { return TILE_LG - bottom; }
 
 struct Schedule {
     std::vector<int> upper;   // layers per upper pass, lowest pass first; empty = the default split
-    int rows_mult = 4;        // row-kernel workgroups per CU (the tuner's usual choice on MI355X)
+    int rows_mult = 4;        // forward row-kernel workgroups per CU (the inverse takes four times as many)
     int zeta_mult = 16;       // zeta-kernel workgroups per CU (likewise)
 };
 
