@@ -904,9 +904,13 @@ static int rows_per_wg(const polymul_ctx *ctx, int lgR)
     return rpw;
 }
 
+// the superset sums of one operand (X, in, len), or of two of the same row
+// count in the same launches (the second as X1, in1, len1; grid y = operand)
 static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t *in, uint64_t len, int lgR, int EW,
-                    bool skew_first, int zeta_mult)
+                    bool skew_first, int zeta_mult, uint64_t *X1 = nullptr, const uint64_t *in1 = nullptr,
+                    uint64_t len1 = 0)
 {
+    const unsigned ny = X1 ? 2 : 1;
     const int nb1 = std::min(lgR, 8), nb2 = lgR - nb1;
     for (int pass = 0; pass < 2; ++pass) {
         const int b0 = pass ? nb1 : 0, nb = pass ? nb2 : nb1;
@@ -924,44 +928,73 @@ static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t
             const uint64_t rt = (1ull << (lgR - nb)) * (uint64_t)(EW >> (12 - nb));
             const unsigned g = (unsigned)std::min<uint64_t>(rt, (uint64_t)ctx->num_cu * zeta_mult);
             if (nb == 8)
-                KLAUNCH(ctx, s, name, k_bc_zeta_r<8>, g, 256, X, in, len, lgR, EW, b0, skew);
+                KLAUNCH(ctx, s, name, k_bc_zeta_r<8>, dim3(g, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
             else if (nb == 7)
-                KLAUNCH(ctx, s, name, k_bc_zeta_r<7>, g, 256, X, in, len, lgR, EW, b0, skew);
+                KLAUNCH(ctx, s, name, k_bc_zeta_r<7>, dim3(g, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
             else
-                KLAUNCH(ctx, s, name, k_bc_zeta_r<6>, g, 256, X, in, len, lgR, EW, b0, skew);
+                KLAUNCH(ctx, s, name, k_bc_zeta_r<6>, dim3(g, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
             continue;
         }
-        KLAUNCH(ctx, s, name, k_bc_zeta, grid, BC_THREADS, X, in, len, lgR, EW, b0, nb, lgWc, skew);
+        KLAUNCH(ctx, s, name, k_bc_zeta, dim3(grid, ny), BC_THREADS, X, in, len, lgR, EW, b0, nb, lgWc, skew, X1, in1,
+                len1);
     }
     return 0;
 }
 
-// operand (len bits) -> BasisCvt -> Encode -> vals (2^(log2n-6) words); X, Y scratch
-static int run_encode_fast(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int log2n, uint64_t *vals,
-                           uint64_t *X, uint64_t *Y, hipStream_t s)
+// rows of 2^16 bits in the fused BasisCvt of a len-bit operand: 2^lgR
+static int bc_lgR(uint64_t len)
+{
+    const uint64_t N = next_pow2(std::max<uint64_t>(len, 1));
+    return N <= (1ull << 16) ? 0 : ilog2(N) - 16;
+}
+
+// one operand of the fused forward steps: its bits, the transform values
+// out (2^(log2n-6) words) and the scratch X (skewed rows), Y (columns)
+struct EncOp {
+    const uint64_t *a;
+    uint64_t len;
+    uint64_t *vals, *X, *Y;
+};
+
+// operand (len bits) -> BasisCvt -> Encode -> vals; with B as well (same row
+// count), both operands go through the same launches, one per grid row y
+static int run_encode_fast(polymul_ctx *ctx, const EncOp &A, const EncOp *B, int log2n, hipStream_t s)
 {
     const int l = log2n - 6;
-    const uint64_t N = next_pow2(std::max<uint64_t>(len, 1));
-    const int lgR = N <= (1ull << 16) ? 0 : ilog2(N) - 16;
+    const int lgR = bc_lgR(A.len);
+    if (B && bc_lgR(B->len) != lgR) return fail(POLYMUL_EIO, "operands of one launch differ in row count");
+    const unsigned ny = B ? 2 : 1;
+    const EncOp &B1 = B ? *B : A;   // a valid second set of arguments, unused when ny = 1
     const int EW = bc_ew(lgR);
     const fpmul_plan::Schedule sc = sched_of(ctx, log2n);
     if (lgR >= 1) {
-        int rc = run_zeta(ctx, s, X, a, len, lgR, EW, true, sc.zeta_mult);
+        int rc = run_zeta(ctx, s, A.X, A.a, A.len, lgR, EW, true, sc.zeta_mult, B ? B->X : nullptr,
+                          B ? B->a : nullptr, B ? B->len : 0);
         if (rc) return rc;
     }
     const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
     const int rpw = rows_per_wg(ctx, lgR);
     const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / rpw,
                                                                               (uint64_t)ctx->num_cu * sc.rows_mult));
-    KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, grows, BC_ROW_THREADS, X, a, len, lgR, EW, Y, inner, rpw);
+    KLAUNCH(ctx, s, "basiscvt_rows", k_bc_fwd_rows, dim3(grows, ny), BC_ROW_THREADS, A.X, A.a, A.len, lgR, EW, A.Y,
+            inner, rpw, B1.X, B1.a, B1.len, B1.Y);
     // short columns: the compact kernel, four workgroups per CU
     if (lgR <= BC_ENC_SMALL_LG)
         KLAUNCH(ctx, s, "basiscvt_outer_encode", (k_bc_outer_encode<2, BC_ENC_SMALL_LG, 4, 4>),
-                (unsigned)std::min(BC_TAU_WORDS, 4 * ctx->num_cu), 256, Y, lgR, l, vals, outer, ctx->tables);
+                dim3((unsigned)std::min(BC_TAU_WORDS, 4 * ctx->num_cu), ny), 256, A.Y, lgR, l, A.vals, outer,
+                ctx->tables, B1.Y, B1.vals);
     else
         KLAUNCH(ctx, s, "basiscvt_outer_encode", (k_bc_outer_encode<4, 14, BC_ENC_PRE, 1>),
-                (unsigned)std::min(BC_TAU_WORDS, ctx->num_cu), BC_COL_THREADS, Y, lgR, l, vals, outer, ctx->tables);
+                dim3((unsigned)std::min(BC_TAU_WORDS, ctx->num_cu), ny), BC_COL_THREADS, A.Y, lgR, l, A.vals, outer,
+                ctx->tables, B1.Y, B1.vals);
     return 0;
+}
+
+static int run_encode_fast(polymul_ctx *ctx, const uint64_t *a, uint64_t len, int log2n, uint64_t *vals,
+                           uint64_t *X, uint64_t *Y, hipStream_t s)
+{
+    const EncOp A{a, len, vals, X, Y};
+    return run_encode_fast(ctx, A, nullptr, log2n, s);
 }
 
 // vals (destroyed? no: read only) -> Decode -> iBasisCvt -> out (len bits)
@@ -1165,8 +1198,16 @@ static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, con
     if ((rc = set_lds_limits())) return rc;
     uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2], *W3 = ctx->ws[3];
     uint64_t *pa, *pb;
-    // forward transforms of A into W0, of B into W1 (W2, W3 scratch)
-    for (int side = 0; side < 2; ++side) {
+    // forward transforms of A into W0, of B into W1.  Operands of one row
+    // count share each launch, their skewed rows in W0 and W1 (free until
+    // Encode writes the values there) and their columns in W2 and W3; else
+    // one after the other with W2, W3 as scratch.
+    const bool paired = fast_path(log2n) && std::max(len_a, len_b) <= (1ull << 30) && bc_lgR(len_a) == bc_lgR(len_b);
+    if (paired) {
+        const EncOp A{a, len_a, W0, W0, W2}, B{b, len_b, W1, W1, W3};
+        if ((rc = run_encode_fast(ctx, A, &B, log2n, s))) return rc;
+    }
+    for (int side = 0; side < 2 && !paired; ++side) {
         const uint64_t *src = side ? b : a;
         const uint64_t len = side ? len_b : len_a;
         uint64_t *dst = side ? W1 : W0;

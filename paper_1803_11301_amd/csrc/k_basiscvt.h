@@ -421,11 +421,16 @@ __device__ void bc_elem_steps(T *v, int lgR, const BcSteps &st, bool inverse, in
 // Superset sum over row-index bits [b0, b0 + nb) of X (R rows of EW words),
 // tile = 2^nb rows (the other row bits fixed) x W words.  With skew_in set the
 // tile is loaded from the unskewed rows of `in` (len bits, row r shifted left
-// by r bits) instead of from X.
-__global__ __launch_bounds__(BC_THREADS) void k_bc_zeta(uint64_t *__restrict__ X, const uint64_t *__restrict__ in,
-                                                        uint64_t len, int lgR, int EW, int b0, int nb, int lgWc,
-                                                        int skew_in)
+// by r bits) instead of from X.  blockIdx.y picks the operand: (X0, in0,
+// len0) or (X1, in1, len1), so that both operands of a product, of the same
+// row count, take one launch.
+__global__ __launch_bounds__(BC_THREADS) void k_bc_zeta(uint64_t *X0, const uint64_t *in0, uint64_t len0, int lgR,
+                                                        int EW, int b0, int nb, int lgWc, int skew_in,
+                                                        uint64_t *X1, const uint64_t *in1, uint64_t len1)
 {
+    uint64_t *__restrict__ X = blockIdx.y ? X1 : X0;
+    const uint64_t *__restrict__ in = blockIdx.y ? in1 : in0;
+    const uint64_t len = blockIdx.y ? len1 : len0;
     __shared__ uint64_t s[BC_ZETA_LDS];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int Wc = 1 << lgWc, rows = 1 << nb;
@@ -523,10 +528,15 @@ __device__ __forceinline__ int bcz_elem(int base, int v)
     return e;
 }
 
+// (operands by blockIdx.y as in k_bc_zeta)
 template <int NB>
-__global__ __launch_bounds__(256) void k_bc_zeta_r(uint64_t *__restrict__ X, const uint64_t *__restrict__ in,
-                                                   uint64_t len, int lgR, int EW, int b0, int skew_in)
+__global__ __launch_bounds__(256) void k_bc_zeta_r(uint64_t *X0, const uint64_t *in0, uint64_t len0, int lgR, int EW,
+                                                   int b0, int skew_in, uint64_t *X1, const uint64_t *in1,
+                                                   uint64_t len1)
 {
+    uint64_t *__restrict__ X = blockIdx.y ? X1 : X0;
+    const uint64_t *__restrict__ in = blockIdx.y ? in1 : in0;
+    const uint64_t len = blockIdx.y ? len1 : len0;
     using Z = BcZetaR<NB>;
     constexpr int LGW = Z::LGW;
     __shared__ uint64_t s[4096 + 512];
@@ -846,12 +856,17 @@ __device__ __forceinline__ uint64_t bc_bits_u(const uint64_t *w, int nw, long of
 }
 
 // rpw: rows per workgroup iteration, a power of two up to BC_ROWS (fewer
-// spread a short operand's few rows over more CUs)
-__global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *__restrict__ X,
-                                                            const uint64_t *__restrict__ in, uint64_t len, int lgR,
-                                                            int EW, uint64_t *__restrict__ Y, BcSteps inner,
-                                                            int rpw)
+// spread a short operand's few rows over more CUs).  blockIdx.y picks the
+// operand: (X0, in0, len0, Y0) or (X1, in1, len1, Y1).
+__global__ __launch_bounds__(BC_ROW_THREADS) void k_bc_fwd_rows(const uint64_t *X0, const uint64_t *in0,
+                                                            uint64_t len0, int lgR, int EW, uint64_t *Y0,
+                                                            BcSteps inner, int rpw, const uint64_t *X1,
+                                                            const uint64_t *in1, uint64_t len1, uint64_t *Y1)
 {
+    const uint64_t *__restrict__ X = blockIdx.y ? X1 : X0;
+    const uint64_t *__restrict__ in = blockIdx.y ? in1 : in0;
+    const uint64_t len = blockIdx.y ? len1 : len0;
+    uint64_t *__restrict__ Y = blockIdx.y ? Y1 : Y0;
     __shared__ __align__(16) uint64_t rows[BC_ROWS * BC_TAU_WORDS];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int R = 1 << lgR, T = R < rpw ? R : rpw;
@@ -1051,13 +1066,17 @@ __device__ __forceinline__ uint64_t bc_win8(const uint64_t (*tab)[256], uint64_t
 // workgroups per CU), so that the columns of a short operand are converted
 // side by side on a CU rather than one after another.  2^LGW waves, columns
 // of up to 2^LGCAP elements (the host launches only lgR <= LGCAP), PRE column
-// words per thread in flight, at least MINW waves per SIMD.
+// words per thread in flight, at least MINW waves per SIMD.  The Encode
+// kernel takes the operand by blockIdx.y: (Y0, vals0) or (Y1, vals1).
 #define BC_ENC_SMALL_LG 10   // compact Encode kernel for lgR up to this
 template <int LGW, int LGCAP, int PRE, int MINW>
-__global__ __launch_bounds__(64 << LGW, MINW) void k_bc_outer_encode(const uint64_t *__restrict__ Y, int lgR, int l,
-                                                                   uint64_t *__restrict__ vals, BcSteps outer,
-                                                                   const DevTables *__restrict__ T)
+__global__ __launch_bounds__(64 << LGW, MINW) void k_bc_outer_encode(const uint64_t *Y0, int lgR, int l,
+                                                                   uint64_t *vals0, BcSteps outer,
+                                                                   const DevTables *__restrict__ T,
+                                                                   const uint64_t *Y1, uint64_t *vals1)
 {
+    const uint64_t *__restrict__ Y = blockIdx.y ? Y1 : Y0;
+    uint64_t *__restrict__ vals = blockIdx.y ? vals1 : vals0;
     constexpr int NT = 64 << LGW, NW = NT / 64;
     static_assert((1 << LGCAP) <= PRE * NT, "a thread's share of the column is in flight at once");
     __shared__ __align__(16) uint64_t col[1 << LGCAP];
