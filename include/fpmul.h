@@ -156,7 +156,7 @@ int polymul_batch(polymul_ctx *ctx, uint32_t count, const uint64_t *a_pool, cons
  * (the field size limit n < (m/2) 2^(m/2) gives 2^20 bits for m = 32):
  * batch items whose transform has at most 2^max_log2n bits (polymul_batch,
  * the batched launches of the server, and polymul_ex products of at most
- * 2^17 bits, which run as one-item batches) are computed over GF(2^32)
+ * 2^16 bits, which run as one-item batches) are computed over GF(2^32)
  * instead of GF(2^64).  The product is the same either way.  0 keeps every
  * item on GF(2^64).  Default: 20.  Affects launches enqueued afterwards (a
  * server created later on ctx takes the value at its creation).

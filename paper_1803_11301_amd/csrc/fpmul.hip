@@ -732,7 +732,7 @@ static int launch_bf3_upper(polymul_ctx *ctx, hipStream_t s, const char *name, u
 }
 
 #define BF3_MIN_L 20    // resident-table bottom pass from 2^20 transform values
-#define SINGLE_VIA_BATCH_LOG2N 17   // polymul_ex of products up to 2^17 bits runs as a one-item batch
+using fpmul_plan::SINGLE_VIA_BATCH_LOG2N;   // polymul_ex of products up to 2^16 bits runs as a one-item batch
 
 // the bottom pass of layers 0 .. nl - 1 (nl = 6 or 7)
 template <bool INV>

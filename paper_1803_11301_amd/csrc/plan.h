@@ -14,7 +14,7 @@ constexpr int TAU_WORDS = 1024;          // tau = 2^16 bits: the row length of t
 constexpr int M64_MAX_LOG2N = 37;        // m = 64 field bound: n <= (m/2) 2^(m/2) = 2^37
 constexpr int FUSED_MIN_LOG2N = 22;      // the fused BasisCvt/Encode/Decode path: 2^22 <= n ...
 constexpr int FUSED_MAX_LOG2N = 31;      // ... <= 2^31 bits
-constexpr int SINGLE_VIA_BATCH_LOG2N = 17;   // polymul_ex of products up to 2^17 bits: a one-item batch
+constexpr int SINGLE_VIA_BATCH_LOG2N = 16;   // polymul_ex of products up to 2^16 bits: a one-item batch
 constexpr int NOALLOC_MAX_LOG2N = 25;        // polymul_ex_noalloc: products up to 2^25 bits
 
 constexpr int ilog2(uint64_t x)   // ceil(log2 x), 0 for x <= 1
@@ -33,16 +33,17 @@ constexpr uint64_t next_pow2(uint64_t x)
 }
 
 // log2 of the transform length of a product of lc bits: n = max(64,
-// 2^ceil(log2 lc)), except that transforms of 2^18 .. 2^21 bits are taken as
+// 2^ceil(log2 lc)), except that transforms of 2^17 .. 2^21 bits are taken as
 // 2^22 bits, which the fused path (from 2^22) computes faster (its chain of
-// launches spreads over the chip, about 0.14 ms for any of these products,
-// where a one-workgroup BasisCvt per operand took 0.20 ms at 2^19 bits and
-// 0.29 ms at 2^20); any n >= lc gives the same product (the transform is a
-// bijection on polynomials of fewer than n bits)
+// launches spreads over the chip, about 0.13 ms for any of these products,
+// where a one-workgroup batch item took 0.145 ms at 2^17 bits and a
+// one-workgroup BasisCvt per operand 0.20 ms at 2^19 and 0.29 ms at 2^20);
+// any n >= lc gives the same product (the transform is a bijection on
+// polynomials of fewer than n bits)
 constexpr int product_log2n(uint64_t lc)
 {
     const int k = std::max(6, ilog2(lc));
-    return (k >= 18 && k <= 21) ? 22 : k;
+    return (k >= 17 && k <= 21) ? 22 : k;
 }
 
 // log2 of the transform length of a GF(2^128) product (m = 128: n >= 128)

@@ -187,7 +187,7 @@ class Context:
         return out_pool
 
     def set_small_field(self, max_log2n: int):
-        """Batch items (and polymul_ex products up to 2^17 bits) with transforms of
+        """Batch items (and polymul_ex products up to 2^16 bits) with transforms of
         at most 2^max_log2n bits run over GF(2^32); 0 keeps GF(2^64)."""
         _check(lib().polymul_set_small_field(self.handle, max_log2n))
 

@@ -44,11 +44,11 @@ def host(t):
     return t.cpu().numpy().view(np.uint64)
 
 
-# the routes of polymul_ex below 2^32 bits: the one-item batch (<= 2^17-bit
+# the routes of polymul_ex below 2^32 bits: the one-item batch (<= 2^16-bit
 # transform), the fused path with a 2^22-bit transform for a shorter product
-# (2^18 .. 2^21 bits), the fused path at its own size (2^22 .. 2^31), and the
+# (2^17 .. 2^21 bits), the fused path at its own size (2^22 .. 2^31), and the
 # fused path with a 3-bit operand (a single row)
-CASES = [("2^16 x 2^16", 1 << 16, 1 << 16), ("100000 x 150001", 100000, 150001),
+CASES = [("2^15 x 2^15", 1 << 15, 1 << 15), ("2^16 x 2^16", 1 << 16, 1 << 16), ("100000 x 150001", 100000, 150001),
          ("2^24 x 2^24", 1 << 24, 1 << 24), ("3 x 2^20+5", 3, (1 << 20) + 5)]
 
 

@@ -390,12 +390,14 @@ def test_pointwise_rejects_bad_arguments(ctx):
         ctx.pointwise(t[:32], t[16:48], 11, fc=t[8:40])   # overlapping output that is neither input
 
 
-@pytest.mark.parametrize("la,lb", [(1 << 17, 1 << 17), ((1 << 18) + 3, (1 << 18) - 7), (1 << 19, 1 << 19),
+@pytest.mark.parametrize("la,lb", [(1 << 16, 1 << 16), ((1 << 16) + 5, (1 << 16) - 9), (1 << 15, (1 << 16) + 1),
+                                   (1 << 17, 1 << 17), ((1 << 18) + 3, (1 << 18) - 7), (1 << 19, 1 << 19),
                                    ((1 << 20) - 10, 5), ((1 << 19) - 1, (1 << 19) + 5), (1 << 20, 1 << 20),
                                    (1000, (1 << 20) - 1), ((1 << 20) + 1, 1 << 10)])
 def test_mid_size_products_exact(ctx, la, lb):
-    """Products of 2^17 .. 2^21 bits, computed with 2^22-bit transforms on the
-    fused path (short operands: few rows, short columns)."""
+    """Products of more than 2^16 and at most 2^21 bits, computed with 2^22-bit
+    transforms on the fused path (short operands: few rows, short columns;
+    operands of different row counts one after the other)."""
     say("mid size", la, lb)
     rng = random.Random(la * 3 + lb)
     a, b = rand_words(rng, la), rand_words(rng, lb)

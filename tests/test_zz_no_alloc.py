@@ -48,10 +48,12 @@ def poisoned(nw):
 
 def test_noalloc_equals_polymul_ex_on_two_calls(ctx):
     # the largest product it takes (2^24 x 2^24 bits, top bits set: the fused
-    # path), then a smaller ragged one (the one-item batch path); the second
-    # call runs on the scratch the first left behind
+    # path), then smaller ragged ones (the fused path with a 2^22-bit
+    # transform, then the one-item batch path); each call runs on the scratch
+    # the one before left behind
     cases = [("2^24 x 2^24 (top bit set)", synth.SEED_MID, 1 << 24, 1 << 24, True),
-             ("12345 x 70001", 0x5EED0A11, 12345, 70001, False)]
+             ("12345 x 70001", 0x5EED0A11, 12345, 70001, False),
+             ("9999 x 30001", 0x5EED0A14, 9999, 30001, False)]
     for name, seed, la, lb, top in cases:
         say("polymul_ex_noalloc", name, f"seed {seed:#x}")
         a = synth.dense_poly(seed, la, top_bit=top)
@@ -70,7 +72,8 @@ def test_noalloc_equals_polymul_ex_on_two_calls(ctx):
 
 
 def test_noalloc_between_mid_sizes(ctx):
-    # a 2^20-bit transform (the one-workgroup BasisCvt path) after the larger calls
+    # a 2^19-bit product (the fused path with a 2^22-bit transform, operands
+    # of different row counts) after the other calls
     la, lb = 300000, 200001
     say("polymul_ex_noalloc", f"{la} x {lb}")
     a = synth.dense_poly(0x5EED0A12, la)
