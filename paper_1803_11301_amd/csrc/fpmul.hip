@@ -804,7 +804,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         // register-resident bottom passes; the pointwise step in between
         const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - B2_TILE_LG), (uint64_t)ctx->num_cu * 2);
         if (mode == BF_PRODUCT) {
-            KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD2>, bt, B2_THREADS, A, B, l, ctx->tables);
+            KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD>, dim3(bt, 2), B2_THREADS, A, B, l, ctx->tables);
             KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
                                                                                    (uint64_t)ctx->num_cu),
                     1024, A, B, n, ctx->tables);

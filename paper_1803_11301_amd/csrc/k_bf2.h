@@ -20,7 +20,6 @@
 
 #define B2_TILE_LG 11
 #define B2_THREADS 256
-#define B2_STAGE_WORDS (2048 + 256)   // one padded operand tile in the exchange area
 
 // byte tables of beta * y on the bit groups of y: t0 (bits 0-2, 8 entries in
 // two words), t1 (bits 3-5), t2 (bits 6-7, 4 entries); 32 bytes per entry
@@ -61,8 +60,8 @@ __device__ __forceinline__ uint64_t b2_mul_acc(const uint64_t *__restrict__ tab,
 
 // One layer on the registers: the layer bit is register bit M; the block
 // index of a pair is b_t | (register bits above M) * bw, beta = iota(2 (b mod 128)).
-template <int M, bool INV, bool TWO>
-__device__ __forceinline__ void b2_layer(uint64_t (&xa)[8], uint64_t (&xb)[8], const uint64_t *__restrict__ tab,
+template <int M, bool INV>
+__device__ __forceinline__ void b2_layer(uint64_t (&xa)[8], const uint64_t *__restrict__ tab,
                                          const PermTab *__restrict__ s_pt, const DevTables *__restrict__ T,
                                          uint32_t bl_t, uint32_t bw1, uint32_t bw2)
 {
@@ -105,11 +104,6 @@ __device__ __forceinline__ void b2_layer(uint64_t (&xa)[8], uint64_t (&xb)[8], c
                 const uint64_t h0 = b2_mul_acc(tab, t01, t2, xa[r1], xa[r0]);
                 xa[r1] ^= h0;
                 xa[r0] = h0;
-                if (TWO) {
-                    const uint64_t g0 = b2_mul_acc(tab, t01, t2, xb[r1], xb[r0]);
-                    xb[r1] ^= g0;
-                    xb[r0] = g0;
-                }
             } else {
                 const uint64_t p1 = xa[r0] ^ xa[r1];
                 xa[r0] = b2_mul_acc(tab, t01, t2, p1, xa[r0]);
@@ -353,8 +347,8 @@ __device__ __forceinline__ B16Tabs b16_xor(const B16Tabs &a, const B16Tabs &b)
 // comes through the iota tables of the low two Cantor bytes (s_io16) and its
 // byte tables from LDS; the blocks that differ in register bits above M add
 // iota(2 bw), the same for the whole workgroup, whose tables are read from T.
-template <int M, bool INV, bool TWO>
-__device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], uint64_t (&xb)[8], const uint64_t *__restrict__ tab,
+template <int M, bool INV>
+__device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], const uint64_t *__restrict__ tab,
                                            const PermTab *__restrict__ s_pt8, const uint16_t (*s_io16)[256],
                                            const DevTables *__restrict__ T, uint32_t b_t, uint32_t bw1,
                                            uint32_t bw2)
@@ -384,11 +378,6 @@ __device__ __forceinline__ void b2_layer16(uint64_t (&xa)[8], uint64_t (&xb)[8],
                 const uint64_t h0 = b2_mul_acc16(tab, t.p0, t.p02, t.p1, t.p12, t.pc, t.pc2, xa[r1], xa[r0]);
                 xa[r1] ^= h0;
                 xa[r0] = h0;
-                if (TWO) {
-                    const uint64_t g0 = b2_mul_acc16(tab, t.p0, t.p02, t.p1, t.p12, t.pc, t.pc2, xb[r1], xb[r0]);
-                    xb[r1] ^= g0;
-                    xb[r0] = g0;
-                }
             } else {
                 const uint64_t p = xa[r0] ^ xa[r1];
                 xa[r0] = b2_mul_acc16(tab, t.p0, t.p02, t.p1, t.p12, t.pc, t.pc2, p, xa[r0]);
@@ -416,8 +405,8 @@ __device__ __forceinline__ void b2_bottom_images(const B2Group &g, uint64_t (*s_
     }
 }
 
-template <bool INV, bool TWO>
-__device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&xa)[8], uint64_t (&xb)[8],
+template <bool INV>
+__device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&xa)[8],
                                                   uint64_t (*s_tab)[2048], const PermTab *s_ptb,
                                                   const PermTab *s_pt8, const uint16_t (*s_io16)[256],
                                                   uint64_t gb_t, const DevTables *__restrict__ T)
@@ -429,11 +418,11 @@ __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&x
         if (b2_wide(i)) {
             const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
             const uint32_t bw1 = (1u << g.s[1]) >> (i + 1), bw2 = (1u << g.s[2]) >> (i + 1);
-            b2_layer16<M, INV, TWO>(xa, xb, s_tab[M], s_pt8, s_io16, T, b_t, bw1 & 0x7FFFu, bw2 & 0x7FFFu);
+            b2_layer16<M, INV>(xa, s_tab[M], s_pt8, s_io16, T, b_t, bw1 & 0x7FFFu, bw2 & 0x7FFFu);
         } else {
             const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
             const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 127u, bw2 = ((1u << g.s[2]) >> (i + 1)) & 127u;
-            b2_layer<M, INV, TWO>(xa, xb, s_tab[M], s_ptb, T, bl_t, bw1, bw2);
+            b2_layer<M, INV>(xa, s_tab[M], s_ptb, T, bl_t, bw1, bw2);
         }
     };
     if (!INV) {
@@ -447,13 +436,16 @@ __device__ __forceinline__ void b2_bottom_compute(const B2Group &g, uint64_t (&x
     }
 }
 
-// MODE: BF_FWD (A), BF_FWD2 (A and B), BF_INV (A); l >= 11; grid <= 2^(l-11)
+// MODE: BF_FWD or BF_INV; l >= 11; grid <= 2^(l-11).  A grid of two rows
+// takes A (y = 0) and B (y = 1), each tile of each transform on a workgroup
+// of its own (a workgroup taking the same tile of both shares its K tables
+// between them but leaves half the workgroups: 7 us slower per product).
 template <int MODE>
-__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restrict__ A,
-                                                                           uint64_t *__restrict__ B, int l,
+__global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *A0, uint64_t *B0, int l,
                                                                            const DevTables *__restrict__ T)
 {
-    constexpr bool INV = MODE == BF_INV, TWO = MODE == BF_FWD2;
+    constexpr bool INV = MODE == BF_INV;
+    uint64_t *__restrict__ A = blockIdx.y ? B0 : A0;
     constexpr int NC = B2Bottom::NC;
     __shared__ __align__(16) uint64_t s_tab[3][2048];   // K tables; the exchange area aliases them
     __shared__ __align__(16) PermTab s_ptb[128];        // tables of iota(2 bl), bl < 128
@@ -461,7 +453,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
     __shared__ uint16_t s_io16[2][256];                 // iota of the low two Cantor bytes (V_16)
     __shared__ uint64_t s_pb[24][64];                   // basis rows of the bits of bh
     __shared__ uint64_t s_img[B2_TILE_LG][64];          // basis images of each layer's K, cached
-    uint64_t *stA = &s_tab[0][0], *stB = stA + B2_STAGE_WORDS;
+    uint64_t *stA = &s_tab[0][0];
     const int tid = threadIdx.x, nth = blockDim.x;
 
     for (int q = tid; q < 128 * 8; q += nth)
@@ -479,7 +471,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
     uint32_t key[B2_TILE_LG];
 #pragma unroll
     for (int i = 0; i < B2_TILE_LG; ++i) key[i] = 0xFFFFFFFFu;
-    uint64_t xa[8], xb[8];
+    uint64_t xa[8];
     for (uint64_t tile = t_beg; tile < t_end; ++tile) {
         const uint64_t gbase = tile << B2_TILE_LG;
 #pragma unroll
@@ -493,7 +485,6 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
                 for (int r = 0; r < 8; ++r) {
                     const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
                     xa[r] = A[gbase | (uint64_t)e];
-                    if (TWO) xb[r] = B[gbase | (uint64_t)e];
                 }
                 __syncthreads();   // the previous tile is done with the tables
                 b2_bottom_images(g, s_img, key, s_pb, gbase, l, T, tid);
@@ -506,7 +497,6 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
                 for (int r = 0; r < 8; ++r) {
                     const int e = ep | ((r & 1) << gp.s[0]) | (((r >> 1) & 1) << gp.s[1]) | ((r >> 2) << gp.s[2]);
                     stA[b2_pad(e)] = xa[r];
-                    if (TWO) stB[b2_pad(e)] = xb[r];
                 }
                 b2_bottom_images(g, s_img, key, s_pb, gbase, l, T, tid);
                 __syncthreads();
@@ -514,7 +504,6 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
                 for (int r = 0; r < 8; ++r) {
                     const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
                     xa[r] = stA[b2_pad(e)];
-                    if (TWO) xb[r] = stB[b2_pad(e)];
                 }
                 __syncthreads();   // exchange area free for the tables
             }
@@ -523,13 +512,12 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *__restri
             for (int m = 0; m < 3; ++m) slot[m] = g.layer[m] ? g.s[m] : 0;
             b2_fill(g, s_tab, s_img, slot, tid, nth);
             __syncthreads();
-            b2_bottom_compute<INV, TWO>(g, xa, xb, s_tab, s_ptb, s_pt8, s_io16, gb_t, T);
+            b2_bottom_compute<INV>(g, xa, s_tab, s_ptb, s_pt8, s_io16, gb_t, T);
             if (cc == NC - 1) {
 #pragma unroll
                 for (int r = 0; r < 8; ++r) {
                     const int e = e_t | ((r & 1) << g.s[0]) | (((r >> 1) & 1) << g.s[1]) | ((r >> 2) << g.s[2]);
                     A[gbase | (uint64_t)e] = xa[r];
-                    if (TWO) B[gbase | (uint64_t)e] = xb[r];
                 }
             }
         }

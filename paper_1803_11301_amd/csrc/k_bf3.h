@@ -45,7 +45,7 @@ __device__ __forceinline__ void bf3_upper_compute(const B2Group &g, uint64_t (&x
         const int row = g.s[M] - LGW, i = i_lo + row;
         const uint32_t bl_t = (uint32_t)(gb_t >> (i + 1)) & 127u;
         const uint32_t bw1 = (uint32_t)(gw[1] >> (i + 1)) & 127u, bw2 = (uint32_t)(gw[2] >> (i + 1)) & 127u;
-        b2_layer<M, INV, false>(x, x, s_tab[row], s_pt, T, bl_t, bw1, bw2);
+        b2_layer<M, INV>(x, s_tab[row], s_pt, T, bl_t, bw1, bw2);
     };
     if (!INV) {
         run(std::integral_constant<int, 2>());
@@ -223,7 +223,7 @@ __device__ __forceinline__ void bf3_bottom_compute(const B2Group &g, uint64_t (&
         const int i = g.s[M];
         const uint32_t b_t = (uint32_t)(gb_t >> (i + 1)) & 0x7FFFu;
         const uint32_t bw1 = ((1u << g.s[1]) >> (i + 1)) & 0x7FFFu, bw2 = ((1u << g.s[2]) >> (i + 1)) & 0x7FFFu;
-        b2_layer16<M, INV, false>(x, x, s_tab[i], s_pt8, s_io16, T, b_t, bw1, bw2);
+        b2_layer16<M, INV>(x, s_tab[i], s_pt8, s_io16, T, b_t, bw1, bw2);
     };
     if (!INV) {
         run(std::integral_constant<int, 2>());

@@ -23,7 +23,7 @@
 #define BF_BOTTOM_R 11        // log2 of the bottom tile
 #define BF_UPPER_MAXK 7       // layers per upper pass
 
-enum { BF_FWD = 0, BF_INV = 1, BF_PRODUCT = 2, BF_FWD2 = 3 };
+enum { BF_FWD = 0, BF_INV = 1, BF_PRODUCT = 2 };
 
 // LDS layout shared by both kernels (bytes)
 #define BF_OFF_MUL8 0
