@@ -777,7 +777,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
                 return rc;
         }
         if (mode == BF_PRODUCT)
-            KLAUNCH(ctx, s, "pointwise", k_pointwise,
+            KLAUNCH(ctx, s, "pointwise", k_pointwise<false>,
                     (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, A, B, n,
                     ctx->tables);
         if (mode != BF_FWD) {
@@ -805,7 +805,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - B2_TILE_LG), (uint64_t)ctx->num_cu * 2);
         if (mode == BF_PRODUCT) {
             KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD>, dim3(bt, 2), B2_THREADS, A, B, l, ctx->tables);
-            KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
+            KLAUNCH(ctx, s, "pointwise", k_pointwise<false>, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
                                                                                    (uint64_t)ctx->num_cu),
                     1024, A, B, n, ctx->tables);
             KLAUNCH(ctx, s, "ibutterfly_bottom", k_bf2_bottom<BF_INV>, bt, B2_THREADS, A, B, l, ctx->tables);
@@ -1198,16 +1198,20 @@ static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, con
     if ((rc = set_lds_limits())) return rc;
     uint64_t *W0 = ctx->ws[0], *W1 = ctx->ws[1], *W2 = ctx->ws[2], *W3 = ctx->ws[3];
     uint64_t *pa, *pb;
+    // a square (the same operand twice): one forward transform, squared
+    // pointwise (Alg. 5 with both transforms equal)
+    const bool square = a == b && len_a == len_b;
     // forward transforms of A into W0, of B into W1.  Operands of one row
     // count share each launch, their skewed rows in W0 and W1 (free until
     // Encode writes the values there) and their columns in W2 and W3; else
     // one after the other with W2, W3 as scratch.
-    const bool paired = fast_path(log2n) && std::max(len_a, len_b) <= (1ull << 30) && bc_lgR(len_a) == bc_lgR(len_b);
+    const bool paired = !square && fast_path(log2n) && std::max(len_a, len_b) <= (1ull << 30) &&
+                        bc_lgR(len_a) == bc_lgR(len_b);
     if (paired) {
         const EncOp A{a, len_a, W0, W0, W2}, B{b, len_b, W1, W1, W3};
         if ((rc = run_encode_fast(ctx, A, &B, log2n, s))) return rc;
     }
-    for (int side = 0; side < 2 && !paired; ++side) {
+    for (int side = 0; side < (square ? 1 : 2) && !paired; ++side) {
         const uint64_t *src = side ? b : a;
         const uint64_t len = side ? len_b : len_a;
         uint64_t *dst = side ? W1 : W0;
@@ -1222,7 +1226,16 @@ static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, con
     }
     pa = W0;
     pb = W1;
-    if ((rc = run_butterflies(ctx, BF_PRODUCT, pa, pb, log2n - 6, s))) return rc;
+    if (square) {
+        const uint64_t nw = 1ull << (log2n - 6);
+        if ((rc = run_butterflies(ctx, BF_FWD, pa, nullptr, log2n - 6, s))) return rc;
+        KLAUNCH(ctx, s, "pointwise", k_pointwise<true>,
+                (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, pa, nullptr, nw,
+                ctx->tables);
+        if ((rc = run_butterflies(ctx, BF_INV, pa, nullptr, log2n - 6, s))) return rc;
+    } else if ((rc = run_butterflies(ctx, BF_PRODUCT, pa, pb, log2n - 6, s))) {
+        return rc;
+    }
     if (fast_path(log2n)) return run_decode_fast(ctx, pa, log2n, out, lc, W2, W3, s);
     uint64_t *cur = pa, *spare = pb;
     if ((rc = run_decode_out(ctx, log2n, cur, spare, s))) return rc;
@@ -1284,8 +1297,8 @@ static int resident_body(polymul_ctx *ctx, const uint64_t *fa, int log2n, const 
         if ((rc = run_encode_in(ctx, b, len_b, log2n, cur, spare, s))) return rc;
     }
     if ((rc = run_butterflies(ctx, BF_FWD, cur, nullptr, log2n - 6, s))) return rc;
-    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu),
-            1024, cur, fa, nw, ctx->tables);
+    KLAUNCH(ctx, s, "pointwise", k_pointwise<false>,
+            (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, cur, fa, nw, ctx->tables);
     if ((rc = run_butterflies(ctx, BF_INV, cur, nullptr, log2n - 6, s))) return rc;
     if (fast_path(log2n)) return run_decode_fast(ctx, cur, log2n, out, lc, ctx->ws[2], ctx->ws[3], s);
     if ((rc = run_decode_out(ctx, log2n, cur, spare, s))) return rc;
@@ -2250,8 +2263,11 @@ int polymul_pointwise(polymul_ctx *ctx, const uint64_t *fa, const uint64_t *fb, 
     } else if (fc != fa) {
         HIP_TRY(hipMemcpyAsync(fc, fa, bytes, hipMemcpyDeviceToDevice, s));
     }
-    KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu),
-            1024, fc, other, n, ctx->tables);
+    const unsigned grid = (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu);
+    if (fa == fb)   // a square: fc holds fa's values now
+        KLAUNCH(ctx, s, "pointwise", k_pointwise<true>, grid, 1024, fc, nullptr, n, ctx->tables);
+    else
+        KLAUNCH(ctx, s, "pointwise", k_pointwise<false>, grid, 1024, fc, other, n, ctx->tables);
     return 0;
 }
 

@@ -526,7 +526,9 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *A0, uint
 
 // ------------------------------------------------------------ pointwise ---
 // A[j] = A[j] * B[j] (Alg. 5, the pointwise step), tower Karatsuba with the
-// GF(2^8) pair table in LDS (MulPairView layout); one workgroup per CU
+// GF(2^8) pair table in LDS (MulPairView layout); one workgroup per CU.
+// SQ: A[j] = A[j]^2 (B is not read; one transform squared)
+template <bool SQ = false>
 __global__ __launch_bounds__(1024) void k_pointwise(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
                                                     uint64_t n, const DevTables *__restrict__ T)
 {
@@ -549,10 +551,13 @@ __global__ __launch_bounds__(1024) void k_pointwise(uint64_t *__restrict__ A, co
 #pragma unroll
         for (int k = 0; k < PW_ILP; ++k) {
             a[k] = A[j + k * G];
-            b[k] = B[j + k * G];
+            b[k] = SQ ? a[k] : B[j + k * G];
         }
 #pragma unroll
         for (int k = 0; k < PW_ILP; ++k) A[j + k * G] = mv.m64(a[k], b[k]);
     }
-    for (; j < n; j += G) A[j] = mv.m64(A[j], B[j]);
+    for (; j < n; j += G) {
+        const uint64_t x = A[j];
+        A[j] = mv.m64(x, SQ ? x : B[j]);
+    }
 }

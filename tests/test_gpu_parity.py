@@ -381,6 +381,53 @@ def test_squaring_through_one_transform_is_bit_spread(ctx, log2n):
     assert np.array_equal(got, want)
 
 
+def bit_spread(words, la):
+    """Words of A(x)^2 for A of la bits: bit i of A at bit 2i (Frobenius over
+    GF(2)), trimmed to the 2 la - 1 bits of the square."""
+    w = np.asarray(words, dtype=np.uint64)[: O.nwords(la)]
+
+    def spread32(x):
+        x = x & np.uint64(0xFFFFFFFF)
+        for sh, m in ((16, 0x0000FFFF0000FFFF), (8, 0x00FF00FF00FF00FF), (4, 0x0F0F0F0F0F0F0F0F),
+                      (2, 0x3333333333333333), (1, 0x5555555555555555)):
+            x = (x | (x << np.uint64(sh))) & np.uint64(m)
+        return x
+
+    out = np.empty(2 * w.size, dtype=np.uint64)
+    out[0::2] = spread32(w)
+    out[1::2] = spread32(w >> np.uint64(32))
+    return out[: O.nwords(2 * la - 1)]
+
+
+@pytest.mark.parametrize("la", [70001, (1 << 20) + 7, (1 << 24) - 3, (1 << 25) + 1, (1 << 29) + 3, (1 << 31) - 5])
+def test_square_through_one_forward_transform(ctx, la):
+    """polymul_ex with the same operand twice takes one forward transform and
+    squares it pointwise: every route (fused with a 2^22-bit transform, the
+    short-transform bottom pass, the resident-table passes, the per-step
+    path above 2^31 bits) against the bit spread of A, and the smallest
+    against the oracle as well."""
+    say("square", la)
+    a = synth.dense_poly(0x5EED5000 + la % 1000, la)
+    ta = dev(a)
+    got = host(ctx.polymul(ta, la, ta, la))[: O.nwords(2 * la - 1)]
+    assert np.array_equal(got, bit_spread(a, la))
+    if la < 1 << 17:
+        assert np.array_equal(got, O.polymul(a, la, a, la, threads=8))
+    del ta
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("la,lb", [(1000, 700), ((1 << 20) + 3, 1 << 20)])
+def test_one_buffer_two_lengths_is_not_a_square(ctx, la, lb):
+    # the same pointer with two lengths multiplies A by its own low lb bits
+    say("one buffer", la, lb)
+    a = rand_words(random.Random(la + lb), la)
+    ta = dev(a)
+    got = host(ctx.polymul(ta, la, ta, lb))[: O.nwords(la + lb - 1)]
+    assert np.array_equal(got, O.polymul(a, la, O.int_to_words(O.words_to_int(a, la) & ((1 << lb) - 1), lb), lb,
+                                         threads=8))
+
+
 def test_pointwise_rejects_bad_arguments(ctx):
     from paper_1803_11301_amd import fpmul
     t = torch.zeros(64, dtype=torch.int64, device="cuda")
