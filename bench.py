@@ -411,6 +411,29 @@ def _m128_at_2e30():
 
 
 SAT_BURSTS = 3   # bursts behind each saturated rate (their median)
+SERVE_TUNE_REQUESTS = 2000
+SERVE_TUNE_P99_MS = 2.5
+
+
+def bench_serve_tune(ctx):
+    """The server settings for the serving measurement, chosen by tune_server
+    on a mix of SERVE_TUNE_REQUESTS requests of the serving distribution
+    (operands log-uniform in [2^12, 2^24] bits, its own seed): the highest
+    saturated rate whose p99 at 0.8 of it stays within SERVE_TUNE_P99_MS."""
+    from paper_1803_11301_amd import synth
+    from paper_1803_11301_amd.serve_tune import tune_server
+    _, la, lb, _, _ = synth.serve_plan(SERVE_TUNE_REQUESTS, 1.0, seed=synth.SEED_SERVE + 7)
+    t0 = time.perf_counter()
+    res = tune_server(ctx, la, lb, rho=0.8, p99_limit_ms=SERVE_TUNE_P99_MS)
+    res["seconds"] = round(time.perf_counter() - t0, 2)
+    for r in res["table"]:
+        log(f"[bench] serve tune: slots {r['slots']} limit 2^{r['batch_limit_bits'].bit_length() - 1} "
+            f"max batch {r['max_batch']}: saturated {r['saturated_per_s']:.0f}/s, p50 {r['p50_ms']} ms, "
+            f"p99 {r['p99_ms']} ms")
+    c = res["choice"]
+    log(f"[bench] serve tune: chose slots {c['slots']}, batch limit {c['batch_limit_bits']} bits, "
+        f"max batch {c['max_batch']} ({res['seconds']} s)")
+    return res
 
 
 def bench_serve(ctx, count: int, warmup: int, rhos, sat_count: int, slots: int = 8,
@@ -705,6 +728,8 @@ def main():
     ap.add_argument("--serve-rhos", default="0.5,0.8,0.95", help="offered loads as fractions of saturation")
     ap.add_argument("--serve-saturation", type=int, default=4000, help="requests submitted at once for X")
     ap.add_argument("--no-resident", action="store_true", help="skip the transform-reuse serving measurement")
+    ap.add_argument("--no-serve-tune", action="store_true",
+                    help="serve with the server's default settings (no tune_server first)")
     ap.add_argument("--no-tune", action="store_true", help="time the default schedule (no polymul_tune first)")
     ap.add_argument("--tune-reps", type=int, default=3, help="timed products per schedule choice of the tuner")
     ap.add_argument("--tune-cache", default=None,
@@ -844,10 +869,16 @@ def main():
     if not args.no_batch and args.workload == "large":
         batch = bench_batch(ctx, args.batch_steps)
 
-    serve = None
+    serve = serve_tune = None
     if not args.no_serve and args.workload == "large":
         rhos = [float(x) for x in args.serve_rhos.split(",") if x]
-        serve = bench_serve(ctx, args.serve_requests, args.serve_warmup, rhos, args.serve_saturation)
+        slots, limit, max_batch = 8, 1 << 20, 512   # the server's defaults
+        if not args.no_serve_tune:
+            serve_tune = bench_serve_tune(ctx)
+            c = serve_tune["choice"]
+            slots, limit, max_batch = c["slots"], c["batch_limit_bits"], c["max_batch"]
+        serve = bench_serve(ctx, args.serve_requests, args.serve_warmup, rhos, args.serve_saturation, slots=slots,
+                            batch_limit_bits=limit, max_batch=max_batch)
 
     serve_resident = None
     if not args.no_serve and not args.no_resident and args.workload == "large":
@@ -895,6 +926,7 @@ def main():
         "latency": latency,
         "batch": batch,
         "serve": serve,
+        "serve_tune": serve_tune,
         "serve_resident": serve_resident,
         "tune": tune,
         "m128": m128,

@@ -258,3 +258,34 @@ def test_resident_operand_in_the_mix(ctx):
     finally:
         srv.close()
         res.close()
+
+
+def test_server_tuner_on_a_small_mix(ctx):
+    # two settings timed on a mix of 300 requests; the choice is one of them,
+    # and a server with it computes the same products as polymul_ex
+    from paper_1803_11301_amd import fpmul
+    from paper_1803_11301_amd.serve_tune import tune_server
+    rng = np.random.default_rng(0x5EED0571)
+    la = np.floor(np.exp2(10 + 8 * rng.random(300))).astype(np.int64)
+    lb = np.floor(np.exp2(10 + 8 * rng.random(300))).astype(np.int64)
+    cands = [(4, 1 << 16, 64), (8, 1 << 20, 512)]
+    say("server tuner", len(la), "requests,", len(cands), "settings")
+    res = tune_server(ctx, la, lb, candidates=cands, bursts=1, p99_limit_ms=1e9)
+    assert [(r["slots"], r["batch_limit_bits"], r["max_batch"]) for r in res["table"]] == cands
+    assert all(r["saturated_per_s"] > 0 and 0 < r["p50_ms"] <= r["p99_ms"] for r in res["table"])
+    c = res["choice"]
+    assert c["saturated_per_s"] == max(r["saturated_per_s"] for r in res["table"])
+    srv = fpmul.Server(ctx, hbm_budget=1 << 30, slots=c["slots"], batch_limit_bits=c["batch_limit_bits"],
+                       max_batch=c["max_batch"])
+    ops = []
+    for k in range(6):
+        x, y = int(la[k]), int(lb[k])
+        a, b = synth.dense_poly(0x5EED0572 + 2 * k, x), synth.dense_poly(0x5EED0573 + 2 * k, y)
+        ops.append((x, y, dev64(a), dev64(b), torch.zeros(O.nwords(x + y - 1), dtype=torch.int64, device="cuda")))
+    torch.cuda.synchronize()
+    for tk in [srv.submit(ta, x, tb, y, out) for x, y, ta, tb, out in ops]:
+        srv.wait(tk)
+    srv.close()
+    for x, y, ta, tb, out in ops:
+        n = O.nwords(x + y - 1)
+        assert np.array_equal(host(out, n), host(ctx.polymul(ta, x, tb, y), n)), (x, y)
