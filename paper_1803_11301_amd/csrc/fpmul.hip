@@ -911,7 +911,9 @@ static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t
                     uint64_t len1 = 0)
 {
     const unsigned ny = X1 ? 2 : 1;
-    const int nb1 = std::min(lgR, 8), nb2 = lgR - nb1;
+    // two passes of 6 .. 8 row bits where they cover lgR (12 .. 16), both on
+    // the register-tile kernel; else up to 8 bits and the rest
+    const int nb1 = lgR >= 12 ? std::min(8, lgR - 6) : std::min(lgR, 8), nb2 = lgR - nb1;
     for (int pass = 0; pass < 2; ++pass) {
         const int b0 = pass ? nb1 : 0, nb = pass ? nb2 : nb1;
         if (nb <= 0) continue;

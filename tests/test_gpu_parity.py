@@ -245,6 +245,25 @@ def test_large_products_exact(ctx, L):
     assert np.array_equal(got, O.polymul(a, L, b, L, threads=16))
 
 
+@pytest.mark.parametrize("la,lb", [(1 << 28, 1 << 28), ((1 << 27) + 9, (1 << 27) - 9), ((1 << 29) - 7, 5)])
+def test_sampled_words_with_twelve_and_thirteen_row_bits(ctx, la, lb):
+    """Operands and products of 2^12 and 2^13 rows of 2^16 bits, whose
+    superset sums run as two register-tile passes (6 + 6 and 7 + 6 row bits):
+    sampled output words from the definition and the evaluation identity at
+    a random point."""
+    say("sampled", la, "x", lb)
+    rng = random.Random(la ^ lb)
+    a = synth.dense_poly(0x5EED2800 + la % 977, la)
+    b = synth.dense_poly(0x5EED2900 + lb % 977, lb)
+    got = gpu_product(ctx, a, la, b, lb)
+    n = O.nwords(la + lb - 1)
+    idx = np.array(sorted({0, 1, n // 3, n // 2, n - 2, n - 1} | {rng.randrange(n) for _ in range(8)}),
+                   dtype=np.uint64)
+    assert np.array_equal(got[idx.astype(np.int64)], O.product_words(a, la, b, lb, idx))
+    z = rng.getrandbits(64) | 1
+    assert O.gf64_mul(O.eval_at(a, la, z), O.eval_at(b, lb, z)) == O.eval_at(got, la + lb - 1, z)
+
+
 def _golden_digest(name):
     import json
     import os
