@@ -192,7 +192,7 @@ def host_cpu() -> dict:
     return {"model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
 
-# One full-size oracle run on the GPU machine's host: `python bench.py --cpu-full`
+# One full-size oracle run on the host of an MI355X machine: `python bench.py --cpu-full`
 # (profiles/cpu_oracle_2e30x2e30.md holds its output); the default bench run
 # times the bounded sample below and reports this measurement beside it.
 CPU_FULL_MEASURED = {"ms": 104283.2, "threads": 16, "cpu_model": "AMD EPYC", "nproc": 16,
