@@ -287,7 +287,9 @@ int polymul_resident_mul(polymul_ctx *ctx, const polymul_resident *res, const ui
  *   together as one batched launch (as polymul_batch), a larger product runs
  *   alone (as polymul_ex); polymul_server_set_policy changes both limits.  A later request may pass an earlier one that
  *   does not fit yet; one passed 64 times blocks later ones until it fits.
- *   Launches on different slots overlap on the device.
+ *   Each slot has a launcher thread that enqueues the slot's kernels, so
+ *   launches on different slots are issued side by side and overlap on the
+ *   device.
  * polymul_submit -- queues C = A * B (same arguments and rules as polymul,
  *   with products of at most POLYMUL_SERVER_MAX_PRODUCT_BITS bits;
  *   device pointers the caller keeps alive and unmodified until the ticket is

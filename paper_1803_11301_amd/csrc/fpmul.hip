@@ -891,6 +891,19 @@ static BcSteps make_steps(uint64_t N)
     return st;
 }
 
+// the step lists of BasisCvt(2^lg) for the fused path's inner (2^16) and
+// outer (up to 2^15 rows) conversions, built once: a list takes a few
+// microseconds of host time, and a product needs four
+static const BcSteps &steps_of(int lg)
+{
+    static const std::vector<BcSteps> all = [] {
+        std::vector<BcSteps> v(17);
+        for (int k = 0; k <= 16; ++k) v[k] = make_steps(1ull << k);
+        return v;
+    }();
+    return all[lg];
+}
+
 using fpmul_plan::bc_ew;
 using fpmul_plan::ws_words_for;
 static_assert(fpmul_plan::TAU_WORDS == BC_TAU_WORDS, "row length of the fused BasisCvt");
@@ -999,7 +1012,7 @@ static int run_encode_fast(polymul_ctx *ctx, const EncOp &A, const EncOp *B, int
                           B ? B->a : nullptr, B ? B->len : 0);
         if (rc) return rc;
     }
-    const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
+    const BcSteps &inner = steps_of(16), &outer = steps_of(lgR);
     const int rpw = rows_per_wg(ctx, lgR);
     const unsigned grows = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((1ull << lgR) / rpw,
                                                                               (uint64_t)ctx->num_cu * sc.rows_mult));
@@ -1030,7 +1043,7 @@ static int run_decode_fast(polymul_ctx *ctx, const uint64_t *vals, int log2n, ui
 {
     const int l = log2n - 6, lgR = log2n - 16, EW = bc_ew(lgR);
     const fpmul_plan::Schedule sc = sched_of(ctx, log2n);
-    const BcSteps inner = make_steps(1ull << 16), outer = make_steps(1ull << lgR);
+    const BcSteps &inner = steps_of(16), &outer = steps_of(lgR);
     if (lgR <= BC_DEC_SMALL_LG)
         KLAUNCH(ctx, s, "decode_outer", (k_bc_decode_outer<2, BC_DEC_SMALL_LG, 4, 4>),
                 (unsigned)std::min(2 * BC_TAU_WORDS, 4 * ctx->num_cu), 256, vals, lgR, l,

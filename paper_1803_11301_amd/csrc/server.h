@@ -1,12 +1,16 @@
 // server.h -- the product server: continuous batching of product requests
 // over several HIP streams, admitted by device-memory footprint.
 //
-// One scheduler thread per server owns every launch.  Requests are queued by
-// polymul_submit; whenever a launch slot (a stream with its own workspace
-// view) is free, the admission policy of server_policy.h picks the next
-// launch: waiting small products (by default at most 2^20 bits, up to 512 of
-// them) together as one batched launch of k_batch, or one larger product
-// through the single-product path.  Its workspace is carved out of the server's arena,
+// One scheduler thread per server admits requests and sees them complete;
+// each launch slot (a stream with its own workspace view) has a launcher
+// thread that enqueues the slot's kernels, outside the server lock, so that
+// the slots' launches (a dozen kernels for a product on the fused path) are
+// issued side by side rather than one after another on the scheduler.
+// Requests are queued by polymul_submit; whenever a slot is free, the
+// admission policy of server_policy.h picks the next launch: waiting small
+// products (by default at most 2^20 bits, up to 512 of them) together as one
+// batched launch of k_batch, or one larger product through the
+// single-product path.  Its workspace is carved out of the server's arena,
 // one device allocation made at creation, so memory use never exceeds the
 // budget and nothing is allocated while serving.  Launches on different
 // slots overlap on the device; a slot is freed, and its arena range
@@ -37,8 +41,11 @@ struct SrvSlot {
     hipEvent_t done = nullptr;
     polymul_ctx *view = nullptr;     // borrows the parent's tables and arena ranges
     BtDesc *host_desc = nullptr;     // pinned, max_batch entries
-    bool busy = false;
+    bool busy = false;               // a plan is admitted on the slot
+    bool go = false;                 // ... and waits for the launcher thread
+    bool launched = false;           // ... and its kernels and `done` are enqueued
     fpmul_srv::Plan plan;
+    std::thread launcher;
 };
 
 uint64_t srv_now_ns(std::chrono::steady_clock::time_point t0)
@@ -60,12 +67,13 @@ struct polymul_server {
     fpmul_srv::Footprint fp;
     std::vector<SrvSlot> slots;
     std::mutex m;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_launch;
     std::deque<fpmul_srv::Req> pending;
     std::unordered_map<uint64_t, SrvTicket> tickets;
     uint64_t next_ticket = 1;
     uint32_t busy = 0;
     bool stop = false;
+    bool stop_launchers = false;
     std::thread th;
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
 };
@@ -84,6 +92,7 @@ static void srv_finish(polymul_server *S, SrvSlot &slot, int rc)
     }
     S->arena.release(slot.plan.off, slot.plan.bytes);
     slot.busy = false;
+    slot.launched = false;
     slot.plan.reqs.clear();
     S->busy--;
 }
@@ -132,14 +141,40 @@ static int srv_launch(polymul_server *S, SrvSlot &slot)
     return 0;
 }
 
+// the launcher thread of one slot: enqueues each plan the scheduler admits on
+// the slot, without holding the server lock
+static void srv_launcher(polymul_server *S, SrvSlot *slot)
+{
+    (void)hipSetDevice(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->m);
+    for (;;) {
+        S->cv_launch.wait(lk, [S, slot] { return slot->go || S->stop_launchers; });
+        if (!slot->go) break;
+        slot->go = false;
+        lk.unlock();
+        const int rc = srv_launch(S, *slot);
+        // nothing of a failed launch runs past this point
+        if (rc) (void)hipStreamSynchronize(slot->stream);
+        lk.lock();
+        if (rc) {
+            srv_finish(S, *slot, rc);   // the message of this thread's failure
+            S->cv_done.notify_all();
+        } else {
+            slot->launched = true;
+        }
+        S->cv_work.notify_all();
+    }
+}
+
 static void srv_loop(polymul_server *S)
 {
     (void)hipSetDevice(S->ctx->device);
     std::unique_lock<std::mutex> lk(S->m);
     for (;;) {
-        // completions
+        // completions (an event not yet recorded reads as complete: only the
+        // launched slots are asked)
         for (SrvSlot &slot : S->slots) {
-            if (!slot.busy) continue;
+            if (!slot.busy || !slot.launched) continue;
             hipError_t q = hipEventQuery(slot.done);
             if (q == hipErrorNotReady) continue;
             srv_finish(S, slot, q == hipSuccess ? 0 : fail(POLYMUL_EIO, hipGetErrorString(q)));
@@ -158,13 +193,8 @@ static void srv_loop(polymul_server *S)
                 it->second.state = 1;
                 it->second.t_start = t;
             }
-            const int rc = srv_launch(S, slot);
-            if (rc) {
-                // nothing of this launch runs: finish its requests with the error
-                (void)hipStreamSynchronize(slot.stream);
-                srv_finish(S, slot, rc);
-                S->cv_done.notify_all();
-            }
+            slot.go = true;
+            S->cv_launch.notify_all();
         }
         if (S->stop && S->pending.empty() && S->busy == 0) break;
         if (S->busy)
@@ -227,6 +257,7 @@ int polymul_server_create(polymul_server **out, polymul_ctx *ctx, size_t hbm_bud
         return fail(POLYMUL_EIO, std::string("server streams: ") + hipGetErrorString(e));
     }
     polymul_server *raw = S.release();
+    for (SrvSlot &slot : raw->slots) slot.launcher = std::thread(srv_launcher, raw, &slot);
     raw->th = std::thread(srv_loop, raw);
     *out = raw;
     return 0;
@@ -240,7 +271,14 @@ int polymul_server_destroy(polymul_server *S)
         S->stop = true;
     }
     S->cv_work.notify_all();
-    if (S->th.joinable()) S->th.join();
+    if (S->th.joinable()) S->th.join();   // every admitted plan has completed
+    {
+        std::lock_guard<std::mutex> lk(S->m);
+        S->stop_launchers = true;
+    }
+    S->cv_launch.notify_all();
+    for (SrvSlot &slot : S->slots)
+        if (slot.launcher.joinable()) slot.launcher.join();
     DeviceGuard g(S->ctx->device);
     for (SrvSlot &slot : S->slots) {
         if (slot.stream) (void)hipStreamSynchronize(slot.stream);
