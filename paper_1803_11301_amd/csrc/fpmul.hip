@@ -777,7 +777,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
                 return rc;
         }
         if (mode == BF_PRODUCT)
-            KLAUNCH(ctx, s, "pointwise", k_pointwise<false>,
+            KLAUNCH(ctx, s, "pointwise", k_pointwise,
                     (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, A, B, n,
                     ctx->tables);
         if (mode != BF_FWD) {
@@ -805,7 +805,7 @@ static int run_butterflies(polymul_ctx *ctx, int mode, uint64_t *A, uint64_t *B,
         const unsigned bt = (unsigned)std::min<uint64_t>(1ull << (l - B2_TILE_LG), (uint64_t)ctx->num_cu * 2);
         if (mode == BF_PRODUCT) {
             KLAUNCH(ctx, s, "butterfly_bottom", k_bf2_bottom<BF_FWD>, dim3(bt, 2), B2_THREADS, A, B, l, ctx->tables);
-            KLAUNCH(ctx, s, "pointwise", k_pointwise<false>, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
+            KLAUNCH(ctx, s, "pointwise", k_pointwise, (unsigned)std::min<uint64_t>((n + 1023) / 1024,
                                                                                    (uint64_t)ctx->num_cu),
                     1024, A, B, n, ctx->tables);
             KLAUNCH(ctx, s, "ibutterfly_bottom", k_bf2_bottom<BF_INV>, bt, B2_THREADS, A, B, l, ctx->tables);
@@ -950,35 +950,32 @@ static int run_zeta(polymul_ctx *ctx, hipStream_t s, uint64_t *X, const uint64_t
                 KLAUNCH(ctx, s, name, k_bc_zeta_r<6>, dim3(g, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
             continue;
         }
-        if (nb <= 5 && !skew) {
+        if (nb <= 3 && !skew) {
             // one word position of 2^nb rows per thread, no tile (for the
             // skewed first pass of short operands the LDS tiles are faster:
             // 2^21 x 2^21 bits 0.129 ms against 0.133)
             const uint64_t groups = (1ull << (lgR - nb)) * (uint64_t)EW;
             const unsigned gs = (unsigned)std::min<uint64_t>((groups + 255) / 256, (uint64_t)ctx->num_cu * zeta_mult);
-            switch (nb) {
-            case 1:
-                KLAUNCH(ctx, s, name, k_bc_zeta_s<1>, dim3(gs, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
-                break;
-            case 2:
-                KLAUNCH(ctx, s, name, k_bc_zeta_s<2>, dim3(gs, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
-                break;
-            case 3:
-                KLAUNCH(ctx, s, name, k_bc_zeta_s<3>, dim3(gs, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
-                break;
-            case 4:
-                KLAUNCH(ctx, s, name, k_bc_zeta_s<4>, dim3(gs, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
-                break;
-            default:
-                KLAUNCH(ctx, s, name, k_bc_zeta_s<5>, dim3(gs, ny), 256, X, in, len, lgR, EW, b0, skew, X1, in1, len1);
-                break;
-            }
+            if (nb == 1)
+                KLAUNCH(ctx, s, name, k_bc_zeta_s<1>, dim3(gs, ny), 256, X, lgR, EW, b0, X1);
+            else if (nb == 2)
+                KLAUNCH(ctx, s, name, k_bc_zeta_s<2>, dim3(gs, ny), 256, X, lgR, EW, b0, X1);
+            else
+                KLAUNCH(ctx, s, name, k_bc_zeta_s<3>, dim3(gs, ny), 256, X, lgR, EW, b0, X1);
             continue;
         }
         KLAUNCH(ctx, s, name, k_bc_zeta, dim3(grid, ny), BC_THREADS, X, in, len, lgR, EW, b0, nb, lgWc, skew, X1, in1,
                 len1);
     }
     return 0;
+}
+
+// workgroups of k_square for n values: eight per CU (16 KiB of LDS each),
+// fewer for short transforms
+static unsigned square_grid(const polymul_ctx *ctx, uint64_t n)
+{
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + SQ_THREADS - 1) / SQ_THREADS,
+                                                              (uint64_t)ctx->num_cu * 8));
 }
 
 // rows of 2^16 bits in the fused BasisCvt of a len-bit operand: 2^lgR
@@ -1269,9 +1266,7 @@ static int product_body(polymul_ctx *ctx, const uint64_t *a, uint64_t len_a, con
     if (square) {
         const uint64_t nw = 1ull << (log2n - 6);
         if ((rc = run_butterflies(ctx, BF_FWD, pa, nullptr, log2n - 6, s))) return rc;
-        KLAUNCH(ctx, s, "pointwise", k_pointwise<true>,
-                (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, pa, nullptr, nw,
-                ctx->tables);
+        KLAUNCH(ctx, s, "pointwise", k_square, square_grid(ctx, nw), SQ_THREADS, pa, nw, ctx->tables);
         if ((rc = run_butterflies(ctx, BF_INV, pa, nullptr, log2n - 6, s))) return rc;
     } else if ((rc = run_butterflies(ctx, BF_PRODUCT, pa, pb, log2n - 6, s))) {
         return rc;
@@ -1337,7 +1332,7 @@ static int resident_body(polymul_ctx *ctx, const uint64_t *fa, int log2n, const 
         if ((rc = run_encode_in(ctx, b, len_b, log2n, cur, spare, s))) return rc;
     }
     if ((rc = run_butterflies(ctx, BF_FWD, cur, nullptr, log2n - 6, s))) return rc;
-    KLAUNCH(ctx, s, "pointwise", k_pointwise<false>,
+    KLAUNCH(ctx, s, "pointwise", k_pointwise,
             (unsigned)std::min<uint64_t>((nw + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, cur, fa, nw, ctx->tables);
     if ((rc = run_butterflies(ctx, BF_INV, cur, nullptr, log2n - 6, s))) return rc;
     if (fast_path(log2n)) return run_decode_fast(ctx, cur, log2n, out, lc, ctx->ws[2], ctx->ws[3], s);
@@ -1519,6 +1514,13 @@ static void fill_dev_tables(const fpmul_host::Tables &H, DevTables &D)
         }
     for (int d = 0; d < 32; ++d)
         for (int t = 0; t < 64; ++t) D.gbasis[d][t] = tw.m64(H.cantor[32 + d], 1ull << t);
+    // squaring is GF(2)-linear (characteristic 2): x^2 is the XOR of the
+    // squares of x's byte windows
+    for (int k = 0; k < 8; ++k)
+        for (int e = 0; e < 256; ++e) {
+            const uint64_t x = (uint64_t)e << (8 * k);
+            D.sq_win[k][e] = tw.m64(x, x);
+        }
     for (int v = 0; v < 24; ++v)
         for (int t = 0; t < 64; ++t) D.pbasis[v][t] = tw.m64(H.cantor[8 + v], 1ull << t);
     std::memcpy(D.mul8, tw.mul8, sizeof(D.mul8));
@@ -2303,11 +2305,12 @@ int polymul_pointwise(polymul_ctx *ctx, const uint64_t *fa, const uint64_t *fb, 
     } else if (fc != fa) {
         HIP_TRY(hipMemcpyAsync(fc, fa, bytes, hipMemcpyDeviceToDevice, s));
     }
-    const unsigned grid = (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu);
     if (fa == fb)   // a square: fc holds fa's values now
-        KLAUNCH(ctx, s, "pointwise", k_pointwise<true>, grid, 1024, fc, nullptr, n, ctx->tables);
+        KLAUNCH(ctx, s, "pointwise", k_square, square_grid(ctx, n), SQ_THREADS, fc, n, ctx->tables);
     else
-        KLAUNCH(ctx, s, "pointwise", k_pointwise<false>, grid, 1024, fc, other, n, ctx->tables);
+        KLAUNCH(ctx, s, "pointwise", k_pointwise,
+                (unsigned)std::min<uint64_t>((n + 1023) / 1024, (uint64_t)ctx->num_cu), 1024, fc, other, n,
+                ctx->tables);
     return 0;
 }
 

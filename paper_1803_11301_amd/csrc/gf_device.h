@@ -33,6 +33,7 @@ struct DevTables {
     uint32_t dec32_win[4][256];  // Decode: byte window k of the value -> bits
     uint32_t kt32[16][1024];     // window tables of v_{16+d}: [d][256 k + e] = v_{16+d} * (e at byte k)
     uint16_t mulp[256][256];     // GF(2^8) products with their v_7 multiples: p | (v_7 p) << 8, p = a b
+    uint64_t sq_win[8][256];     // squares: byte window k of a value -> (e << 8k)^2
 };
 
 // ----------------------------------------------------------------- tmul ----

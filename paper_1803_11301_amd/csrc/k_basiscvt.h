@@ -483,22 +483,17 @@ __global__ __launch_bounds__(BC_THREADS) void k_bc_zeta(uint64_t *X0, const uint
     }
 }
 
-// The same superset sums over few row bits (NB = 1 .. 5), for the passes
+// The same superset sums over few row bits (NB = 1 .. 3), for the passes
 // left over after a register-tile pass, whose tiles would hold too little
-// work per workgroup: each thread takes one word
-// position of the 2^NB rows that differ in bits [b0, b0 + NB), sums them in
-// registers and stores all but the last (which no sum changes).  Consecutive
-// threads take consecutive words of a row.  Operands by blockIdx.y as in
-// k_bc_zeta; skew_in as there.
+// work per workgroup: each thread takes one word position of the 2^NB rows
+// that differ in bits [b0, b0 + NB), sums them in registers and stores all
+// but the last (which no sum changes).  Consecutive threads take consecutive
+// words of a row.  Operands by blockIdx.y as in k_bc_zeta.
 template <int NB>
-__global__ __launch_bounds__(256) void k_bc_zeta_s(uint64_t *X0, const uint64_t *in0, uint64_t len0, int lgR, int EW,
-                                                   int b0, int skew_in, uint64_t *X1, const uint64_t *in1,
-                                                   uint64_t len1)
+__global__ __launch_bounds__(256) void k_bc_zeta_s(uint64_t *X0, int lgR, int EW, int b0, uint64_t *X1)
 {
+    static_assert(NB >= 1 && NB <= 3, "short passes only");
     uint64_t *__restrict__ X = blockIdx.y ? X1 : X0;
-    const uint64_t *__restrict__ in = blockIdx.y ? in1 : in0;
-    const uint64_t len = blockIdx.y ? len1 : len0;
-    const uint64_t inwords = (len + 63) / 64;
     const uint64_t ngroups = (1ull << (lgR - NB)) * (uint64_t)EW;
     for (uint64_t gi = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; gi < ngroups;
          gi += (uint64_t)gridDim.x * blockDim.x) {
@@ -507,33 +502,14 @@ __global__ __launch_bounds__(256) void k_bc_zeta_s(uint64_t *X0, const uint64_t 
         const uint64_t r0 = ((rt >> b0) << (b0 + NB)) | (rt & ((1ull << b0) - 1));
         uint64_t v[1 << NB];
 #pragma unroll
-        for (int k = 0; k < (1 << NB); ++k) {
-            const uint64_t r = r0 | ((uint64_t)k << b0);
-            if (skew_in) {
-                // stored word w of row r = bits [64 w - r, 64 w - r + 64) of the input row r
-                const long off = 64L * w - (long)r;
-                const uint64_t rb = r * BC_TAU_WORDS;
-                const long i0 = off >> 6;
-                const int sh = (int)(off & 63);
-                uint64_t a = 0, b = 0;
-                if (i0 >= 0 && i0 < BC_TAU_WORDS && rb + i0 < inwords) a = in[rb + i0];
-                if (i0 + 1 >= 0 && i0 + 1 < BC_TAU_WORDS && rb + i0 + 1 < inwords) b = in[rb + i0 + 1];
-                if ((len & 63) && i0 >= 0 && rb + i0 == inwords - 1) a &= (~0ull) >> (64 - (len & 63));
-                if ((len & 63) && i0 + 1 >= 0 && rb + i0 + 1 == inwords - 1) b &= (~0ull) >> (64 - (len & 63));
-                v[k] = sh ? ((a >> sh) | (b << (64 - sh))) : a;
-            } else {
-                v[k] = X[r * EW + w];
-            }
-        }
+        for (int k = 0; k < (1 << NB); ++k) v[k] = X[(r0 | ((uint64_t)k << b0)) * EW + w];
 #pragma unroll
         for (int t = 0; t < NB; ++t)
 #pragma unroll
             for (int k = 0; k < (1 << NB); ++k)
                 if (!((k >> t) & 1)) v[k] ^= v[k | (1 << t)];
-        // with a skewed input every row is new; else the last row is unchanged
 #pragma unroll
-        for (int k = 0; k < (1 << NB); ++k)
-            if (skew_in || k < (1 << NB) - 1) X[(r0 | ((uint64_t)k << b0)) * EW + w] = v[k];
+        for (int k = 0; k < (1 << NB) - 1; ++k) X[(r0 | ((uint64_t)k << b0)) * EW + w] = v[k];
     }
 }
 

@@ -526,9 +526,7 @@ __global__ __launch_bounds__(B2_THREADS, 2) void k_bf2_bottom(uint64_t *A0, uint
 
 // ------------------------------------------------------------ pointwise ---
 // A[j] = A[j] * B[j] (Alg. 5, the pointwise step), tower Karatsuba with the
-// GF(2^8) pair table in LDS (MulPairView layout); one workgroup per CU.
-// SQ: A[j] = A[j]^2 (B is not read; one transform squared)
-template <bool SQ = false>
+// GF(2^8) pair table in LDS (MulPairView layout); one workgroup per CU
 __global__ __launch_bounds__(1024) void k_pointwise(uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
                                                     uint64_t n, const DevTables *__restrict__ T)
 {
@@ -551,13 +549,31 @@ __global__ __launch_bounds__(1024) void k_pointwise(uint64_t *__restrict__ A, co
 #pragma unroll
         for (int k = 0; k < PW_ILP; ++k) {
             a[k] = A[j + k * G];
-            b[k] = SQ ? a[k] : B[j + k * G];
+            b[k] = B[j + k * G];
         }
 #pragma unroll
         for (int k = 0; k < PW_ILP; ++k) A[j + k * G] = mv.m64(a[k], b[k]);
     }
-    for (; j < n; j += G) {
+    for (; j < n; j += G) A[j] = mv.m64(A[j], B[j]);
+}
+
+// A[j] = A[j]^2: the pointwise step of a square (Alg. 5 with both transforms
+// equal).  Squaring is GF(2)-linear in characteristic 2, so a value's square
+// is the XOR of its eight byte windows' squares, one lookup each in a 16 KiB
+// table in LDS; the kernel streams the transform once.
+#define SQ_THREADS 256
+__global__ __launch_bounds__(SQ_THREADS) void k_square(uint64_t *__restrict__ A, uint64_t n,
+                                                       const DevTables *__restrict__ T)
+{
+    __shared__ uint64_t s_sq[8][256];
+    for (int q = threadIdx.x; q < 8 * 256; q += blockDim.x) (&s_sq[0][0])[q] = (&T->sq_win[0][0])[q];
+    __syncthreads();
+    const uint64_t G = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += G) {
         const uint64_t x = A[j];
-        A[j] = mv.m64(x, SQ ? x : B[j]);
+        uint64_t r = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) r ^= s_sq[k][(x >> (8 * k)) & 255u];
+        A[j] = r;
     }
 }
