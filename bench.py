@@ -116,21 +116,21 @@ STAGES = [
 COUNTER_SOURCES = ("paper_1803_11301_amd/csrc/fpmul.hip", "paper_1803_11301_amd/csrc/k_basiscvt.h",
                    "paper_1803_11301_amd/csrc/k_bf3.h", "paper_1803_11301_amd/csrc/k_bf2.h",
                    "paper_1803_11301_amd/csrc/gf_device.h")
-COUNTERS_SHA256 = "efdedc0bec8464857487ec50411321ece118c9254ead50c2835caab5622cab04"
+COUNTERS_SHA256 = "e42b846d2daf55ef9d39942581a388064e3bf43ae2be8f729d77ccebc9ab1725"
 COUNTERS = {
     # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB, SQ_INSTS_VALU) per dispatch
     "basiscvt_zeta": (213081, 327680, 2.715e+07),
-    "basiscvt_rows": (151677, 262144, 1.181e+08),
-    "basiscvt_outer_encode": (131401, 524288, 1.463e+08),
-    "butterfly_upper": (262516, 524288, 1.475e+08),
-    "butterfly_bottom": (262612, 524288, 3.087e+08),
-    "pointwise": (262762, 262144, 1.05e+08),
+    "basiscvt_rows": (151700, 262144, 1.181e+08),
+    "basiscvt_outer_encode": (131399, 524288, 1.463e+08),
+    "butterfly_upper": (262514, 524288, 1.475e+08),
+    "butterfly_bottom": (262606, 524288, 3.087e+08),
+    "pointwise": (262770, 262144, 1.05e+08),
     "ibutterfly_bottom": (131478, 262144, 1.529e+08),
     "ibutterfly_upper": (131371, 262144, 7.336e+07),
-    "decode_outer": (131537, 262144, 1.41e+08),
-    "ibasiscvt_rows": (132548, 393216, 1.139e+08),
+    "decode_outer": (131472, 262144, 1.41e+08),
+    "ibasiscvt_rows": (132524, 393216, 1.139e+08),
     "ibasiscvt_zeta": (196694, 393216, 2.047e+07),
-    "ibasiscvt_store": (168408, 262144, 1.91e+07),
+    "ibasiscvt_store": (168444, 262144, 1.91e+07),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 

@@ -195,7 +195,9 @@ int polymul_set_large_field(polymul_ctx *ctx, int min_log2n);
  * grid, up to one row group per workgroup).  polymul_tune times them on ctx's device for 2^log2n-bit
  * transforms (operands of 2^(log2n-1) bits from a fixed generator; the path
  * is data-oblivious), by coordinate descent from the default with `reps`
- * timed products per choice (1..100), keeps the fastest in ctx, checks
+ * timed products per choice (1..100), keeps the fastest in ctx (a choice
+ * other than the default only if, timed again alternately with the default
+ * three times each, its median is 0.5% faster), checks
  * that it gives the default schedule's product word for word
  * (POLYMUL_EIO otherwise, the previous choice kept), appends the line
  * "<arch> cu=<CUs> log2n=<k> upper=<a,b,..> rows=<r> zeta=<z> ms=<t>" to
