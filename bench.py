@@ -108,7 +108,7 @@ STAGES = [
 ]
 
 # Counters per dispatch measured with rocprofv3 on the 2^30 x 2^30-bit product
-# (profiles/): FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
+# (profiles/), and applied to that workload only: FETCH_SIZE and WRITE_SIZE in KiB, each scaled by what the
 # counter reads for a plain 1 GiB device copy (fetch x2.000, write x1.000), and
 # SQ_INSTS_VALU (wave instructions summed over the chip).  They hold only for
 # the kernel sources they were taken on: the sha256 of the listed files must
@@ -116,21 +116,21 @@ STAGES = [
 COUNTER_SOURCES = ("paper_1803_11301_amd/csrc/fpmul.hip", "paper_1803_11301_amd/csrc/k_basiscvt.h",
                    "paper_1803_11301_amd/csrc/k_bf3.h", "paper_1803_11301_amd/csrc/k_bf2.h",
                    "paper_1803_11301_amd/csrc/gf_device.h")
-COUNTERS_SHA256 = "e42b846d2daf55ef9d39942581a388064e3bf43ae2be8f729d77ccebc9ab1725"
+COUNTERS_SHA256 = "0fa576d8b43d28be870b1854605f1dd2fcd8ac5fa926cb80bbc653e39e3b076e"
 COUNTERS = {
     # kernel: (FETCH_SIZE KiB, WRITE_SIZE KiB, SQ_INSTS_VALU) per dispatch
     "basiscvt_zeta": (213081, 327680, 2.715e+07),
-    "basiscvt_rows": (151700, 262144, 1.181e+08),
+    "basiscvt_rows": (151725, 262144, 1.181e+08),
     "basiscvt_outer_encode": (131399, 524288, 1.463e+08),
     "butterfly_upper": (262514, 524288, 1.475e+08),
     "butterfly_bottom": (262606, 524288, 3.087e+08),
-    "pointwise": (262770, 262144, 1.05e+08),
+    "pointwise": (262769, 262144, 1.05e+08),
     "ibutterfly_bottom": (131478, 262144, 1.529e+08),
     "ibutterfly_upper": (131371, 262144, 7.336e+07),
     "decode_outer": (131472, 262144, 1.41e+08),
-    "ibasiscvt_rows": (132524, 393216, 1.139e+08),
+    "ibasiscvt_rows": (132739, 393216, 1.139e+08),
     "ibasiscvt_zeta": (196694, 393216, 2.047e+07),
-    "ibasiscvt_store": (168444, 262144, 1.91e+07),
+    "ibasiscvt_store": (168391, 262144, 1.91e+07),
 }
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
@@ -656,9 +656,12 @@ def bench_latency(ctx, names=("small", "mid"), runs=(100, 20)):
     return res
 
 
-def kernel_table(prof: dict, steps: int, A: int, B: int, N: int, log2n: int, la_log2: int, fused: bool):
+def kernel_table(prof: dict, steps: int, A: int, B: int, N: int, log2n: int, la_log2: int, fused: bool,
+                 counters_apply: bool = True):
     """Per-kernel times with their algorithmic bytes, achieved rate, measured
-    traffic and VALU utilisation; and the dominant kernel's roofline entry."""
+    traffic and VALU utilisation (the stored counters: only for the workload
+    they were taken on, counters_apply); and the dominant kernel's roofline
+    entry."""
     kb = kernel_bytes_per_product(A, B, N, log2n, la_log2) if fused else {}
     per_kernel = {}
     for name, (cnt, tot) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
@@ -673,10 +676,10 @@ def kernel_table(prof: dict, steps: int, A: int, B: int, N: int, log2n: int, la_
             rec["algorithmic_bytes_per_launch"] = int(per_launch)
             rec["achieved_GBs"] = round(per_launch / avg_s / 1e9, 1)
             rec["hbm_frac"] = round(per_launch / avg_s / 1e9 / HBM_PEAK_GBS, 4)
-            t = measured_traffic(name)
+            t = measured_traffic(name) if counters_apply else None
             rec["traffic_bytes_per_launch"] = t
             rec["traffic_over_algorithmic"] = None if t is None else round(t / per_launch, 3)
-        v = valu_utilisation(name, avg_s)
+        v = valu_utilisation(name, avg_s) if counters_apply else None
         rec["valu_utilisation"] = None if v is None else round(v, 3)
         per_kernel[name] = rec
         log(f"[bench] {name:26s} {cnt / steps:6.1f} launches/step {tot / steps:9.4f} ms/step "
@@ -701,7 +704,7 @@ def kernel_table(prof: dict, steps: int, A: int, B: int, N: int, log2n: int, la_
                 continue
             ms = sum(prof[k][1] for k in ks) / steps
             nb = fn(A, B, N)
-            tr = [measured_traffic(k) for k in ks]
+            tr = [measured_traffic(k) if counters_apply else None for k in ks]
             traffic = None if any(t is None for t in tr) else sum(t * prof[k][0] / steps for t, k in zip(tr, ks))
             stages.append({"stage": stage, "kernels": ks, "ms_per_product": round(ms, 4), "nominal_bytes": nb,
                            "achieved_GBs": round(nb / (ms / 1e3) / 1e9, 1),
@@ -845,7 +848,8 @@ def main():
     N = (1 << log2n) // 8
     nominal = nominal_bytes(A, B, N)
     fused = 22 <= log2n <= 31
-    per_kernel, roof, stages = kernel_table(prof, args.steps, A, B, N, log2n, L.bit_length() - 1, fused)
+    per_kernel, roof, stages = kernel_table(prof, args.steps, A, B, N, log2n, L.bit_length() - 1, fused,
+                                            counters_apply=args.workload == "large")
     # multiplications by constants in the butterfly kernels: (l/2) n_p per
     # transform, three transforms; their rate per CU per clock
     bfly = [n for n in prof if "butterfly" in n]

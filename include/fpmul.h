@@ -192,7 +192,9 @@ int polymul_set_large_field(polymul_ctx *ctx, int min_log2n);
  * way whose lowest pass has at least 12 minus the bottom's layers, and the
  * row and zeta kernels of BasisCvt (Alg. 1) with 1, 2, 4 or 8 and 4, 8, 16
  * or 32 workgroups per CU (the inverse row kernel with four times the row
- * grid, up to one row group per workgroup).  polymul_tune times them on ctx's device for 2^log2n-bit
+ * grid, up to one row group per workgroup; below 2^26-bit transforms the
+ * butterflies take a fixed split and only the grids are searched).
+ * polymul_tune times them on ctx's device for 2^log2n-bit
  * transforms (operands of 2^(log2n-1) bits from a fixed generator; the path
  * is data-oblivious), by coordinate descent from the default with `reps`
  * timed products per choice (1..100), keeps the fastest in ctx (a choice

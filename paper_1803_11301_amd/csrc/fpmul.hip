@@ -2065,7 +2065,9 @@ int polymul_tune(polymul_ctx *ctx, int log2n, int reps, const char *cache_path, 
         }
         return r;
     };
-    for (const auto &u : fpmul_plan::upper_candidates(l)) {
+    // below BF3_MIN_L transform values the short-transform passes take their
+    // own fixed split: only the grids are searched
+    for (const auto &u : l >= BF3_MIN_L ? fpmul_plan::upper_candidates(l) : std::vector<std::vector<int>>()) {
         if (u == best.upper) continue;
         fpmul_plan::Schedule sc = best;
         sc.upper = u;
