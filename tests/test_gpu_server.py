@@ -289,3 +289,62 @@ def test_server_tuner_on_a_small_mix(ctx):
     for x, y, ta, tb, out in ops:
         n = O.nwords(x + y - 1)
         assert np.array_equal(host(out, n), host(ctx.polymul(ta, x, tb, y), n)), (x, y)
+
+
+def _mixed_requests(seed, count, lo=10, hi=22):
+    rng = np.random.default_rng(seed)
+    la = np.floor(np.exp2(lo + (hi - lo) * rng.random(count))).astype(np.int64)
+    lb = np.floor(np.exp2(lo + (hi - lo) * rng.random(count))).astype(np.int64)
+    ops = []
+    for k in range(count):
+        x, y = int(la[k]), int(lb[k])
+        a, b = synth.dense_poly(seed + 2 * k, x), synth.dense_poly(seed + 2 * k + 1, y)
+        ops.append((x, y, dev64(a), dev64(b), torch.zeros(O.nwords(x + y - 1), dtype=torch.int64, device="cuda")))
+    torch.cuda.synchronize()
+    return ops
+
+
+def test_destroy_completes_outstanding_requests(ctx):
+    # the server is destroyed with every request still outstanding: destroy
+    # returns once all of them ran (their launcher threads stop after that)
+    from paper_1803_11301_amd import fpmul
+    ops = _mixed_requests(0x5EED0580, 120)
+    say("destroy with", len(ops), "outstanding requests")
+    srv = fpmul.Server(ctx, hbm_budget=1 << 30, slots=6)
+    for x, y, ta, tb, out in ops:
+        srv.submit(ta, x, tb, y, out)
+    srv.close()
+    for x, y, ta, tb, out in ops[::7]:
+        n = O.nwords(x + y - 1)
+        assert np.array_equal(host(out, n), host(ctx.polymul(ta, x, tb, y), n)), (x, y)
+
+
+def test_submits_from_several_host_threads(ctx):
+    # four host threads submit and wait at once; every product is right
+    import threading
+    from paper_1803_11301_amd import fpmul
+    ops = _mixed_requests(0x5EED0590, 160)
+    say("4 threads x", len(ops) // 4, "requests")
+    srv = fpmul.Server(ctx, hbm_budget=1 << 30, slots=8)
+    errors = []
+
+    def worker(part):
+        try:
+            tks = [srv.submit(ta, x, tb, y, out) for x, y, ta, tb, out in part]
+            for tk in tks:
+                srv.wait(tk)
+        except Exception as ex:   # reported below, in the test's own thread
+            errors.append(ex)
+
+    threads = [threading.Thread(target=worker, args=(ops[k::4],)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+    assert not any(th.is_alive() for th in threads), "a submitting thread did not finish"
+    assert not errors, errors
+    assert srv.outstanding() == 0
+    srv.close()
+    for x, y, ta, tb, out in ops[::9]:
+        n = O.nwords(x + y - 1)
+        assert np.array_equal(host(out, n), host(ctx.polymul(ta, x, tb, y), n)), (x, y)
