@@ -86,6 +86,31 @@ def test_product_graph_replays(ctx, name, la, lb):
         g.close()
 
 
+def test_square_graph_replays(ctx):
+    # a square (one buffer for both operands) is captured as one forward
+    # transform and the squares; each replay reads the buffer's new contents
+    from paper_1803_11301_amd import fpmul
+    la = (1 << 20) + 77
+    say("graph square", la)
+    nw = (2 * la - 1 + 63) // 64
+    a = dev(synth.dense_poly(0x5EED0B80, la))
+    out = torch.full((nw,), -1, dtype=torch.int64, device="cuda")
+    g = fpmul.Graph.product(ctx, a, la, a, la, out)
+    try:
+        for rep in range(3):
+            if rep:
+                a.copy_(dev(synth.dense_poly(0x5EED0B80 + rep, la)))
+            out.fill_(-1)
+            g.launch()
+            torch.cuda.synchronize()
+            A = host(a)
+            got = host(out)
+            assert np.array_equal(got, host(ctx.polymul(a, la, a, la))), f"square replay {rep}"
+            assert np.array_equal(got, O.polymul(A, la, A, la, threads=4)), f"square replay {rep}"
+    finally:
+        g.close()
+
+
 def test_batch_graph_replays_with_new_lengths(ctx):
     from paper_1803_11301_amd import fpmul
     count, max_bits = 96, 1 << 21

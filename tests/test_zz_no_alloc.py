@@ -86,6 +86,29 @@ def test_noalloc_between_mid_sizes(ctx):
     assert np.array_equal(host(got), O.polymul(a, la, b, lb, threads=4))
 
 
+def test_noalloc_square(ctx):
+    # the same buffer twice: one forward transform in the scratch, squared
+    la = (1 << 22) + 3
+    say("polymul_ex_noalloc square", la)
+    a = synth.dense_poly(0x5EED0A15, la)
+    ta = dev(a)
+    nw = (2 * la - 1 + 63) // 64
+    got, ref = poisoned(nw), poisoned(nw)
+    ctx.polymul_noalloc(ta, la, ta, la, got)
+    ctx.polymul(ta, la, ta, la, out=ref)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(got), host(ref))
+    spread = np.zeros(2 * nw, dtype=np.uint64)   # bit i of A at bit 2i (Frobenius)
+    w = np.asarray(a, dtype=np.uint64)
+    for half, sh in ((0, 0), (1, 32)):
+        x = (w >> np.uint64(sh)) & np.uint64(0xFFFFFFFF)
+        for s_, m in ((16, 0x0000FFFF0000FFFF), (8, 0x00FF00FF00FF00FF), (4, 0x0F0F0F0F0F0F0F0F),
+                      (2, 0x3333333333333333), (1, 0x5555555555555555)):
+            x = (x | (x << np.uint64(s_))) & np.uint64(m)
+        spread[half:2 * w.size:2] = x
+    assert np.array_equal(host(got), spread[:nw])
+
+
 def test_noalloc_rejects_longer_products(ctx):
     from paper_1803_11301_amd import fpmul
     # host-side check: nothing is launched
