@@ -94,8 +94,14 @@ def tune_server(ctx, len_a, len_b, candidates=DEFAULT_CANDIDATES, rho: float = 0
             tks = []
             t0 = time.perf_counter()
             for k in range(n):
-                while time.perf_counter() - t0 < due[k]:
-                    pass
+                # sleep through the longer gaps, spin the last 0.1 ms (the
+                # launcher threads of the server need the host's cores too)
+                while True:
+                    left = due[k] - (time.perf_counter() - t0)
+                    if left <= 0:
+                        break
+                    if left > 2e-4:
+                        time.sleep(left - 1e-4)
                 tks.append(srv.submit(*args[k]))
             done = [srv.wait(tk) for tk in tks]
         finally:
