@@ -67,9 +67,9 @@ typedef struct polymul_ctx polymul_ctx;
  *      len_a + len_b - 1 bits are written and the rest of the last word is
  *      zeroed.  If len_a or len_b is 0 the product is empty and nothing is
  *      written.  out must not overlap a_bits or b_bits.
- * The same pointer and length for both operands make a square: from 2^17
- * bits it takes one forward transform, squared pointwise (Alg. 5 with both
- * transforms equal).
+ * The same pointer and length for both operands make a square: a product
+ * of more than 2^16 bits then takes one forward transform, squared
+ * pointwise (Alg. 5 with both transforms equal).
  * Uses a context owned by the library for the current HIP device and that
  * device's null stream; returns after the result is in out.
  * len_a + len_b - 1 > POLYMUL_MAX_PRODUCT_BITS -> POLYMUL_EINVAL.
