@@ -39,3 +39,18 @@ def test_binding_refuses_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(fpmul, "_lib", None)
     with pytest.raises(FileNotFoundError):
         fpmul.lib()
+
+
+def test_library_exports_nothing_undeclared():
+    # every polymul* function the library exports is declared in fpmul.h
+    import shutil
+    import subprocess
+    from paper_1803_11301_amd import fpmul
+    if not os.path.exists(fpmul.LIB_PATH) or not shutil.which("nm"):
+        pytest.skip("libfpmul.so not built or nm missing")
+    out = subprocess.run(["nm", "-D", "--defined-only", fpmul.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {f[2] for f in (line.split() for line in out.splitlines())
+                if len(f) == 3 and f[1] == "T" and f[2].startswith("polymul")}
+    assert exported, "no polymul* symbols found"
+    assert exported <= set(declared_functions()), sorted(exported - set(declared_functions()))
